@@ -1,0 +1,294 @@
+"""Pins for the dense oracle: each check compares it with something other than itself.
+
+* brute-force (Leibniz) determinants on tiny inputs,
+* closed-form spectral log-determinants of the prior (cosine eigenbasis of the grid Laplacian,
+  continuant recurrence for the per-mode temporal tridiagonals),
+* complex-step derivatives (analytic to rounding) of the prior precision and of the objective
+  evaluated through LU instead of Cholesky,
+* exact special cases (no observations; the theta1 scale identity; theta1 + tau identity),
+* the coregional weights of Eq. 9 written directly from the paper,
+* BTA selected-inverse identities.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_model, named_config, neumann_second_difference
+from workloads.bta import random_bta
+
+
+def leibniz_det(M):
+    n = M.shape[0]
+    total = 0.0
+    for perm in itertools.permutations(range(n)):
+        inv = sum(1 for i in range(n) for j in range(i + 1, n) if perm[i] > perm[j])
+        prod = 1.0
+        for i in range(n):
+            prod *= M[i, perm[i]]
+        total += (-1) ** inv * prod
+    return total
+
+
+def continuant_logdet(diag, off):
+    """log det of a symmetric tridiagonal matrix by the three-term continuant recurrence."""
+    f_prev, f = 1.0, diag[0]
+    logscale = 0.0
+    for t in range(1, len(diag)):
+        f_prev, f = f, diag[t] * f - off[t - 1] ** 2 * f_prev
+        s = abs(f)
+        f_prev, f = f_prev / s, f / s
+        logscale += np.log(s)
+    return logscale + np.log(f) + (0.0 if len(diag) > 1 else 0.0)
+
+
+def spectral_field_logdet(model, rng_par, tmp_par):
+    """log|M0 (x) K2 + e^tmp M1 (x) K1 + M2 (x) c0| via the closed-form Neumann eigenvalues."""
+    jx = np.arange(model.nx)
+    jy = np.arange(model.ny)
+    lx = 4 * np.sin(np.pi * jx / (2 * model.nx)) ** 2
+    ly = 4 * np.sin(np.pi * jy / (2 * model.ny)) ** 2
+    mu = (ly[:, None] + lx[None, :]).reshape(-1) + 0.1
+    k2 = np.exp(2 * rng_par)
+    m0d, m0o = model.m0
+    m1d, m1o = model.m1
+    m2d, m2o = model.m2
+    total = 0.0
+    for u in mu:
+        K1 = k2 + u
+        K2 = k2 * k2 + 2 * k2 * u + u * u
+        diag = m0d * K2 + np.exp(tmp_par) * m1d * K1 + m2d
+        off = m0o * K2 + np.exp(tmp_par) * m1o * K1 + m2o
+        total += continuant_logdet(diag, off)
+    return total
+
+
+def tiny_model(seed=3, a=1, obs=2):
+    return make_model(1, 2, 1, 2, a, obs, seed)
+
+
+# --------------------------------------------------------------------------------------------
+
+def test_generator_deterministic():
+    m1 = named_config("uni_6x5_nt5", seed=5)
+    m2 = named_config("uni_6x5_nt5", seed=5)
+    for f in ("obs_node", "obs_w", "X", "y", "theta"):
+        assert np.array_equal(getattr(m1, f), getattr(m2, f))
+    m3 = named_config("uni_6x5_nt5", seed=6)
+    assert not np.array_equal(m1.y, m3.y)
+
+
+def test_leibniz_logdets_tiny():
+    m = tiny_model()
+    assert m.N <= 7
+    ev = oracle.objective(m, m.theta)
+    assert np.isclose(ev["logdet_p"], np.log(leibniz_det(ev["Qp"])), rtol=1e-13, atol=1e-13)
+    assert np.isclose(ev["logdet_c"], np.log(leibniz_det(ev["Qc"])), rtol=1e-13, atol=1e-13)
+
+
+def test_bta_pattern_of_prior():
+    m = named_config("uni_6x5_nt5", seed=1)
+    Qp = oracle.prior_precision(m, m.theta)
+    b = m.b
+    for i in range(m.nt - 2):
+        assert np.all(Qp[(i + 2) * b:(i + 3) * b, i * b:(i + 1) * b] == 0.0)
+    assert np.all(Qp[:m.nt * b, m.nt * b:] == 0.0)  # prior has no arrow
+    assert np.array_equal(Qp, Qp.T)
+
+
+@pytest.mark.parametrize("name,seed", [("uni_6x5_nt5", 0), ("uni_8x8_nt8", 1), ("uni_9x7_nt4", 2)])
+def test_prior_logdet_spectral_univariate(name, seed):
+    m = named_config(name, seed=seed)
+    th = m.theta
+    ld = oracle.objective(m, th)["logdet_p"]
+    ref = m.ns * m.nt * th[0] + spectral_field_logdet(m, th[1], th[2]) + m.a * np.log(m.tip_prec)
+    assert np.isclose(ld, ref, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("name,seed", [("coreg3_4x4_nt4", 0), ("coreg3_5x4_nt3", 4)])
+def test_prior_logdet_spectral_coreg(name, seed):
+    m = named_config(name, seed=seed)
+    th = m.theta
+    lay = oracle.theta_layout(m)
+    ld = oracle.objective(m, th)["logdet_p"]
+    ref = sum(spectral_field_logdet(m, th[lay["range"][j]], th[lay["temporal"][j]]) for j in range(m.k))
+    ref += m.ns * m.nt * sum(th[i] for i in lay["prec"])  # -2 nt ns log|Lambda|
+    ref += m.a * np.log(m.tip_prec)
+    assert np.isclose(ld, ref, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("name", ["uni_6x5_nt5", "coreg3_4x4_nt4"])
+def test_jacobian_complex_step(name):
+    m = named_config(name, seed=2)
+    J = oracle.prior_precision_jacobian(m, m.theta)
+    h = 1e-30
+    for k in range(m.d):
+        th = m.theta.astype(complex)
+        th[k] += 1j * h
+        cs = oracle.prior_precision(m, th).imag / h
+        scale = max(np.abs(cs).max(), 1.0)
+        assert np.abs(J[k] - cs).max() <= 1e-13 * scale, k
+
+
+@pytest.mark.parametrize("name,seed", [("uni_6x5_nt5", 0), ("coreg3_4x4_nt4", 1), ("uni_9x7_nt4", 3)])
+def test_gradient_complex_step(name, seed):
+    m = named_config(name, seed=seed)
+    g = oracle.gradient(m, m.theta)["grad"]
+    h = 1e-30
+    cs = np.zeros(m.d)
+    for k in range(m.d):
+        th = m.theta.astype(complex)
+        th[k] += 1j * h
+        cs[k] = oracle.objective(m, th, factor="lu")["f"].imag / h
+    assert np.abs(g - cs).max() <= 1e-11 * np.abs(cs).max()
+
+
+def test_gradient_central_differences():
+    m = named_config("uni_6x5_nt5", seed=7)
+    g = oracle.gradient(m, m.theta)["grad"]
+    fd, f0 = oracle.fd_gradient(m, m.theta, h=1e-4)
+    assert np.isclose(f0, oracle.objective(m, m.theta)["f"])
+    assert np.abs(g - fd).max() <= 1e-6 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_no_observations_reduces_to_prior(k):
+    m = make_model(k, 4, 3, 3, 2, 0, seed=11)
+    assert m.n_obs == 0
+    out = oracle.gradient(m, m.theta)
+    s2 = m.sigma_prior ** 2
+    logp = np.sum(-m.theta ** 2 / (2 * s2)) - 0.5 * m.d * np.log(2 * np.pi * s2)
+    assert np.isclose(out["f"], logp, rtol=1e-12, atol=1e-12)
+    assert np.allclose(out["grad"], -m.theta / s2, rtol=1e-10, atol=1e-10)
+
+
+def test_theta1_scale_identity():
+    m = named_config("uni_8x8_nt8", seed=0)
+    out = oracle.gradient(m, m.theta)
+    # dQ_x/dtheta1 = Q_x, so 1/2 tr(Qp^-1 dQp/dtheta1) = ns*nt/2 exactly
+    assert np.isclose(out["phaseC"][0], 0.5 * m.ns * m.nt, rtol=1e-12)
+
+
+def test_theta1_plus_tau_identity():
+    m = named_config("uni_6x5_nt5", seed=3)
+    out = oracle.gradient(m, m.theta)
+    nb = m.nt * m.b
+    ZT = out["Zc"][nb:, nb:]
+    lhs = -2.0 * (out["phaseA"][0] + out["phaseA"][3])
+    assert np.isclose(lhs, m.N - m.tip_prec * np.trace(ZT), rtol=1e-12)
+
+
+def test_mode_stationarity():
+    m = named_config("coreg3_4x4_nt4", seed=5)
+    ev = oracle.objective(m, m.theta)
+    A, x = ev["A"], ev["x"]
+    grad_x = ev["Qp"] @ x - A.T @ (ev["tau_obs"] * (m.y - A @ x))
+    assert np.abs(grad_x).max() <= 1e-10 * np.abs(ev["r"]).max()
+
+
+def test_scalar_model_closed_form():
+    # one node, one time step, one covariate, one observation: everything is 2x2
+    m = make_model(1, 1, 1, 1, 1, 1, seed=9)
+    t1, t2, t3, t4 = m.theta
+    k2 = np.exp(2 * t2)
+    g1 = 0.1
+    K1, K2 = k2 + g1, k2 * k2 + 2 * k2 * g1 + g1 * g1
+    q = np.exp(t1) * (1.0 * K2 + np.exp(t3) * 0.0 * K1 + 2.0)  # M0=1, M1=L1(1)=0, M2=2
+    w, xr, y = m.obs_w[0].sum(), m.X[0, 0], m.y[0]
+    tau = np.exp(t4)
+    Qp = np.array([[q, 0.0], [0.0, m.tip_prec]])
+    av = np.array([w, xr])
+    Qc = Qp + tau * np.outer(av, av)
+    det_p = q * m.tip_prec
+    det_c = Qc[0, 0] * Qc[1, 1] - Qc[0, 1] ** 2
+    inv_c = np.array([[Qc[1, 1], -Qc[0, 1]], [-Qc[1, 0], Qc[0, 0]]]) / det_c
+    x = inv_c @ (tau * y * av)
+    res = y - av @ x
+    s2 = 0.25
+    f = (0.5 * np.log(det_p) - 0.5 * np.log(det_c) - 0.5 * x @ Qp @ x
+         + 0.5 * t4 - 0.5 * tau * res ** 2 - 0.5 * np.log(2 * np.pi)
+         + np.sum(-m.theta ** 2 / (2 * s2)) - 2 * np.log(2 * np.pi * s2))
+    assert np.isclose(oracle.objective(m, m.theta)["f"], f, rtol=1e-13)
+
+
+def test_coreg_matches_eq9_weights():
+    m = named_config("coreg3_4x4_nt4", seed=8)
+    th = m.theta
+    lay = oracle.theta_layout(m)
+    Qp = oracle.prior_precision(m, th)
+    k, ns, nt, b = m.k, m.ns, m.nt, m.b
+    Lam = np.zeros((k, k))
+    for j in range(k):
+        Lam[j, j] = np.exp(-0.5 * th[lay["prec"][j]])
+    Lam[1, 0], Lam[2, 0], Lam[2, 1] = th[lay["lambda"]]
+    Li = np.linalg.inv(Lam)
+    c0, g1, g2 = m.c0.toarray(), m.g1.toarray(), m.g2.toarray()
+    M0 = oracle.temporal_dense(m.m0)
+    M1 = oracle.temporal_dense(m.m1)
+    M2 = oracle.temporal_dense(m.m2)
+    ref = np.zeros((nt * b, nt * b))
+    for mm in range(k):
+        kk2 = np.exp(2 * th[lay["range"][mm]])
+        K1 = kk2 * c0 + g1
+        K2 = kk2 ** 2 * c0 + 2 * kk2 * g1 + g2
+        e3 = np.exp(th[lay["temporal"][mm]])
+        for t in range(nt):
+            for s in range(nt):
+                blk = M0[t, s] * K2 + e3 * M1[t, s] * K1 + M2[t, s] * c0
+                for i in range(k):
+                    for j in range(k):
+                        W = Li[mm, i] * Li[mm, j]  # Eq. 9 coregional weight
+                        ref[t * b + i * ns:t * b + (i + 1) * ns, s * b + j * ns:s * b + (j + 1) * ns] += W * blk
+    assert np.allclose(Qp[:nt * b, :nt * b], ref, rtol=1e-13, atol=1e-12)
+
+
+def test_coreg_k1_equals_univariate():
+    mu = make_model(1, 4, 3, 3, 2, 3, seed=12)
+    mc = make_model(1, 4, 3, 3, 2, 3, seed=12, kind="coreg")
+    # univariate [scale, range, temporal, tau]  <->  coreg(1) [range, temporal, prec, tau]
+    th_u = mu.theta
+    th_c = np.array([th_u[1], th_u[2], th_u[0], th_u[3]])
+    gu = oracle.gradient(mu, th_u)
+    gc = oracle.gradient(mc, th_c)
+    assert np.isclose(gu["f"], gc["f"], rtol=1e-13)
+    assert np.allclose(gu["grad"][[1, 2, 0, 3]], gc["grad"], rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,b,a", [(4, 5, 2), (1, 6, 3), (3, 4, 0), (5, 3, 1)])
+def test_selected_inverse_identities(n, b, a):
+    blk = random_bta(n, b, a, seed=n * 100 + b * 10 + a)
+    Q = oracle.bta_dense(blk["D"], blk["B"], blk["C"], blk["T"])
+    Z = oracle.selected_inverse(Q, n, b, a)
+    D, B, C, T = blk["D"], blk["B"], blk["C"], blk["T"]
+    for i in range(n):
+        acc = D[i] @ Z["D"][i]
+        if i > 0:
+            acc += B[i - 1] @ Z["B"][i - 1].T
+        if i < n - 1:
+            acc += B[i].T @ Z["B"][i]
+        if a:
+            acc += C[i].T @ Z["C"][i]
+        assert np.allclose(acc, np.eye(b), atol=1e-12)
+        assert np.allclose(Z["D"][i], Z["D"][i].T, atol=1e-14)
+    if a:
+        acc = T @ Z["T"] + sum(C[i] @ Z["C"][i].T for i in range(n))
+        assert np.allclose(acc, np.eye(a), atol=1e-12)
+
+
+def test_bta_cholesky_no_fill_and_leibniz():
+    blk = random_bta(2, 2, 1, seed=4)
+    Q = oracle.bta_dense(blk["D"], blk["B"], blk["C"], blk["T"])
+    ch = oracle.dense_cholesky(Q, blk["rhs"])
+    assert np.isclose(ch["logdet"], np.log(leibniz_det(Q)), rtol=1e-13)
+    assert np.allclose(Q @ ch["x"], blk["rhs"], atol=1e-12)
+    big = random_bta(4, 3, 2, seed=5)
+    Qb = oracle.bta_dense(big["D"], big["B"], big["C"], big["T"])
+    L = oracle.dense_cholesky(Qb)["L"]
+    for i in range(2):  # no fill two blocks below the diagonal
+        assert np.all(np.abs(L[(i + 2) * 3:(i + 3) * 3, i * 3:(i + 1) * 3]) < 1e-15)
+
+
+def test_neumann_second_difference():
+    d, o = neumann_second_difference(4)
+    assert np.array_equal(d, [1, 2, 2, 1]) and np.array_equal(o, [-1, -1, -1])
