@@ -1,0 +1,208 @@
+/*
+ * adelia.h: C ABI of the MI355X (gfx950) library for the INLA objective over
+ * block-tridiagonal-arrowhead (BTA) precision matrices and its exact reverse-mode gradient.
+ *
+ * Paper: "ADELIA: Automatic Differentiation for Efficient Laplace Inference Approximations"
+ * (arXiv 2605.06392).  Section/equation numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Precision: FP64 everywhere.  Matrices are column-major.
+ * - BTA shape (Sec. II-B): n diagonal blocks of size b x b, sub-diagonal blocks
+ *   B_i = [Q]_{i+1,i} (i = 0..n-2), arrow blocks C_i = [Q]_{T,i} of size a x b and the
+ *   arrowhead tip T (a x a).  N = n*b + a.  Vectors of length N are time-major with the
+ *   tip last.
+ * - Device pointers unless stated otherwise.  The caller owns every buffer; no entry point
+ *   keeps a pointer after it returns (except an inla_model, which owns its own copies).
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).  Every call
+ *   only enqueues work on that stream and returns without synchronising, allocating or
+ *   printing, so calls may be captured into a hipGraph.  Exceptions: adelia_create,
+ *   inla_model_create/destroy (set-up time).
+ * - Return codes: 0 = enqueued.  -k = argument k (1-based) is invalid.  ADELIA_E_* below.
+ *   Numerical failure is reported asynchronously through a device int `info`: 0 = success,
+ *   j > 0 = the leading minor of global order j is not positive definite (LAPACK POTRF
+ *   convention); outputs are then undefined.  Nothing aborts and no exception crosses the ABI.
+ * - Workspaces are caller-allocated device memory of at least the queried size, 256-byte
+ *   aligned.  Workspace contents are scratch unless stated otherwise.
+ * - Threading: a context is read-only after creation.  A workspace (and a model's saved
+ *   factors inside it) must be used by one stream at a time.
+ */
+#ifndef ADELIA_H
+#define ADELIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ADELIA_OK 0
+#define ADELIA_E_SHAPE (-100)       /* inconsistent or unsupported sizes                   */
+#define ADELIA_E_WORKSPACE (-101)   /* workspace too small or misaligned                     */
+#define ADELIA_E_HIP (-102)         /* a HIP runtime call failed                             */
+#define ADELIA_E_UNSUPPORTED (-103) /* a valid request this build does not implement         */
+#define ADELIA_E_STATE (-104)       /* e.g. inla_grad with REUSE but no saved forward pass   */
+
+typedef struct adelia_ctx_s* adelia_ctx;
+typedef struct inla_model_s* inla_model;
+
+typedef struct {
+  int32_t n; /* number of diagonal blocks, >= 1 */
+  int32_t b; /* block size, >= 1                */
+  int32_t a; /* arrowhead width, 0..64          */
+} adelia_bta_shape;
+
+/* Context bound to one HIP device (made current by the call).  Returns 0 or ADELIA_E_HIP. */
+int adelia_create(adelia_ctx* ctx, int device);
+int adelia_destroy(adelia_ctx ctx);
+/* Static English text for a return code. */
+const char* adelia_strerror(int code);
+/* Library version string. */
+const char* adelia_version(void);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched FP64 GEMM on matrix cores (v_mfma_f64_16x16x4): for z in [0, batch):
+ *   C_z = alpha * op(A_z) * op(B_z) + beta * C_z,  op(X) = X or X^T (trans* = 0 or 1),
+ * with A_z = A + z*strideA etc.  C is M x N (ld ldc); op(A) is M x K; op(B) is K x N.
+ * `uplo` = 0 writes all of C, 1 writes only the lower triangle (r >= c) of C.
+ * A helper entry point used by the factorisations; exported for testing and for callers
+ * that want the same tile kernel.  beta == 0 never reads C.
+ * --------------------------------------------------------------------------------------- */
+int adelia_dgemm(adelia_ctx ctx, int transA, int transB, int M, int N, int K, double alpha,
+                 const double* A, int lda, long long strideA, const double* B, int ldb,
+                 long long strideB, double beta, double* C, int ldc, long long strideC,
+                 int batch, int uplo, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * BTA factorisation (Sec. III-A-1, Alg. 1): the fused block Cholesky with the lower
+ * triangular solve.  For i = 1..n:
+ *   L_Di = chol(D_i - L_B{i-1} L_B{i-1}^T),  L_Bi = B_i L_Di^-T,
+ *   L_Ci = (C_i - L_C{i-1} L_B{i-1}^T) L_Di^-T,  z_i = L_Di^-1 (r_i - L_B{i-1} z_{i-1}),
+ * then L_T = chol(T - sum_i L_Ci L_Ci^T) and z_T = L_T^-1 (r_T - sum_i L_Ci z_i).
+ * In/out (device, column-major):
+ *   D    n blocks b x b (block i at D + i*b*b, ld b).  Lower triangle read; on exit holds L_Di
+ *        (lower; the upper triangle of each block is overwritten with zeros).
+ *   B    n-1 blocks b x b (ld b): in B_i = [Q]_{i+1,i}, out L_Bi.  May be NULL iff n == 1.
+ *   C    n blocks a x b (ld a): in C_i, out L_Ci.  May be NULL iff a == 0.
+ *   T    a x a (ld a): lower triangle in, out L_T (upper zeroed).  May be NULL iff a == 0.
+ *   Dinv n blocks b x b (ld b): out G_i = L_Di^-1 (lower, upper zeroed).  Required: it is the
+ *        form in which bta_solve and bta_selinv consume the diagonal factors.
+ *   rhs  NULL, or length N: in r, out z = L^-1 r (forward solve fused into the sweep).
+ *   logdet  device scalar out: log|Q| = 2 sum log diag(L).
+ *   info    device int32 out (see conventions).
+ * Workspace: adelia_bta_workspace_bytes(shape, ADELIA_WS_FACTOR).
+ * --------------------------------------------------------------------------------------- */
+#define ADELIA_WS_FACTOR 1
+#define ADELIA_WS_SOLVE 2
+#define ADELIA_WS_SELINV 4
+size_t adelia_bta_workspace_bytes(adelia_bta_shape shape, int which);
+
+int bta_factor(adelia_ctx ctx, adelia_bta_shape shape, double* D, double* B, double* C,
+               double* T, double* Dinv, double* rhs, double* logdet, int32_t* info, void* ws,
+               size_t ws_bytes, void* stream);
+
+/* log|Q| from a factor produced by bta_factor (Sec. II-A: log|Q| = 2 sum log diag L):
+ * reads the diagonals of the n blocks LD (ld b) and of LT (a x a, ld a; NULL iff a == 0).
+ * out: device scalar. */
+int bta_logdet(adelia_ctx ctx, adelia_bta_shape shape, const double* LD, const double* LT,
+               double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Solve Q x = rhs with the factor (Sec. III-A-2, Eqs. 3-5 for the upper sweep).
+ * Dinv, LB, LC, LT as produced by bta_factor.  x: length N; in rhs (or z = L^-1 rhs when
+ * flags & ADELIA_Z_INPUT), out Q^-1 rhs. */
+#define ADELIA_Z_INPUT 1
+int bta_solve(adelia_ctx ctx, adelia_bta_shape shape, const double* Dinv, const double* LB,
+              const double* LC, const double* LT, double* x, int flags, void* ws,
+              size_t ws_bytes, void* stream);
+
+/* Selected inversion (Sec. III-A, Phase A): the blocks of Q^-1 on the BTA pattern,
+ *   ZD_i = [Q^-1]_{i,i} (b x b, full symmetric), ZB_i = [Q^-1]_{i+1,i} (b x b),
+ *   ZC_i = [Q^-1]_{T,i} (a x b, ld a), ZT = [Q^-1]_{T,T} (a x a),
+ * swept from block n to 1 from the factor (Dinv, LB, LC, LT).  ZB may be NULL iff n == 1;
+ * ZC, ZT may be NULL iff a == 0. */
+int bta_selinv(adelia_ctx ctx, adelia_bta_shape shape, const double* Dinv, const double* LB,
+               const double* LC, const double* LT, double* ZD, double* ZB, double* ZC,
+               double* ZT, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * INLA model (Sec. II-A, II-B; Sec. III-B for k coregionalised fields).
+ * The model is given by HOST arrays; inla_model_create validates every index, builds the
+ * per-column observation lists and the union pattern of the spatial base matrices (integer
+ * work), and copies everything to device memory it owns until inla_model_destroy.
+ * --------------------------------------------------------------------------------------- */
+#define ADELIA_PARAM_UNIVARIATE 1 /* theta = [log scale, range, temporal, log tau], k == 1 */
+#define ADELIA_PARAM_COREG 2      /* theta = [range(k), temporal(k), prec(k),
+                                       lambda(k(k-1)/2) row-major strictly lower, log tau(k)] */
+typedef struct {
+  int32_t param;   /* ADELIA_PARAM_*                                                     */
+  int32_t k;       /* fields, 1..4                                                        */
+  int32_t ns;      /* spatial nodes per field; b = k*ns                                    */
+  int32_t nt;      /* time steps (n)                                                       */
+  int32_t a;       /* fixed effects (arrowhead width), 0..64                               */
+  int32_t n_obs;   /* observations                                                         */
+  /* spatial base matrices c0, g1, g2 (ns x ns, symmetric) in CSR */
+  const int32_t* c0_ptr; const int32_t* c0_idx; const double* c0_val;
+  const int32_t* g1_ptr; const int32_t* g1_idx; const double* g1_val;
+  const int32_t* g2_ptr; const int32_t* g2_idx; const double* g2_val;
+  /* temporal matrices M0, M1, M2 (nt x nt, symmetric tridiagonal): diagonal (nt) and
+   * sub-diagonal (nt-1) */
+  const double* m0_diag; const double* m0_off;
+  const double* m1_diag; const double* m1_off;
+  const double* m2_diag; const double* m2_off;
+  /* observations, sorted by (time, field): each touches 4 nodes of one field at one time
+   * step with bilinear weights, plus the a covariates */
+  const int32_t* obs_t; const int32_t* obs_field; const int32_t* obs_node; /* n_obs x 4 */
+  const double* obs_w;  /* n_obs x 4 */
+  const double* X;      /* n_obs x a, row-major */
+  const double* y;      /* n_obs */
+  double sigma_prior;   /* theta_k ~ N(0, sigma^2) */
+  double tip_prec;      /* prior precision of the fixed effects */
+} inla_model_desc;
+
+/* Returns 0, ADELIA_E_SHAPE (with a message available from adelia_last_error), or a
+ * negative argument index. */
+int inla_model_create(adelia_ctx ctx, const inla_model_desc* desc, inla_model* out);
+int inla_model_destroy(inla_model model);
+/* Number of hyperparameters d of the model. */
+int inla_model_dim(inla_model model);
+/* Thread-local text of the last validation failure (set-up calls only). */
+const char* adelia_last_error(void);
+
+/* Workspace for evaluating `batch` theta points (mode = ADELIA_MODE_OBJECTIVE), or for a
+ * gradient (mode = ADELIA_MODE_GRAD; batch must be 1): the forward factors of Qc and Qp are
+ * kept in it between inla_objective(SAVE) and inla_grad(REUSE). */
+#define ADELIA_MODE_OBJECTIVE 0
+#define ADELIA_MODE_GRAD 1
+size_t inla_workspace_bytes(inla_model model, int batch, int mode);
+
+/* f(theta) of Eq. 1 for `batch` points theta (device, batch x d, row-major):
+ *   f = 1/2 log|Qp| - 1/2 log|Qc| - 1/2 x*^T Qp x* + log l(y|x*,theta) + log p(theta),
+ * Gaussian likelihood with precision tau_m = exp(theta_tau_m) per field, theta_k ~ N(0,s^2),
+ * Qp = blkdiag(Q_x(theta), tip_prec I).  f: device, batch.  info: device int32, batch.
+ * flags & ADELIA_SAVE_FACTORS (batch == 1, GRAD workspace): keep the factors for inla_grad. */
+#define ADELIA_SAVE_FACTORS 1
+int inla_objective(inla_model model, const double* theta, int32_t batch, double* f,
+                   int32_t* info, void* ws, size_t ws_bytes, int flags, void* stream);
+
+/* f and its exact gradient (Sec. III-A-3, Eq. 5: Phases A, B, C plus the likelihood and
+ * prior terms; Eqs. 10-11 for the coregional parameters).  theta, grad: device, d.
+ * flags & ADELIA_REUSE_FACTORS: skip the forward pass and use the factors saved by the
+ * preceding inla_objective(SAVE_FACTORS) on the same workspace and theta. */
+#define ADELIA_REUSE_FACTORS 1
+int inla_grad(inla_model model, const double* theta, double* f, double* grad, int32_t* info,
+              void* ws, size_t ws_bytes, int flags, void* stream);
+
+/* Central finite-difference gradient (Sec. II-C, Eq. 2) on the GPU: the 2d+1 points
+ * theta, theta +- h e_j are evaluated as batched objectives (in sub-batches of at most
+ * `max_batch` points, sized by the caller's workspace = inla_workspace_bytes(model,
+ * max_batch, OBJECTIVE)); grad_j = (f(theta+h e_j) - f(theta-h e_j)) / 2h, f = f(theta).
+ * info: device int32, 2d+1 entries. */
+int inla_fd_grad(inla_model model, const double* theta, double h, int32_t max_batch,
+                 double* f, double* grad, int32_t* info, void* ws, size_t ws_bytes,
+                 void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADELIA_H */

@@ -1,0 +1,323 @@
+// Host orchestration of the BTA sweeps.  Every launch covers all `nz` chains of a batch
+// (grid.z), so a gradient (Qc and Qp) or a finite-difference stencil (2 chains per theta)
+// runs its block steps as single launches.
+//
+// Forward (Sec. III-A-1, Alg. 1), per block i:
+//   1. chol(D_i) by 64-wide panels (potrf.hip) plus trailing GEMM updates; the panel kernels
+//      leave the 64 x 64 diagonal inverses in G_i.
+//   2. G_i = L_Di^-1 completed by recursive doubling: X21 = -X22 L21 X11 (two GEMMs per level).
+//   3. [L_Bi; L_Ci] = [B_i; C~_i] G_i^T: one triangular GEMM.  The right-hand side travels as
+//      an extra arrow row (C~_i's last row is r~_i^T), so the same product gives z_i^T as the
+//      last row of L_Ci -- the forward solve fused into the sweep.
+//   4. [[D_{i+1}], [C~_{i+1}, T~]] -= [L_Bi; L_Ci][L_Bi; L_Ci]^T: one lower-triangular GEMM
+//      updating the next diagonal block, the next arrow block (and r~_{i+1}), the tip (and
+//      v_T, and -|z_i|^2 in the tip's corner).
+// Selected inversion (Sec. III-A, Phase A; the recurrence follows from Sigma L = L^-T):
+//   [W; V] = [L_Bj; L_Cj] G_j,
+//   [Z_Bj; Z_Cj] = -[[Z_D{j+1}, Z_C{j+1}^T], [Z_C{j+1}, Z_T]] [W; V],
+//   Z_Dj = G_j^T G_j - [Z_Bj; Z_Cj]^T [W; V].
+#include "common.h"
+#include "launchers.h"
+
+namespace adelia {
+
+static inline long long blk_off(int t, int slots, long long bb) { return (long long)(t % slots) * bb; }
+
+int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
+  const int b = c.b, ap = c.ap, n = c.n, nz = c.nz;
+  const long long bb = (long long)b * b;
+  const int npanel = (b + kPanel - 1) / kPanel;
+  double* Dblk = c.D + blk_off(i, c.slotsD, bb);
+  double* Gblk = c.G + blk_off(i, c.slotsG, bb);
+  // 1. blocked Cholesky of D_i
+  for (int k = 0; k < npanel; ++k) {
+    const int c0 = k * kPanel;
+    if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, c.ldpart + (long long)i * npanel + k, c.zLd,
+                           c.info, b, c0, (long long)i * b, nz, s))
+      return ADELIA_E_HIP_INTERNAL;
+    const int rest = b - c0 - kPanel;
+    if (rest > 0) {
+      GemmArgs g{};
+      g.nph = 1;
+      g.ph[0].A = view_plain(Dblk + (c0 + kPanel) + (long long)c0 * b, b, c.zD);
+      g.ph[0].B = view_plain(Dblk + (c0 + kPanel) + (long long)c0 * b, b, c.zD, true);
+      g.ph[0].K = g.ph[0].Klast = kPanel;
+      g.ph[0].kmode = KR_FULL;
+      g.ph[0].alpha = -1.0;
+      g.C = view_plain(Dblk + (c0 + kPanel) + (long long)(c0 + kPanel) * b, b, c.zD);
+      g.M = g.N = g.Mlast = g.Nlast = rest;
+      g.beta = 1.0;
+      g.omode = OUT_LOWER;
+      if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    }
+  }
+  // 2. G_i = L_Di^-1 by recursive doubling over the 64 x 64 diagonal inverses
+  for (int sz = kPanel; sz < b; sz *= 2) {
+    const int P = (b - sz + 2 * sz - 1) / (2 * sz);
+    const int s2 = b - 2 * (P - 1) * sz - sz < sz ? b - 2 * (P - 1) * sz - sz : sz;
+    const long long ystep = 2LL * sz * (b + 1);
+    double* S = c.scratch;
+    {  // T = L21 * X11  (X11 lower)
+      GemmArgs g{};
+      g.nph = 1;
+      g.ph[0].A = view_plain(Dblk + sz, b, c.zD);
+      g.ph[0].B = view_plain(Gblk, b, c.zG);
+      g.ph[0].K = g.ph[0].Klast = sz;
+      g.ph[0].kmode = KR_GE_N0;
+      g.ph[0].triB = TRI_LOWER;
+      g.ph[0].alpha = 1.0;
+      view_set_y(g.ph[0].A, ystep);
+      view_set_y(g.ph[0].B, ystep);
+      g.C = view_plain(S + sz, b, c.zS);
+      view_set_y(g.C, ystep);
+      g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
+      g.beta = 0.0;
+      g.omode = OUT_ALL;
+      if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    }
+    {  // X21 = -X22 * T  (X22 lower)
+      GemmArgs g{};
+      g.nph = 1;
+      g.ph[0].A = view_plain(Gblk + sz + (long long)sz * b, b, c.zG);
+      g.ph[0].B = view_plain(S + sz, b, c.zS);
+      g.ph[0].K = sz; g.ph[0].Klast = s2;
+      g.ph[0].kmode = KR_LT_M1;
+      g.ph[0].triA = TRI_LOWER;
+      g.ph[0].alpha = -1.0;
+      view_set_y(g.ph[0].A, ystep);
+      view_set_y(g.ph[0].B, ystep);
+      g.C = view_plain(Gblk + sz, b, c.zG);
+      view_set_y(g.C, ystep);
+      g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
+      g.beta = 0.0;
+      g.omode = OUT_ALL;
+      if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    }
+  }
+  // 3. [L_B; L_C] = [B_i; C~_i] G_i^T
+  const bool hasB = i < n - 1;
+  double* Cblk = c.C + (long long)i * ap * b;
+  double* LCblk = c.LC + (long long)i * ap * b;
+  double* LBblk = hasB ? c.LB + blk_off(i, c.slotsLB, bb) : nullptr;
+  {
+    GemmArgs g{};
+    g.nph = 1;
+    if (hasB) {
+      const double* Bi = c.Bin + blk_off(i, c.slotsB, bb);
+      g.ph[0].A = view_rowsplit(const_cast<double*>(Bi), b, c.zB, Cblk, ap, c.zC, b);
+      g.C = view_rowsplit(LBblk, b, c.zLB, LCblk, ap, c.zLC, b);
+      g.M = g.Mlast = b + ap;
+    } else {
+      g.ph[0].A = view_plain(Cblk, ap, c.zC);
+      g.C = view_plain(LCblk, ap, c.zLC);
+      g.M = g.Mlast = ap;
+    }
+    g.ph[0].B = view_plain(Gblk, b, c.zG, true);
+    g.ph[0].K = g.ph[0].Klast = b;
+    g.ph[0].kmode = KR_LT_N1;
+    g.ph[0].triB = TRI_UPPER;
+    g.ph[0].alpha = 1.0;
+    g.N = g.Nlast = b;
+    g.beta = 0.0;
+    g.omode = OUT_ALL;
+    if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  }
+  // 4. Schur update of the next diagonal block, next arrow block and the tip
+  {
+    GemmArgs g{};
+    g.nph = 1;
+    g.ph[0].alpha = -1.0;
+    g.ph[0].K = g.ph[0].Klast = b;
+    g.ph[0].kmode = KR_FULL;
+    g.beta = 1.0;
+    g.omode = OUT_LOWER;
+    if (hasB) {
+      double* Dn = c.D + blk_off(i + 1, c.slotsD, bb);
+      double* Cn = c.C + (long long)(i + 1) * ap * b;
+      g.ph[0].A = view_rowsplit(LBblk, b, c.zLB, LCblk, ap, c.zLC, b);
+      g.ph[0].B = view_rowsplit(LBblk, b, c.zLB, LCblk, ap, c.zLC, b, true);
+      View v = view_plain(Dn, b, c.zD);
+      v.rs = b; v.cs = b;
+      v.p[1] = Cn; v.sr[1] = 1; v.sc[1] = ap; v.zs[1] = c.zC;
+      v.p[3] = c.T; v.sr[3] = 1; v.sc[3] = ap; v.zs[3] = c.zT;
+      g.C = v;
+      g.M = g.N = g.Mlast = g.Nlast = b + ap;
+    } else {
+      g.ph[0].A = view_plain(LCblk, ap, c.zLC);
+      g.ph[0].B = view_plain(LCblk, ap, c.zLC, true);
+      g.C = view_plain(c.T, ap, c.zT);
+      g.M = g.N = g.Mlast = g.Nlast = ap;
+    }
+    if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  }
+  return 0;
+}
+
+int bta_tip(const BtaChains& c, hipStream_t s) {
+  const int npanel = (c.b + kPanel - 1) / kPanel;
+  if (c.ap == 0) {
+    // no tip and no rhs row: an empty tip contributes log 1 = 0
+    return launch_fill_strided(c.ldpart + (long long)c.n * npanel, c.zLd, c.nz, 0.0, s)
+               ? ADELIA_E_HIP_INTERNAL : 0;
+  }
+  if (launch_tip(c.T, c.zT, c.a, c.ap, c.ldpart + (long long)c.n * npanel, c.zLd, c.info,
+                 (long long)c.n * c.b, c.zsq, c.ZT, c.zZT, c.xT, c.zXT, c.nz, s))
+    return ADELIA_E_HIP_INTERNAL;
+  return 0;
+}
+
+int bta_forward(const BtaChains& c, hipStream_t s) {
+  for (int i = 0; i < c.n; ++i) {
+    int r = bta_forward_block(c, i, s);
+    if (r) return r;
+  }
+  return bta_tip(c, s);
+}
+
+int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
+  const int b = c.b, a = c.a, n = c.n, nz = c.nz;
+  const long long bb = (long long)b * b;
+  const double* Gj = c.G + blk_off(j, c.slotsG, bb);
+  const double* LCj = c.LC + (long long)j * c.ldLC * b;
+  double* Wm = c.W;
+  double* V = c.W + bb;
+  double* ZDj = c.ZD + blk_off(j, c.slotsZD, bb);
+  double* ZCj = a ? c.ZC + blk_off(j, c.slotsZC, (long long)a * b) : nullptr;
+  const bool last = (j == n - 1);
+  const double* LBj = last ? nullptr : c.LB + blk_off(j, c.slotsLB, bb);
+  double* ZBj = last ? nullptr : c.ZB + blk_off(j, c.slotsZB, bb);
+  double* ZDn = last ? nullptr : c.ZD + blk_off(j + 1, c.slotsZD, bb);
+  double* ZCn = (last || !a) ? nullptr : c.ZC + blk_off(j + 1, c.slotsZC, (long long)a * b);
+  const long long zW = c.zW;
+  // S1: [W; V] = [L_Bj; L_Cj] G_j
+  {
+    GemmArgs g{};
+    g.nph = 1;
+    if (!last) {
+      g.ph[0].A = view_rowsplit(const_cast<double*>(LBj), b, c.zLB, const_cast<double*>(LCj),
+                                c.ldLC, c.zLC, b);
+      g.C = view_rowsplit(Wm, b, zW, V, a ? a : 1, zW, b);
+      g.M = g.Mlast = b + a;
+    } else {
+      g.ph[0].A = view_plain(const_cast<double*>(LCj), c.ldLC, c.zLC);
+      g.C = view_plain(V, a ? a : 1, zW);
+      g.M = g.Mlast = a;
+    }
+    g.ph[0].B = view_plain(const_cast<double*>(Gj), b, c.zG);
+    g.ph[0].K = g.ph[0].Klast = b;
+    g.ph[0].kmode = KR_GE_N0;
+    g.ph[0].triB = TRI_LOWER;
+    g.ph[0].alpha = 1.0;
+    g.N = g.Nlast = b;
+    g.beta = 0.0;
+    g.omode = OUT_ALL;
+    if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  }
+  // S2: [Z_Bj; Z_Cj] = -Zhat_{j+1} [W; V]
+  if (!last) {
+    GemmArgs g{};
+    g.nph = 1;
+    View A = view_plain(ZDn, b, c.zZD);
+    A.rs = b; A.cs = b;
+    if (a) {
+      A.p[1] = ZCn; A.sr[1] = 1; A.sc[1] = a; A.zs[1] = c.zZC;          // Z_C(r-b, c)
+      A.p[2] = ZCn; A.sr[2] = a; A.sc[2] = 1; A.zs[2] = c.zZC;          // Z_C^T
+      A.p[3] = const_cast<double*>(c.ZT); A.sr[3] = 1; A.sc[3] = a; A.zs[3] = c.zZT;
+    }
+    g.ph[0].A = A;
+    g.ph[0].B = view_rowsplit(Wm, b, zW, V, a ? a : 1, zW, b);
+    g.ph[0].K = g.ph[0].Klast = b + a;
+    g.ph[0].kmode = KR_FULL;
+    g.ph[0].alpha = -1.0;
+    g.C = view_rowsplit(ZBj, b, c.zZB, ZCj ? ZCj : ZBj, a ? a : 1, c.zZC, b);
+    g.M = g.Mlast = b + a;
+    g.N = g.Nlast = b;
+    g.beta = 0.0;
+    g.omode = OUT_ALL;
+    if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  } else if (a) {
+    GemmArgs g{};
+    g.nph = 1;
+    g.ph[0].A = view_plain(const_cast<double*>(c.ZT), a, c.zZT);
+    g.ph[0].B = view_plain(V, a, zW);
+    g.ph[0].K = g.ph[0].Klast = a;
+    g.ph[0].kmode = KR_FULL;
+    g.ph[0].alpha = -1.0;
+    g.C = view_plain(ZCj, a, c.zZC);
+    g.M = g.Mlast = a;
+    g.N = g.Nlast = b;
+    g.beta = 0.0;
+    g.omode = OUT_ALL;
+    if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  }
+  // S3: Z_Dj = G^T G - [Z_Bj; Z_Cj]^T [W; V]  (lower, mirrored to a full symmetric block)
+  {
+    GemmArgs g{};
+    g.ph[0].A = view_plain(const_cast<double*>(Gj), b, c.zG, true);
+    g.ph[0].B = view_plain(const_cast<double*>(Gj), b, c.zG);
+    g.ph[0].K = g.ph[0].Klast = b;
+    g.ph[0].kmode = KR_GE_MAX;
+    g.ph[0].triA = TRI_UPPER;
+    g.ph[0].triB = TRI_LOWER;
+    g.ph[0].alpha = 1.0;
+    g.nph = 1;
+    if (!last) {
+      g.ph[1].A = view_rowsplit(ZBj, b, c.zZB, ZCj ? ZCj : ZBj, a ? a : 1, c.zZC, b, true);
+      g.ph[1].B = view_rowsplit(Wm, b, zW, V, a ? a : 1, zW, b);
+      g.ph[1].K = g.ph[1].Klast = b + a;
+      g.nph = 2;
+    } else if (a) {
+      g.ph[1].A = view_plain(ZCj, a, c.zZC, true);
+      g.ph[1].B = view_plain(V, a, zW);
+      g.ph[1].K = g.ph[1].Klast = a;
+      g.nph = 2;
+    }
+    g.ph[1].kmode = KR_FULL;
+    g.ph[1].alpha = -1.0;
+    g.C = view_plain(ZDj, b, c.zZD);
+    g.M = g.N = g.Mlast = g.Nlast = b;
+    g.beta = 0.0;
+    g.omode = OUT_LOWER_MIRROR;
+    if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  }
+  return 0;
+}
+
+int bta_upper_solve(const SolveChains& c, hipStream_t s) {
+  const int b = c.b, a = c.a, n = c.n, nz = c.nz;
+  const long long bb = (long long)b * b;
+  for (int i = n - 1; i >= 0; --i) {
+    const double* LCi = c.LC + (long long)i * c.ldLC * b;
+    GemvT g{};
+    if (i < n - 1) {
+      g.A = c.LB + blk_off(i, c.slotsLB, bb); g.ld = b; g.zA = c.zLB;
+      g.x = c.x + (long long)(i + 1) * b; g.zx = c.zx; g.incx = 1;
+      g.alpha = -1.0;
+    }
+    if (a) {
+      g.A2 = LCi; g.ld2 = c.ldLC; g.zA2 = c.zLC; g.r2 = a;
+      g.x2 = c.xT; g.zx2 = c.zxT;
+      g.alpha2 = -1.0;
+    }
+    g.y0 = c.z + (long long)i * c.sz_blk; g.zy0 = c.zz; g.incy0 = c.sz_elem;
+    g.beta = 1.0;
+    g.y = c.y; g.zy = c.zy; g.incy = 1;
+    g.M = b; g.K = b; g.lowerA = 0;
+    if (launch_gemv_t(g, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    GemvT h{};
+    h.A = c.G + blk_off(i, c.slotsG, bb); h.ld = b; h.zA = c.zG;
+    h.x = c.y; h.zx = c.zy; h.incx = 1;
+    h.alpha = 1.0;
+    h.y = c.x + (long long)i * b; h.zy = c.zx; h.incy = 1;
+    h.M = b; h.K = b; h.lowerA = 1;
+    if (launch_gemv_t(h, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  }
+  // the tip part of x
+  if (a && c.xT) {
+    if (launch_copy2d(c.xT, a, c.zxT, c.x + (long long)n * b, a, c.zx, a, 1, nz, s))
+      return ADELIA_E_HIP_INTERNAL;
+  }
+  return 0;
+}
+
+}  // namespace adelia

@@ -1,0 +1,145 @@
+// Internal declarations shared by the HIP translation units of libadelia.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define ADELIA_CHECK_HIP(expr)                                  \
+  do {                                                          \
+    hipError_t e_ = (expr);                                     \
+    if (e_ != hipSuccess) return ADELIA_E_HIP;                  \
+  } while (0)
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+namespace adelia {
+
+constexpr int kMaxFields = 4;
+constexpr int kMaxTheta = 4 * kMaxFields + kMaxFields * (kMaxFields - 1) / 2;
+constexpr int kPanel = 64;  // POTRF panel width == GEMM tile edge
+
+// A strided view of a logical matrix split into up to four quadrants at (rs, cs):
+// q = (r >= rs) + 2 * (c >= cs).  Element (r, c) of quadrant q lives at
+//   p[q] + z * zs[q] + y * ys[q] + (r - rs*[r>=rs]) * sr[q] + (c - cs*[c>=cs]) * sc[q],
+// where z = blockIdx.z (independent chain) and y = blockIdx.y (sub-problem).
+// Transposition is expressed through the strides.
+struct View {
+  double* p[4];
+  long long sr[4];
+  long long sc[4];
+  long long zs[4];
+  long long ys[4];
+  int rs, cs;
+};
+
+enum KRange {
+  KR_FULL = 0,
+  KR_GE_N0 = 1,   // op(B)(k, n) == 0 for k < n  (B lower triangular)
+  KR_LT_N1 = 2,   // op(B)(k, n) == 0 for k > n  (B upper triangular)
+  KR_LT_M1 = 3,   // op(A)(m, k) == 0 for k > m  (A lower triangular)
+  KR_GE_MAX = 4,  // op(A) upper and op(B) lower
+};
+
+enum Tri { TRI_NONE = 0, TRI_LOWER = 1, TRI_UPPER = 2 };  // zero where col > row / row > col
+
+enum OutMode { OUT_ALL = 0, OUT_LOWER = 1, OUT_LOWER_MIRROR = 2 };
+
+struct GemmPhase {
+  View A, B;
+  int K, Klast;   // Klast: K for the last grid.y sub-problem
+  int kmode;
+  int triA, triB;
+  double alpha;
+};
+
+struct GemmArgs {
+  GemmPhase ph[2];
+  int nph;
+  View C;
+  int M, N, Mlast, Nlast;
+  double beta;
+  int omode;
+};
+
+// ---- host helpers (gemm.hip) --------------------------------------------------------------
+View view_plain(double* p, long long ld, long long zstride, bool trans = false);
+View view_rowsplit(double* p0, long long ld0, long long zs0, double* p1, long long ld1,
+                   long long zs1, int rsplit, bool trans = false);
+void view_set_y(View& v, long long ystride);
+int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s);
+
+// ---- small kernels (util.hip) -------------------------------------------------------------
+int launch_fill(double* p, long long n, double v, hipStream_t s);
+int launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t s);
+int launch_copy2d(const double* src, long long lds, long long zs_src, double* dst, long long ldd,
+                  long long zs_dst, int rows, int cols, int nz, hipStream_t s);
+int launch_zero_upper(double* p, int b, long long ld, long long blockstride, int nblk,
+                      long long zs, int nz, hipStream_t s);
+
+// ---- BTA sweeps (bta.hip) -----------------------------------------------------------------
+// Uniform batch of `nz` BTA chains with identical (n, b, a).  Chain z's arrays start at
+// base + z * stride.  Arrow buffers have `ap` rows (a arrow rows, plus one right-hand-side row
+// when ap == a + 1).  Block t of an array with `slots` slots lives at slot t % slots.
+struct BtaChains {
+  int n, b, a, ap, nz;
+  double* D; long long zD; int slotsD;      // in: D_t (lower) ; out: L_Dt
+  const double* Bin; long long zB; int slotsB; long long ldB_block;  // B_t, ld b
+  double* LB; long long zLB; int slotsLB;   // out: L_Bt
+  double* C; long long zC;                  // n blocks ap x b (ld ap): in C_t|r_t, updated in place
+  double* LC; long long zLC;                // n blocks ap x b (ld ap): out L_Ct | z_t
+  double* T; long long zT;                  // ap x ap (ld ap): in T|r_T, out L_T | z_T
+  double* G; long long zG; int slotsG;      // out: L_Dt^-1
+  double* ldpart; long long zLd;            // logdet partials, n*npanel + 1 per chain
+  int32_t* info;                            // per chain (stride 1)
+  double* scratch; long long zS;            // b*b per chain (TRTRI temporaries)
+  double* zsq;                              // per chain: |z|^2 (if ap == a+1), may be null
+  double* ZT; long long zZT;                // a x a per chain: [Q^-1]_{T,T} (may be null)
+  double* xT; long long zXT;                // a per chain: L_T^-T z_T (may be null)
+};
+int bta_forward(const BtaChains& c, hipStream_t s);
+int bta_forward_block(const BtaChains& c, int i, hipStream_t s);  // one block step
+int bta_tip(const BtaChains& c, hipStream_t s);
+int bta_logdet_reduce(const double* ldpart, long long zLd, int nparts, double* out, long long zout,
+                      int nz, hipStream_t s);
+
+struct SelinvChains {
+  int n, b, a, nz;
+  const double* G; long long zG; int slotsG;
+  const double* LB; long long zLB; int slotsLB;
+  const double* LC; long long zLC; int ldLC;     // LC blocks, ld ldLC (>= a), first a rows
+  const double* ZT; long long zZT;               // a x a (ld a)
+  double* ZD; long long zZD; int slotsZD;        // b x b blocks (full symmetric)
+  double* ZB; long long zZB; int slotsZB;
+  double* ZC; long long zZC; int slotsZC;        // a x b (ld a)
+  double* W; long long zW;                       // scratch: b*b + a*b
+};
+// One backward step (block j, from n-1 down to 0).  Requires ZD/ZC of block j+1 present.
+int selinv_block(const SelinvChains& c, int j, hipStream_t s);
+
+// Upper triangular solve x = L^-T z (Sec. III-A-2, Eqs. 3-5), all chains.
+struct SolveChains {
+  int n, b, a, nz;
+  const double* G; long long zG; int slotsG;
+  const double* LB; long long zLB; int slotsLB;
+  const double* LC; long long zLC; int ldLC;
+  const double* z; long long zz; long long sz_blk; long long sz_elem;  // z_t element at z + t*sz_blk + r*sz_elem
+  const double* xT; long long zxT;               // a
+  double* x; long long zx;                        // length n*b + a (contiguous)
+  double* y; long long zy;                        // scratch b
+};
+int bta_upper_solve(const SolveChains& c, hipStream_t s);
+
+// y(m) = beta*y0(m) + alpha * sum_k A(k, m) x(k) over k in [klo(m), K), A column-major (ld),
+// plus optional alpha2 * sum_c A2(c, m) x2(c) (A2 is r2 x M, ld2).  klo(m) = m if lowerA.
+struct GemvT {
+  const double* A; long long ld; long long zA;
+  const double* x; long long zx; long long incx;
+  const double* A2; long long ld2; long long zA2; int r2;
+  const double* x2; long long zx2;
+  const double* y0; long long zy0; long long incy0;
+  double* y; long long zy; long long incy;
+  int M, K; int lowerA; double alpha, alpha2, beta;
+};
+int launch_gemv_t(const GemvT& g, int nz, hipStream_t s);
+
+}  // namespace adelia

@@ -1,0 +1,361 @@
+// FP64 matrix-core GEMM for gfx950.
+//
+// C = beta*C + sum_ph alpha_ph * op(A_ph) * op(B_ph) over one or two "phases", batched over
+// grid.z (independent chains) and grid.y (sub-problems).  Operands are strided quadrant views
+// (common.h), which lets one kernel read the block-plus-arrow operands of the BTA sweeps
+// ([L_B; L_C], the augmented inverse [[Z_D, Z_C^T]; [Z_C, Z_T]]) without copies.
+//
+// Tiling: a 256-thread workgroup owns a 64 x 64 tile of C; each of its four wavefronts owns
+// a 32 x 32 quarter as 2 x 2 fragments of v_mfma_f64_16x16x4.  K advances 16 at a time
+// through LDS with the next tile prefetched into registers.  On this instruction lane l holds
+// A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4v][l%16] (v = 0..3); the kernel feeds the
+// B-fragment as the instruction's A operand so that each lane's results lie along a column of
+// C and 16 consecutive lanes write 16 consecutive doubles.
+#include "common.h"
+#include <climits>
+#include <cmath>
+
+namespace adelia {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int LDS_ROW = BM + 4;  // padded row (doubles); keeps 16-byte alignment
+
+struct QuadSel {
+  const double* p;
+  long long sr, sc;
+};
+
+__device__ __forceinline__ QuadSel pick(const View& v, int q, int z, int y) {
+  // all four quadrants are read (uniform kernel arguments) and selected per lane; an indexed
+  // access would make the compiler spill the argument block to scratch
+  const bool hi = (q & 1) != 0, right = (q & 2) != 0;
+  const double* p01 = hi ? v.p[1] : v.p[0];
+  const double* p23 = hi ? v.p[3] : v.p[2];
+  const long long sr01 = hi ? v.sr[1] : v.sr[0], sr23 = hi ? v.sr[3] : v.sr[2];
+  const long long sc01 = hi ? v.sc[1] : v.sc[0], sc23 = hi ? v.sc[3] : v.sc[2];
+  const long long zs01 = hi ? v.zs[1] : v.zs[0], zs23 = hi ? v.zs[3] : v.zs[2];
+  const long long ys01 = hi ? v.ys[1] : v.ys[0], ys23 = hi ? v.ys[3] : v.ys[2];
+  QuadSel s;
+  s.sr = right ? sr23 : sr01;
+  s.sc = right ? sc23 : sc01;
+  const long long zs = right ? zs23 : zs01, ys = right ? ys23 : ys01;
+  s.p = (right ? p23 : p01) + (long long)z * zs + (long long)y * ys;
+  return s;
+}
+
+__device__ __forceinline__ double* elem_ptr(const View& v, int r, int c, int z, int y) {
+  const bool rb = r >= v.rs, cb = c >= v.cs;
+  const int q = (rb ? 1 : 0) + (cb ? 2 : 0);
+  QuadSel s = pick(v, q, z, y);
+  const int rr = rb ? r - v.rs : r;
+  const int cc = cb ? c - v.cs : c;
+  return const_cast<double*>(s.p + rr * s.sr + cc * s.sc);
+}
+
+// Whole region [r0, r0+R) x [c0, c0+Cn) inside one quadrant?  Returns quadrant or -1.
+__device__ __forceinline__ int uniform_quad(const View& v, int r0, int R, int c0, int Cn) {
+  const bool rb0 = r0 >= v.rs, rb1 = (r0 + R - 1) >= v.rs;
+  const bool cb0 = c0 >= v.cs, cb1 = (c0 + Cn - 1) >= v.cs;
+  if (rb0 != rb1 || cb0 != cb1) return -1;
+  return (rb0 ? 1 : 0) + (cb0 ? 2 : 0);
+}
+
+__device__ __forceinline__ bool tri_zero(int tri, int r, int c) {
+  return (tri == TRI_LOWER && c > r) || (tri == TRI_UPPER && r > c);
+}
+
+// Load the BM x BK tile of logical A at (m0, k0) into registers (4 values per thread), in the
+// thread->element mapping implied by `mode` (0: m fastest, 1: k fastest).
+struct TileRegs {
+  double v[4];
+  int mode;
+};
+
+__device__ __forceinline__ void load_a(const View& A, int M, int K, int m0, int k0, int tri,
+                                       double alpha, int z, int y, TileRegs& t) {
+  const int tid = threadIdx.x;
+  const bool inb = (m0 + BM <= M) && (k0 + BK <= K);
+  const int q = inb ? uniform_quad(A, m0, BM, k0, BK) : -1;
+  if (q >= 0) {
+    QuadSel s = pick(A, q, z, y);
+    const int mo = (q & 1) ? m0 - A.rs : m0;
+    const int ko = (q & 2) ? k0 - A.cs : k0;
+    const double* base = s.p + mo * s.sr + ko * s.sc;
+    if (s.sc == 1 && s.sr != 1) {
+      t.mode = 1;
+      const int k = tid & 15, mq = tid >> 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = mq + 16 * j;
+        double val = base[m * s.sr + k];
+        if (tri && tri_zero(tri, m0 + m, k0 + k)) val = 0.0;
+        t.v[j] = alpha * val;
+      }
+    } else {
+      t.mode = 0;
+      const int m = tid & 63, kq = tid >> 6;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kq + 4 * j;
+        double val = base[m * s.sr + k * s.sc];
+        if (tri && tri_zero(tri, m0 + m, k0 + k)) val = 0.0;
+        t.v[j] = alpha * val;
+      }
+    }
+    return;
+  }
+  t.mode = 0;
+  const int m = tid & 63, kq = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = kq + 4 * j;
+    const int gm = m0 + m, gk = k0 + k;
+    double val = 0.0;
+    if (gm < M && gk < K && !(tri && tri_zero(tri, gm, gk))) val = *elem_ptr(A, gm, gk, z, y);
+    t.v[j] = alpha * val;
+  }
+}
+
+__device__ __forceinline__ void store_a(const TileRegs& t, double (*As)[LDS_ROW]) {
+  const int tid = threadIdx.x;
+  if (t.mode == 1) {
+    const int k = tid & 15, mq = tid >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) As[k][mq + 16 * j] = t.v[j];
+  } else {
+    const int m = tid & 63, kq = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) As[kq + 4 * j][m] = t.v[j];
+  }
+}
+
+// Logical B(k, n), tile BK x BN at (k0, n0); stored in LDS as Bs[k][n].
+__device__ __forceinline__ void load_b(const View& B, int K, int N, int k0, int n0, int tri, int z,
+                                       int y, TileRegs& t) {
+  const int tid = threadIdx.x;
+  const bool inb = (n0 + BN <= N) && (k0 + BK <= K);
+  const int q = inb ? uniform_quad(B, k0, BK, n0, BN) : -1;
+  if (q >= 0) {
+    QuadSel s = pick(B, q, z, y);
+    const int ko = (q & 1) ? k0 - B.rs : k0;
+    const int no = (q & 2) ? n0 - B.cs : n0;
+    const double* base = s.p + ko * s.sr + no * s.sc;
+    if (s.sr == 1 && s.sc != 1) {
+      t.mode = 1;  // k fastest
+      const int k = tid & 15, nq = tid >> 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = nq + 16 * j;
+        double val = base[k + n * s.sc];
+        if (tri && tri_zero(tri, k0 + k, n0 + n)) val = 0.0;
+        t.v[j] = val;
+      }
+    } else {
+      t.mode = 0;  // n fastest
+      const int n = tid & 63, kq = tid >> 6;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kq + 4 * j;
+        double val = base[k * s.sr + n * s.sc];
+        if (tri && tri_zero(tri, k0 + k, n0 + n)) val = 0.0;
+        t.v[j] = val;
+      }
+    }
+    return;
+  }
+  t.mode = 0;
+  const int n = tid & 63, kq = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = kq + 4 * j;
+    const int gk = k0 + k, gn = n0 + n;
+    double val = 0.0;
+    if (gk < K && gn < N && !(tri && tri_zero(tri, gk, gn))) val = *elem_ptr(B, gk, gn, z, y);
+    t.v[j] = val;
+  }
+}
+
+__device__ __forceinline__ void store_b(const TileRegs& t, double (*Bs)[LDS_ROW]) {
+  const int tid = threadIdx.x;
+  if (t.mode == 1) {
+    const int k = tid & 15, nq = tid >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bs[k][nq + 16 * j] = t.v[j];
+  } else {
+    const int n = tid & 63, kq = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bs[kq + 4 * j][n] = t.v[j];
+  }
+}
+
+__device__ __forceinline__ void krange(int mode, int K, int m0, int n0, int& klo, int& khi) {
+  klo = 0;
+  khi = K;
+  switch (mode) {
+    case KR_GE_N0: klo = n0; break;
+    case KR_LT_N1: khi = min(K, n0 + BN); break;
+    case KR_LT_M1: khi = min(K, m0 + BM); break;
+    case KR_GE_MAX: klo = max(m0, n0); break;
+    default: break;
+  }
+  klo = (klo / BK) * BK;
+  if (klo > K) klo = K;
+}
+
+__device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
+                                          bool lasty, int z, int y, int wm, int wn, int lane,
+                                          double (*As)[LDS_ROW], double (*Bs)[LDS_ROW],
+                                          v4d (&acc)[2][2]) {
+  const int K = lasty ? ph.Klast : ph.K;
+  int klo, khi;
+  krange(ph.kmode, K, m0, n0, klo, khi);
+  if (klo >= khi) return;
+  TileRegs ra, rb;
+  load_a(ph.A, M, K, m0, klo, ph.triA, ph.alpha, z, y, ra);
+  load_b(ph.B, K, N, klo, n0, ph.triB, z, y, rb);
+  for (int k0 = klo; k0 < khi; k0 += BK) {
+    store_a(ra, As);
+    store_b(rb, Bs);
+    __syncthreads();
+    if (k0 + BK < khi) {
+      load_a(ph.A, M, K, m0, k0 + BK, ph.triA, ph.alpha, z, y, ra);
+      load_b(ph.B, K, N, k0 + BK, n0, ph.triB, z, y, rb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      const double a0 = As[kr][wm + (lane & 15)];
+      const double a1 = As[kr][wm + 16 + (lane & 15)];
+      const double b0 = Bs[kr][wn + (lane & 15)];
+      const double b1 = Bs[kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmArgs args) {
+  __shared__ double As[BK][LDS_ROW];
+  __shared__ double Bs[BK][LDS_ROW];
+  const int z = blockIdx.z, y = blockIdx.y;
+  const bool lasty = (y == (int)gridDim.y - 1);
+  const int M = lasty ? args.Mlast : args.M;
+  const int N = lasty ? args.Nlast : args.N;
+  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  int ti, tj;
+  if (args.omode == OUT_ALL) {
+    const int L = blockIdx.x;
+    if (L >= tilesM * tilesN) return;
+    ti = L % tilesM;
+    tj = L / tilesM;
+  } else {
+    const int L = blockIdx.x;
+    if (L >= tilesM * (tilesM + 1) / 2) return;
+    ti = (int)((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > L) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= L) ++ti;
+    tj = L - ti * (ti + 1) / 2;
+  }
+  const int m0 = ti * BM, n0 = tj * BN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  run_phase(args.ph[0], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
+  if (args.nph > 1) run_phase(args.ph[1], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
+
+  // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v)
+  const View& C = args.C;
+  const bool full = (m0 + BM <= M) && (n0 + BN <= N);
+  const int qc = full ? uniform_quad(C, m0, BM, n0, BN) : -1;
+  const double beta = args.beta;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + bi * 16 + (lane & 15);
+        const int n = n0 + wn + bj * 16 + (lane >> 4) + 4 * v;
+        if (m >= M || n >= N) continue;
+        if (args.omode != OUT_ALL && m < n) continue;
+        double* dst;
+        if (qc >= 0) {
+          QuadSel s = pick(C, qc, z, y);
+          const int mo = (qc & 1) ? m - C.rs : m;
+          const int no = (qc & 2) ? n - C.cs : n;
+          dst = const_cast<double*>(s.p + mo * s.sr + no * s.sc);
+        } else {
+          dst = elem_ptr(C, m, n, z, y);
+        }
+        double val = acc[bi][bj][v];
+        if (beta != 0.0) val += beta * (*dst);
+        *dst = val;
+        if (args.omode == OUT_LOWER_MIRROR && m > n) *elem_ptr(C, n, m, z, y) = val;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+View view_plain(double* p, long long ld, long long zstride, bool trans) {
+  View v;
+  for (int q = 0; q < 4; ++q) {
+    v.p[q] = p;
+    v.sr[q] = trans ? ld : 1;
+    v.sc[q] = trans ? 1 : ld;
+    v.zs[q] = zstride;
+    v.ys[q] = 0;
+  }
+  v.rs = INT_MAX;
+  v.cs = INT_MAX;
+  return v;
+}
+
+View view_rowsplit(double* p0, long long ld0, long long zs0, double* p1, long long ld1,
+                   long long zs1, int rsplit, bool trans) {
+  View v = view_plain(p0, ld0, zs0, trans);
+  // the stored matrix is [X0 (rsplit rows); X1]; a transposed view splits logical columns
+  const int q1 = trans ? 2 : 1;
+  v.p[q1] = p1;
+  v.sr[q1] = trans ? ld1 : 1;
+  v.sc[q1] = trans ? 1 : ld1;
+  v.zs[q1] = zs1;
+  if (trans) v.cs = rsplit; else v.rs = rsplit;
+  return v;
+}
+
+void view_set_y(View& v, long long ystride) {
+  for (int q = 0; q < 4; ++q) v.ys[q] = ystride;
+}
+
+int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || ny <= 0 || nz <= 0) return 0;
+  if (a.nph < 1 || a.nph > 2) return -1;
+  if (ny > 65535 || nz > 65535) return -1;
+  const int tM = (a.M + BM - 1) / BM, tN = (a.N + BN - 1) / BN;
+  long long gx;
+  if (a.omode == OUT_ALL) {
+    gx = (long long)tM * tN;
+  } else {
+    if (a.M != a.N || a.Mlast != a.Nlast) return -1;
+    gx = (long long)tM * (tM + 1) / 2;
+  }
+  if (gx <= 0) return 0;
+  if (gx > INT_MAX) return -1;
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)gx, ny, nz), dim3(256), 0, s, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace adelia

@@ -1,0 +1,11 @@
+// Cross-file host helpers of the C ABI layer.
+#pragma once
+#include "common.h"
+#include <string>
+
+namespace adelia {
+void set_last_error(const std::string& s);
+size_t align_up(size_t v);
+int launch_finalize_info(int32_t* info, int n, hipStream_t s);
+int launch_lt_gram_inverse(const double* L, int a, long long ld, double* ZT, hipStream_t s);
+}  // namespace adelia

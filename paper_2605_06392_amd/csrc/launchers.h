@@ -1,0 +1,23 @@
+// Launch wrappers implemented in potrf.hip / util.hip (host side).
+#pragma once
+#include "common.h"
+
+#define ADELIA_E_HIP_INTERNAL (-102)
+
+namespace adelia {
+int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,
+                       long long zLd, int32_t* info, int b, int c0, long long gcol0, int nz,
+                       hipStream_t s);
+int launch_tip(double* T, long long zT, int a, int ap, double* ldp, long long zLd, int32_t* info,
+               long long gcol0, double* zsq, double* ZT, long long zZT, double* xT,
+               long long zXT, int nz, hipStream_t s);
+int launch_gemv_n(const double* A, long long ld, long long zA, const double* x, long long zx,
+                  long long incx, const double* y0, long long zy0, long long incy0, double* y,
+                  long long zy, long long incy, int M, int K, int lowerA, double alpha,
+                  double beta, int nz, hipStream_t s);
+int launch_tri_small(const double* L, long long ld, long long zL, double* v, long long zv, int a,
+                     int trans, int nz, hipStream_t s);
+int launch_logdiag(const double* L, int b, long long ld, long long bs, int nblk, double* part,
+                   long long zL, long long zp, int nz, hipStream_t s);
+int launch_fill_strided(double* p, long long stride, int count, double v, hipStream_t s);
+}  // namespace adelia

@@ -1,0 +1,140 @@
+"""GPU parity of the BTA entry points and the batched GEMM against the dense CPU oracle.
+
+Inputs: seeded random SPD BTA matrices (workloads.bta) with sizes that span several 64-wide
+tiles and ragged tails, n = 1 and a = 0 edge cases.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+import oracle
+from workloads.bta import random_bta
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1, 0), (1, 7, 2), (2, 64, 2), (3, 70, 3), (2, 130, 0), (4, 100, 8), (3, 200, 1),
+          (2, 257, 5), (5, 33, 4)]
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _to_dev_blocks(arr, dev):
+    # row-major numpy blocks (k, r, c) -> column-major device blocks
+    from paper_2605_06392_amd.bta import to_cm
+    return to_cm(torch.from_numpy(np.ascontiguousarray(arr)).to(dev))
+
+
+def _cm_to_np(t):
+    return t.transpose(-1, -2).cpu().numpy()
+
+
+@pytest.mark.parametrize("M,N,K,tA,tB,batch,lower", [
+    (64, 64, 64, 0, 0, 1, 0), (100, 37, 129, 0, 1, 2, 0), (17, 200, 5, 1, 0, 3, 0),
+    (130, 130, 70, 1, 1, 1, 1), (1, 1, 1, 0, 0, 1, 0), (257, 65, 300, 0, 0, 2, 0)])
+def test_dgemm(M, N, K, tA, tB, batch, lower):
+    dev = _dev()
+    from paper_2605_06392_amd import bta
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.standard_normal((batch, K, M) if tA else (batch, M, K))
+    B = rng.standard_normal((batch, N, K) if tB else (batch, K, N))
+    Cm = rng.standard_normal((batch, M, N))
+    ref = np.einsum("bij,bjk->bik", A.transpose(0, 2, 1) if tA else A,
+                    B.transpose(0, 2, 1) if tB else B) * 1.5 + 0.5 * Cm
+    dA = _to_dev_blocks(A, dev)
+    dB = _to_dev_blocks(B, dev)
+    dC = _to_dev_blocks(Cm, dev)
+    bta.dgemm(dA, dB, dC, transA=bool(tA), transB=bool(tB), alpha=1.5, beta=0.5, lower=bool(lower))
+    torch.cuda.synchronize()
+    got = _cm_to_np(dC)
+    if lower:
+        il = np.tril_indices(M)
+        for z in range(batch):
+            assert np.allclose(got[z][il], ref[z][il], rtol=1e-12, atol=1e-11)
+            iu = np.triu_indices(M, 1)
+            assert np.array_equal(got[z][iu], Cm[z][iu])
+    else:
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-11)
+
+
+def _factor_case(n, b, a, seed, with_rhs=True):
+    dev = _dev()
+    from paper_2605_06392_amd import bta
+    blk = random_bta(n, b, a, seed)
+    Q = oracle.bta_dense(blk["D"], blk["B"], blk["C"], blk["T"])
+    dD = _to_dev_blocks(blk["D"], dev)
+    dB = _to_dev_blocks(blk["B"] if n > 1 else np.zeros((1, b, b)), dev)
+    dC = _to_dev_blocks(blk["C"] if a else np.zeros((n, 1, b)), dev)
+    dT = _to_dev_blocks(blk["T"][None], dev)[0] if a else None
+    rhs = torch.from_numpy(blk["rhs"].copy()).to(dev) if with_rhs else None
+    Dinv, logdet, info = bta.bta_factor(dD, dB, dC, dT, rhs)
+    torch.cuda.synchronize()
+    return blk, Q, dict(D=dD, B=dB, C=dC, T=dT, rhs=rhs, Dinv=Dinv, logdet=logdet, info=info)
+
+
+@pytest.mark.parametrize("n,b,a", SHAPES)
+def test_bta_factor_vs_dense_cholesky(n, b, a):
+    blk, Q, out = _factor_case(n, b, a, seed=n * 1000 + b * 10 + a)
+    ref = oracle.dense_cholesky(Q, blk["rhs"])
+    Lb = oracle.bta_split(ref["L"], n, b, a)
+    assert int(out["info"].item()) == 0
+    scale = np.abs(ref["L"]).max()
+    LD = _cm_to_np(out["D"])
+    assert np.abs(LD - Lb["D"]).max() <= 1e-12 * scale
+    if n > 1:
+        assert np.abs(_cm_to_np(out["B"]) - Lb["B"]).max() <= 1e-12 * scale
+    if a:
+        assert np.abs(_cm_to_np(out["C"]) - Lb["C"]).max() <= 1e-12 * scale
+        assert np.abs(_cm_to_np(out["T"]) - np.tril(Lb["T"])).max() <= 1e-12 * scale
+    Ginv = np.stack([sla.solve_triangular(Lb["D"][i], np.eye(b), lower=True) for i in range(n)])
+    assert np.abs(_cm_to_np(out["Dinv"]) - Ginv).max() <= 1e-11 * max(1.0, np.abs(Ginv).max())
+    assert abs(out["logdet"].item() - ref["logdet"]) <= 1e-12 * abs(ref["logdet"]) + 1e-12
+    z = out["rhs"].cpu().numpy()
+    assert np.abs(z - ref["z"]).max() <= 1e-11 * np.abs(ref["z"]).max()
+
+
+@pytest.mark.parametrize("n,b,a", SHAPES)
+def test_bta_logdet_solve_selinv(n, b, a):
+    from paper_2605_06392_amd import bta
+    blk, Q, out = _factor_case(n, b, a, seed=7 + n * 31 + b + a, with_rhs=False)
+    ld = bta.bta_logdet(out["D"], out["T"])
+    ref_ld = oracle.dense_cholesky(Q)["logdet"]
+    torch.cuda.synchronize()
+    assert abs(ld.item() - ref_ld) <= 1e-12 * abs(ref_ld) + 1e-12
+    rhs = torch.from_numpy(blk["rhs"].copy()).to(out["D"].device)
+    bta.bta_solve(out["Dinv"], out["B"], out["C"], out["T"], rhs)
+    torch.cuda.synchronize()
+    xref = np.linalg.solve(Q, blk["rhs"])
+    assert np.abs(rhs.cpu().numpy() - xref).max() <= 1e-11 * np.abs(xref).max()
+    ZD, ZB, ZC, ZT = bta.bta_selinv(out["Dinv"], out["B"], out["C"], out["T"])
+    torch.cuda.synchronize()
+    Zr = oracle.selected_inverse(Q, n, b, a)
+    sc = np.abs(Zr["D"]).max()
+    assert np.abs(_cm_to_np(ZD) - Zr["D"]).max() <= 1e-11 * sc
+    if n > 1:
+        assert np.abs(_cm_to_np(ZB)[: n - 1] - Zr["B"]).max() <= 1e-11 * sc
+    if a:
+        assert np.abs(_cm_to_np(ZC) - Zr["C"]).max() <= 1e-11 * sc
+        assert np.abs(_cm_to_np(ZT[None])[0] - Zr["T"]).max() <= 1e-11 * sc
+
+
+def test_bta_factor_reports_first_failing_column():
+    from paper_2605_06392_amd import bta
+    n, b, a = 3, 70, 2
+    blk = random_bta(n, b, a, seed=99)
+    blk["D"][1][5, 5] = -50.0  # breaks positive definiteness inside block 1
+    Q = oracle.bta_dense(blk["D"], blk["B"], blk["C"], blk["T"])
+    _, lapack_info = sla.lapack.dpotrf(Q, lower=1)
+    dev = _dev()
+    dD = _to_dev_blocks(blk["D"], dev)
+    dB = _to_dev_blocks(blk["B"], dev)
+    dC = _to_dev_blocks(blk["C"], dev)
+    dT = _to_dev_blocks(blk["T"][None], dev)[0]
+    _, _, info = bta.bta_factor(dD, dB, dC, dT, None)
+    torch.cuda.synchronize()
+    assert lapack_info > 0
+    assert int(info.item()) == lapack_info
