@@ -10,10 +10,6 @@
 #include <cstring>
 #include <string>
 
-struct adelia_ctx_s {
-  int device;
-};
-
 namespace adelia {
 
 thread_local std::string g_last_error;

@@ -1,11 +1,516 @@
-// INLA entry points (placeholder until the model path is in place).
+// INLA entry points: model set-up (validation, integer index structures, upload), workspace
+// layout and the orchestration of one objective / gradient evaluation (Sec. III-A, Eq. 5).
+//
+// Chains: for theta point p, chain 2p is the conditional precision Qc (BTA, arrow = fixed
+// effects plus the right-hand-side row) and chain 2p+1 the prior Qp (its arrow blocks are zero
+// and its tip is tip_prec * I), so both run through the same batched launches.
 #include "../../include/adelia.h"
-extern "C" {
-int inla_model_create(adelia_ctx, const inla_model_desc*, inla_model*) { return ADELIA_E_UNSUPPORTED; }
-int inla_model_destroy(inla_model) { return 0; }
-int inla_model_dim(inla_model) { return 0; }
-size_t inla_workspace_bytes(inla_model, int, int) { return 0; }
-int inla_objective(inla_model, const double*, int32_t, double*, int32_t*, void*, size_t, int, void*) { return ADELIA_E_UNSUPPORTED; }
-int inla_grad(inla_model, const double*, double*, double*, int32_t*, void*, size_t, int, void*) { return ADELIA_E_UNSUPPORTED; }
-int inla_fd_grad(inla_model, const double*, double, int32_t, double*, double*, int32_t*, void*, size_t, void*) { return ADELIA_E_UNSUPPORTED; }
+#include "common.h"
+#include "inla_dev.h"
+#include "internal_api.h"
+#include "launchers.h"
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace adelia;
+
+struct inla_model_s {
+  int device;
+  int param;
+  ModelDev M;
+  void* dev_mem;
+};
+
+namespace {
+
+struct InlaWs {
+  int batch, nz, n, b, a, ap, k, d, npanel;
+  bool grad;
+  int slotsD, slotsB, slotsLB, slotsG;
+  double *D, *Bin, *LB, *G, *C, *LC, *T, *S, *ldpart, *ld, *zsq, *ZT, *xT;
+  long long zD, zB, zLB, zG, zC, zLC, zT, zS, zLd, zZT, zXT;
+  int32_t* info;
+  double *phi, *dphi, *tau;
+  double *Th, *fv;
+  int32_t* finfo;
+  double *x, *y, *W, *ZD, *ZB, *ZC, *TD, *TB, *O, *qD, *qB, *resid;
+  long long zx, zy, zW, zZD, zZB, zZC, zTr, zO;
+  size_t bytes;
+};
+
+InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
+  InlaWs w{};
+  w.batch = batch;
+  w.nz = 2 * batch;
+  w.n = M.nt; w.b = M.b; w.a = M.a; w.ap = M.a + 1; w.k = M.k; w.d = M.d;
+  w.npanel = (M.b + kPanel - 1) / kPanel;
+  w.grad = grad;
+  const long long bb = (long long)M.b * M.b;
+  const int n = M.nt;
+  w.slotsD = 2;
+  w.slotsB = 1;
+  w.slotsLB = grad ? std::max(n - 1, 1) : 1;
+  w.slotsG = grad ? n : 1;
+  size_t off = 0;
+  auto take = [&](long long per_chain, int chains, long long& stride) {
+    stride = per_chain;
+    double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
+    off = align_up(off + (size_t)per_chain * chains * sizeof(double));
+    return p;
+  };
+  long long dummy;
+  // finite-difference stencil scratch first: its place does not depend on the batch size
+  const int npts = 2 * M.d + 1;
+  w.Th = take((long long)npts * M.d, 1, dummy);
+  w.fv = take(npts, 1, dummy);
+  {
+    double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
+    w.finfo = reinterpret_cast<int32_t*>(p);
+    off = align_up(off + (size_t)npts * sizeof(int32_t));
+  }
+  const int nz = w.nz;
+  w.D = take(w.slotsD * bb, nz, w.zD);
+  w.Bin = take(w.slotsB * bb, nz, w.zB);
+  w.LB = take(w.slotsLB * bb, nz, w.zLB);
+  w.G = take(w.slotsG * bb, nz, w.zG);
+  w.C = take((long long)n * w.ap * M.b, nz, w.zC);
+  w.LC = take((long long)n * w.ap * M.b, nz, w.zLC);
+  w.T = take((long long)w.ap * w.ap, nz, w.zT);
+  w.S = take(bb, nz, w.zS);
+  w.ldpart = take((long long)n * w.npanel + 1, nz, w.zLd);
+  w.ld = take(1, nz, dummy);
+  w.zsq = take(1, nz, dummy);
+  w.ZT = take(std::max(1, w.a * w.a), nz, w.zZT);
+  w.xT = take(std::max(1, w.a), nz, w.zXT);
+  {
+    double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
+    w.info = reinterpret_cast<int32_t*>(p);
+    off = align_up(off + (size_t)nz * sizeof(int32_t));
+  }
+  const long long NE = 9LL * M.k * M.k;
+  w.phi = take(NE, batch, dummy);
+  w.dphi = take(NE * M.d, batch, dummy);
+  w.tau = take(M.k, batch, dummy);
+  if (grad) {
+    const long long Nlat = (long long)n * M.b + M.a;
+    w.x = take(Nlat, nz, w.zx);
+    w.y = take(M.b, nz, w.zy);
+    w.W = take(bb + (long long)M.a * M.b, nz, w.zW);
+    w.ZD = take(2 * bb, nz, w.zZD);
+    w.ZB = take(bb, nz, w.zZB);
+    w.ZC = take(std::max(1LL, 2LL * M.a * M.b), nz, w.zZC);
+    w.TD = take((long long)n * 3 * M.k * M.k, nz, w.zTr);
+    w.TB = take((long long)n * 3 * M.k * M.k, nz, dummy);
+    w.O = take((long long)n * M.k, nz, w.zO);
+    w.qD = take((long long)n * 3 * M.k * M.k, 1, dummy);
+    w.qB = take((long long)n * 3 * M.k * M.k, 1, dummy);
+    w.resid = take(M.k, 1, dummy);
+  }
+  w.bytes = off + 256;
+  return w;
 }
+
+BtaChains chains_of(const InlaWs& w) {
+  BtaChains c{};
+  c.n = w.n; c.b = w.b; c.a = w.a; c.ap = w.ap; c.nz = w.nz;
+  c.D = w.D; c.zD = w.zD; c.slotsD = w.slotsD;
+  c.Bin = w.Bin; c.zB = w.zB; c.slotsB = w.slotsB;
+  c.LB = w.LB; c.zLB = w.zLB; c.slotsLB = w.slotsLB;
+  c.C = w.C; c.zC = w.zC;
+  c.LC = w.LC; c.zLC = w.zLC;
+  c.T = w.T; c.zT = w.zT;
+  c.G = w.G; c.zG = w.zG; c.slotsG = w.slotsG;
+  c.ldpart = w.ldpart; c.zLd = w.zLd;
+  c.info = w.info;
+  c.scratch = w.S; c.zS = w.zS;
+  c.zsq = w.zsq;
+  if (w.grad && w.a > 0) {
+    c.ZT = w.ZT; c.zZT = w.zZT;
+    c.xT = w.xT; c.zXT = w.zXT;
+  }
+  return c;
+}
+
+#define LAUNCH_OK() (hipGetLastError() == hipSuccess)
+
+// Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
+int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStream_t s) {
+  const int nz = w.nz, n = w.n, b = w.b;
+  hipLaunchKernelGGL(param_kernel, dim3(w.batch), dim3(256), 0, s, M, theta, w.phi, w.dphi,
+                     w.tau);
+  if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  if (launch_fill_i32(w.info, nz, INT32_MAX, s)) return ADELIA_E_HIP;
+  const long long nb = (long long)n * b;
+  hipLaunchKernelGGL(assemble_arrow_kernel, dim3((unsigned)((nb + 255) / 256), 1, nz), dim3(256),
+                     0, s, M, w.C, w.zC, w.ap, w.tau);
+  hipLaunchKernelGGL(assemble_tip_kernel, dim3(w.ap * w.ap, 1, nz), dim3(256), 0, s, M, w.T,
+                     w.zT, w.ap, w.tau);
+  if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  const long long bb = (long long)b * b;
+  const dim3 agrid((b + 63) / 64, 1, nz);
+  BtaChains c = chains_of(w);
+  hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(256), 0, s, M, 0, -1, w.D, w.zD,
+                     w.Bin, w.zB, w.phi, w.tau);
+  for (int i = 0; i < n; ++i) {
+    const int td = i + 1 < n ? i + 1 : -1;
+    const int tb = i < n - 1 ? i : -1;
+    if (td >= 0 || tb >= 0) {
+      double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * bb;
+      hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(256), 0, s, M, td, tb, Dslot,
+                         w.zD, w.Bin, w.zB, w.phi, w.tau);
+      if (!LAUNCH_OK()) return ADELIA_E_HIP;
+    }
+    if (bta_forward_block(c, i, s)) return ADELIA_E_HIP;
+  }
+  if (bta_tip(c, s)) return ADELIA_E_HIP;
+  if (bta_logdet_reduce(w.ldpart, w.zLd, n * w.npanel + 1, w.ld, 1, nz, s)) return ADELIA_E_HIP;
+  return 0;
+}
+
+int run_objective(const ModelDev& M, const InlaWs& w, const double* theta, double* f,
+                  int32_t* info, hipStream_t s) {
+  int r = run_forward(M, w, theta, s);
+  if (r) return r;
+  hipLaunchKernelGGL(objective_kernel, dim3((w.batch + 63) / 64), dim3(64), 0, s, M, theta,
+                     w.batch, w.tau, w.ld, w.zsq, w.info, f, info);
+  return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+}
+
+int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double* f, double* grad,
+                 int32_t* info, hipStream_t s) {
+  const int n = w.n, b = w.b, a = w.a, ap = w.ap, nz = w.nz;
+  // x* = Qc^-1 r by the upper sweep (Eqs. 3-5); z_t is the rhs row of L_C
+  SolveChains sc{};
+  sc.n = n; sc.b = b; sc.a = a; sc.nz = nz;
+  sc.G = w.G; sc.zG = w.zG; sc.slotsG = w.slotsG;
+  sc.LB = w.LB; sc.zLB = w.zLB; sc.slotsLB = w.slotsLB;
+  sc.LC = w.LC; sc.zLC = w.zLC; sc.ldLC = ap;
+  sc.z = w.LC + a; sc.zz = w.zLC; sc.sz_blk = (long long)ap * b; sc.sz_elem = ap;
+  sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
+  sc.x = w.x; sc.zx = w.zx;
+  sc.y = w.y; sc.zy = w.zy;
+  if (bta_upper_solve(sc, s)) return ADELIA_E_HIP;
+  // selected inversion of Qc and Qp with the trace epilogue per block (Eq. 6)
+  SelinvChains si{};
+  si.n = n; si.b = b; si.a = a; si.nz = nz;
+  si.G = w.G; si.zG = w.zG; si.slotsG = w.slotsG;
+  si.LB = w.LB; si.zLB = w.zLB; si.slotsLB = w.slotsLB;
+  si.LC = w.LC; si.zLC = w.zLC; si.ldLC = ap;
+  si.ZT = w.ZT; si.zZT = w.zZT;
+  si.ZD = w.ZD; si.zZD = w.zZD; si.slotsZD = 2;
+  si.ZB = w.ZB; si.zZB = w.zZB; si.slotsZB = 1;
+  si.ZC = w.ZC; si.zZC = w.zZC; si.slotsZC = 2;
+  si.W = w.W; si.zW = w.zW;
+  const long long bb = (long long)b * b;
+  const int ntrace = 2 * M.k * M.k + M.k;
+  for (int j = n - 1; j >= 0; --j) {
+    if (selinv_block(si, j, s)) return ADELIA_E_HIP;
+    const double* ZDj = w.ZD + (long long)(j % 2) * bb;
+    const double* ZCj = w.ZC + (long long)(j % 2) * a * b;
+    hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, s, M, j, ZDj, w.zZD,
+                       w.ZB, w.zZB, ZCj, w.zZC, w.ZT, w.zZT, w.TD, w.TB, w.O, w.zTr, w.zO);
+    if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  }
+  // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 0)
+  hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k), dim3(256), 0, s, M, w.x, w.qD, w.qB);
+  hipLaunchKernelGGL(resid_kernel, dim3(M.k), dim3(256), 0, s, M, w.x, w.resid);
+  hipLaunchKernelGGL(grad_kernel, dim3(1), dim3(256), 0, s, M, theta, w.phi, w.dphi, w.tau, w.TD,
+                     w.TB, w.zTr, w.O, w.qD, w.qB, w.resid, w.ld, w.zsq, w.info, f, grad, info);
+  return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+}
+
+bool aligned(const void* p, size_t al) { return ((uintptr_t)p % al) == 0; }
+
+int fail(const std::string& msg) {
+  set_last_error(msg);
+  return ADELIA_E_SHAPE;
+}
+
+// CSR validation; returns an empty string when valid
+std::string check_csr(const char* name, const int32_t* ptr, const int32_t* idx, const double* val,
+                      int ns) {
+  if (!ptr || !idx || !val) return std::string(name) + ": null CSR array";
+  if (ptr[0] != 0) return std::string(name) + ": row pointer must start at 0";
+  for (int r = 0; r < ns; ++r) {
+    if (ptr[r + 1] < ptr[r]) return std::string(name) + ": row pointer decreases";
+    for (int e = ptr[r]; e < ptr[r + 1]; ++e)
+      if (idx[e] < 0 || idx[e] >= ns) return std::string(name) + ": column index out of range";
+  }
+  // symmetry (values included)
+  std::map<std::pair<int, int>, double> ent;
+  for (int r = 0; r < ns; ++r)
+    for (int e = ptr[r]; e < ptr[r + 1]; ++e) ent[{r, idx[e]}] += val[e];
+  for (const auto& kv : ent) {
+    auto it = ent.find({kv.first.second, kv.first.first});
+    if (it == ent.end() || it->second != kv.second) return std::string(name) + ": not symmetric";
+  }
+  return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out) {
+  set_last_error("");
+  if (!ctx) return -1;
+  if (!d) return -2;
+  if (!out) return -3;
+  if (d->param != ADELIA_PARAM_UNIVARIATE && d->param != ADELIA_PARAM_COREG)
+    return fail("unknown parameterisation");
+  const int k = d->k, ns = d->ns, nt = d->nt, a = d->a, n_obs = d->n_obs;
+  if (k < 1 || k > kMaxFields) return fail("k must be 1..4");
+  if (d->param == ADELIA_PARAM_UNIVARIATE && k != 1) return fail("univariate model needs k == 1");
+  if (ns < 1 || nt < 1 || a < 0 || a > 64 || n_obs < 0) return fail("bad sizes");
+  const long long b = (long long)k * ns;
+  if (b * nt + a > INT_MAX || b * b > (1LL << 40)) return fail("model too large");
+  if (!(d->sigma_prior > 0.0) || !(d->tip_prec > 0.0)) return fail("sigma and tip_prec must be > 0");
+  std::string e;
+  if (!(e = check_csr("c0", d->c0_ptr, d->c0_idx, d->c0_val, ns)).empty()) return fail(e);
+  if (!(e = check_csr("g1", d->g1_ptr, d->g1_idx, d->g1_val, ns)).empty()) return fail(e);
+  if (!(e = check_csr("g2", d->g2_ptr, d->g2_idx, d->g2_val, ns)).empty()) return fail(e);
+  if (!d->m0_diag || !d->m1_diag || !d->m2_diag) return fail("null temporal diagonal");
+  if (nt > 1 && (!d->m0_off || !d->m1_off || !d->m2_off)) return fail("null temporal sub-diagonal");
+  if (n_obs > 0 && (!d->obs_t || !d->obs_field || !d->obs_node || !d->obs_w || !d->y))
+    return fail("null observation array");
+  if (n_obs > 0 && a > 0 && !d->X) return fail("null covariate matrix");
+  long long prev = -1;
+  for (int o = 0; o < n_obs; ++o) {
+    const int t = d->obs_t[o], m = d->obs_field[o];
+    if (t < 0 || t >= nt || m < 0 || m >= k) return fail("observation time/field out of range");
+    const long long key = (long long)t * k + m;
+    if (key < prev) return fail("observations must be sorted by (time, field)");
+    prev = key;
+    for (int q = 0; q < 4; ++q)
+      if (d->obs_node[4 * o + q] < 0 || d->obs_node[4 * o + q] >= ns)
+        return fail("observation node out of range");
+  }
+  // union pattern of the three base matrices
+  std::vector<int32_t> uptr(ns + 1, 0), uidx;
+  std::vector<double> u0, u1, u2;
+  const int32_t* ptrs[3] = {d->c0_ptr, d->g1_ptr, d->g2_ptr};
+  const int32_t* idxs[3] = {d->c0_idx, d->g1_idx, d->g2_idx};
+  const double* vals[3] = {d->c0_val, d->g1_val, d->g2_val};
+  for (int r = 0; r < ns; ++r) {
+    std::map<int, double> row[3];
+    std::vector<int> cols;
+    for (int s = 0; s < 3; ++s)
+      for (int q = ptrs[s][r]; q < ptrs[s][r + 1]; ++q) {
+        row[s][idxs[s][q]] += vals[s][q];
+        cols.push_back(idxs[s][q]);
+      }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    for (int c : cols) {
+      uidx.push_back(c);
+      u0.push_back(row[0].count(c) ? row[0][c] : 0.0);
+      u1.push_back(row[1].count(c) ? row[1][c] : 0.0);
+      u2.push_back(row[2].count(c) ? row[2][c] : 0.0);
+    }
+    uptr[r + 1] = (int32_t)uidx.size();
+  }
+  const int nnz = (int)uidx.size();
+  std::vector<double> uval;
+  uval.insert(uval.end(), u0.begin(), u0.end());
+  uval.insert(uval.end(), u1.begin(), u1.end());
+  uval.insert(uval.end(), u2.begin(), u2.end());
+  std::vector<double> tm(3 * (2 * nt - 1), 0.0);
+  const double* diags[3] = {d->m0_diag, d->m1_diag, d->m2_diag};
+  const double* offs[3] = {d->m0_off, d->m1_off, d->m2_off};
+  for (int r = 0; r < 3; ++r) {
+    for (int t = 0; t < nt; ++t) tm[r * (2 * nt - 1) + t] = diags[r][t];
+    for (int t = 0; t < nt - 1; ++t) tm[r * (2 * nt - 1) + nt + t] = offs[r][t];
+  }
+  std::vector<int32_t> obs_off(nt * k + 1, 0);
+  std::vector<int32_t> nobs(k, 0);
+  for (int o = 0; o < n_obs; ++o) {
+    obs_off[d->obs_t[o] * k + d->obs_field[o] + 1]++;
+    nobs[d->obs_field[o]]++;
+  }
+  for (int i = 0; i < nt * k; ++i) obs_off[i + 1] += obs_off[i];
+  const long long ncolg = (long long)nt * b;
+  std::vector<int32_t> colptr(ncolg + 1, 0);
+  for (int o = 0; o < n_obs; ++o)
+    for (int q = 0; q < 4; ++q) {
+      const long long g = (long long)d->obs_t[o] * b + (long long)d->obs_field[o] * ns + d->obs_node[4 * o + q];
+      colptr[g + 1]++;
+    }
+  for (long long g = 0; g < ncolg; ++g) colptr[g + 1] += colptr[g];
+  std::vector<int32_t> col_o(colptr[ncolg]), col_e(colptr[ncolg]);
+  {
+    std::vector<int32_t> fillp(colptr.begin(), colptr.end() - 1);
+    for (int o = 0; o < n_obs; ++o)
+      for (int q = 0; q < 4; ++q) {
+        const long long g = (long long)d->obs_t[o] * b + (long long)d->obs_field[o] * ns + d->obs_node[4 * o + q];
+        col_o[fillp[g]] = o;
+        col_e[fillp[g]] = q;
+        fillp[g]++;
+      }
+  }
+  // device upload: one allocation, set-up time only
+  std::vector<std::pair<const void*, size_t>> parts = {
+      {uptr.data(), uptr.size() * 4},    {uidx.data(), uidx.size() * 4},
+      {uval.data(), uval.size() * 8},    {tm.data(), tm.size() * 8},
+      {d->obs_t, (size_t)n_obs * 4},     {d->obs_field, (size_t)n_obs * 4},
+      {d->obs_node, (size_t)n_obs * 16}, {d->obs_w, (size_t)n_obs * 32},
+      {d->X, (size_t)n_obs * a * 8},     {d->y, (size_t)n_obs * 8},
+      {obs_off.data(), obs_off.size() * 4}, {colptr.data(), colptr.size() * 4},
+      {col_o.data(), col_o.size() * 4},  {col_e.data(), col_e.size() * 4},
+      {nullptr, (size_t)k * 8}};
+  size_t total = 0;
+  std::vector<size_t> offsets;
+  for (auto& pr : parts) {
+    offsets.push_back(total);
+    total = align_up(total + std::max<size_t>(pr.second, 8));
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return ADELIA_E_HIP;
+  char* mem = nullptr;
+  if (hipMalloc(&mem, total) != hipSuccess) return ADELIA_E_HIP;
+  for (size_t i = 0; i < parts.size(); ++i)
+    if (parts[i].first && parts[i].second &&
+        hipMemcpy(mem + offsets[i], parts[i].first, parts[i].second, hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(mem);
+      return ADELIA_E_HIP;
+    }
+  inla_model m = new inla_model_s;
+  m->device = ctx->device;
+  m->param = d->param;
+  m->dev_mem = mem;
+  ModelDev& M = m->M;
+  std::memset(&M, 0, sizeof(M));
+  M.k = k; M.ns = ns; M.nt = nt; M.a = a; M.b = (int)b; M.n_obs = n_obs; M.nnz = nnz;
+  M.sigma = d->sigma_prior; M.tip = d->tip_prec;
+  M.uptr = (const int32_t*)(mem + offsets[0]);
+  M.uidx = (const int32_t*)(mem + offsets[1]);
+  M.uval = (const double*)(mem + offsets[2]);
+  M.tm = (const double*)(mem + offsets[3]);
+  M.obs_t = (const int32_t*)(mem + offsets[4]);
+  M.obs_f = (const int32_t*)(mem + offsets[5]);
+  M.obs_node = (const int32_t*)(mem + offsets[6]);
+  M.obs_w = (const double*)(mem + offsets[7]);
+  M.X = (const double*)(mem + offsets[8]);
+  M.y = (const double*)(mem + offsets[9]);
+  M.obs_off = (const int32_t*)(mem + offsets[10]);
+  M.colptr = (const int32_t*)(mem + offsets[11]);
+  M.col_o = (const int32_t*)(mem + offsets[12]);
+  M.col_e = (const int32_t*)(mem + offsets[13]);
+  M.yy = (const double*)(mem + offsets[14]);
+  for (int i = 0; i < k; ++i) M.nobs_field[i] = nobs[i];
+  const int nl = k * (k - 1) / 2;
+  if (d->param == ADELIA_PARAM_UNIVARIATE) {
+    M.d = 4;
+    M.idx_prec[0] = 0; M.idx_range[0] = 1; M.idx_temporal[0] = 2; M.idx_tau[0] = 3;
+    M.role_kind[0] = ROLE_COUPLING; M.role_idx[0] = 0;
+    M.role_kind[1] = ROLE_RANGE; M.role_idx[1] = 0;
+    M.role_kind[2] = ROLE_TEMPORAL; M.role_idx[2] = 0;
+    M.role_kind[3] = ROLE_TAU; M.role_idx[3] = 0;
+  } else {
+    M.d = 4 * k + nl;
+    for (int i = 0; i < k; ++i) {
+      M.idx_range[i] = i; M.role_kind[i] = ROLE_RANGE; M.role_idx[i] = i;
+      M.idx_temporal[i] = k + i; M.role_kind[k + i] = ROLE_TEMPORAL; M.role_idx[k + i] = i;
+      M.idx_prec[i] = 2 * k + i; M.role_kind[2 * k + i] = ROLE_COUPLING; M.role_idx[2 * k + i] = i;
+      M.idx_tau[i] = 3 * k + nl + i;
+      M.role_kind[3 * k + nl + i] = ROLE_TAU; M.role_idx[3 * k + nl + i] = i;
+    }
+    for (int l = 0; l < nl; ++l) {
+      M.idx_lambda[l] = 3 * k + l;
+      M.role_kind[3 * k + l] = ROLE_COUPLING; M.role_idx[3 * k + l] = k + l;
+    }
+  }
+  hipLaunchKernelGGL(yy_kernel, dim3(k), dim3(256), 0, 0, M, (double*)M.yy);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    hipFree(mem);
+    delete m;
+    return ADELIA_E_HIP;
+  }
+  *out = m;
+  return 0;
+}
+
+int inla_model_destroy(inla_model m) {
+  if (!m) return 0;
+  hipFree(m->dev_mem);
+  delete m;
+  return 0;
+}
+
+int inla_model_dim(inla_model m) { return m ? m->M.d : 0; }
+
+size_t inla_workspace_bytes(inla_model m, int batch, int mode) {
+  if (!m || batch < 1 || batch > 32767) return 0;
+  if (mode == ADELIA_MODE_GRAD && batch != 1) return 0;
+  return layout(m->M, batch, mode == ADELIA_MODE_GRAD, nullptr).bytes;
+}
+
+int inla_objective(inla_model m, const double* theta, int32_t batch, double* f, int32_t* info,
+                   void* ws, size_t ws_bytes, int flags, void* stream) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (batch < 1 || batch > 32767) return -3;
+  if (!f || !aligned(f, 8)) return -4;
+  if (!info || !aligned(info, 4)) return -5;
+  if (!ws || !aligned(ws, 256)) return -6;
+  if (flags & ~ADELIA_SAVE_FACTORS) return -8;
+  const bool save = flags & ADELIA_SAVE_FACTORS;
+  if (save && batch != 1) return -3;
+  InlaWs w = layout(m->M, batch, save, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  return run_objective(m->M, w, theta, f, info, (hipStream_t)stream);
+}
+
+int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_t* info, void* ws,
+              size_t ws_bytes, int flags, void* stream) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (!f || !aligned(f, 8)) return -3;
+  if (!grad || !aligned(grad, 8)) return -4;
+  if (!info || !aligned(info, 4)) return -5;
+  if (!ws || !aligned(ws, 256)) return -6;
+  if (flags & ~ADELIA_REUSE_FACTORS) return -8;
+  InlaWs w = layout(m->M, 1, true, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (!(flags & ADELIA_REUSE_FACTORS)) {
+    int r = run_forward(m->M, w, theta, s);
+    if (r) return r;
+  }
+  return run_backward(m->M, w, theta, f, grad, info, s);
+}
+
+int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch, double* f,
+                 double* grad, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (!(h > 0.0)) return -3;
+  if (max_batch < 1 || max_batch > 32767) return -4;
+  if (!f || !aligned(f, 8)) return -5;
+  if (!grad || !aligned(grad, 8)) return -6;
+  if (!info || !aligned(info, 4)) return -7;
+  if (!ws || !aligned(ws, 256)) return -8;
+  const int d = m->M.d, npts = 2 * d + 1;
+  const int bmax = std::min<int>(max_batch, npts);
+  InlaWs w = layout(m->M, bmax, false, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d, h,
+                     w.Th);
+  if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  for (int p0 = 0; p0 < npts; p0 += bmax) {
+    const int bs = std::min(bmax, npts - p0);
+    // a smaller last sub-batch uses a prefix of the same workspace; the stencil scratch sits
+    // at a fixed place in front of it
+    InlaWs wb = layout(m->M, bs, false, reinterpret_cast<char*>(ws));
+    int r = run_objective(m->M, wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s);
+    if (r) return r;
+  }
+  hipLaunchKernelGGL(fd_kernel, dim3((d + 63) / 64), dim3(64), 0, s, w.fv, d, h, f, grad);
+  return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+}
+
+}  // extern "C"

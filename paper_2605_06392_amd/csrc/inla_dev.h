@@ -1,0 +1,61 @@
+// Device-resident INLA model description (passed by value to the kernels).
+#pragma once
+#include "common.h"
+
+namespace adelia {
+
+enum Role { ROLE_RANGE = 0, ROLE_TEMPORAL = 1, ROLE_COUPLING = 2, ROLE_TAU = 3 };
+
+struct ModelDev {
+  int k, ns, nt, a, b, n_obs, d, nnz;
+  double sigma, tip;
+  const int32_t* uptr;   // union pattern of c0, g1, g2 (CSR, ns + 1)
+  const int32_t* uidx;   // nnz
+  const double* uval;    // 3 * nnz: value of c0, g1, g2 on the union pattern
+  const double* tm;      // 3 x (2 nt - 1): diagonal then sub-diagonal of M0, M1, M2
+  const int32_t* obs_t;
+  const int32_t* obs_f;
+  const int32_t* obs_node;  // n_obs x 4
+  const double* obs_w;      // n_obs x 4
+  const double* X;          // n_obs x a
+  const double* y;
+  const int32_t* obs_off;   // nt*k + 1: first observation of (t, field)
+  const int32_t* colptr;    // nt*b + 1: observation entries touching (t, column)
+  const int32_t* col_o;
+  const int32_t* col_e;
+  const double* yy;         // k: sum of y^2 per field
+  int nobs_field[kMaxFields];
+  int idx_range[kMaxFields], idx_temporal[kMaxFields], idx_prec[kMaxFields];
+  int idx_lambda[kMaxFields * (kMaxFields - 1) / 2], idx_tau[kMaxFields];
+  int role_kind[kMaxTheta], role_idx[kMaxTheta];
+};
+
+__global__ void param_kernel(const ModelDev M, const double* theta, double* phi, double* dphi,
+                             double* tau);
+__global__ void assemble_blocks_kernel(const ModelDev M, int td, int tb, double* D, long long zD,
+                                       double* B, long long zB, const double* phi,
+                                       const double* tau);
+__global__ void assemble_arrow_kernel(const ModelDev M, double* C, long long zC, int ap,
+                                      const double* tau);
+__global__ void assemble_tip_kernel(const ModelDev M, double* T, long long zT, int ap,
+                                    const double* tau);
+__global__ void trace_kernel(const ModelDev M, int j, const double* ZD, long long zZD,
+                             const double* ZB, long long zZB, const double* ZC, long long zZC,
+                             const double* ZT, long long zZT, double* TD, double* TB, double* O,
+                             long long zTr, long long zO);
+__global__ void phaseb_kernel(const ModelDev M, const double* x, double* qD, double* qB);
+__global__ void resid_kernel(const ModelDev M, const double* x, double* resid);
+__global__ void objective_kernel(const ModelDev M, const double* theta, int batch,
+                                 const double* tau, const double* ld, const double* zsq,
+                                 const int32_t* info, double* f, int32_t* info_out);
+__global__ void grad_kernel(const ModelDev M, const double* theta, const double* phi,
+                            const double* dphi, const double* tau, const double* TD,
+                            const double* TB, long long zTr, const double* O, const double* qD,
+                            const double* qB, const double* resid, const double* ld,
+                            const double* zsq, const int32_t* info, double* f, double* grad,
+                            int32_t* info_out);
+__global__ void yy_kernel(const ModelDev M, double* yy);
+__global__ void stencil_kernel(const double* theta, int d, double h, double* Th);
+__global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad);
+
+}  // namespace adelia

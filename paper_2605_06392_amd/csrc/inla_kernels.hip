@@ -1,0 +1,477 @@
+// Device kernels of the INLA objective and gradient around the BTA sweeps.
+//
+// Model (Sec. II-A; Sec. III-B, Eq. 9): every sub-block (i1, i2) of a temporal block is a
+// combination of the three spatial base matrices c0, g1, g2:
+//   [D_t]^(i1,i2) = sum_s sum_r M_r(t,t)   phi[r][i1][i2][s] * base_s,
+//   [B_t]^(i1,i2) = sum_s sum_r M_r(t+1,t) phi[r][i1][i2][s] * base_s,
+// with phi[r][i1][i2][s] = sum_m W^(m)_{i1 i2} kappa_m[r][s], W^(m)_{ij} = Li[m][i] Li[m][j]
+// (Li = Lambda^-1, Eq. 9) and kappa_m = (K2 coefficients, e^{t_m} K1 coefficients, c0) for
+// K1 = e^{2 r_m} c0 + g1, K2 = e^{4 r_m} c0 + 2 e^{2 r_m} g1 + g2.  The univariate model is the
+// k = 1 case with W = e^{theta_1}.  Jacobians (Eqs. 10-11): per-field parameters act on kappa_m,
+// coupling parameters on W^(m).
+//
+// Gradient (Sec. III-A-3, Eq. 5), with G^c, G^p the traces of Z = Q^-1 against the base
+// matrices (Eq. 6) and q the quadratic forms of x* (Eq. 8):
+//   g_k = sum dphi_k . [ M_diag (1/2 (G^p_D - G^c_D - q_D)) + M_off (G^p_B - G^c_B - q_B) ]
+//         - 1/2 tau_m sum_o a_o^T Z^c a_o + n_m/2 - tau_m/2 |y_m - A_m x*|^2   (k = tau_m)
+//         - theta_k / sigma^2.
+#include "common.h"
+#include "inla_dev.h"
+#include <cmath>
+
+namespace adelia {
+
+namespace {
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  red[tid] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// temporal entry M_r(t, t) (off = 0) or M_r(t+1, t) (off = 1)
+__device__ __forceinline__ double tmat(const ModelDev& M, int r, int t, int off) {
+  const double* base = M.tm + (long long)r * (2 * M.nt - 1);
+  return off ? base[M.nt + t] : base[t];
+}
+
+}  // namespace
+
+// ---- per-theta coefficients ------------------------------------------------------------------
+__global__ __launch_bounds__(256) void param_kernel(const ModelDev M, const double* theta,
+                                                    double* phi, double* dphi, double* tau) {
+  __shared__ double Li[kMaxFields][kMaxFields];
+  __shared__ double dLi[kMaxTheta][kMaxFields][kMaxFields];  // indexed by coupling slot
+  __shared__ double k2s[kMaxFields], e3s[kMaxFields];
+  const int p = blockIdx.x;
+  const int k = M.k, d = M.d;
+  const double* th = theta + (long long)p * d;
+  const int ncoup = k + k * (k - 1) / 2;
+  if (threadIdx.x == 0) {
+    double Lam[kMaxFields][kMaxFields];
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Lam[i][j] = 0.0;
+    for (int m = 0; m < k; ++m) Lam[m][m] = exp(-0.5 * th[M.idx_prec[m]]);
+    int l = 0;
+    for (int i = 1; i < k; ++i)
+      for (int j = 0; j < i; ++j) Lam[i][j] = th[M.idx_lambda[l++]];
+    // Li = Lambda^-1 (lower triangular, forward substitution per column)
+    for (int c = 0; c < k; ++c)
+      for (int r = 0; r < k; ++r) {
+        double s = (r == c) ? 1.0 : 0.0;
+        for (int m = c; m < r; ++m) s -= Lam[r][m] * Li[m][c];
+        Li[r][c] = (r >= c) ? s / Lam[r][r] : 0.0;
+      }
+    // dLi = -Li dLambda Li for each coupling slot (prec m, then lambda l)
+    for (int cs = 0; cs < ncoup; ++cs) {
+      double dL[kMaxFields][kMaxFields];
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) dL[i][j] = 0.0;
+      if (cs < k) {
+        dL[cs][cs] = -0.5 * exp(-0.5 * th[M.idx_prec[cs]]);
+      } else {
+        int ll = cs - k, ii = 1, jj = 0;
+        while (ll > 0) { ++jj; if (jj == ii) { ++ii; jj = 0; } --ll; }
+        dL[ii][jj] = 1.0;
+      }
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+          double s = 0.0;
+          for (int a1 = 0; a1 < k; ++a1)
+            for (int a2 = 0; a2 < k; ++a2) s += Li[i][a1] * dL[a1][a2] * Li[a2][j];
+          dLi[cs][i][j] = -s;
+        }
+    }
+    for (int m = 0; m < k; ++m) {
+      k2s[m] = exp(2.0 * th[M.idx_range[m]]);
+      e3s[m] = exp(th[M.idx_temporal[m]]);
+      tau[(long long)p * k + m] = exp(th[M.idx_tau[m]]);
+    }
+  }
+  __syncthreads();
+  const int NE = 9 * k * k;
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    const int s = e % 3;
+    const int i2 = (e / 3) % k;
+    const int i1 = (e / (3 * k)) % k;
+    const int r = e / (3 * k * k);
+    double kap[kMaxFields], dkr[kMaxFields], dkt[kMaxFields];
+    for (int m = 0; m < k; ++m) {
+      const double k2 = k2s[m], e3 = e3s[m];
+      const double K2[3] = {k2 * k2, 2.0 * k2, 1.0};
+      const double K1[3] = {k2, 1.0, 0.0};
+      const double dK2[3] = {4.0 * k2 * k2, 4.0 * k2, 0.0};
+      const double dK1[3] = {2.0 * k2, 0.0, 0.0};
+      if (r == 0) { kap[m] = K2[s]; dkr[m] = dK2[s]; dkt[m] = 0.0; }
+      else if (r == 1) { kap[m] = e3 * K1[s]; dkr[m] = e3 * dK1[s]; dkt[m] = e3 * K1[s]; }
+      else { kap[m] = (s == 0) ? 1.0 : 0.0; dkr[m] = 0.0; dkt[m] = 0.0; }
+    }
+    double v = 0.0;
+    for (int m = 0; m < k; ++m) v += Li[m][i1] * Li[m][i2] * kap[m];
+    phi[(long long)p * NE + e] = v;
+    for (int q = 0; q < d; ++q) {
+      const int kind = M.role_kind[q], idx = M.role_idx[q];
+      double dv = 0.0;
+      if (kind == ROLE_RANGE) {
+        dv = Li[idx][i1] * Li[idx][i2] * dkr[idx];
+      } else if (kind == ROLE_TEMPORAL) {
+        dv = Li[idx][i1] * Li[idx][i2] * dkt[idx];
+      } else if (kind == ROLE_COUPLING) {
+        for (int m = 0; m < k; ++m)
+          dv += (dLi[idx][m][i1] * Li[m][i2] + Li[m][i1] * dLi[idx][m][i2]) * kap[m];
+      }
+      dphi[((long long)p * d + q) * NE + e] = dv;
+    }
+  }
+}
+
+// ---- assembly ----------------------------------------------------------------------------------
+// Fills block td of D (if td >= 0) and block tb of B (if tb >= 0) for every chain:
+// zero the 64 columns [q0, q0+64), then each column's thread writes its base-matrix entries and,
+// for Qc chains (z even), adds the observation term tau_m a_o a_o^T in a fixed order.
+__global__ __launch_bounds__(256) void assemble_blocks_kernel(const ModelDev M, int td, int tb,
+                                                              double* D, long long zD,
+                                                              double* B, long long zB,
+                                                              const double* phi,
+                                                              const double* tau) {
+  const int z = blockIdx.z;
+  const int p = z >> 1;
+  const bool qc = (z & 1) == 0;
+  const int b = M.b, ns = M.ns, k = M.k;
+  const int q0 = blockIdx.x * 64;
+  double* Dz = td >= 0 ? D + (long long)z * zD : nullptr;
+  double* Bz = tb >= 0 ? B + (long long)z * zB : nullptr;
+  const int ncols = min(64, b - q0);
+  for (long long e = threadIdx.x; e < (long long)ncols * b; e += 256) {
+    const long long row = e % b, col = q0 + e / b;
+    if (Dz) Dz[row + col * b] = 0.0;
+    if (Bz) Bz[row + col * b] = 0.0;
+  }
+  __threadfence_block();
+  __syncthreads();
+  if ((int)threadIdx.x >= ncols) return;
+  const int q = q0 + threadIdx.x;
+  const int i2 = q / ns, qq = q % ns;
+  const int NE = 9 * k * k;
+  const double* ph = phi + (long long)p * NE;
+  const int e0 = M.uptr[qq], e1 = M.uptr[qq + 1];
+  for (int i1 = 0; i1 < k; ++i1) {
+    double cD[3] = {0.0, 0.0, 0.0}, cB[3] = {0.0, 0.0, 0.0};
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s) {
+        const double f = ph[((r * k + i1) * k + i2) * 3 + s];
+        if (Dz) cD[s] += tmat(M, r, td, 0) * f;
+        if (Bz) cB[s] += tmat(M, r, tb, 1) * f;
+      }
+    for (int e = e0; e < e1; ++e) {
+      const long long row = (long long)i1 * ns + M.uidx[e];
+      const double v0 = M.uval[e], v1 = M.uval[M.nnz + e], v2 = M.uval[2 * M.nnz + e];
+      if (Dz) Dz[row + (long long)q * b] = cD[0] * v0 + cD[1] * v1 + cD[2] * v2;
+      if (Bz) Bz[row + (long long)q * b] = cB[0] * v0 + cB[1] * v1 + cB[2] * v2;
+    }
+  }
+  if (Dz && qc) {
+    const long long g = (long long)td * b + q;
+    for (int j = M.colptr[g]; j < M.colptr[g + 1]; ++j) {
+      const int o = M.col_o[j];
+      const double wq = M.obs_w[4 * o + M.col_e[j]];
+      const int m = M.obs_f[o];
+      const double tq = tau[(long long)p * k + m] * wq;
+      for (int e = 0; e < 4; ++e) {
+        const long long row = (long long)m * ns + M.obs_node[4 * o + e];
+        Dz[row + (long long)q * b] += tq * M.obs_w[4 * o + e];
+      }
+    }
+  }
+}
+
+// Arrow rows of every block: C_t = sum_o tau X_o^T a_o (rows 0..a-1) and the rhs row
+// r_t = sum_o tau y_o a_o (row a); zero for the prior chains.
+__global__ __launch_bounds__(256) void assemble_arrow_kernel(const ModelDev M, double* C,
+                                                             long long zC, int ap,
+                                                             const double* tau) {
+  const int z = blockIdx.z;
+  const int p = z >> 1;
+  const bool qc = (z & 1) == 0;
+  const long long g = blockIdx.x * 256LL + threadIdx.x;
+  const long long total = (long long)M.nt * M.b;
+  if (g >= total) return;
+  const int a = M.a;
+  double acc[65];
+  for (int c = 0; c < ap; ++c) acc[c] = 0.0;
+  if (qc) {
+    for (int j = M.colptr[g]; j < M.colptr[g + 1]; ++j) {
+      const int o = M.col_o[j];
+      const double tw = tau[(long long)p * M.k + M.obs_f[o]] * M.obs_w[4 * o + M.col_e[j]];
+      for (int c = 0; c < a; ++c) acc[c] += tw * M.X[(long long)o * a + c];
+      if (ap > a) acc[a] += tw * M.y[o];
+    }
+  }
+  // element (c, q) of block t at t*ap*b + q*ap + c == g*ap + c
+  double* Cz = C + (long long)z * zC + g * ap;
+  for (int c = 0; c < ap; ++c) Cz[c] = acc[c];
+}
+
+// Arrowhead tip entries (r >= c) of the ap x ap tip, one workgroup per entry.
+__global__ __launch_bounds__(256) void assemble_tip_kernel(const ModelDev M, double* T,
+                                                           long long zT, int ap,
+                                                           const double* tau) {
+  __shared__ double red[256];
+  const int z = blockIdx.z;
+  const int p = z >> 1;
+  const bool qc = (z & 1) == 0;
+  const int r = blockIdx.x % ap, c = blockIdx.x / ap;
+  if (r < c) return;
+  const int a = M.a;
+  double s = 0.0;
+  if (qc && c < a) {
+    for (int o = threadIdx.x; o < M.n_obs; o += 256) {
+      const double t = tau[(long long)p * M.k + M.obs_f[o]];
+      const double xr = (r < a) ? M.X[(long long)o * a + r] : M.y[o];
+      s += t * xr * M.X[(long long)o * a + c];
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    double v = s;
+    if (r == c && r < a) v += M.tip;
+    T[(long long)z * zT + r + (long long)c * ap] = (c < a) ? v : 0.0;  // corner starts at 0
+  }
+}
+
+// ---- Phase A / C traces of one selected-inverse block ------------------------------------------
+// grid.x: k*k workgroups for <Z_D^(i1,i2), base_s>, k*k for <Z_B^(i1,i2), base_s>, k for the
+// observation term sum_o a_o^T Zhat a_o per field.
+__global__ __launch_bounds__(256) void trace_kernel(const ModelDev M, int j, const double* ZD,
+                                                    long long zZD, const double* ZB,
+                                                    long long zZB, const double* ZC,
+                                                    long long zZC, const double* ZT,
+                                                    long long zZT, double* TD, double* TB,
+                                                    double* O, long long zTr, long long zO) {
+  __shared__ double red[256];
+  const int z = blockIdx.z;
+  const int k = M.k, ns = M.ns, b = M.b, a = M.a;
+  const int w = blockIdx.x;
+  const int kk = k * k;
+  if (w < 2 * kk) {
+    const bool isB = w >= kk;
+    const int i1 = (w % kk) / k, i2 = (w % kk) % k;
+    const double* Z = isB ? ZB : ZD;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (!isB || j < M.nt - 1) {
+      Z += (long long)z * (isB ? zZB : zZD);
+      for (int pr = threadIdx.x; pr < ns; pr += 256) {
+        const long long row = (long long)i1 * ns + pr;
+        for (int e = M.uptr[pr]; e < M.uptr[pr + 1]; ++e) {
+          const double v = Z[row + ((long long)i2 * ns + M.uidx[e]) * b];
+          s0 += v * M.uval[e];
+          s1 += v * M.uval[M.nnz + e];
+          s2 += v * M.uval[2 * M.nnz + e];
+        }
+      }
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+      double* out = (isB ? TB : TD) + (long long)z * zTr + ((long long)j * kk + i1 * k + i2) * 3;
+      out[0] = s0; out[1] = s1; out[2] = s2;
+    }
+    return;
+  }
+  const int m = w - 2 * kk;
+  const double* Zd = ZD + (long long)z * zZD;
+  const double* Zc = a ? ZC + (long long)z * zZC : nullptr;
+  const double* Zt = a ? ZT + (long long)z * zZT : nullptr;
+  double s = 0.0;
+  const int o0 = M.obs_off[j * k + m], o1 = M.obs_off[j * k + m + 1];
+  for (int o = o0 + threadIdx.x; o < o1; o += 256) {
+    long long gidx[4];
+    double wv[4];
+    for (int e = 0; e < 4; ++e) {
+      gidx[e] = (long long)m * ns + M.obs_node[4 * o + e];
+      wv[e] = M.obs_w[4 * o + e];
+    }
+    double v = 0.0;
+    for (int e = 0; e < 4; ++e)
+      for (int e2 = 0; e2 < 4; ++e2) v += wv[e] * wv[e2] * Zd[gidx[e] + gidx[e2] * b];
+    const double* xo = M.X + (long long)o * a;
+    for (int e = 0; e < 4; ++e)
+      for (int c = 0; c < a; ++c) v += 2.0 * wv[e] * xo[c] * Zc[c + gidx[e] * a];
+    for (int c = 0; c < a; ++c)
+      for (int c2 = 0; c2 < a; ++c2) v += xo[c] * xo[c2] * Zt[c + (long long)c2 * a];
+    s += v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) O[(long long)z * zO + (long long)j * k + m] = s;
+}
+
+// ---- Phase B: quadratic forms of the mode (Eq. 8) and the data residual -----------------------
+__global__ __launch_bounds__(256) void phaseb_kernel(const ModelDev M, const double* x,
+                                                     double* qD, double* qB) {
+  __shared__ double red[256];
+  const int k = M.k, ns = M.ns, b = M.b;
+  const int t = blockIdx.x / k, i2 = blockIdx.x % k;
+  const bool hasB = t < M.nt - 1;
+  double aD[kMaxFields][3], aB[kMaxFields][3];
+  for (int i = 0; i < k; ++i)
+    for (int s = 0; s < 3; ++s) aD[i][s] = aB[i][s] = 0.0;
+  const double* xt = x + (long long)t * b;
+  for (int pr = threadIdx.x; pr < ns; pr += 256) {
+    double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+    for (int e = M.uptr[pr]; e < M.uptr[pr + 1]; ++e) {
+      const double xv = xt[(long long)i2 * ns + M.uidx[e]];
+      u0 += M.uval[e] * xv;
+      u1 += M.uval[M.nnz + e] * xv;
+      u2 += M.uval[2 * M.nnz + e] * xv;
+    }
+    for (int i1 = 0; i1 < k; ++i1) {
+      const double xa = xt[(long long)i1 * ns + pr];
+      aD[i1][0] += xa * u0; aD[i1][1] += xa * u1; aD[i1][2] += xa * u2;
+      if (hasB) {
+        const double xb = xt[b + (long long)i1 * ns + pr];
+        aB[i1][0] += xb * u0; aB[i1][1] += xb * u1; aB[i1][2] += xb * u2;
+      }
+    }
+  }
+  for (int i1 = 0; i1 < k; ++i1)
+    for (int s = 0; s < 3; ++s) {
+      const double vD = block_sum(aD[i1][s], red);
+      const double vB = block_sum(aB[i1][s], red);
+      if (threadIdx.x == 0) {
+        const long long off = ((long long)t * k * k + i1 * k + i2) * 3 + s;
+        qD[off] = vD;
+        qB[off] = vB;
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void resid_kernel(const ModelDev M, const double* x,
+                                                    double* resid) {
+  __shared__ double red[256];
+  const int m = blockIdx.x;
+  const int a = M.a, b = M.b, ns = M.ns;
+  const double* xT = x + (long long)M.nt * b;
+  double s = 0.0;
+  for (int o = threadIdx.x; o < M.n_obs; o += 256) {
+    if (M.obs_f[o] != m) continue;
+    const long long base = (long long)M.obs_t[o] * b + (long long)m * ns;
+    double yh = 0.0;
+    for (int e = 0; e < 4; ++e) yh += M.obs_w[4 * o + e] * x[base + M.obs_node[4 * o + e]];
+    for (int c = 0; c < a; ++c) yh += M.X[(long long)o * a + c] * xT[c];
+    const double rr = M.y[o] - yh;
+    s += rr * rr;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) resid[m] = s;
+}
+
+__device__ double objective_value(const ModelDev& M, const double* th, const double* tau,
+                                  double ldc, double ldp, double zsq) {
+  double yy = 0.0, lt = 0.0;
+  for (int m = 0; m < M.k; ++m) {
+    yy += tau[m] * M.yy[m];
+    lt += 0.5 * M.nobs_field[m] * th[M.idx_tau[m]];
+  }
+  const double s2 = M.sigma * M.sigma;
+  double lp = -0.5 * M.d * log(2.0 * M_PI * s2);
+  for (int q = 0; q < M.d; ++q) lp -= th[q] * th[q] / (2.0 * s2);
+  return 0.5 * ldp - 0.5 * ldc - 0.5 * (yy - zsq) + lt - 0.5 * M.n_obs * log(2.0 * M_PI) + lp;
+}
+
+// f for every theta point; chain 2p is Qc, 2p+1 is Qp.
+__global__ void objective_kernel(const ModelDev M, const double* theta, int batch,
+                                 const double* tau, const double* ld, const double* zsq,
+                                 const int32_t* info, double* f, int32_t* info_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= batch) return;
+  f[p] = objective_value(M, theta + (long long)p * M.d, tau + (long long)p * M.k, ld[2 * p],
+                         ld[2 * p + 1], zsq[2 * p]);
+  const int32_t ic = info[2 * p], ip = info[2 * p + 1];
+  info_out[p] = (ic != 0 && ic != INT32_MAX) ? ic : ((ip != INT32_MAX) ? ip : 0);
+}
+
+// Gradient assembly for one theta point (chains 0 = Qc, 1 = Qp).
+__global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const double* theta,
+                                                   const double* phi, const double* dphi,
+                                                   const double* tau, const double* TD,
+                                                   const double* TB, long long zTr,
+                                                   const double* O, const double* qD,
+                                                   const double* qB, const double* resid,
+                                                   const double* ld, const double* zsq,
+                                                   const int32_t* info, double* f, double* grad,
+                                                   int32_t* info_out) {
+  __shared__ double S[9 * kMaxFields * kMaxFields];
+  const int k = M.k, kk = k * k, nt = M.nt, d = M.d;
+  const int NE = 9 * kk;
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    const int r = e / (3 * kk);
+    const int rest = e % (3 * kk);  // (i1*k + i2)*3 + s
+    double acc = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      const long long o = (long long)t * kk * 3 + rest;
+      const double wD = 0.5 * (TD[zTr + o] - TD[o] - qD[o]);
+      acc += tmat(M, r, t, 0) * wD;
+      if (t < nt - 1) {
+        const double wB = TB[zTr + o] - TB[o] - qB[o];
+        acc += tmat(M, r, t, 1) * wB;
+      }
+    }
+    S[e] = acc;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < d; q += blockDim.x) {
+    double g = 0.0;
+    for (int e = 0; e < NE; ++e) g += dphi[(long long)q * NE + e] * S[e];
+    if (M.role_kind[q] == ROLE_TAU) {
+      const int m = M.role_idx[q];
+      double so = 0.0;
+      for (int t = 0; t < nt; ++t) so += O[(long long)t * k + m];
+      g += -0.5 * tau[m] * so + 0.5 * M.nobs_field[m] - 0.5 * tau[m] * resid[m];
+    }
+    g -= theta[q] / (M.sigma * M.sigma);
+    grad[q] = g;
+  }
+  if (threadIdx.x == 0) {
+    f[0] = objective_value(M, theta, tau, ld[0], ld[1], zsq[0]);
+    const int32_t ic = info[0], ip = info[1];
+    info_out[0] = (ic != 0 && ic != INT32_MAX) ? ic : ((ip != INT32_MAX) ? ip : 0);
+  }
+}
+
+__global__ void yy_kernel(const ModelDev M, double* yy) {
+  __shared__ double red[256];
+  const int m = blockIdx.x;
+  double s = 0.0;
+  for (int o = threadIdx.x; o < M.n_obs; o += 256)
+    if (M.obs_f[o] == m) s += M.y[o] * M.y[o];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) yy[m] = s;
+}
+
+__global__ void stencil_kernel(const double* theta, int d, double h, double* Th) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int npts = 2 * d + 1;
+  if (i >= npts * d) return;
+  const int p = i / d, q = i % d;
+  double v = theta[q];
+  if (p > 0) {
+    const int j = (p - 1) / 2;
+    if (j == q) v += ((p - 1) % 2 == 0) ? h : -h;
+  }
+  Th[i] = v;
+}
+
+__global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) f[0] = fv[0];
+  if (j < d) grad[j] = (fv[1 + 2 * j] - fv[2 + 2 * j]) / (2.0 * h);
+}
+
+}  // namespace adelia

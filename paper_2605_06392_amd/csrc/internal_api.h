@@ -3,6 +3,10 @@
 #include "common.h"
 #include <string>
 
+struct adelia_ctx_s {
+  int device;
+};
+
 namespace adelia {
 void set_last_error(const std::string& s);
 size_t align_up(size_t v);

@@ -1,0 +1,200 @@
+"""Python surface of the INLA entry points (argument marshalling only).
+
+``InlaModel`` uploads a model once (``inla_model_create``); ``objective`` evaluates f for a
+batch of theta points, ``grad`` returns f and the exact gradient (Sec. III-A-3, Eq. 5),
+``fd_grad`` the (2d+1)-point central-difference gradient on the GPU (Sec. II-C, Eq. 2), and
+``InlaObjective`` is the torch.autograd.Function whose forward keeps the Cholesky factors of
+Qc and Qp in the model's workspace and whose backward runs the hand-written reverse pass
+(selected inversion + traces) from them.
+"""
+import ctypes as C
+import itertools
+
+import numpy as np
+import torch
+from torch.autograd.function import once_differentiable
+
+from ._lib import ModelDesc, check, lib
+from .bta import context
+
+PARAM_UNIVARIATE = 1
+PARAM_COREG = 2
+MODE_OBJECTIVE = 0
+MODE_GRAD = 1
+SAVE_FACTORS = 1
+REUSE_FACTORS = 1
+
+_token = itertools.count(1)
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None and a.size else C.c_void_p(0)
+
+
+class InlaModel:
+    """A model on one HIP device.  ``spec`` provides: kind ("univariate" | "coreg"), k, nx, ny,
+    nt, a, base matrices c0, g1, g2 (scipy CSR), temporal (diag, off) pairs m0, m1, m2, the
+    observations (obs_t, obs_field, obs_node, obs_w, X, y), sigma_prior and tip_prec."""
+
+    def __init__(self, spec, device="cuda:0"):
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.k = int(spec.k)
+        self.ns = int(spec.nx * spec.ny)
+        self.nt = int(spec.nt)
+        self.a = int(spec.a)
+        self.b = self.k * self.ns
+        host = {}
+
+        def i32(x):
+            return np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+
+        def f64(x):
+            return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+        for name in ("c0", "g1", "g2"):
+            mtx = getattr(spec, name).tocsr()
+            mtx.sort_indices()
+            host[name] = (i32(mtx.indptr), i32(mtx.indices), f64(mtx.data))
+        for name in ("m0", "m1", "m2"):
+            dg, off = getattr(spec, name)
+            host[name] = (f64(dg), f64(off) if len(off) else np.zeros(1))
+        host["obs_t"] = i32(spec.obs_t)
+        host["obs_field"] = i32(spec.obs_field)
+        host["obs_node"] = i32(spec.obs_node).reshape(-1)
+        host["obs_w"] = f64(spec.obs_w).reshape(-1)
+        host["X"] = f64(spec.X).reshape(-1)
+        host["y"] = f64(spec.y)
+        desc = ModelDesc()
+        desc.param = PARAM_UNIVARIATE if spec.kind == "univariate" else PARAM_COREG
+        desc.k, desc.ns, desc.nt, desc.a = self.k, self.ns, self.nt, self.a
+        desc.n_obs = int(len(spec.y))
+        desc.c0_ptr, desc.c0_idx, desc.c0_val = (_ptr(v) for v in host["c0"])
+        desc.g1_ptr, desc.g1_idx, desc.g1_val = (_ptr(v) for v in host["g1"])
+        desc.g2_ptr, desc.g2_idx, desc.g2_val = (_ptr(v) for v in host["g2"])
+        desc.m0_diag, desc.m0_off = (_ptr(v) for v in host["m0"])
+        desc.m1_diag, desc.m1_off = (_ptr(v) for v in host["m1"])
+        desc.m2_diag, desc.m2_off = (_ptr(v) for v in host["m2"])
+        desc.obs_t = _ptr(host["obs_t"])
+        desc.obs_field = _ptr(host["obs_field"])
+        desc.obs_node = _ptr(host["obs_node"])
+        desc.obs_w = _ptr(host["obs_w"])
+        desc.X = _ptr(host["X"])
+        desc.y = _ptr(host["y"])
+        desc.sigma_prior = float(spec.sigma_prior)
+        desc.tip_prec = float(spec.tip_prec)
+        h = C.c_void_p()
+        dev_index = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        check(lib().inla_model_create(context(dev_index), C.byref(desc), C.byref(h)),
+              "inla_model_create")
+        self._h = h
+        self.d = lib().inla_model_dim(h)
+        self._ws = {}
+        self.saved_token = 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().inla_model_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    # -- workspaces (torch-owned device memory, kept per (batch, mode)) -----------------------
+    def workspace(self, batch, mode):
+        key = (batch, mode)
+        if key not in self._ws:
+            nbytes = lib().inla_workspace_bytes(self._h, batch, mode)
+            if nbytes == 0:
+                raise ValueError("invalid workspace request")
+            buf = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=self.device)
+            self._ws[key] = (buf, nbytes)
+        buf, nbytes = self._ws[key]
+        p = buf.data_ptr()
+        return C.c_void_p(p + ((-p) % 256)), nbytes
+
+    def workspace_bytes(self, batch, mode):
+        return int(lib().inla_workspace_bytes(self._h, batch, mode))
+
+    @staticmethod
+    def _stream():
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _theta(self, theta):
+        t = torch.as_tensor(theta, dtype=torch.float64, device=self.device)
+        return t.contiguous()
+
+    # -- evaluations ---------------------------------------------------------------------------
+    def objective(self, theta, out=None, info=None):
+        th = self._theta(theta)
+        th2 = th.reshape(-1, self.d)
+        batch = th2.shape[0]
+        f = out if out is not None else torch.empty(batch, dtype=torch.float64, device=self.device)
+        inf = info if info is not None else torch.empty(batch, dtype=torch.int32, device=self.device)
+        ws, nb = self.workspace(batch, MODE_OBJECTIVE)
+        check(lib().inla_objective(self._h, C.c_void_p(th2.data_ptr()), batch,
+                                   C.c_void_p(f.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb, 0,
+                                   self._stream()), "inla_objective")
+        return f, inf
+
+    def forward_saved(self, theta):
+        th = self._theta(theta).reshape(self.d)
+        f = torch.empty(1, dtype=torch.float64, device=self.device)
+        inf = torch.empty(1, dtype=torch.int32, device=self.device)
+        ws, nb = self.workspace(1, MODE_GRAD)
+        check(lib().inla_objective(self._h, C.c_void_p(th.data_ptr()), 1, C.c_void_p(f.data_ptr()),
+                                   C.c_void_p(inf.data_ptr()), ws, nb, SAVE_FACTORS,
+                                   self._stream()), "inla_objective(save)")
+        self.saved_token = next(_token)
+        return f, inf, self.saved_token
+
+    def grad(self, theta, reuse=False, f=None, g=None, info=None):
+        th = self._theta(theta).reshape(self.d)
+        f = f if f is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        g = g if g is not None else torch.empty(self.d, dtype=torch.float64, device=self.device)
+        inf = info if info is not None else torch.empty(1, dtype=torch.int32, device=self.device)
+        ws, nb = self.workspace(1, MODE_GRAD)
+        check(lib().inla_grad(self._h, C.c_void_p(th.data_ptr()), C.c_void_p(f.data_ptr()),
+                              C.c_void_p(g.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb,
+                              REUSE_FACTORS if reuse else 0, self._stream()), "inla_grad")
+        return f, g, inf
+
+    def fd_grad(self, theta, h=1e-3, max_batch=None, f=None, g=None, info=None):
+        th = self._theta(theta).reshape(self.d)
+        npts = 2 * self.d + 1
+        mb = npts if max_batch is None else int(max_batch)
+        mb = min(mb, npts)
+        f = f if f is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        g = g if g is not None else torch.empty(self.d, dtype=torch.float64, device=self.device)
+        inf = info if info is not None else torch.empty(npts, dtype=torch.int32, device=self.device)
+        ws, nb = self.workspace(mb, MODE_OBJECTIVE)
+        check(lib().inla_fd_grad(self._h, C.c_void_p(th.data_ptr()), float(h), mb,
+                                 C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()),
+                                 C.c_void_p(inf.data_ptr()), ws, nb, self._stream()),
+              "inla_fd_grad")
+        return f, g, inf
+
+
+class InlaObjective(torch.autograd.Function):
+    """f = InlaObjective.apply(theta, model); f.backward() fills theta.grad.
+
+    The forward pass stores the factors of Qc and Qp in the model's gradient workspace; the
+    backward pass reuses them when no other forward pass on the model came in between, and
+    recomputes them otherwise.  The backward itself is not differentiable."""
+
+    @staticmethod
+    def forward(ctx, theta, model):
+        f, info, token = model.forward_saved(theta.detach())
+        ctx.model = model
+        ctx.token = token
+        ctx.save_for_backward(theta.detach())
+        return f.reshape(())
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, grad_out):
+        (theta,) = ctx.saved_tensors
+        model = ctx.model
+        reuse = model.saved_token == ctx.token
+        _, g, _ = model.grad(theta, reuse=reuse)
+        return grad_out * g, None
