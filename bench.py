@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the AD-INLA hot path on one MI355X.
+
+A step is one exact gradient of the INLA objective (forward sweeps of Qc and Qp with the
+fused forward solve, then the upper solve, selected inversion with trace epilogues, Phase B
+and gradient assembly) on the synthetic univariate SPDE model with a 32x32 grid (b = 1024),
+50 time steps, 6 covariates, 200 observations per step and d = 4.  It is compared with the
+GPU's own (2d+1)-point central-difference gradient (all 9 objective evaluations batched into
+one pass of the same kernels).  Steps are captured once into a hipGraph and replayed.
+
+Printed: one JSON line (value = AD gradients per second).  A separate, event-profiled pass
+gives the roofline numbers of the dominant kernel; the dense CPU oracle is timed on a bounded
+sample of the same workload as the CPU baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gradients/sec AD vs 2d+1 FD at rel 1e-8; FP64 MFMA % peak for BTA factor+selinv"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uni_32x32_nt50")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a hipGraph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-nt", type=int, default=5)
+    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the event-profiled gradient steps (the command rocprofv3 traces)")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup, use_graph, torch):
+    """Mean ms per call of fn() over `steps` calls (after `warmup`), timed with events on the
+    current stream (the library launches on that stream)."""
+    if use_graph:
+        fn()  # allocations (workspaces) happen outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        run = g.replay
+    else:
+        run = fn
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def algorithmic_flops(b, n, a):
+    """Dense-block work of the method per block and matrix (flops, multiply-add = 2):
+    forward (Alg. 1) POTRF b^3/3 + TRSM b^3 + SYRK b^3 per block (the last block: POTRF);
+    selected inversion (14/3) b^3 per block."""
+    fwd = 2 * ((n - 1) * (7.0 / 3.0) + 1.0 / 3.0) * b ** 3
+    si = 2 * (14.0 / 3.0) * n * b ** 3
+    return fwd, si
+
+
+def profiled_pass(args, ad_step, bta, torch):
+    """Per-kernel time and algorithmic work of `profile_steps` gradient steps.  The device is
+    first held busy (torch.cuda._sleep) so that every launch and event of the profiled steps is
+    already queued when they run: the event intervals then bracket the kernels back to back
+    instead of including host launch latency."""
+    ad_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with bta.profile() as P0:
+        ad_step()
+    host_s = time.perf_counter() - t0  # host time to enqueue one step with its events
+    # ~2.0e9 cycles/s: hold for twice the enqueue time of the profiled steps
+    hold_cycles = int(2.0 * host_s * args.profile_steps * 2.0e9) + 50_000_000
+    with bta.profile() as P:
+        torch.cuda._sleep(hold_cycles)
+        for _ in range(args.profile_steps):
+            ad_step()
+    stats = P.stats
+    gemm_like = {k: v for k, v in stats.items() if ":" not in k}
+    name, st = max(gemm_like.items(), key=lambda kv: kv[1]["ms"])
+    per_launch_ms = st["ms"] / max(st["launches"], 1)
+    if st["flops"] > 0 and name not in ("gemv", "assemble", "trace"):
+        achieved = st["flops"] / (st["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+    else:
+        achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof.update({"kernel": name, "launches_per_step": st["launches"] / args.profile_steps,
+                 "avg_launch_us": per_launch_ms * 1e3,
+                 "algorithmic_per_launch": (st["flops"] or st["bytes"]) / max(st["launches"], 1),
+                 "host_enqueue_ms_per_step": host_s * 1e3})
+    return stats, roof
+
+
+def cpu_baseline(spec_name, seed, nt_sample):
+    import numpy as np
+    import oracle
+    from workloads import NAMED_CONFIGS, make_model
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    k, nx, ny, nt, a, obs = NAMED_CONFIGS[spec_name]
+    sample = make_model(k, nx, ny, nt_sample, a, obs, seed)
+    t0 = time.perf_counter()
+    oracle.gradient(sample, sample.theta)
+    ts = time.perf_counter() - t0
+    N_full = nt * k * nx * ny + a
+    scale = (N_full / sample.N) ** 3
+    return {
+        "value": 1.0 / (ts * scale),
+        "unit": "gradients/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"dense oracle f + exact gradient on the same grid and covariates with "
+                   f"nt={nt_sample} (N={sample.N}) took {ts:.2f} s on {threads} BLAS threads; "
+                   f"scaled by (N/N_sample)^3 = {scale:.4g} to the full N={N_full}"),
+        "sample_seconds": ts,
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path; "
+              "the stencil points or the time axis would be split across GPUs", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from workloads import NAMED_CONFIGS, named_config
+    from paper_2605_06392_amd import bta, inla
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = named_config(args.workload, seed=args.seed)
+    model = inla.InlaModel(spec, device=dev)
+    d = model.d
+    npts = 2 * d + 1
+    theta = torch.tensor(spec.theta, dtype=torch.float64, device=dev)
+    f_ad = torch.empty(1, dtype=torch.float64, device=dev)
+    g_ad = torch.empty(d, dtype=torch.float64, device=dev)
+    i_ad = torch.empty(1, dtype=torch.int32, device=dev)
+    f_fd = torch.empty(1, dtype=torch.float64, device=dev)
+    g_fd = torch.empty(d, dtype=torch.float64, device=dev)
+    i_fd = torch.empty(npts, dtype=torch.int32, device=dev)
+
+    if args.roofline_only:
+        ad_only = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
+        for _ in range(args.warmup):
+            ad_only()
+        stats, roof = profiled_pass(args, ad_only, bta, torch)
+        print(json.dumps({"roofline": roof, "kernels": stats}), flush=True)
+        return
+
+    # accuracy at full size: AD vs GPU central differences with h = 1e-4
+    model.grad(theta, f=f_ad, g=g_ad, info=i_ad)
+    model.fd_grad(theta, h=1e-4, f=f_fd, g=g_fd, info=i_fd)
+    torch.cuda.synchronize()
+    gad = g_ad.cpu().numpy()
+    gfd = g_fd.cpu().numpy()
+    ad_fd_rel = float(np.abs(gad - gfd).max() / np.abs(gad).max())
+    ok = int(i_ad.item()) == 0 and bool((i_fd.cpu().numpy() == 0).all())
+
+    use_graph = not args.no_graph
+    ad_step = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
+    fd_step = lambda: model.fd_grad(theta, h=1e-3, max_batch=npts, f=f_fd, g=g_fd, info=i_fd)  # noqa: E731
+    fwd_step = lambda: model.forward_saved(theta)  # noqa: E731
+    ms_ad = timed(ad_step, args.steps, args.warmup, use_graph, torch)
+    ms_fd = timed(fd_step, args.steps, args.warmup, use_graph, torch)
+    ms_fwd = timed(fwd_step, max(3, args.steps // 2), 1, use_graph, torch)
+    ms_bwd = timed(lambda: model.grad(theta, reuse=True, f=f_ad, g=g_ad, info=i_ad),
+                   max(3, args.steps // 2), 1, use_graph, torch)
+
+    stats, roof = profiled_pass(args, ad_step, bta, torch)
+
+    k, nx, ny, nt, a, obs = NAMED_CONFIGS[args.workload]
+    b = k * nx * ny
+    fwd_fl, si_fl = algorithmic_flops(b, nt, a)
+    line = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_ad,
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_ad,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "b": b, "n": nt, "a": a, "d": d,
+                   "N": nt * b + a, "obs_per_step": obs * k, "seed": args.seed,
+                   "graph": use_graph},
+        "fd_gradients_per_s": 1000.0 / ms_fd,
+        "ms_per_fd_gradient": ms_fd,
+        "ad_over_fd_speedup": ms_fd / ms_ad,
+        "ms_forward": ms_fwd,
+        "ms_backward": ms_bwd,
+        "beta_bwd_over_fwd": ms_bwd / ms_fwd,
+        "c_AD": ms_ad / (ms_fd / npts),
+        "ad_tflops_paper_flop_model": (fwd_fl + si_fl) / (ms_ad * 1e-3) / 1e12,
+        "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": ad_fd_rel, "info_ok": ok},
+        "kernels": {kname: {"launches_per_step": v["launches"] / args.profile_steps,
+                            "ms_per_step": v["ms"] / args.profile_steps,
+                            "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None}
+                    for kname, v in stats.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_sample_nt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

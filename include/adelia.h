@@ -202,6 +202,25 @@ int inla_fd_grad(inla_model model, const double* theta, double h, int32_t max_ba
                  double* f, double* grad, int32_t* info, void* ws, size_t ws_bytes,
                  void* stream);
 
+
+/* ---------------------------------------------------------------------------------------
+ * Opt-in kernel timing for measurement runs.  Between adelia_profile_start and
+ * adelia_profile_stop every launch of the library's main kernels is bracketed by two HIP events
+ * recorded on the launch's own stream (this inserts small gaps between launches, so time
+ * whole calls without it).  stop() synchronises the device and returns, per kernel, the number
+ * of launches, the summed event time, and the algorithmic flops and HBM bytes of those launches
+ * (the work the method needs, not the padded tile work).  Not hipGraph-capture safe.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} adelia_kernel_stats;
+int adelia_profile_start(adelia_ctx ctx, int max_launches);
+int adelia_profile_stop(adelia_ctx ctx, adelia_kernel_stats* out, int max_entries, int* n_entries);
+
 #ifdef __cplusplus
 }
 #endif

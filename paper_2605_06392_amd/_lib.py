@@ -39,6 +39,11 @@ class ModelDesc(C.Structure):
     ]
 
 
+class KernelStats(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "adelia_create": (c_int, [C.POINTER(vp), c_int]),
@@ -60,6 +65,8 @@ SIGNATURES = {
     "inla_objective": (c_int, [vp, vp, c_int32, vp, vp, vp, c_size_t, c_int, vp]),
     "inla_grad": (c_int, [vp, vp, vp, vp, vp, vp, c_size_t, c_int, vp]),
     "inla_fd_grad": (c_int, [vp, vp, c_double, c_int32, vp, vp, vp, vp, c_size_t, vp]),
+    "adelia_profile_start": (c_int, [vp, c_int]),
+    "adelia_profile_stop": (c_int, [vp, C.POINTER(KernelStats), c_int, C.POINTER(c_int)]),
 }
 
 

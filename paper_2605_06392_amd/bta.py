@@ -128,3 +128,28 @@ def bta_selinv(Dinv, LB, LC, LT):
                          nbytes, _stream())
     check(r, "bta_selinv")
     return ZD, ZB, ZC, ZT
+
+
+class profile:
+    """Context manager around adelia_profile_start/stop.  ``stats`` maps kernel name to
+    dict(launches, ms, flops, bytes) after exit (the exit synchronises the device)."""
+
+    def __init__(self, max_launches=200000, device=None):
+        self.max_launches = max_launches
+        self.device = device
+        self.stats = {}
+
+    def __enter__(self):
+        check(lib().adelia_profile_start(context(self.device), self.max_launches), "profile_start")
+        return self
+
+    def __exit__(self, *exc):
+        from ._lib import KernelStats
+        arr = (KernelStats * 16)()
+        n = C.c_int(0)
+        check(lib().adelia_profile_stop(context(self.device), arr, 16, C.byref(n)), "profile_stop")
+        for i in range(n.value):
+            s = arr[i]
+            self.stats[s.name.decode()] = dict(launches=int(s.launches), ms=float(s.ms),
+                                               flops=float(s.flops), bytes=float(s.bytes))
+        return False

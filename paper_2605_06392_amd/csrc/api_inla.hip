@@ -9,6 +9,7 @@
 #include "inla_dev.h"
 #include "internal_api.h"
 #include "launchers.h"
+#include "profile.h"
 
 #include <algorithm>
 #include <climits>
@@ -161,8 +162,10 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
     const int tb = i < n - 1 ? i : -1;
     if (td >= 0 || tb >= 0) {
       double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * bb;
+      const ProfToken t = prof_begin(s);
       hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(256), 0, s, M, td, tb, Dslot,
                          w.zD, w.Bin, w.zB, w.phi, w.tau);
+      if (t.valid) prof_end(t, s, PK_ASSEMBLE, 0.0, 8.0 * bb * nz * ((td >= 0) + (tb >= 0)));
       if (!LAUNCH_OK()) return ADELIA_E_HIP;
     }
     if (bta_forward_block(c, i, s)) return ADELIA_E_HIP;
@@ -212,8 +215,11 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
     if (selinv_block(si, j, s)) return ADELIA_E_HIP;
     const double* ZDj = w.ZD + (long long)(j % 2) * bb;
     const double* ZCj = w.ZC + (long long)(j % 2) * a * b;
+    const ProfToken t = prof_begin(s);
     hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, s, M, j, ZDj, w.zZD,
                        w.ZB, w.zZB, ZCj, w.zZC, w.ZT, w.zZT, w.TD, w.TB, w.O, w.zTr, w.zO);
+    if (t.valid)  // the band of Z_D and Z_B at the base-matrix pattern, per sub-block pair
+      prof_end(t, s, PK_TRACE, 0.0, 8.0 * nz * 2.0 * M.k * M.k * M.nnz);
     if (!LAUNCH_OK()) return ADELIA_E_HIP;
   }
   // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 0)

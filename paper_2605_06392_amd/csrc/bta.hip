@@ -48,6 +48,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.M = g.N = g.Mlast = g.Nlast = rest;
       g.beta = 1.0;
       g.omode = OUT_LOWER;
+      g.tag = GT_TRAIL;
       if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
@@ -73,6 +74,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
       g.beta = 0.0;
       g.omode = OUT_ALL;
+      g.tag = GT_TRTRI;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
     {  // X21 = -X22 * T  (X22 lower)
@@ -91,6 +93,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
       g.beta = 0.0;
       g.omode = OUT_ALL;
+      g.tag = GT_TRTRI;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
@@ -120,6 +123,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
     g.N = g.Nlast = b;
     g.beta = 0.0;
     g.omode = OUT_ALL;
+    g.tag = GT_TRMM;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // 4. Schur update of the next diagonal block, next arrow block and the tip
@@ -148,6 +152,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.C = view_plain(c.T, ap, c.zT);
       g.M = g.N = g.Mlast = g.Nlast = ap;
     }
+    g.tag = GT_SYRK;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;
@@ -211,6 +216,7 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     g.N = g.Nlast = b;
     g.beta = 0.0;
     g.omode = OUT_ALL;
+    g.tag = GT_SI_W;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // S2: [Z_Bj; Z_Cj] = -Zhat_{j+1} [W; V]
@@ -234,6 +240,7 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     g.N = g.Nlast = b;
     g.beta = 0.0;
     g.omode = OUT_ALL;
+    g.tag = GT_SI_Z;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   } else if (a) {
     GemmArgs g{};
@@ -248,6 +255,7 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     g.N = g.Nlast = b;
     g.beta = 0.0;
     g.omode = OUT_ALL;
+    g.tag = GT_SI_Z;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // S3: Z_Dj = G^T G - [Z_Bj; Z_Cj]^T [W; V]  (lower, mirrored to a full symmetric block)
@@ -278,6 +286,7 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     g.M = g.N = g.Mlast = g.Nlast = b;
     g.beta = 0.0;
     g.omode = OUT_LOWER_MIRROR;
+    g.tag = GT_SI_D;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;

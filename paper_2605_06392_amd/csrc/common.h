@@ -59,7 +59,10 @@ struct GemmArgs {
   int M, N, Mlast, Nlast;
   double beta;
   int omode;
+  int tag;  // role of the launch, for the opt-in profiler (GemmTag)
 };
+
+enum GemmTag { GT_OTHER = 0, GT_TRAIL, GT_TRTRI, GT_TRMM, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D, GT_COUNT };
 
 // ---- host helpers (gemm.hip) --------------------------------------------------------------
 View view_plain(double* p, long long ld, long long zstride, bool trans = false);

@@ -12,8 +12,10 @@
 // B-fragment as the instruction's A operand so that each lane's results lie along a column of
 // C and 16 consecutive lanes write 16 consecutive doubles.
 #include "common.h"
+#include "profile.h"
 #include <climits>
 #include <cmath>
+#include <algorithm>
 
 namespace adelia {
 
@@ -309,6 +311,45 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmArgs args) {
 
 }  // namespace
 
+
+// Algorithmic flops of one phase: 2 x the number of (m, n, k) products the mathematics needs,
+// given the triangular structure of the operands and the written part of C.
+double phase_flops(const GemmPhase& ph, int M, int N, int K, int omode) {
+  if (M <= 0 || N <= 0 || K <= 0) return 0.0;
+  const bool low = omode != OUT_ALL;
+  double s = 0.0;
+  if (ph.triA == TRI_UPPER && ph.triB == TRI_LOWER) {
+    for (int m = 0; m < M; ++m) {
+      const double cols = low ? std::min(N, m + 1) : N;
+      // k >= max(m, n): for n <= m this is K - m
+      s += cols * std::max(0, K - m);
+    }
+  } else if (ph.triB == TRI_LOWER) {
+    for (int n = 0; n < N; ++n) s += (double)(low ? std::max(0, M - n) : M) * std::max(0, K - n);
+  } else if (ph.triB == TRI_UPPER) {
+    for (int n = 0; n < N; ++n) s += (double)(low ? std::max(0, M - n) : M) * std::min(K, n + 1);
+  } else if (ph.triA == TRI_LOWER) {
+    for (int m = 0; m < M; ++m) s += (double)(low ? std::min(N, m + 1) : N) * std::min(K, m + 1);
+  } else {
+    double outs = 0.0;
+    if (low) for (int m = 0; m < M; ++m) outs += std::min(N, m + 1);
+    else outs = (double)M * N;
+    s = outs * K;
+  }
+  return 2.0 * s;
+}
+
+double gemm_flops(const GemmArgs& a, int ny) {
+  double f = 0.0;
+  for (int y = 0; y < ny; ++y) {
+    const bool last = y == ny - 1;
+    const int M = last ? a.Mlast : a.M, N = last ? a.Nlast : a.N;
+    for (int p = 0; p < a.nph; ++p)
+      f += phase_flops(a.ph[p], M, N, last ? a.ph[p].Klast : a.ph[p].K, a.omode);
+  }
+  return f;
+}
+
 View view_plain(double* p, long long ld, long long zstride, bool trans) {
   View v;
   for (int q = 0; q < 4; ++q) {
@@ -354,7 +395,10 @@ int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s) {
   }
   if (gx <= 0) return 0;
   if (gx > INT_MAX) return -1;
+  const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)gx, ny, nz), dim3(256), 0, s, a);
+  if (t.valid) prof_end_role(t, s, PK_GEMM, (a.tag >= 0 && a.tag < GT_COUNT) ? a.tag : 0,
+                            gemm_flops(a, ny) * nz, 0.0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

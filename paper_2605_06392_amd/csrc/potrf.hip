@@ -10,6 +10,7 @@
 // tip_kernel: factors the a x a arrowhead tip after the sweep, finishes the forward solve
 // (z_T), and forms Z_T = L_T^-T L_T^-1 and x_T = L_T^-T z_T for the backward pass.
 #include "common.h"
+#include "profile.h"
 #include <cmath>
 
 namespace adelia {
@@ -30,6 +31,7 @@ struct PanelArgs {
 
 __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   __shared__ double colb[2][NB];
+  __shared__ double pivs[NB];
   __shared__ double xrow[2][NB];
   __shared__ double Xs[NB][PAD];   // Xs[k][n] = Linv(n, k)  (B operand, k-major)
   __shared__ double As[NB][PAD];   // As[k][m] = A(m, k)
@@ -67,57 +69,84 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   }
   __syncthreads();
 
-  double logsum = 0.0;
-  int fail = -1;
+  // One column per step, one barrier per step.  Masks are folded into the operands so the
+  // 4 x 4 updates are branch-free: lc is zero for finished columns (c <= j), lrx is zero for
+  // rows r <= j and xj is zero for c > j.
   for (int j = 0; j < NB; ++j) {
     const int cur = j & 1, nxt = cur ^ 1;
     const double djj = colb[cur][j];
-    if (!(djj > 0.0) && fail < 0 && j < w) fail = j;
     const double piv = sqrt(djj);
     const double invs = 1.0 / piv;
-    if (j < w) logsum += log(piv);
-    double lr[4], lc[4], xj[4];
+    if (tid == 0) pivs[j] = djj;
+    double lr[4], lrx[4], lc[4], xj[4];
 #pragma unroll
-    for (int ii = 0; ii < 4; ++ii) lr[ii] = colb[cur][4 * br + ii] * invs;
+    for (int ii = 0; ii < 4; ++ii) {
+      lr[ii] = colb[cur][4 * br + ii] * invs;
+      lrx[ii] = (4 * br + ii > j) ? lr[ii] : 0.0;
+    }
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
-      lc[jj] = colb[cur][4 * bc + jj] * invs;
-      xj[jj] = xrow[cur][4 * bc + jj] * invs;
+      const int c = 4 * bc + jj;
+      lc[jj] = (c > j) ? colb[cur][c] * invs : 0.0;
+      xj[jj] = (c <= j) ? xrow[cur][c] * invs : 0.0;
     }
-    if (active) {
 #pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        const int r = 4 * br + ii;
+    for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int c = 4 * bc + jj;
-          // Cholesky: trailing update and finalisation of column j
-          if (c > j && r >= c) a[ii][jj] -= lr[ii] * lc[jj];
-          if (c == j && r >= j) a[ii][jj] = (r == j) ? piv : lr[ii];
-          // inverse by right-looking forward substitution on the identity
-          if (c <= j) {
-            if (r > j) x[ii][jj] -= lr[ii] * xj[jj];
-            else if (r == j) x[ii][jj] = xj[jj];
-          }
-        }
+      for (int jj = 0; jj < 4; ++jj) {
+        a[ii][jj] = fma(-lr[ii], lc[jj], a[ii][jj]);
+        x[ii][jj] = fma(-lrx[ii], xj[jj], x[ii][jj]);
       }
-      // publish column j+1 of A (rows >= j+1) and row j+1 of X (cols <= j+1)
-      if (j + 1 < NB) {
+    const int jq = j >> 2, jr = j & 3;
+    if (bc == jq) {  // finalise column j of L in the owning threads
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+        if (jj == jr) {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) a[ii][jj] = (4 * br + ii == j) ? piv : lr[ii];
+        }
+    }
+    if (br == jq) {  // row j of L^-1 is final
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+        if (ii == jr) {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) x[ii][jj] = xj[jj];
+        }
+    }
+    if (j + 1 < NB) {
+      const int nq = (j + 1) >> 2, nr = (j + 1) & 3;
+      if (bc == nq && active) {
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
-          if (4 * bc + jj == j + 1) {
+          if (jj == nr) {
 #pragma unroll
             for (int ii = 0; ii < 4; ++ii) colb[nxt][4 * br + ii] = a[ii][jj];
           }
+      }
+      if (br == nq && active) {
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii)
-          if (4 * br + ii == j + 1) {
+          if (ii == nr) {
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) xrow[nxt][4 * bc + jj] = x[ii][jj];
           }
       }
     }
     __syncthreads();
+  }
+  // log-diagonal sum and the first failing pivot, once, by wave 0
+  double logsum = 0.0;
+  int fail = -1;
+  if (tid < 64) {
+    const double dj = pivs[tid];
+    double lg = (tid < w) ? 0.5 * log(dj) : 0.0;
+    const bool bad = (tid < w) && !(dj > 0.0);
+    const unsigned long long badmask = __ballot(bad);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lg += __shfl_xor(lg, off, 64);
+    logsum = lg;
+    if (badmask) fail = __ffsll((long long)badmask) - 1;
   }
 
   if (blockIdx.x == 0) {
@@ -298,7 +327,14 @@ int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double*
                        hipStream_t s) {
   PanelArgs P{D, zD, G, zG, ldp, zLd, info, b, c0, gcol0};
   const int rows = (b - c0 + NB - 1) / NB;
+  const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(potrf_panel_kernel, dim3(rows, 1, nz), dim3(256), 0, s, P);
+  if (t.valid) {
+    // the panel's share of the Cholesky: w^3/3 for the tile, w^2 per row below it
+    const double w = (b - c0) < NB ? (b - c0) : NB;
+    const double below = (double)(b - c0) - w;
+    prof_end(t, s, PK_PANEL, nz * (w * w * w / 3.0 + below * w * w), 0.0);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -307,7 +343,9 @@ int launch_tip(double* T, long long zT, int a, int ap, double* ldp, long long zL
                long long zXT, int nz, hipStream_t s) {
   if (ap > 65) return -1;
   TipArgs P{T, zT, a, ap, ldp, zLd, info, gcol0, zsq, ZT, zZT, xT, zXT};
+  const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(tip_kernel, dim3(nz), dim3(64), 0, s, P);
+  if (t.valid) prof_end(t, s, PK_TIP, nz * (double)a * a * a / 3.0, 0.0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -1,0 +1,24 @@
+// Internal hooks of the opt-in event profiler (profile.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace adelia {
+
+enum ProfKind {
+  PK_GEMM = 0, PK_PANEL, PK_GEMV, PK_ASSEMBLE, PK_TRACE, PK_TIP,
+  PK_GEMM_ROLE0,  // + GemmTag: per-role copies of the GEMM statistics
+  PK_COUNT = PK_GEMM_ROLE0 + 8
+};
+
+struct ProfToken {
+  hipEvent_t a, b;
+  bool valid;
+};
+
+bool prof_active();
+ProfToken prof_begin(hipStream_t s);
+void prof_end(const ProfToken& t, hipStream_t s, int kind, double flops, double bytes);
+void prof_end_role(const ProfToken& t, hipStream_t s, int kind, int role, double flops,
+                   double bytes);
+
+}  // namespace adelia

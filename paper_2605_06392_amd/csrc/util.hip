@@ -2,6 +2,7 @@
 // the triangular solves (Sec. III-A-2, Eqs. 3-5).  Reductions use a fixed order (no atomics)
 // so that repeated runs are bitwise identical.
 #include "common.h"
+#include "profile.h"
 #include <climits>
 
 namespace adelia {
@@ -193,7 +194,12 @@ int launch_zero_upper(double* p, int b, long long ld, long long blockstride, int
 int launch_gemv_t(const GemvT& g, int nz, hipStream_t s) {
   if (g.M <= 0 || nz <= 0) return 0;
   if (g.r2 > 64) return -1;
+  const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(gemv_t_kernel, dim3((g.M + 3) / 4, 1, nz), dim3(256), 0, s, g);
+  if (t.valid) {
+    const double elems = g.A ? (g.lowerA ? 0.5 * g.M * (g.M + 1.0) : (double)g.M * g.K) : 0.0;
+    prof_end(t, s, PK_GEMV, nz * 2.0 * elems, nz * 8.0 * (elems + (double)g.r2 * g.M + 2.0 * g.M));
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -18,7 +18,7 @@ def declared_functions():
     return sorted(set(n for n in names if n not in ("if", "while")))
 
 
-def test_header_declares_north_star_calls():
+def test_header_declares_hot_path_calls():
     names = declared_functions()
     for n in ["bta_factor", "bta_logdet", "bta_solve", "bta_selinv", "inla_objective", "inla_grad"]:
         assert n in names

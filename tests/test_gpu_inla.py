@@ -147,3 +147,28 @@ def test_repeat_runs_bitwise_identical():
         outs.append((f.item(), g.cpu().numpy().copy()))
     for f, g in outs[1:]:
         assert f == outs[0][0] and np.array_equal(g, outs[0][1])
+
+
+def test_graph_replay_matches_eager():
+    """A captured gradient replays to the eager result, with eager work on the same workspace
+    between replays."""
+    spec, m = gpu_model("uni_12x12_nt6", 4)
+    theta = torch.tensor(spec.theta, device="cuda:0")
+    f = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    g = torch.empty(spec.d, dtype=torch.float64, device="cuda:0")
+    info = torch.empty(1, dtype=torch.int32, device="cuda:0")
+    m.grad(theta, f=f, g=g, info=info)
+    torch.cuda.synchronize()
+    f_ref, g_ref = f.item(), g.cpu().numpy().copy()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        m.grad(theta, f=f, g=g, info=info)
+    other = torch.tensor(spec.theta[::-1].copy(), device="cuda:0")
+    for _ in range(3):
+        f.zero_()
+        g.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert f.item() == f_ref and np.array_equal(g.cpu().numpy(), g_ref)
+        m.grad(other)  # eager work on the same workspace in between
+        torch.cuda.synchronize()
