@@ -193,6 +193,14 @@ int inla_objective(inla_model model, const double* theta, int32_t batch, double*
 int inla_grad(inla_model model, const double* theta, double* f, double* grad, int32_t* info,
               void* ws, size_t ws_bytes, int flags, void* stream);
 
+/* inla_grad with its decomposition, for diagnostics and identities: terms (device,
+ * 5 + 6d doubles) = [f, log|Qp|, log|Qc|, |z|^2 (z = L_c^-1 r), tr([Qc^-1]_{T,T}),
+ * PhaseA(d), PhaseB(d), PhaseC(d), dlog l/dtheta(d), dlog p/dtheta(d), grad(d)], where
+ * PhaseA = -1/2 tr(Qc^-1 dQc), PhaseB = -1/2 x*^T dQp x*, PhaseC = 1/2 tr(Qp^-1 dQp)
+ * (Sec. III-A-3, Eq. 5).  Same workspace and flags as inla_grad. */
+int inla_grad_terms(inla_model model, const double* theta, double* terms, int32_t* info,
+                    void* ws, size_t ws_bytes, int flags, void* stream);
+
 /* Central finite-difference gradient (Sec. II-C, Eq. 2) on the GPU: the 2d+1 points
  * theta, theta +- h e_j are evaluated as batched objectives (in sub-batches of at most
  * `max_batch` points, sized by the caller's workspace = inla_workspace_bytes(model,

@@ -153,9 +153,9 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
                      w.zT, w.ap, w.tau);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
   const long long bb = (long long)b * b;
-  const dim3 agrid((b + 63) / 64, 1, nz);
+  const dim3 agrid(b, 1, nz);
   BtaChains c = chains_of(w);
-  hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(256), 0, s, M, 0, -1, w.D, w.zD,
+  hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, 0, -1, w.D, w.zD,
                      w.Bin, w.zB, w.phi, w.tau);
   for (int i = 0; i < n; ++i) {
     const int td = i + 1 < n ? i + 1 : -1;
@@ -163,7 +163,7 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
     if (td >= 0 || tb >= 0) {
       double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * bb;
       const ProfToken t = prof_begin(s);
-      hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(256), 0, s, M, td, tb, Dslot,
+      hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, td, tb, Dslot,
                          w.zD, w.Bin, w.zB, w.phi, w.tau);
       if (t.valid) prof_end(t, s, PK_ASSEMBLE, 0.0, 8.0 * bb * nz * ((td >= 0) + (tb >= 0)));
       if (!LAUNCH_OK()) return ADELIA_E_HIP;
@@ -185,7 +185,7 @@ int run_objective(const ModelDev& M, const InlaWs& w, const double* theta, doubl
 }
 
 int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double* f, double* grad,
-                 int32_t* info, hipStream_t s) {
+                 int32_t* info, double* terms, hipStream_t s) {
   const int n = w.n, b = w.b, a = w.a, ap = w.ap, nz = w.nz;
   // x* = Qc^-1 r by the upper sweep (Eqs. 3-5); z_t is the rhs row of L_C
   SolveChains sc{};
@@ -226,7 +226,8 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k), dim3(256), 0, s, M, w.x, w.qD, w.qB);
   hipLaunchKernelGGL(resid_kernel, dim3(M.k), dim3(256), 0, s, M, w.x, w.resid);
   hipLaunchKernelGGL(grad_kernel, dim3(1), dim3(256), 0, s, M, theta, w.phi, w.dphi, w.tau, w.TD,
-                     w.TB, w.zTr, w.O, w.qD, w.qB, w.resid, w.ld, w.zsq, w.info, f, grad, info);
+                     w.TB, w.zTr, w.O, w.qD, w.qB, w.resid, w.ld, w.zsq, w.ZT, w.info, f, grad,
+                     info, terms);
   return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
 }
 
@@ -486,7 +487,26 @@ int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_
     int r = run_forward(m->M, w, theta, s);
     if (r) return r;
   }
-  return run_backward(m->M, w, theta, f, grad, info, s);
+  return run_backward(m->M, w, theta, f, grad, info, nullptr, s);
+}
+
+int inla_grad_terms(inla_model m, const double* theta, double* terms, int32_t* info, void* ws,
+                    size_t ws_bytes, int flags, void* stream) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (!terms || !aligned(terms, 8)) return -3;
+  if (!info || !aligned(info, 4)) return -4;
+  if (!ws || !aligned(ws, 256)) return -5;
+  if (flags & ~ADELIA_REUSE_FACTORS) return -7;
+  InlaWs w = layout(m->M, 1, true, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (!(flags & ADELIA_REUSE_FACTORS)) {
+    int r = run_forward(m->M, w, theta, s);
+    if (r) return r;
+  }
+  const int d = m->M.d;
+  return run_backward(m->M, w, theta, terms, terms + 5 + 5 * d, info, terms, s);
 }
 
 int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch, double* f,

@@ -21,7 +21,7 @@ namespace adelia {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int LDS_ROW = BM + 4;  // padded row (doubles); keeps 16-byte alignment
 
 struct QuadSel {
@@ -68,12 +68,18 @@ __device__ __forceinline__ bool tri_zero(int tri, int r, int c) {
   return (tri == TRI_LOWER && c > r) || (tri == TRI_UPPER && r > c);
 }
 
-// Load the BM x BK tile of logical A at (m0, k0) into registers (4 values per thread), in the
-// thread->element mapping implied by `mode` (0: m fastest, 1: k fastest).
+// Tile loads.  A BM x BK tile of logical A (and a BK x BN tile of logical B) goes through 8
+// registers per thread.  Fast paths (tile inside one quadrant and in bounds) use 16-byte loads
+// along the contiguous dimension; mode records the thread -> element mapping for the LDS store:
+//   0: pairs along M (N for B), 1: pairs along K, 2: generic scalar (M/N fastest).
 struct TileRegs {
-  double v[4];
+  double v[8];
   int mode;
 };
+
+__device__ __forceinline__ bool vec_ok(const double* base, long long other_stride) {
+  return ((reinterpret_cast<uintptr_t>(base) & 15) == 0) && ((other_stride & 1) == 0);
+}
 
 __device__ __forceinline__ void load_a(const View& A, int M, int K, int m0, int k0, int tri,
                                        double alpha, int z, int y, TileRegs& t) {
@@ -85,33 +91,55 @@ __device__ __forceinline__ void load_a(const View& A, int M, int K, int m0, int 
     const int mo = (q & 1) ? m0 - A.rs : m0;
     const int ko = (q & 2) ? k0 - A.cs : k0;
     const double* base = s.p + mo * s.sr + ko * s.sc;
-    if (s.sc == 1 && s.sr != 1) {
+    if (s.sr == 1 && vec_ok(base, s.sc)) {
+      t.mode = 0;
+      const int m = (tid & 31) * 2, kq = tid >> 5;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kq + 8 * j;
+        const double2 v = *reinterpret_cast<const double2*>(base + m + k * s.sc);
+        double v0 = v.x, v1 = v.y;
+        if (tri) {
+          if (tri_zero(tri, m0 + m, k0 + k)) v0 = 0.0;
+          if (tri_zero(tri, m0 + m + 1, k0 + k)) v1 = 0.0;
+        }
+        t.v[2 * j] = alpha * v0;
+        t.v[2 * j + 1] = alpha * v1;
+      }
+      return;
+    }
+    if (s.sc == 1 && vec_ok(base, s.sr)) {
       t.mode = 1;
-      const int k = tid & 15, mq = tid >> 4;
+      const int k = (tid & 15) * 2, mq = tid >> 4;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int m = mq + 16 * j;
-        double val = base[m * s.sr + k];
-        if (tri && tri_zero(tri, m0 + m, k0 + k)) val = 0.0;
-        t.v[j] = alpha * val;
+        const double2 v = *reinterpret_cast<const double2*>(base + m * s.sr + k);
+        double v0 = v.x, v1 = v.y;
+        if (tri) {
+          if (tri_zero(tri, m0 + m, k0 + k)) v0 = 0.0;
+          if (tri_zero(tri, m0 + m, k0 + k + 1)) v1 = 0.0;
+        }
+        t.v[2 * j] = alpha * v0;
+        t.v[2 * j + 1] = alpha * v1;
       }
-    } else {
-      t.mode = 0;
-      const int m = tid & 63, kq = tid >> 6;
+      return;
+    }
+    t.mode = 2;
+    const int m = tid & 63, kq = tid >> 6;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = kq + 4 * j;
-        double val = base[m * s.sr + k * s.sc];
-        if (tri && tri_zero(tri, m0 + m, k0 + k)) val = 0.0;
-        t.v[j] = alpha * val;
-      }
+    for (int j = 0; j < 8; ++j) {
+      const int k = kq + 4 * j;
+      double val = base[m * s.sr + k * s.sc];
+      if (tri && tri_zero(tri, m0 + m, k0 + k)) val = 0.0;
+      t.v[j] = alpha * val;
     }
     return;
   }
-  t.mode = 0;
+  t.mode = 2;
   const int m = tid & 63, kq = tid >> 6;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 8; ++j) {
     const int k = kq + 4 * j;
     const int gm = m0 + m, gk = k0 + k;
     double val = 0.0;
@@ -122,14 +150,22 @@ __device__ __forceinline__ void load_a(const View& A, int M, int K, int m0, int 
 
 __device__ __forceinline__ void store_a(const TileRegs& t, double (*As)[LDS_ROW]) {
   const int tid = threadIdx.x;
-  if (t.mode == 1) {
-    const int k = tid & 15, mq = tid >> 4;
+  if (t.mode == 0) {
+    const int m = (tid & 31) * 2, kq = tid >> 5;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) As[k][mq + 16 * j] = t.v[j];
+    for (int j = 0; j < 4; ++j)
+      *reinterpret_cast<double2*>(&As[kq + 8 * j][m]) = make_double2(t.v[2 * j], t.v[2 * j + 1]);
+  } else if (t.mode == 1) {
+    const int k = (tid & 15) * 2, mq = tid >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      As[k][mq + 16 * j] = t.v[2 * j];
+      As[k + 1][mq + 16 * j] = t.v[2 * j + 1];
+    }
   } else {
     const int m = tid & 63, kq = tid >> 6;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) As[kq + 4 * j][m] = t.v[j];
+    for (int j = 0; j < 8; ++j) As[kq + 4 * j][m] = t.v[j];
   }
 }
 
@@ -144,33 +180,55 @@ __device__ __forceinline__ void load_b(const View& B, int K, int N, int k0, int 
     const int ko = (q & 1) ? k0 - B.rs : k0;
     const int no = (q & 2) ? n0 - B.cs : n0;
     const double* base = s.p + ko * s.sr + no * s.sc;
-    if (s.sr == 1 && s.sc != 1) {
-      t.mode = 1;  // k fastest
-      const int k = tid & 15, nq = tid >> 4;
+    if (s.sc == 1 && vec_ok(base, s.sr)) {
+      t.mode = 0;
+      const int n = (tid & 31) * 2, kq = tid >> 5;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kq + 8 * j;
+        const double2 v = *reinterpret_cast<const double2*>(base + k * s.sr + n);
+        double v0 = v.x, v1 = v.y;
+        if (tri) {
+          if (tri_zero(tri, k0 + k, n0 + n)) v0 = 0.0;
+          if (tri_zero(tri, k0 + k, n0 + n + 1)) v1 = 0.0;
+        }
+        t.v[2 * j] = v0;
+        t.v[2 * j + 1] = v1;
+      }
+      return;
+    }
+    if (s.sr == 1 && vec_ok(base, s.sc)) {
+      t.mode = 1;
+      const int k = (tid & 15) * 2, nq = tid >> 4;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int n = nq + 16 * j;
-        double val = base[k + n * s.sc];
-        if (tri && tri_zero(tri, k0 + k, n0 + n)) val = 0.0;
-        t.v[j] = val;
+        const double2 v = *reinterpret_cast<const double2*>(base + k + n * s.sc);
+        double v0 = v.x, v1 = v.y;
+        if (tri) {
+          if (tri_zero(tri, k0 + k, n0 + n)) v0 = 0.0;
+          if (tri_zero(tri, k0 + k + 1, n0 + n)) v1 = 0.0;
+        }
+        t.v[2 * j] = v0;
+        t.v[2 * j + 1] = v1;
       }
-    } else {
-      t.mode = 0;  // n fastest
-      const int n = tid & 63, kq = tid >> 6;
+      return;
+    }
+    t.mode = 2;
+    const int n = tid & 63, kq = tid >> 6;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = kq + 4 * j;
-        double val = base[k * s.sr + n * s.sc];
-        if (tri && tri_zero(tri, k0 + k, n0 + n)) val = 0.0;
-        t.v[j] = val;
-      }
+    for (int j = 0; j < 8; ++j) {
+      const int k = kq + 4 * j;
+      double val = base[k * s.sr + n * s.sc];
+      if (tri && tri_zero(tri, k0 + k, n0 + n)) val = 0.0;
+      t.v[j] = val;
     }
     return;
   }
-  t.mode = 0;
+  t.mode = 2;
   const int n = tid & 63, kq = tid >> 6;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 8; ++j) {
     const int k = kq + 4 * j;
     const int gk = k0 + k, gn = n0 + n;
     double val = 0.0;
@@ -181,14 +239,22 @@ __device__ __forceinline__ void load_b(const View& B, int K, int N, int k0, int 
 
 __device__ __forceinline__ void store_b(const TileRegs& t, double (*Bs)[LDS_ROW]) {
   const int tid = threadIdx.x;
-  if (t.mode == 1) {
-    const int k = tid & 15, nq = tid >> 4;
+  if (t.mode == 0) {
+    const int n = (tid & 31) * 2, kq = tid >> 5;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Bs[k][nq + 16 * j] = t.v[j];
+    for (int j = 0; j < 4; ++j)
+      *reinterpret_cast<double2*>(&Bs[kq + 8 * j][n]) = make_double2(t.v[2 * j], t.v[2 * j + 1]);
+  } else if (t.mode == 1) {
+    const int k = (tid & 15) * 2, nq = tid >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Bs[k][nq + 16 * j] = t.v[2 * j];
+      Bs[k + 1][nq + 16 * j] = t.v[2 * j + 1];
+    }
   } else {
     const int n = tid & 63, kq = tid >> 6;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Bs[kq + 4 * j][n] = t.v[j];
+    for (int j = 0; j < 8; ++j) Bs[kq + 4 * j][n] = t.v[j];
   }
 }
 
@@ -206,9 +272,11 @@ __device__ __forceinline__ void krange(int mode, int K, int m0, int n0, int& klo
   if (klo > K) klo = K;
 }
 
+// One phase of the K loop: double-buffered LDS (one barrier per 32-wide K step); the next
+// step's tiles travel global -> registers while the current step runs on the matrix cores.
 __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
-                                          double (*As)[LDS_ROW], double (*Bs)[LDS_ROW],
+                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW],
                                           v4d (&acc)[2][2]) {
   const int K = lasty ? ph.Klast : ph.K;
   int klo, khi;
@@ -217,33 +285,49 @@ __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int
   TileRegs ra, rb;
   load_a(ph.A, M, K, m0, klo, ph.triA, ph.alpha, z, y, ra);
   load_b(ph.B, K, N, klo, n0, ph.triB, z, y, rb);
+  __syncthreads();  // the previous phase may still read buffer 0
+  store_a(ra, As[0]);
+  store_b(rb, Bs[0]);
+  __syncthreads();
+  int cur = 0;
   for (int k0 = klo; k0 < khi; k0 += BK) {
-    store_a(ra, As);
-    store_b(rb, Bs);
-    __syncthreads();
-    if (k0 + BK < khi) {
+    const bool more = k0 + BK < khi;
+    if (more) {
       load_a(ph.A, M, K, m0, k0 + BK, ph.triA, ph.alpha, z, y, ra);
       load_b(ph.B, K, N, k0 + BK, n0, ph.triB, z, y, rb);
     }
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      const double a0 = As[kr][wm + (lane & 15)];
-      const double a1 = As[kr][wm + 16 + (lane & 15)];
-      const double b0 = Bs[kr][wn + (lane & 15)];
-      const double b1 = Bs[kr][wn + 16 + (lane & 15)];
+      const double a0 = As[cur][kr][wm + (lane & 15)];
+      const double a1 = As[cur][kr][wm + 16 + (lane & 15)];
+      const double b0 = Bs[cur][kr][wn + (lane & 15)];
+      const double b1 = Bs[cur][kr][wn + 16 + (lane & 15)];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
     }
+    if (more) {
+      store_a(ra, As[cur ^ 1]);
+      store_b(rb, Bs[cur ^ 1]);
+    }
     __syncthreads();
+    cur ^= 1;
   }
 }
 
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmArgs args) {
-  __shared__ double As[BK][LDS_ROW];
-  __shared__ double Bs[BK][LDS_ROW];
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
+// a contiguous range of tiles so that neighbouring tiles, which share operand tiles, share an L2.
+__device__ __forceinline__ int xcd_remap(int L, int T) {
+  const int x = L & 7, idx = L >> 3;
+  const int per = T >> 3, rem = T & 7;
+  return x * per + min(x, rem) + idx;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemm_f64_kernel(const GemmArgs args) {
+  __shared__ double As[2][BK][LDS_ROW];
+  __shared__ double Bs[2][BK][LDS_ROW];
   const int z = blockIdx.z, y = blockIdx.y;
   const bool lasty = (y == (int)gridDim.y - 1);
   const int M = lasty ? args.Mlast : args.M;
@@ -251,13 +335,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmArgs args) {
   const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
   int ti, tj;
   if (args.omode == OUT_ALL) {
-    const int L = blockIdx.x;
-    if (L >= tilesM * tilesN) return;
+    const int T = tilesM * tilesN;
+    if ((int)blockIdx.x >= T) return;
+    const int L = (int)gridDim.x == T ? xcd_remap(blockIdx.x, T) : blockIdx.x;
     ti = L % tilesM;
     tj = L / tilesM;
   } else {
-    const int L = blockIdx.x;
-    if (L >= tilesM * (tilesM + 1) / 2) return;
+    const int T = tilesM * (tilesM + 1) / 2;
+    if ((int)blockIdx.x >= T) return;
+    const int L = (int)gridDim.x == T ? xcd_remap(blockIdx.x, T) : blockIdx.x;
     ti = (int)((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
     while (ti * (ti + 1) / 2 > L) --ti;
     while ((ti + 1) * (ti + 2) / 2 <= L) ++ti;

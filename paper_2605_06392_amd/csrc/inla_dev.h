@@ -52,8 +52,8 @@ __global__ void grad_kernel(const ModelDev M, const double* theta, const double*
                             const double* dphi, const double* tau, const double* TD,
                             const double* TB, long long zTr, const double* O, const double* qD,
                             const double* qB, const double* resid, const double* ld,
-                            const double* zsq, const int32_t* info, double* f, double* grad,
-                            int32_t* info_out);
+                            const double* zsq, const double* ZTc, const int32_t* info, double* f,
+                            double* grad, int32_t* info_out, double* terms);
 __global__ void yy_kernel(const ModelDev M, double* yy);
 __global__ void stencil_kernel(const double* theta, int d, double h, double* Th);
 __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad);

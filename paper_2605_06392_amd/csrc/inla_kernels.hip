@@ -132,31 +132,28 @@ __global__ __launch_bounds__(256) void param_kernel(const ModelDev M, const doub
 }
 
 // ---- assembly ----------------------------------------------------------------------------------
-// Fills block td of D (if td >= 0) and block tb of B (if tb >= 0) for every chain:
-// zero the 64 columns [q0, q0+64), then each column's thread writes its base-matrix entries and,
-// for Qc chains (z even), adds the observation term tau_m a_o a_o^T in a fixed order.
-__global__ __launch_bounds__(256) void assemble_blocks_kernel(const ModelDev M, int td, int tb,
-                                                              double* D, long long zD,
-                                                              double* B, long long zB,
-                                                              const double* phi,
-                                                              const double* tau) {
+// Fills block td of D (if td >= 0) and block tb of B (if tb >= 0) for every chain, one
+// 64-lane workgroup per column q: the lanes zero the column (coalesced), then write the
+// base-matrix entries of the column in parallel (distinct rows), and lane 0 adds the
+// observation term tau_m a_o a_o^T for Qc chains (z even) in a fixed order.
+__global__ __launch_bounds__(64) void assemble_blocks_kernel(const ModelDev M, int td, int tb,
+                                                             double* D, long long zD,
+                                                             double* B, long long zB,
+                                                             const double* phi,
+                                                             const double* tau) {
   const int z = blockIdx.z;
   const int p = z >> 1;
   const bool qc = (z & 1) == 0;
   const int b = M.b, ns = M.ns, k = M.k;
-  const int q0 = blockIdx.x * 64;
-  double* Dz = td >= 0 ? D + (long long)z * zD : nullptr;
-  double* Bz = tb >= 0 ? B + (long long)z * zB : nullptr;
-  const int ncols = min(64, b - q0);
-  for (long long e = threadIdx.x; e < (long long)ncols * b; e += 256) {
-    const long long row = e % b, col = q0 + e / b;
-    if (Dz) Dz[row + col * b] = 0.0;
-    if (Bz) Bz[row + col * b] = 0.0;
+  const int q = blockIdx.x;
+  const int lane = threadIdx.x;
+  double* Dc = td >= 0 ? D + (long long)z * zD + (long long)q * b : nullptr;
+  double* Bc = tb >= 0 ? B + (long long)z * zB + (long long)q * b : nullptr;
+  for (int r = lane; r < b; r += 64) {
+    if (Dc) Dc[r] = 0.0;
+    if (Bc) Bc[r] = 0.0;
   }
-  __threadfence_block();
   __syncthreads();
-  if ((int)threadIdx.x >= ncols) return;
-  const int q = q0 + threadIdx.x;
   const int i2 = q / ns, qq = q % ns;
   const int NE = 9 * k * k;
   const double* ph = phi + (long long)p * NE;
@@ -166,17 +163,18 @@ __global__ __launch_bounds__(256) void assemble_blocks_kernel(const ModelDev M, 
     for (int r = 0; r < 3; ++r)
       for (int s = 0; s < 3; ++s) {
         const double f = ph[((r * k + i1) * k + i2) * 3 + s];
-        if (Dz) cD[s] += tmat(M, r, td, 0) * f;
-        if (Bz) cB[s] += tmat(M, r, tb, 1) * f;
+        if (Dc) cD[s] += tmat(M, r, td, 0) * f;
+        if (Bc) cB[s] += tmat(M, r, tb, 1) * f;
       }
-    for (int e = e0; e < e1; ++e) {
+    for (int e = e0 + lane; e < e1; e += 64) {
       const long long row = (long long)i1 * ns + M.uidx[e];
       const double v0 = M.uval[e], v1 = M.uval[M.nnz + e], v2 = M.uval[2 * M.nnz + e];
-      if (Dz) Dz[row + (long long)q * b] = cD[0] * v0 + cD[1] * v1 + cD[2] * v2;
-      if (Bz) Bz[row + (long long)q * b] = cB[0] * v0 + cB[1] * v1 + cB[2] * v2;
+      if (Dc) Dc[row] = cD[0] * v0 + cD[1] * v1 + cD[2] * v2;
+      if (Bc) Bc[row] = cB[0] * v0 + cB[1] * v1 + cB[2] * v2;
     }
   }
-  if (Dz && qc) {
+  __syncthreads();
+  if (Dc && qc && lane == 0) {
     const long long g = (long long)td * b + q;
     for (int j = M.colptr[g]; j < M.colptr[g + 1]; ++j) {
       const int o = M.col_o[j];
@@ -185,7 +183,7 @@ __global__ __launch_bounds__(256) void assemble_blocks_kernel(const ModelDev M, 
       const double tq = tau[(long long)p * k + m] * wq;
       for (int e = 0; e < 4; ++e) {
         const long long row = (long long)m * ns + M.obs_node[4 * o + e];
-        Dz[row + (long long)q * b] += tq * M.obs_w[4 * o + e];
+        Dc[row] += tq * M.obs_w[4 * o + e];
       }
     }
   }
@@ -397,7 +395,9 @@ __global__ void objective_kernel(const ModelDev M, const double* theta, int batc
   info_out[p] = (ic != 0 && ic != INT32_MAX) ? ic : ((ip != INT32_MAX) ? ip : 0);
 }
 
-// Gradient assembly for one theta point (chains 0 = Qc, 1 = Qp).
+// Gradient assembly for one theta point (chains 0 = Qc, 1 = Qp).  Optionally writes the
+// decomposition terms = [f, log|Qp|, log|Qc|, |z|^2, tr(Z_T of Qc), PhaseA(d), PhaseB(d),
+// PhaseC(d), dlog l(d), dlog p(d), grad(d)].
 __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const double* theta,
                                                    const double* phi, const double* dphi,
                                                    const double* tau, const double* TD,
@@ -405,43 +405,77 @@ __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const doubl
                                                    const double* O, const double* qD,
                                                    const double* qB, const double* resid,
                                                    const double* ld, const double* zsq,
-                                                   const int32_t* info, double* f, double* grad,
-                                                   int32_t* info_out) {
-  __shared__ double S[9 * kMaxFields * kMaxFields];
+                                                   const double* ZTc, const int32_t* info,
+                                                   double* f, double* grad, int32_t* info_out,
+                                                   double* terms) {
+  __shared__ double SA[9 * kMaxFields * kMaxFields];
+  __shared__ double SB[9 * kMaxFields * kMaxFields];
+  __shared__ double SC[9 * kMaxFields * kMaxFields];
   const int k = M.k, kk = k * k, nt = M.nt, d = M.d;
   const int NE = 9 * kk;
   for (int e = threadIdx.x; e < NE; e += blockDim.x) {
     const int r = e / (3 * kk);
     const int rest = e % (3 * kk);  // (i1*k + i2)*3 + s
-    double acc = 0.0;
+    double a = 0.0, bq = 0.0, c = 0.0;
     for (int t = 0; t < nt; ++t) {
       const long long o = (long long)t * kk * 3 + rest;
-      const double wD = 0.5 * (TD[zTr + o] - TD[o] - qD[o]);
-      acc += tmat(M, r, t, 0) * wD;
+      const double md = tmat(M, r, t, 0);
+      a -= 0.5 * md * TD[o];
+      bq -= 0.5 * md * qD[o];
+      c += 0.5 * md * TD[zTr + o];
       if (t < nt - 1) {
-        const double wB = TB[zTr + o] - TB[o] - qB[o];
-        acc += tmat(M, r, t, 1) * wB;
+        const double mo = tmat(M, r, t, 1);
+        a -= mo * TB[o];
+        bq -= mo * qB[o];
+        c += mo * TB[zTr + o];
       }
     }
-    S[e] = acc;
+    SA[e] = a;
+    SB[e] = bq;
+    SC[e] = c;
   }
   __syncthreads();
+  const double fval = objective_value(M, theta, tau, ld[0], ld[1], zsq[0]);
   for (int q = threadIdx.x; q < d; q += blockDim.x) {
-    double g = 0.0;
-    for (int e = 0; e < NE; ++e) g += dphi[(long long)q * NE + e] * S[e];
+    double pa = 0.0, pb = 0.0, pc = 0.0, dl = 0.0;
+    for (int e = 0; e < NE; ++e) {
+      const double w = dphi[(long long)q * NE + e];
+      pa += w * SA[e];
+      pb += w * SB[e];
+      pc += w * SC[e];
+    }
     if (M.role_kind[q] == ROLE_TAU) {
       const int m = M.role_idx[q];
       double so = 0.0;
       for (int t = 0; t < nt; ++t) so += O[(long long)t * k + m];
-      g += -0.5 * tau[m] * so + 0.5 * M.nobs_field[m] - 0.5 * tau[m] * resid[m];
+      pa += -0.5 * tau[m] * so;
+      dl = 0.5 * M.nobs_field[m] - 0.5 * tau[m] * resid[m];
     }
-    g -= theta[q] / (M.sigma * M.sigma);
+    const double dp = -theta[q] / (M.sigma * M.sigma);
+    const double g = pa + pb + pc + dl + dp;
     grad[q] = g;
+    if (terms) {
+      terms[5 + q] = pa;
+      terms[5 + d + q] = pb;
+      terms[5 + 2 * d + q] = pc;
+      terms[5 + 3 * d + q] = dl;
+      terms[5 + 4 * d + q] = dp;
+      terms[5 + 5 * d + q] = g;
+    }
   }
   if (threadIdx.x == 0) {
-    f[0] = objective_value(M, theta, tau, ld[0], ld[1], zsq[0]);
+    f[0] = fval;
     const int32_t ic = info[0], ip = info[1];
     info_out[0] = (ic != 0 && ic != INT32_MAX) ? ic : ((ip != INT32_MAX) ? ip : 0);
+    if (terms) {
+      double tr = 0.0;
+      for (int c = 0; c < M.a; ++c) tr += ZTc[c + (long long)c * M.a];
+      terms[0] = fval;
+      terms[1] = ld[1];
+      terms[2] = ld[0];
+      terms[3] = zsq[0];
+      terms[4] = tr;
+    }
   }
 }
 

@@ -159,6 +159,23 @@ class InlaModel:
                               REUSE_FACTORS if reuse else 0, self._stream()), "inla_grad")
         return f, g, inf
 
+    def grad_terms(self, theta, reuse=False):
+        """f, gradient and its decomposition as a dict of host numpy values."""
+        th = self._theta(theta).reshape(self.d)
+        d = self.d
+        terms = torch.empty(5 + 6 * d, dtype=torch.float64, device=self.device)
+        inf = torch.empty(1, dtype=torch.int32, device=self.device)
+        ws, nb = self.workspace(1, MODE_GRAD)
+        check(lib().inla_grad_terms(self._h, C.c_void_p(th.data_ptr()), C.c_void_p(terms.data_ptr()),
+                                    C.c_void_p(inf.data_ptr()), ws, nb,
+                                    REUSE_FACTORS if reuse else 0, self._stream()),
+              "inla_grad_terms")
+        t = terms.cpu().numpy()
+        return {"f": t[0], "logdet_p": t[1], "logdet_c": t[2], "zsq": t[3], "trZT": t[4],
+                "phaseA": t[5:5 + d], "phaseB": t[5 + d:5 + 2 * d], "phaseC": t[5 + 2 * d:5 + 3 * d],
+                "dloglik": t[5 + 3 * d:5 + 4 * d], "dlogprior": t[5 + 4 * d:5 + 5 * d],
+                "grad": t[5 + 5 * d:5 + 6 * d], "info": int(inf.item())}
+
     def fd_grad(self, theta, h=1e-3, max_batch=None, f=None, g=None, info=None):
         th = self._theta(theta).reshape(self.d)
         npts = 2 * self.d + 1

@@ -172,3 +172,18 @@ def test_graph_replay_matches_eager():
         assert f.item() == f_ref and np.array_equal(g.cpu().numpy(), g_ref)
         m.grad(other)  # eager work on the same workspace in between
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,seed", [("uni_8x8_nt8", 0), ("coreg3_4x4_nt4", 0)])
+def test_gradient_phases_match_oracle(name, seed):
+    spec, m = gpu_model(name, seed)
+    t = m.grad_terms(torch.tensor(spec.theta))
+    ref = oracle.gradient(spec, spec.theta)
+    ev = oracle.objective(spec, spec.theta)
+    scale = np.abs(ref["grad"]).max()
+    for key in ("phaseA", "phaseB", "phaseC", "dloglik", "dlogprior", "grad"):
+        assert np.abs(t[key] - ref[key]).max() <= 1e-8 * max(scale, np.abs(ref[key]).max()), key
+    assert abs(t["logdet_p"] - ev["logdet_p"]) <= 1e-11 * abs(ev["logdet_p"])
+    assert abs(t["logdet_c"] - ev["logdet_c"]) <= 1e-11 * abs(ev["logdet_c"])
+    nb = spec.nt * spec.b
+    assert abs(t["trZT"] - np.trace(ref["Zc"][nb:, nb:])) <= 1e-10 * abs(t["trZT"])

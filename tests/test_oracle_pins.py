@@ -18,6 +18,8 @@ import oracle
 from workloads import make_model, named_config, neumann_second_difference
 from workloads.bta import random_bta
 
+from tests import spectral
+
 
 def leibniz_det(M):
     n = M.shape[0]
@@ -32,36 +34,11 @@ def leibniz_det(M):
 
 
 def continuant_logdet(diag, off):
-    """log det of a symmetric tridiagonal matrix by the three-term continuant recurrence."""
-    f_prev, f = 1.0, diag[0]
-    logscale = 0.0
-    for t in range(1, len(diag)):
-        f_prev, f = f, diag[t] * f - off[t - 1] ** 2 * f_prev
-        s = abs(f)
-        f_prev, f = f_prev / s, f / s
-        logscale += np.log(s)
-    return logscale + np.log(f) + (0.0 if len(diag) > 1 else 0.0)
+    return spectral.continuant_logdet(diag, off)
 
 
 def spectral_field_logdet(model, rng_par, tmp_par):
-    """log|M0 (x) K2 + e^tmp M1 (x) K1 + M2 (x) c0| via the closed-form Neumann eigenvalues."""
-    jx = np.arange(model.nx)
-    jy = np.arange(model.ny)
-    lx = 4 * np.sin(np.pi * jx / (2 * model.nx)) ** 2
-    ly = 4 * np.sin(np.pi * jy / (2 * model.ny)) ** 2
-    mu = (ly[:, None] + lx[None, :]).reshape(-1) + 0.1
-    k2 = np.exp(2 * rng_par)
-    m0d, m0o = model.m0
-    m1d, m1o = model.m1
-    m2d, m2o = model.m2
-    total = 0.0
-    for u in mu:
-        K1 = k2 + u
-        K2 = k2 * k2 + 2 * k2 * u + u * u
-        diag = m0d * K2 + np.exp(tmp_par) * m1d * K1 + m2d
-        off = m0o * K2 + np.exp(tmp_par) * m1o * K1 + m2o
-        total += continuant_logdet(diag, off)
-    return total
+    return spectral.field_logdet(model, rng_par, tmp_par)
 
 
 def tiny_model(seed=3, a=1, obs=2):
