@@ -79,6 +79,7 @@ int check_shape(const adelia_bta_shape& sh) {
 
 struct FactorWs {
   double *Caug, *LCaug, *Taug, *LBs, *S, *ldpart, *zsq;
+  int32_t* cnt;
   size_t bytes;
 };
 
@@ -99,6 +100,7 @@ FactorWs factor_ws_layout(const adelia_bta_shape& sh, int ap, char* base) {
   w.S = take(b * b);
   w.ldpart = take(n * npanel + 1);
   w.zsq = take(1);
+  w.cnt = reinterpret_cast<int32_t*>(take(1));
   w.bytes = off;
   return w;
 }
@@ -220,6 +222,7 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double
   if (nb > INT_MAX) return ADELIA_E_SHAPE;
   int e = 0;
   e |= launch_fill_i32(info, 1, INT32_MAX, s);
+  e |= launch_fill_i32(w.cnt, 1, 0, s);
   if (ap > 0) {
     if (a > 0) {
       e |= launch_copy2d(C, a, 0, w.Caug, ap, 0, a, (int)nb, 1, s);
@@ -243,6 +246,7 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double
   c.G = Dinv; c.zG = 0; c.slotsG = n;
   c.ldpart = w.ldpart; c.zLd = 0;
   c.info = info;
+  c.cnt = w.cnt;
   c.scratch = w.S; c.zS = 0;
   c.zsq = w.zsq;
   for (int i = 0; i < n; ++i) {

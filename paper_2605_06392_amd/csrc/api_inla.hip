@@ -36,6 +36,7 @@ struct InlaWs {
   double *D, *Bin, *LB, *G, *C, *LC, *T, *S, *ldpart, *ld, *zsq, *ZT, *xT;
   long long zD, zB, zLB, zG, zC, zLC, zT, zS, zLd, zZT, zXT;
   int32_t* info;
+  int32_t* cnt;   // panel write-back counters (nz), zero between launches
   double *phi, *dphi, *tau;
   double *Th, *fv;
   int32_t* finfo;
@@ -91,7 +92,8 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
   {
     double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
     w.info = reinterpret_cast<int32_t*>(p);
-    off = align_up(off + (size_t)nz * sizeof(int32_t));
+    w.cnt = w.info ? w.info + nz : nullptr;
+    off = align_up(off + (size_t)2 * nz * sizeof(int32_t));
   }
   const long long NE = 9LL * M.k * M.k;
   w.phi = take(NE, batch, dummy);
@@ -128,6 +130,7 @@ BtaChains chains_of(const InlaWs& w) {
   c.G = w.G; c.zG = w.zG; c.slotsG = w.slotsG;
   c.ldpart = w.ldpart; c.zLd = w.zLd;
   c.info = w.info;
+  c.cnt = w.cnt;
   c.scratch = w.S; c.zS = w.zS;
   c.zsq = w.zsq;
   if (w.grad && w.a > 0) {
@@ -146,6 +149,7 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
                      w.tau);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
   if (launch_fill_i32(w.info, nz, INT32_MAX, s)) return ADELIA_E_HIP;
+  if (launch_fill_i32(w.cnt, nz, 0, s)) return ADELIA_E_HIP;
   const long long nb = (long long)n * b;
   hipLaunchKernelGGL(assemble_arrow_kernel, dim3((unsigned)((nb + 255) / 256), 1, nz), dim3(256),
                      0, s, M, w.C, w.zC, w.ap, w.tau);

@@ -33,7 +33,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
   for (int k = 0; k < npanel; ++k) {
     const int c0 = k * kPanel;
     if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, c.ldpart + (long long)i * npanel + k, c.zLd,
-                           c.info, b, c0, (long long)i * b, nz, s))
+                           c.info, c.cnt, b, c0, (long long)i * b, nz, s))
       return ADELIA_E_HIP_INTERNAL;
     const int rest = b - c0 - kPanel;
     if (rest > 0) {

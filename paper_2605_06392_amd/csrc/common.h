@@ -94,6 +94,7 @@ struct BtaChains {
   double* G; long long zG; int slotsG;      // out: L_Dt^-1
   double* ldpart; long long zLd;            // logdet partials, n*npanel + 1 per chain
   int32_t* info;                            // per chain (stride 1)
+  int32_t* cnt;                             // per chain (stride 1), zero: panel write-back counters
   double* scratch; long long zS;            // b*b per chain (TRTRI temporaries)
   double* zsq;                              // per chain: |z|^2 (if ap == a+1), may be null
   double* ZT; long long zZT;                // a x a per chain: [Q^-1]_{T,T} (may be null)

@@ -1,0 +1,310 @@
+// Panel step of the blocked Cholesky of a diagonal block (Sec. III-A-1, Alg. 1, chol()).
+//
+// The 64 x 64 diagonal tile of panel k is factored, together with its inverse, as two 32 x 32
+// leaves: each leaf is eliminated column by column by ONE wavefront (registers hold 4 x 4
+// sub-blocks, the current column travels through LDS; a single wave needs no workgroup
+// barrier between columns because its LDS operations complete in program order), and the
+// off-diagonal solve L21 = A21 X11^T, the update A22 -= L21 L21^T and the inverse merge
+// X21 = -X22 L21 X11 run on the matrix cores across the four waves.  Workgroup x > 0 also
+// solves its 64-row tile of the panel as A_jk L_kk^-T.
+//
+// Every workgroup reads the unfactored diagonal tile, so L_kk may only be written back once
+// all of them have loaded it: each workgroup bumps a per-chain counter after its load, and the
+// one that sees the count complete stores L_kk, L_kk^-1, the log-diagonal sum and the pivot
+// check (all workgroups compute bit-identical tiles) and resets the counter for the next
+// launch.  No workgroup ever waits on another.
+#include "common.h"
+#include "profile.h"
+#include <cmath>
+
+namespace adelia {
+
+namespace {
+
+constexpr int NB = kPanel;  // 64
+constexpr int HB = NB / 2;  // 32
+constexpr int LP = NB + 1;  // LDS pitch of the square tiles
+
+struct PanelArgs {
+  double* D; long long zD;
+  double* G; long long zG;
+  double* ldp; long long zLd;
+  int32_t* info;
+  int32_t* cnt;  // per chain, zero between launches
+  int b, c0;
+  long long gcol0;
+};
+
+// Orders the LDS traffic of one wavefront: the LDS unit serves a wave's operations in issue
+// order, so a compiler-level barrier is all a single wave needs between producer and consumer.
+__device__ __forceinline__ void wave_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1/sqrt(d) from the hardware estimate refined by two Newton steps (each squares the relative
+// error), and sqrt(d) = d / sqrt(d).  A non-positive d gives a NaN or an infinity, which the
+// caller reports through the pivot check.
+__device__ __forceinline__ void pivot(double d, double& pv, double& invs) {
+  double r = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  invs = r;
+  pv = d * r;
+}
+
+// Column j = 4 jq + JR of the leaf: scale the pivot column, rank-1 update of the trailing part
+// of L and of the rows of L^-1 below j, then publish column j+1 and row j+1 of L^-1.  Every LDS
+// load is unconditional (all indices are inside the leaf) and masks are selects, so the step
+// has no divergent branch around a memory access.
+template <int JR>
+__device__ __forceinline__ void leaf_step(double (&a)[4][4], double (&x)[4][4], double* col,
+                                          double* xr, double* piv, int o, int jq, int br, int bc,
+                                          bool active, int lane) {
+  const int j = 4 * jq + JR;
+  double cr[4], cc[4], xc[4];
+  const double djj = col[j];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cr[q] = col[4 * br + q];
+    cc[q] = col[4 * bc + q];
+    xc[q] = xr[4 * bc + q];
+  }
+  double pv, invs;
+  pivot(djj, pv, invs);
+  if (lane == 0) piv[o + j] = djj;
+  double lr[4], lrx[4], lc[4], xj[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    lr[q] = cr[q] * invs;
+    lrx[q] = (4 * br + q > j) ? lr[q] : 0.0;
+    lc[q] = (4 * bc + q > j) ? cc[q] * invs : 0.0;
+    xj[q] = (4 * bc + q <= j) ? xc[q] * invs : 0.0;
+  }
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      a[ii][jj] = fma(-lr[ii], lc[jj], a[ii][jj]);
+      x[ii][jj] = fma(-lrx[ii], xj[jj], x[ii][jj]);
+    }
+  if (bc == jq) {
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) a[ii][JR] = (4 * br + ii == j) ? pv : lr[ii];
+  }
+  if (br == jq) {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) x[JR][jj] = xj[jj];
+  }
+  wave_order();  // every lane has read column j before it is replaced
+  constexpr int NR = (JR + 1) & 3;
+  const int nq = jq + (JR == 3 ? 1 : 0);
+  if (JR != 3 || nq < HB / 4) {
+    if (bc == nq && active) {
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) col[4 * br + ii] = a[ii][NR];
+    }
+    if (br == nq && active) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) xr[4 * bc + jj] = x[NR][jj];
+    }
+  }
+  wave_order();
+}
+
+// Factor the HB x HB leaf at (o, o) of S (lower triangle, already updated) with one wavefront.
+// On exit S holds L (lower, zeros above) and X holds L^-1 on that leaf; piv[o + j] = pivot^2.
+__device__ void leaf_factor(double (*S)[LP], double (*X)[LP], double* col, double* xr, double* piv,
+                            int o) {
+  const int lane = threadIdx.x & 63;
+  const int br = lane >> 3, bc = lane & 7;
+  const bool active = br >= bc;
+  double a[4][4], x[4][4];
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = 4 * br + ii, c = 4 * bc + jj;
+      const double v = S[o + r][o + c];
+      a[ii][jj] = (r >= c) ? v : 0.0;
+      x[ii][jj] = (r == c) ? 1.0 : 0.0;
+    }
+  if (bc == 0 && active) {
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) col[4 * br + ii] = a[ii][0];
+  }
+  if (lane < 8) xr[4 * lane] = (lane == 0) ? 1.0 : 0.0;
+  wave_order();
+  for (int jq = 0; jq < HB / 4; ++jq) {
+    leaf_step<0>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
+    leaf_step<1>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
+    leaf_step<2>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
+    leaf_step<3>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
+  }
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = 4 * br + ii, c = 4 * bc + jj;
+      const bool low = active && r >= c;
+      S[o + r][o + c] = low ? a[ii][jj] : 0.0;
+      X[o + r][o + c] = low ? x[ii][jj] : 0.0;
+    }
+}
+
+// One 16 x 16 fragment of a 32 x 32 product C = sum_k A(m, k) B(k, n), k < 32, computed by
+// the calling wavefront: lane holds C(fm + lane%16, fn + lane/16 + 4v).
+template <class FA, class FB>
+__device__ __forceinline__ v4d frag32(FA A, FB B, int fm, int fn) {
+  const int lane = threadIdx.x & 63;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < HB / 4; ++kk) {
+    const int k = kk * 4 + (lane >> 4);
+    const double av = A(fm + (lane & 15), k);
+    const double bv = B(k, fn + (lane & 15));
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
+  __shared__ double S[NB][LP];
+  __shared__ double X[NB][LP];
+  __shared__ double col[HB], xr[HB], piv[NB];
+  __shared__ int writer;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int z = blockIdx.z;
+  const int b = P.b, c0 = P.c0;
+  const int w = min(NB, b - c0);
+  double* D = P.D + (long long)z * P.zD;
+  // diagonal tile (lower) with identity padding past w
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    double v = 0.0;
+    if (r >= c) {
+      if (r < w && c < w) v = D[(long long)(c0 + r) + (long long)(c0 + c) * b];
+      else if (r == c) v = 1.0;
+    }
+    S[r][c] = v;
+    X[r][c] = 0.0;
+  }
+  __syncthreads();  // this workgroup's reads of the diagonal tile have completed
+  if (tid == 0) {
+    const int seen = atomicAdd(P.cnt + z, 1);
+    const bool last = seen == (int)gridDim.x - 1;
+    if (last) atomicExch(P.cnt + z, 0);
+    writer = last ? 1 : 0;
+  }
+  if (wave == 0) leaf_factor(S, X, col, xr, piv, 0);
+  __syncthreads();
+  const int fm = (wave & 1) * 16, fn = (wave >> 1) * 16;
+  // L21 = A21 X11^T
+  v4d t = frag32([&](int m, int k) { return S[HB + m][k]; },
+                 [&](int k, int n) { return X[n][k]; }, fm, fn);
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) S[HB + fm + (lane & 15)][fn + (lane >> 4) + 4 * v] = t[v];
+  __syncthreads();
+  // A22 -= L21 L21^T (each wave owns its fragment; the strictly upper one is never read)
+  t = frag32([&](int m, int k) { return S[HB + m][k]; },
+             [&](int k, int n) { return S[HB + n][k]; }, fm, fn);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) S[HB + fm + (lane & 15)][HB + fn + (lane >> 4) + 4 * v] -= t[v];
+  __syncthreads();
+  if (wave == 0) leaf_factor(S, X, col, xr, piv, HB);
+  __syncthreads();
+  // X21 = -X22 (L21 X11)
+  t = frag32([&](int m, int k) { return S[HB + m][k]; },
+             [&](int k, int n) { return X[k][n]; }, fm, fn);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[HB + fm + (lane & 15)][fn + (lane >> 4) + 4 * v] = t[v];
+  __syncthreads();
+  t = frag32([&](int m, int k) { return X[HB + m][HB + k]; },
+             [&](int k, int n) { return X[HB + k][n]; }, fm, fn);
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[HB + fm + (lane & 15)][fn + (lane >> 4) + 4 * v] = -t[v];
+  __syncthreads();
+
+  if (writer) {
+    double* G = P.G + (long long)z * P.zG;
+    for (int e = tid; e < w * w; e += 256) {
+      const int r = e % w, c = e / w;
+      const long long off = (long long)(c0 + r) + (long long)(c0 + c) * b;
+      D[off] = (r >= c) ? S[r][c] : 0.0;
+      G[off] = (r >= c) ? X[r][c] : 0.0;
+    }
+    if (wave == 0) {
+      const double dj = piv[lane];
+      double lg = (lane < w) ? 0.5 * log(dj) : 0.0;
+      const bool bad = (lane < w) && !(dj > 0.0);
+      const unsigned long long badmask = __ballot(bad);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) lg += __shfl_xor(lg, off, 64);
+      if (lane == 0) {
+        P.ldp[(long long)z * P.zLd] = lg;
+        if (badmask) atomicMin(P.info + z, (int32_t)(P.gcol0 + c0 + __ffsll((long long)badmask) - 1 + 1));
+      }
+    }
+  }
+  if (blockIdx.x == 0) return;
+  // panel rows r0..r0+h: L(m, n) = sum_k A(m, k) X(n, k); the tile replaces S
+  const int r0 = c0 + NB * blockIdx.x;
+  const int h = min(NB, b - r0);
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int m = e & 63, k = e >> 6;
+    S[m][k] = (m < h && k < w) ? D[(long long)(r0 + m) + (long long)(c0 + k) * b] : 0.0;
+  }
+  __syncthreads();
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kk = 0; kk < NB / 4; ++kk) {
+    const int k = kk * 4 + (lane >> 4);
+    const double a0 = S[wm + (lane & 15)][k];
+    const double a1 = S[wm + 16 + (lane & 15)][k];
+    const double b0 = X[wn + (lane & 15)][k];
+    const double b1 = X[wn + 16 + (lane & 15)][k];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = wm + bi * 16 + (lane & 15);
+        const int n = wn + bj * 16 + (lane >> 4) + 4 * v;
+        if (m < h && n < w) D[(long long)(r0 + m) + (long long)(c0 + n) * b] = acc[bi][bj][v];
+      }
+}
+
+}  // namespace
+
+int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,
+                       long long zLd, int32_t* info, int32_t* cnt, int b, int c0,
+                       long long gcol0, int nz, hipStream_t s) {
+  if (!cnt) return -1;
+  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, b, c0, gcol0};
+  const int rows = (b - c0 + NB - 1) / NB;
+  const ProfToken t = prof_begin(s);
+  hipLaunchKernelGGL(potrf_panel_kernel, dim3(rows, 1, nz), dim3(256), 0, s, P);
+  if (t.valid) {
+    const double ww = (b - c0) < NB ? (b - c0) : NB;
+    const double below = (double)(b - c0) - ww;
+    prof_end(t, s, PK_PANEL, nz * (ww * ww * ww / 3.0 + below * ww * ww), 0.0);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace adelia

@@ -6,7 +6,11 @@ Pins that hold at any size (no dense matrix needed):
   of all prec parameters (coregional), so 1/2 tr(Qp^-1 dQp) over those components is exactly
   (nt*b)/2;
 * Phase A identity: the same scale derivative plus the tau derivatives of Qc sum to
-  Qc - blkdiag(0, tip I), so the matching sum of Phase A terms is -(N - tip tr(Z_T))/2;
+  Qc - blkdiag(0, tip I), so the matching sum of Phase A terms is -(N - tip tr(Z_T))/2.  For
+  the coregional model a uniform scaling of Lambda moves the prec parameters by -2 and each
+  coupling lambda_ij by lambda_ij, so the combination is sum(prec) - 1/2 sum(lambda_ij d/dlambda_ij)
+  + sum(tau); the coupling terms of Phase C vanish because |Qp| depends on Lambda's diagonal
+  only (Eq. 9-11);
 * the no-observation model gives f = log p(theta) and grad = -theta/sigma^2 exactly;
 * the exact gradient agrees with the GPU's central differences (h = 1e-4) to 1e-5.
 The gradient here runs in the same launch configuration the benchmark times.
@@ -31,15 +35,20 @@ def _dev():
 def _identities(spec, t):
     k = spec.k
     N = spec.N
+    lam_idx = []
     if spec.kind == "univariate":
         scale_idx = [0]
         tau_idx = [3]
     else:
         scale_idx = [2 * k + m for m in range(k)]
+        lam_idx = list(range(3 * k, 3 * k + k * (k - 1) // 2))
         tau_idx = [spec.d - k + m for m in range(k)]
     phase_c = sum(t["phaseC"][i] for i in scale_idx)
     assert abs(phase_c - 0.5 * spec.nt * spec.b) <= 1e-10 * 0.5 * spec.nt * spec.b
-    lhs = -2.0 * (sum(t["phaseA"][i] for i in scale_idx) + sum(t["phaseA"][i] for i in tau_idx))
+    for i in lam_idx:
+        assert abs(t["phaseC"][i]) <= 1e-10 * 0.5 * spec.nt * spec.b
+    lhs = -2.0 * (sum(t["phaseA"][i] for i in scale_idx) + sum(t["phaseA"][i] for i in tau_idx)
+                  - 0.5 * sum(spec.theta[i] * t["phaseA"][i] for i in lam_idx))
     rhs = N - spec.tip_prec * t["trZT"]
     assert abs(lhs - rhs) <= 1e-10 * N
     ref = spectral.prior_logdet(spec, spec.theta)

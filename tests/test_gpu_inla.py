@@ -18,7 +18,8 @@ from workloads import make_model, named_config
 pytestmark = pytest.mark.gpu
 
 CASES = [("uni_8x8_nt8", 0), ("uni_8x8_nt8", 1), ("uni_6x5_nt5", 2), ("coreg3_4x4_nt4", 0),
-         ("uni_9x7_nt4", 3), ("uni_12x12_nt6", 4), ("coreg3_5x4_nt3", 5)]
+         ("uni_9x7_nt4", 3), ("uni_12x12_nt6", 4), ("coreg3_5x4_nt3", 5),
+         ("coreg3_9x7_nt4", 6), ("coreg3_12x10_nt3", 7)]
 
 _models = {}
 

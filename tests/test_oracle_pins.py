@@ -156,6 +156,25 @@ def test_theta1_plus_tau_identity():
     assert np.isclose(lhs, m.N - m.tip_prec * np.trace(ZT), rtol=1e-12)
 
 
+def test_coreg_lambda_scaling_identities():
+    # Scaling every entry of Lambda by c (prec -> prec - 2 log c, lambda_ij -> c lambda_ij)
+    # scales the latent prior by c^-2, so the direction (prec: 1, lambda_ij: -lambda_ij/2)
+    # of dQp is Qp's latent part; with the tau derivatives it gives Qc - blkdiag(0, tip I).
+    # |Qp| depends on the diagonal of Lambda only, so Phase C has no coupling terms.
+    m = named_config("coreg3_9x7_nt4", seed=2)
+    out = oracle.gradient(m, m.theta)
+    lay = oracle.theta_layout(m)
+    nb = m.nt * m.b
+    ZT = out["Zc"][nb:, nb:]
+    A, C = out["phaseA"], out["phaseC"]
+    comb = (sum(A[i] for i in lay["prec"]) + sum(A[i] for i in lay["tau"])
+            - 0.5 * sum(m.theta[i] * A[i] for i in lay["lambda"]))
+    assert np.isclose(-2.0 * comb, m.N - m.tip_prec * np.trace(ZT), rtol=1e-12)
+    assert np.isclose(sum(C[i] for i in lay["prec"]), 0.5 * m.nt * m.b, rtol=1e-12)
+    for i in lay["lambda"]:
+        assert abs(C[i]) <= 1e-12 * m.nt * m.b
+
+
 def test_mode_stationarity():
     m = named_config("coreg3_4x4_nt4", seed=5)
     ev = oracle.objective(m, m.theta)

@@ -286,6 +286,9 @@ NAMED_CONFIGS = {
     "coreg3_4x4_nt4": (3, 4, 4, 4, 6, 5),
     "coreg3_5x4_nt3": (3, 5, 4, 3, 6, 6),
     "uni_9x7_nt4": (1, 9, 7, 4, 3, 9),
+    # coregionalised replicas with several 64-wide panels and a ragged last panel
+    "coreg3_9x7_nt4": (3, 9, 7, 4, 6, 12),
+    "coreg3_12x10_nt3": (3, 12, 10, 3, 6, 15),
 }
 
 
