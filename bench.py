@@ -24,6 +24,10 @@ sys.path.insert(0, ROOT)
 METRIC = "gradients/sec AD vs 2d+1 FD at rel 1e-8; FP64 MFMA % peak for BTA factor+selinv"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# profiler names of the library's kernel groups -> device kernel symbols (as rocprofv3 lists them)
+KERNEL_SYMBOLS = {"gemm_f64": "gemm_f64_kernel", "potrf_panel": "potrf_panel_kernel",
+                  "gemv": "gemv_t_kernel", "assemble": "assemble_blocks_kernel",
+                  "trace": "trace_kernel", "tip": "tip_kernel"}
 
 
 def parse():
@@ -39,7 +43,33 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the event-profiled gradient steps (the command rocprofv3 traces)")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="with --roofline-only: also run one plain device copy of this many MiB, "
+                         "the reference dispatch for scaling HBM byte counters")
     return ap.parse_args()
+
+
+def source_digest(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE runs scaled by a plain copy of known size), or None when there is none or the
+    kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != source_digest(rec.get("sources", [])):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def timed(fn, steps, warmup, use_graph, torch):
@@ -105,7 +135,8 @@ def profiled_pass(args, ad_step, bta, torch):
         achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof.update({"kernel": name, "launches_per_step": st["launches"] / args.profile_steps,
+    roof.update({"kernel": name, "kernel_symbol": KERNEL_SYMBOLS.get(name, name),
+                 "launches_per_step": st["launches"] / args.profile_steps,
                  "avg_launch_us": per_launch_ms * 1e3,
                  "algorithmic_per_launch": (st["flops"] or st["bytes"]) / max(st["launches"], 1),
                  "host_enqueue_ms_per_step": host_s * 1e3})
@@ -171,6 +202,15 @@ def main():
         for _ in range(args.warmup):
             ad_only()
         stats, roof = profiled_pass(args, ad_only, bta, torch)
+        if args.calibration_copy_mib > 0:
+            n = args.calibration_copy_mib * (1 << 20) // 8
+            src = torch.ones(n, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            roof["calibration_copy_bytes_each_way"] = n * 8
+        roof["traffic"] = measured_traffic(roof["kernel_symbol"], args.workload)
         print(json.dumps({"roofline": roof, "kernels": stats}), flush=True)
         return
 
@@ -194,6 +234,7 @@ def main():
                    max(3, args.steps // 2), 1, use_graph, torch)
 
     stats, roof = profiled_pass(args, ad_step, bta, torch)
+    roof["traffic"] = measured_traffic(roof["kernel_symbol"], args.workload)
 
     k, nx, ny, nt, a, obs = NAMED_CONFIGS[args.workload]
     b = k * nx * ny

@@ -102,6 +102,31 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape shape, double* D, double* B, dou
                double* T, double* Dinv, double* rhs, double* logdet, int32_t* info, void* ws,
                size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Uneven batch (Sec. III-A-1, Alg. 1, applied to many independent matrices at once; the
+ * batched evaluation of many instances is the setting of Sec. IV): factorises `count`
+ * independent BTA matrices whose (n, b, a) differ, with the same in/out contract per matrix
+ * as bta_factor.  Matrices with equal b share every launch of their block sweep (one launch
+ * per step covers all of them; a matrix with fewer blocks drops out of the launches past its
+ * last block, a smaller arrow is padded with identity rows).  Groups with different b run one
+ * after the other on `stream`.
+ *   shapes               host array [count]: the (n, b, a) of each matrix.
+ *   D, B, C, T, Dinv     host arrays [count] of device pointers, laid out as for bta_factor
+ *                        (B[i] may be NULL iff n_i == 1, C[i] and T[i] iff a_i == 0).
+ *   rhs                  NULL (no solve), or a host array [count] of device pointers, all
+ *                        non-NULL: length N_i, in r_i, out z_i = L_i^-1 r_i.
+ *   logdet, info         device arrays [count].
+ * Workspace: adelia_bta_batched_workspace_bytes(count, shapes, rhs != NULL).  Matrices are
+ * copied into the workspace and back, so they must not overlap each other.
+ * Errors: ADELIA_E_SHAPE for an invalid shape (nothing is launched); argument errors as for
+ * bta_factor, numbered for the first offending matrix.
+ * --------------------------------------------------------------------------------------- */
+size_t adelia_bta_batched_workspace_bytes(int count, const adelia_bta_shape* shapes, int with_rhs);
+int bta_factor_batched(adelia_ctx ctx, int count, const adelia_bta_shape* shapes,
+                       double* const* D, double* const* B, double* const* C, double* const* T,
+                       double* const* Dinv, double* const* rhs, double* logdet, int32_t* info,
+                       void* ws, size_t ws_bytes, void* stream);
+
 /* log|Q| from a factor produced by bta_factor (Sec. II-A: log|Q| = 2 sum log diag L):
  * reads the diagonals of the n blocks LD (ld b) and of LT (a x a, ld a; NULL iff a == 0).
  * out: device scalar. */

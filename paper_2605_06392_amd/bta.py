@@ -86,6 +86,37 @@ def bta_factor(D, B, C_arrow, T, rhs=None):
     return Dinv, logdet, info
 
 
+def bta_factor_batched(mats, with_rhs=False):
+    """Uneven batch: mats is a list of dicts with D (n,b,b), B (n-1,b,b) or None, C (n,b,a) or
+    None, T (a,a) or None and, with with_rhs, rhs (N,).  Factorised in place as bta_factor does
+    for each; returns (list of Dinv, logdet (count,), info (count,))."""
+    count = len(mats)
+    dev = mats[0]["D"].device
+    shapes = (BtaShape * count)()
+    ptr = lambda t: (t.data_ptr() if t is not None else None)  # noqa: E731
+    arr = lambda vals: (C.c_void_p * count)(*vals)  # noqa: E731
+    dinv = []
+    for i, m in enumerate(mats):
+        n, b = m["D"].shape[0], m["D"].shape[1]
+        a = m["T"].shape[0] if m.get("T") is not None else 0
+        shapes[i] = BtaShape(n, b, a)
+        dinv.append(torch.empty_like(m["D"]))
+    nbytes = lib().adelia_bta_batched_workspace_bytes(count, shapes, int(with_rhs))
+    if nbytes == 0:
+        raise ValueError("invalid shapes for bta_factor_batched")
+    ws = workspace(nbytes, dev)
+    logdet = torch.empty(count, dtype=torch.float64, device=dev)
+    info = torch.empty(count, dtype=torch.int32, device=dev)
+    r = lib().bta_factor_batched(
+        context(), count, shapes, arr([ptr(m["D"]) for m in mats]),
+        arr([ptr(m.get("B")) for m in mats]), arr([ptr(m.get("C")) for m in mats]),
+        arr([ptr(m.get("T")) for m in mats]), arr([ptr(t) for t in dinv]),
+        arr([ptr(m["rhs"]) for m in mats]) if with_rhs else None,
+        _p(logdet), _p(info), C.c_void_p(_ws_ptr(ws)), nbytes, _stream())
+    check(r, "bta_factor_batched")
+    return dinv, logdet, info
+
+
 def bta_logdet(LD, LT):
     n, b = LD.shape[0], LD.shape[1]
     a = LT.shape[0] if LT is not None else 0

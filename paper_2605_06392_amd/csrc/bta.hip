@@ -33,7 +33,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
   for (int k = 0; k < npanel; ++k) {
     const int c0 = k * kPanel;
     if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, c.ldpart + (long long)i * npanel + k, c.zLd,
-                           c.info, c.cnt, b, c0, (long long)i * b, nz, s))
+                           c.info, c.cnt, c.zn, i, b, c0, (long long)i * b, nz, s))
       return ADELIA_E_HIP_INTERNAL;
     const int rest = b - c0 - kPanel;
     if (rest > 0) {
@@ -49,6 +49,8 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.beta = 1.0;
       g.omode = OUT_LOWER;
       g.tag = GT_TRAIL;
+      g.zn = c.zn;
+      g.step = i;
       if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
@@ -75,6 +77,8 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
+      g.zn = c.zn;
+      g.step = i;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
     {  // X21 = -X22 * T  (X22 lower)
@@ -94,6 +98,8 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
+      g.zn = c.zn;
+      g.step = i;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
@@ -124,6 +130,8 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_TRMM;
+    g.zn = c.zn;
+    g.step = i;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // 4. Schur update of the next diagonal block, next arrow block and the tip
@@ -153,6 +161,8 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       g.M = g.N = g.Mlast = g.Nlast = ap;
     }
     g.tag = GT_SYRK;
+    g.zn = c.zn;
+    g.step = i;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;

@@ -60,6 +60,9 @@ struct GemmArgs {
   double beta;
   int omode;
   int tag;  // role of the launch, for the opt-in profiler (GemmTag)
+  // Uneven batches: chain z takes part only while step < zn[z] (zn == nullptr: always).
+  const int32_t* zn;
+  int step;
 };
 
 enum GemmTag { GT_OTHER = 0, GT_TRAIL, GT_TRTRI, GT_TRMM, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D, GT_COUNT };
@@ -95,6 +98,7 @@ struct BtaChains {
   double* ldpart; long long zLd;            // logdet partials, n*npanel + 1 per chain
   int32_t* info;                            // per chain (stride 1)
   int32_t* cnt;                             // per chain (stride 1), zero: panel write-back counters
+  const int32_t* zn;                        // per chain block count (uneven batch) or nullptr
   double* scratch; long long zS;            // b*b per chain (TRTRI temporaries)
   double* zsq;                              // per chain: |z|^2 (if ap == a+1), may be null
   double* ZT; long long zZT;                // a x a per chain: [Q^-1]_{T,T} (may be null)

@@ -24,40 +24,57 @@ namespace {
 constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int LDS_ROW = BM + 4;  // padded row (doubles); keeps 16-byte alignment
 
+// A view with the chain (z) and sub-problem (y) offsets applied: four quadrant bases and
+// strides, formed once per workgroup from the uniform kernel arguments.
+struct VP {
+  const double* b[4];
+  long long sr[4], sc[4];
+  int rs, cs;
+};
+
+__device__ __forceinline__ VP make_vp(const View& v, int z, int y) {
+  VP o;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    o.b[q] = v.p[q] + (long long)z * v.zs[q] + (long long)y * v.ys[q];
+    o.sr[q] = v.sr[q];
+    o.sc[q] = v.sc[q];
+  }
+  o.rs = v.rs;
+  o.cs = v.cs;
+  return o;
+}
+
 struct QuadSel {
   const double* p;
   long long sr, sc;
 };
 
-__device__ __forceinline__ QuadSel pick(const View& v, int q, int z, int y) {
-  // all four quadrants are read (uniform kernel arguments) and selected per lane; an indexed
-  // access would make the compiler spill the argument block to scratch
+// Quadrant q of a view; q may differ between lanes, so the four candidates are selected
+// rather than indexed (an indexed access would put the argument block in scratch).
+__device__ __forceinline__ QuadSel pick(const VP& v, int q) {
   const bool hi = (q & 1) != 0, right = (q & 2) != 0;
-  const double* p01 = hi ? v.p[1] : v.p[0];
-  const double* p23 = hi ? v.p[3] : v.p[2];
+  QuadSel s;
+  const double* p01 = hi ? v.b[1] : v.b[0];
+  const double* p23 = hi ? v.b[3] : v.b[2];
   const long long sr01 = hi ? v.sr[1] : v.sr[0], sr23 = hi ? v.sr[3] : v.sr[2];
   const long long sc01 = hi ? v.sc[1] : v.sc[0], sc23 = hi ? v.sc[3] : v.sc[2];
-  const long long zs01 = hi ? v.zs[1] : v.zs[0], zs23 = hi ? v.zs[3] : v.zs[2];
-  const long long ys01 = hi ? v.ys[1] : v.ys[0], ys23 = hi ? v.ys[3] : v.ys[2];
-  QuadSel s;
+  s.p = right ? p23 : p01;
   s.sr = right ? sr23 : sr01;
   s.sc = right ? sc23 : sc01;
-  const long long zs = right ? zs23 : zs01, ys = right ? ys23 : ys01;
-  s.p = (right ? p23 : p01) + (long long)z * zs + (long long)y * ys;
   return s;
 }
 
-__device__ __forceinline__ double* elem_ptr(const View& v, int r, int c, int z, int y) {
+__device__ __forceinline__ double* elem_ptr(const VP& v, int r, int c) {
   const bool rb = r >= v.rs, cb = c >= v.cs;
-  const int q = (rb ? 1 : 0) + (cb ? 2 : 0);
-  QuadSel s = pick(v, q, z, y);
+  QuadSel s = pick(v, (rb ? 1 : 0) + (cb ? 2 : 0));
   const int rr = rb ? r - v.rs : r;
   const int cc = cb ? c - v.cs : c;
   return const_cast<double*>(s.p + rr * s.sr + cc * s.sc);
 }
 
 // Whole region [r0, r0+R) x [c0, c0+Cn) inside one quadrant?  Returns quadrant or -1.
-__device__ __forceinline__ int uniform_quad(const View& v, int r0, int R, int c0, int Cn) {
+__device__ __forceinline__ int uniform_quad(const VP& v, int r0, int R, int c0, int Cn) {
   const bool rb0 = r0 >= v.rs, rb1 = (r0 + R - 1) >= v.rs;
   const bool cb0 = c0 >= v.cs, cb1 = (c0 + Cn - 1) >= v.cs;
   if (rb0 != rb1 || cb0 != cb1) return -1;
@@ -69,192 +86,82 @@ __device__ __forceinline__ bool tri_zero(int tri, int r, int c) {
 }
 
 // Tile loads.  A BM x BK tile of logical A (and a BK x BN tile of logical B) goes through 8
-// registers per thread.  Fast paths (tile inside one quadrant and in bounds) use 16-byte loads
-// along the contiguous dimension; mode records the thread -> element mapping for the LDS store:
-//   0: pairs along M (N for B), 1: pairs along K, 2: generic scalar (M/N fastest).
+// registers per thread.  The eight addresses are formed first (one branch, on the tile's
+// placement) and the eight 8-byte loads are issued after it, back to back, with no use of the
+// loaded values: they stay in flight while the current K step runs on the matrix cores.  The
+// lanes of a wavefront walk the operand's contiguous dimension, so every load instruction reads
+// 256 or 512 consecutive bytes.  Addresses outside the operand are clamped onto it; bounds,
+// triangle masks and alpha are applied when the registers are written to LDS.  mode records
+// the thread -> element mapping:
+//   0: lanes along the tile's M/N dimension, 1: lanes along K.
 struct TileRegs {
   double v[8];
   int mode;
 };
 
-__device__ __forceinline__ bool vec_ok(const double* base, long long other_stride) {
-  return ((reinterpret_cast<uintptr_t>(base) & 15) == 0) && ((other_stride & 1) == 0);
+// (row, col) of register j of a tile; rows run along M (or N), cols along K.
+__device__ __forceinline__ void tile_pos(int mode, int j, int& r, int& c) {
+  const int tid = threadIdx.x;
+  const int r0 = tid & 63, c0 = (tid >> 6) + 4 * j;
+  const int r1 = (tid >> 5) + 8 * j, c1 = tid & 31;
+  r = mode ? r1 : r0;
+  c = mode ? c1 : c0;
 }
 
-__device__ __forceinline__ void load_a(const View& A, int M, int K, int m0, int k0, int tri,
-                                       double alpha, int z, int y, TileRegs& t) {
-  const int tid = threadIdx.x;
-  const bool inb = (m0 + BM <= M) && (k0 + BK <= K);
-  const int q = inb ? uniform_quad(A, m0, BM, k0, BK) : -1;
+// Loads the tile rows [r0, r0+64) x cols [c0, c0+32).  colsfirst: the view's first index is
+// the K coordinate (logical B(k, n) is stored as the view's (k, n)).
+__device__ __forceinline__ void load_tile(const VP& V, int R, int Cn, int r0, int c0, bool colsfirst,
+                                          TileRegs& t) {
+  const bool inb = (r0 + BM <= R) && (c0 + BK <= Cn);
+  const int q = !inb ? -1
+                     : (colsfirst ? uniform_quad(V, c0, BK, r0, BM) : uniform_quad(V, r0, BM, c0, BK));
+  // global address space: plain (flat) loads would also count against the LDS counter and
+  // make the K step's LDS waits wait for them
+  typedef const double __attribute__((address_space(1)))* gptr;
+  gptr ptr[8];
   if (q >= 0) {
-    QuadSel s = pick(A, q, z, y);
-    const int mo = (q & 1) ? m0 - A.rs : m0;
-    const int ko = (q & 2) ? k0 - A.cs : k0;
-    const double* base = s.p + mo * s.sr + ko * s.sc;
-    if (s.sr == 1 && vec_ok(base, s.sc)) {
-      t.mode = 0;
-      const int m = (tid & 31) * 2, kq = tid >> 5;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = kq + 8 * j;
-        const double2 v = *reinterpret_cast<const double2*>(base + m + k * s.sc);
-        double v0 = v.x, v1 = v.y;
-        if (tri) {
-          if (tri_zero(tri, m0 + m, k0 + k)) v0 = 0.0;
-          if (tri_zero(tri, m0 + m + 1, k0 + k)) v1 = 0.0;
-        }
-        t.v[2 * j] = alpha * v0;
-        t.v[2 * j + 1] = alpha * v1;
-      }
-      return;
-    }
-    if (s.sc == 1 && vec_ok(base, s.sr)) {
-      t.mode = 1;
-      const int k = (tid & 15) * 2, mq = tid >> 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = mq + 16 * j;
-        const double2 v = *reinterpret_cast<const double2*>(base + m * s.sr + k);
-        double v0 = v.x, v1 = v.y;
-        if (tri) {
-          if (tri_zero(tri, m0 + m, k0 + k)) v0 = 0.0;
-          if (tri_zero(tri, m0 + m, k0 + k + 1)) v1 = 0.0;
-        }
-        t.v[2 * j] = alpha * v0;
-        t.v[2 * j + 1] = alpha * v1;
-      }
-      return;
-    }
-    t.mode = 2;
-    const int m = tid & 63, kq = tid >> 6;
+    QuadSel s = pick(V, q);
+    const int vr0 = colsfirst ? c0 : r0, vc0 = colsfirst ? r0 : c0;
+    const int ro = (q & 1) ? vr0 - V.rs : vr0;
+    const int co = (q & 2) ? vc0 - V.cs : vc0;
+    const double* base = s.p + ro * s.sr + co * s.sc;
+    const long long sR = colsfirst ? s.sc : s.sr;  // stride along the tile's rows (M/N)
+    const long long sC = colsfirst ? s.sr : s.sc;  // stride along K
+    t.mode = (sR != 1 && sC == 1) ? 1 : 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = kq + 4 * j;
-      double val = base[m * s.sr + k * s.sc];
-      if (tri && tri_zero(tri, m0 + m, k0 + k)) val = 0.0;
-      t.v[j] = alpha * val;
-    }
-    return;
-  }
-  t.mode = 2;
-  const int m = tid & 63, kq = tid >> 6;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int k = kq + 4 * j;
-    const int gm = m0 + m, gk = k0 + k;
-    double val = 0.0;
-    if (gm < M && gk < K && !(tri && tri_zero(tri, gm, gk))) val = *elem_ptr(A, gm, gk, z, y);
-    t.v[j] = alpha * val;
-  }
-}
-
-__device__ __forceinline__ void store_a(const TileRegs& t, double (*As)[LDS_ROW]) {
-  const int tid = threadIdx.x;
-  if (t.mode == 0) {
-    const int m = (tid & 31) * 2, kq = tid >> 5;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      *reinterpret_cast<double2*>(&As[kq + 8 * j][m]) = make_double2(t.v[2 * j], t.v[2 * j + 1]);
-  } else if (t.mode == 1) {
-    const int k = (tid & 15) * 2, mq = tid >> 4;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      As[k][mq + 16 * j] = t.v[2 * j];
-      As[k + 1][mq + 16 * j] = t.v[2 * j + 1];
+      int r, c;
+      tile_pos(t.mode, j, r, c);
+      ptr[j] = (gptr)(base + r * sR + c * sC);
     }
   } else {
-    const int m = tid & 63, kq = tid >> 6;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) As[kq + 4 * j][m] = t.v[j];
-  }
-}
-
-// Logical B(k, n), tile BK x BN at (k0, n0); stored in LDS as Bs[k][n].
-__device__ __forceinline__ void load_b(const View& B, int K, int N, int k0, int n0, int tri, int z,
-                                       int y, TileRegs& t) {
-  const int tid = threadIdx.x;
-  const bool inb = (n0 + BN <= N) && (k0 + BK <= K);
-  const int q = inb ? uniform_quad(B, k0, BK, n0, BN) : -1;
-  if (q >= 0) {
-    QuadSel s = pick(B, q, z, y);
-    const int ko = (q & 1) ? k0 - B.rs : k0;
-    const int no = (q & 2) ? n0 - B.cs : n0;
-    const double* base = s.p + ko * s.sr + no * s.sc;
-    if (s.sc == 1 && vec_ok(base, s.sr)) {
-      t.mode = 0;
-      const int n = (tid & 31) * 2, kq = tid >> 5;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = kq + 8 * j;
-        const double2 v = *reinterpret_cast<const double2*>(base + k * s.sr + n);
-        double v0 = v.x, v1 = v.y;
-        if (tri) {
-          if (tri_zero(tri, k0 + k, n0 + n)) v0 = 0.0;
-          if (tri_zero(tri, k0 + k, n0 + n + 1)) v1 = 0.0;
-        }
-        t.v[2 * j] = v0;
-        t.v[2 * j + 1] = v1;
-      }
-      return;
-    }
-    if (s.sr == 1 && vec_ok(base, s.sc)) {
-      t.mode = 1;
-      const int k = (tid & 15) * 2, nq = tid >> 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = nq + 16 * j;
-        const double2 v = *reinterpret_cast<const double2*>(base + k + n * s.sc);
-        double v0 = v.x, v1 = v.y;
-        if (tri) {
-          if (tri_zero(tri, k0 + k, n0 + n)) v0 = 0.0;
-          if (tri_zero(tri, k0 + k + 1, n0 + n)) v1 = 0.0;
-        }
-        t.v[2 * j] = v0;
-        t.v[2 * j + 1] = v1;
-      }
-      return;
-    }
-    t.mode = 2;
-    const int n = tid & 63, kq = tid >> 6;
+    t.mode = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = kq + 4 * j;
-      double val = base[k * s.sr + n * s.sc];
-      if (tri && tri_zero(tri, k0 + k, n0 + n)) val = 0.0;
-      t.v[j] = val;
+      int r, c;
+      tile_pos(0, j, r, c);
+      const int gr = min(r0 + r, R - 1), gc = min(c0 + c, Cn - 1);
+      ptr[j] = (gptr)(colsfirst ? elem_ptr(V, gc, gr) : elem_ptr(V, gr, gc));
     }
-    return;
   }
-  t.mode = 2;
-  const int n = tid & 63, kq = tid >> 6;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int k = kq + 4 * j;
-    const int gk = k0 + k, gn = n0 + n;
-    double val = 0.0;
-    if (gk < K && gn < N && !(tri && tri_zero(tri, gk, gn))) val = *elem_ptr(B, gk, gn, z, y);
-    t.v[j] = val;
-  }
+  for (int j = 0; j < 8; ++j) t.v[j] = *ptr[j];
 }
 
-__device__ __forceinline__ void store_b(const TileRegs& t, double (*Bs)[LDS_ROW]) {
-  const int tid = threadIdx.x;
-  if (t.mode == 0) {
-    const int n = (tid & 31) * 2, kq = tid >> 5;
+// Write a tile to LDS as T[c][r] (K-major), zeroing what lies outside the operand or on the
+// zero side of a triangular operand, scaled by alpha.  tri is given in the view's own (row,
+// col) orientation: for A that is (m, k), for B it is (k, n).
+__device__ __forceinline__ void store_tile(const TileRegs& t, double (*T)[LDS_ROW], int R, int Cn,
+                                           int r0, int c0, int tri, bool colsfirst, double alpha) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      *reinterpret_cast<double2*>(&Bs[kq + 8 * j][n]) = make_double2(t.v[2 * j], t.v[2 * j + 1]);
-  } else if (t.mode == 1) {
-    const int k = (tid & 15) * 2, nq = tid >> 4;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      Bs[k][nq + 16 * j] = t.v[2 * j];
-      Bs[k + 1][nq + 16 * j] = t.v[2 * j + 1];
-    }
-  } else {
-    const int n = tid & 63, kq = tid >> 6;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Bs[kq + 4 * j][n] = t.v[j];
+  for (int j = 0; j < 8; ++j) {
+    int r, c;
+    tile_pos(t.mode, j, r, c);
+    const int gr = r0 + r, gc = c0 + c;
+    bool ok = gr < R && gc < Cn;
+    if (tri) ok = ok && !(colsfirst ? tri_zero(tri, gc, gr) : tri_zero(tri, gr, gc));
+    const double v = alpha * t.v[j];
+    T[c][r] = ok ? v : 0.0;
   }
 }
 
@@ -272,8 +179,27 @@ __device__ __forceinline__ void krange(int mode, int K, int m0, int n0, int& klo
   if (klo > K) klo = K;
 }
 
-// One phase of the K loop: double-buffered LDS (one barrier per 32-wide K step); the next
-// step's tiles travel global -> registers while the current step runs on the matrix cores.
+// One K step on the matrix cores: 8 x 4 MFMAs per wave over a 32-deep slice of the LDS tiles.
+__device__ __forceinline__ void mfma_step(const double (*As)[LDS_ROW], const double (*Bs)[LDS_ROW],
+                                          int wm, int wn, int lane, v4d (&acc)[2][2]) {
+#pragma unroll
+  for (int kk = 0; kk < BK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+    const double a0 = As[kr][wm + (lane & 15)];
+    const double a1 = As[kr][wm + 16 + (lane & 15)];
+    const double b0 = Bs[kr][wn + (lane & 15)];
+    const double b1 = Bs[kr][wn + 16 + (lane & 15)];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// One phase as a software pipeline with a single site per stage (the kernel stays small, which
+// matters for short launches: every workgroup streams the kernel's code through the
+// instruction cache).  Iteration t issues the global loads of K tile t, runs tile t-1 from LDS
+// on the matrix cores, then writes tile t to the other LDS buffer; one barrier per iteration.
 __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
                                           double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW],
@@ -281,39 +207,21 @@ __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int
   const int K = lasty ? ph.Klast : ph.K;
   int klo, khi;
   krange(ph.kmode, K, m0, n0, klo, khi);
-  if (klo >= khi) return;
+  const int nk = klo < khi ? (khi - klo + BK - 1) / BK : 0;
+  const VP A = make_vp(ph.A, z, y), B = make_vp(ph.B, z, y);
   TileRegs ra, rb;
-  load_a(ph.A, M, K, m0, klo, ph.triA, ph.alpha, z, y, ra);
-  load_b(ph.B, K, N, klo, n0, ph.triB, z, y, rb);
-  __syncthreads();  // the previous phase may still read buffer 0
-  store_a(ra, As[0]);
-  store_b(rb, Bs[0]);
-  __syncthreads();
-  int cur = 0;
-  for (int k0 = klo; k0 < khi; k0 += BK) {
-    const bool more = k0 + BK < khi;
-    if (more) {
-      load_a(ph.A, M, K, m0, k0 + BK, ph.triA, ph.alpha, z, y, ra);
-      load_b(ph.B, K, N, k0 + BK, n0, ph.triB, z, y, rb);
+  for (int t = 0; t <= nk; ++t) {
+    const int k0 = klo + t * BK;
+    if (t < nk) {
+      load_tile(A, M, K, m0, k0, false, ra);
+      load_tile(B, N, K, n0, k0, true, rb);
     }
-#pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
-      const double a0 = As[cur][kr][wm + (lane & 15)];
-      const double a1 = As[cur][kr][wm + 16 + (lane & 15)];
-      const double b0 = Bs[cur][kr][wn + (lane & 15)];
-      const double b1 = Bs[cur][kr][wn + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
-    }
-    if (more) {
-      store_a(ra, As[cur ^ 1]);
-      store_b(rb, Bs[cur ^ 1]);
+    if (t > 0) mfma_step(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
+    if (t < nk) {
+      store_tile(ra, As[t & 1], M, K, m0, k0, ph.triA, false, ph.alpha);
+      store_tile(rb, Bs[t & 1], N, K, n0, k0, ph.triB, true, 1.0);
     }
     __syncthreads();
-    cur ^= 1;
   }
 }
 
@@ -329,6 +237,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   __shared__ double As[2][BK][LDS_ROW];
   __shared__ double Bs[2][BK][LDS_ROW];
   const int z = blockIdx.z, y = blockIdx.y;
+  if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
   const bool lasty = (y == (int)gridDim.y - 1);
   const int M = lasty ? args.Mlast : args.M;
   const int N = lasty ? args.Nlast : args.N;
@@ -353,20 +262,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
 
+  const VP C = make_vp(args.C, z, y);
+  const double beta = args.beta;
+  const bool lowerC = args.omode != OUT_ALL;
   v4d acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int p = 0; p < args.nph; ++p)
+    run_phase(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
 
-  run_phase(args.ph[0], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
-  if (args.nph > 1) run_phase(args.ph[1], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
-
-  // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v)
-  const View& C = args.C;
-  const bool full = (m0 + BM <= M) && (n0 + BN <= N);
-  const int qc = full ? uniform_quad(C, m0, BM, n0, BN) : -1;
-  const double beta = args.beta;
+  // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v).  Its sixteen
+  // addresses are formed once (clamped into C; out-of-range entries are never stored); with
+  // beta != 0 all sixteen reads of C are issued before any is used.
+  double* cp[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cp[bi][bj][v] = elem_ptr(C, min(m0 + wm + bi * 16 + (lane & 15), M - 1),
+                                 min(n0 + wn + bj * 16 + (lane >> 4) + 4 * v, N - 1));
+  if (beta != 0.0) {
+    double cv[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[bi][bj][v] = fma(beta, cv[bi][bj][v], acc[bi][bj][v]);
+  }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
@@ -376,20 +309,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         const int m = m0 + wm + bi * 16 + (lane & 15);
         const int n = n0 + wn + bj * 16 + (lane >> 4) + 4 * v;
         if (m >= M || n >= N) continue;
-        if (args.omode != OUT_ALL && m < n) continue;
-        double* dst;
-        if (qc >= 0) {
-          QuadSel s = pick(C, qc, z, y);
-          const int mo = (qc & 1) ? m - C.rs : m;
-          const int no = (qc & 2) ? n - C.cs : n;
-          dst = const_cast<double*>(s.p + mo * s.sr + no * s.sc);
-        } else {
-          dst = elem_ptr(C, m, n, z, y);
-        }
-        double val = acc[bi][bj][v];
-        if (beta != 0.0) val += beta * (*dst);
-        *dst = val;
-        if (args.omode == OUT_LOWER_MIRROR && m > n) *elem_ptr(C, n, m, z, y) = val;
+        if (lowerC && m < n) continue;
+        const double val = acc[bi][bj][v];
+        *cp[bi][bj][v] = val;
+        if (args.omode == OUT_LOWER_MIRROR && m > n) *elem_ptr(C, n, m) = val;
       }
     }
   }

@@ -31,6 +31,8 @@ struct PanelArgs {
   double* ldp; long long zLd;
   int32_t* info;
   int32_t* cnt;  // per chain, zero between launches
+  const int32_t* zn;  // per chain block count (uneven batch) or nullptr
+  int step;
   int b, c0;
   long long gcol0;
 };
@@ -177,6 +179,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   __shared__ int writer;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int z = blockIdx.z;
+  if (P.zn && P.step >= P.zn[z]) return;  // chain z has no block at this step
   const int b = P.b, c0 = P.c0;
   const int w = min(NB, b - c0);
   double* D = P.D + (long long)z * P.zD;
@@ -292,10 +295,10 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
 }  // namespace
 
 int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,
-                       long long zLd, int32_t* info, int32_t* cnt, int b, int c0,
-                       long long gcol0, int nz, hipStream_t s) {
+                       long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
+                       int b, int c0, long long gcol0, int nz, hipStream_t s) {
   if (!cnt) return -1;
-  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, b, c0, gcol0};
+  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0};
   const int rows = (b - c0 + NB - 1) / NB;
   const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(potrf_panel_kernel, dim3(rows, 1, nz), dim3(256), 0, s, P);

@@ -1,0 +1,130 @@
+"""GPU parity of the uneven batched factorisation (many independent BTA matrices with different
+(n, b, a) in one call) against the dense CPU oracle and against one-at-a-time factorisation.
+
+Inputs: seeded random SPD BTA matrices (workloads.bta); the batch mixes block sizes (grouped
+by b), block counts (chains that drop out of later launches), arrow widths (identity-padded
+tips, including a = 0 next to a > 0) and n = 1.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+import oracle
+from workloads.bta import random_bta
+
+pytestmark = pytest.mark.gpu
+
+BATCH = [(3, 70, 3), (1, 70, 0), (5, 70, 2), (2, 130, 4), (4, 130, 0), (1, 7, 2), (2, 64, 2),
+         (3, 70, 1)]
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _to_dev_blocks(arr, dev):
+    from paper_2605_06392_amd.bta import to_cm
+    return to_cm(torch.from_numpy(np.ascontiguousarray(arr)).to(dev))
+
+
+def _cm_to_np(t):
+    return t.transpose(-1, -2).cpu().numpy()
+
+
+def _mats(shapes, seed0, dev, with_rhs):
+    blks, mats = [], []
+    for i, (n, b, a) in enumerate(shapes):
+        blk = random_bta(n, b, a, seed0 + i)
+        m = {"D": _to_dev_blocks(blk["D"], dev),
+             "B": _to_dev_blocks(blk["B"], dev) if n > 1 else None,
+             "C": _to_dev_blocks(blk["C"], dev) if a else None,
+             "T": _to_dev_blocks(blk["T"][None], dev)[0] if a else None}
+        if with_rhs:
+            m["rhs"] = torch.from_numpy(blk["rhs"].copy()).to(dev)
+        blks.append(blk)
+        mats.append(m)
+    return blks, mats
+
+
+@pytest.mark.parametrize("with_rhs", [True, False])
+def test_uneven_batch_matches_dense_cholesky(with_rhs):
+    from paper_2605_06392_amd import bta
+    dev = _dev()
+    blks, mats = _mats(BATCH, 500, dev, with_rhs)
+    dinv, logdet, info = bta.bta_factor_batched(mats, with_rhs=with_rhs)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    for i, ((n, b, a), blk, m) in enumerate(zip(BATCH, blks, mats)):
+        Q = oracle.bta_dense(blk["D"], blk["B"], blk["C"], blk["T"])
+        ref = oracle.dense_cholesky(Q, blk["rhs"])
+        Lb = oracle.bta_split(ref["L"], n, b, a)
+        scale = np.abs(ref["L"]).max()
+        assert np.abs(_cm_to_np(m["D"]) - Lb["D"]).max() <= 1e-12 * scale, i
+        if n > 1:
+            assert np.abs(_cm_to_np(m["B"]) - Lb["B"]).max() <= 1e-12 * scale, i
+        if a:
+            assert np.abs(_cm_to_np(m["C"]) - Lb["C"]).max() <= 1e-12 * scale, i
+            assert np.abs(_cm_to_np(m["T"]) - np.tril(Lb["T"])).max() <= 1e-12 * scale, i
+        G = np.stack([sla.solve_triangular(Lb["D"][t], np.eye(b), lower=True) for t in range(n)])
+        assert np.abs(_cm_to_np(dinv[i]) - G).max() <= 1e-11 * max(1.0, np.abs(G).max()), i
+        assert abs(logdet[i].item() - ref["logdet"]) <= 1e-12 * abs(ref["logdet"]) + 1e-12, i
+        if with_rhs:
+            z = m["rhs"].cpu().numpy()
+            assert np.abs(z - ref["z"]).max() <= 1e-11 * np.abs(ref["z"]).max(), i
+
+
+def test_uneven_batch_agrees_with_single_factorisations():
+    from paper_2605_06392_amd import bta
+    dev = _dev()
+    _, mats = _mats(BATCH, 900, dev, True)
+    _, single = _mats(BATCH, 900, dev, True)
+    dinv, logdet, _ = bta.bta_factor_batched(mats, with_rhs=True)
+    for (n, b, a), m, s, gi in zip(BATCH, mats, single, dinv):
+        Ds, ld, _ = bta.bta_factor(s["D"], s["B"] if n > 1 else torch.zeros(1, b, b, dtype=torch.float64, device=dev),
+                                    s["C"] if a else torch.zeros(n, 1, b, dtype=torch.float64, device=dev),
+                                    s["T"], s["rhs"])
+        torch.cuda.synchronize()
+        sc = m["D"].abs().max().item()
+        assert (m["D"] - s["D"]).abs().max().item() <= 1e-13 * sc
+        assert (gi - Ds).abs().max().item() <= 1e-12 * max(1.0, Ds.abs().max().item())
+        assert (m["rhs"] - s["rhs"]).abs().max().item() <= 1e-12 * s["rhs"].abs().max().item()
+
+
+def test_uneven_batch_reports_failures_per_matrix():
+    from paper_2605_06392_amd import bta
+    dev = _dev()
+    shapes = [(3, 70, 2), (2, 70, 3), (4, 130, 2), (2, 130, 3)]
+    blks = [random_bta(n, b, a, 40 + i) for i, (n, b, a) in enumerate(shapes)]
+    blks[0]["D"][1][5, 5] = -50.0      # block 1 of matrix 0: column 70 + 5 (1-based 76)
+    blks[3]["T"][2, 2] = -1.0e6         # tip of matrix 3, which has fewer blocks than its group:
+    #                                     column 2 * 130 + 2 (1-based 263)
+    mats = []
+    for (n, b, a), blk in zip(shapes, blks):
+        mats.append({"D": _to_dev_blocks(blk["D"], dev),
+                     "B": _to_dev_blocks(blk["B"], dev) if n > 1 else None,
+                     "C": _to_dev_blocks(blk["C"], dev) if a else None,
+                     "T": _to_dev_blocks(blk["T"][None], dev)[0] if a else None})
+    _, _, info = bta.bta_factor_batched(mats)
+    torch.cuda.synchronize()
+    got = info.cpu().numpy().tolist()
+    ref = []
+    for (n, b, a), blk in zip(shapes, blks):
+        Q = oracle.bta_dense(blk["D"], blk["B"], blk["C"], blk["T"])
+        ref.append(_first_bad_pivot(Q))
+    assert got == ref
+    assert got == [76, 0, 0, 263]
+
+
+def _first_bad_pivot(Q):
+    """1-based index of the first non-positive pivot of the unpivoted Cholesky, 0 if none."""
+    A = Q.copy()
+    N = A.shape[0]
+    for j in range(N):
+        if not A[j, j] > 0:
+            return j + 1
+        A[j:, j] /= np.sqrt(A[j, j])
+        A[j + 1:, j + 1:] -= np.outer(A[j + 1:, j], A[j + 1:, j])
+    return 0
