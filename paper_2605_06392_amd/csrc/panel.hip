@@ -57,119 +57,160 @@ __device__ __forceinline__ void pivot(double d, double& pv, double& invs) {
   pv = d * r;
 }
 
-// Column j = 4 jq + JR of the leaf: scale the pivot column, rank-1 update of the trailing part
-// of L and of the rows of L^-1 below j, then publish column j+1 and row j+1 of L^-1.  Every LDS
-// load is unconditional (all indices are inside the leaf) and masks are selects, so the step
-// has no divergent branch around a memory access.
+constexpr int QB = 16;  // edge of the serially eliminated leaves
+
+// Column j = 2 jq + JR of a 16 x 16 leaf held as 2 x 2 blocks, one per lane (36 of the 64 lanes
+// cover the lower triangle): scale the pivot column, rank-1 update of the trailing part of L and
+// of the rows of L^-1 below j, then publish column j+1 and row j+1 of L^-1.  Every LDS load is
+// unconditional (all indices lie inside the leaf) and masks are selects, so the step has no
+// divergent branch around a memory access.
 template <int JR>
-__device__ __forceinline__ void leaf_step(double (&a)[4][4], double (&x)[4][4], double* col,
+__device__ __forceinline__ void leaf_step(double (&a)[2][2], double (&x)[2][2], double* col,
                                           double* xr, double* piv, int o, int jq, int br, int bc,
                                           bool active, int lane) {
-  const int j = 4 * jq + JR;
-  double cr[4], cc[4], xc[4];
+  const int j = 2 * jq + JR;
   const double djj = col[j];
+  double cr[2], cc[2], xc[2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    cr[q] = col[4 * br + q];
-    cc[q] = col[4 * bc + q];
-    xc[q] = xr[4 * bc + q];
+  for (int q = 0; q < 2; ++q) {
+    cr[q] = col[2 * br + q];
+    cc[q] = col[2 * bc + q];
+    xc[q] = xr[2 * bc + q];
   }
   double pv, invs;
   pivot(djj, pv, invs);
   if (lane == 0) piv[o + j] = djj;
-  double lr[4], lrx[4], lc[4], xj[4];
+  double lr[2], lrx[2], lc[2], xj[2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 2; ++q) {
     lr[q] = cr[q] * invs;
-    lrx[q] = (4 * br + q > j) ? lr[q] : 0.0;
-    lc[q] = (4 * bc + q > j) ? cc[q] * invs : 0.0;
-    xj[q] = (4 * bc + q <= j) ? xc[q] * invs : 0.0;
+    lrx[q] = (2 * br + q > j) ? lr[q] : 0.0;
+    lc[q] = (2 * bc + q > j) ? cc[q] * invs : 0.0;
+    xj[q] = (2 * bc + q <= j) ? xc[q] * invs : 0.0;
   }
 #pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
+  for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
+    for (int jj = 0; jj < 2; ++jj) {
       a[ii][jj] = fma(-lr[ii], lc[jj], a[ii][jj]);
       x[ii][jj] = fma(-lrx[ii], xj[jj], x[ii][jj]);
     }
   if (bc == jq) {
 #pragma unroll
-    for (int ii = 0; ii < 4; ++ii) a[ii][JR] = (4 * br + ii == j) ? pv : lr[ii];
+    for (int ii = 0; ii < 2; ++ii) a[ii][JR] = (2 * br + ii == j) ? pv : lr[ii];
   }
   if (br == jq) {
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) x[JR][jj] = xj[jj];
+    for (int jj = 0; jj < 2; ++jj) x[JR][jj] = xj[jj];
   }
   wave_order();  // every lane has read column j before it is replaced
-  constexpr int NR = (JR + 1) & 3;
-  const int nq = jq + (JR == 3 ? 1 : 0);
-  if (JR != 3 || nq < HB / 4) {
+  constexpr int NR = (JR + 1) & 1;
+  const int nq = jq + (JR == 1 ? 1 : 0);
+  if (JR != 1 || nq < QB / 2) {
     if (bc == nq && active) {
 #pragma unroll
-      for (int ii = 0; ii < 4; ++ii) col[4 * br + ii] = a[ii][NR];
+      for (int ii = 0; ii < 2; ++ii) col[2 * br + ii] = a[ii][NR];
     }
     if (br == nq && active) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) xr[4 * bc + jj] = x[NR][jj];
+      for (int jj = 0; jj < 2; ++jj) xr[2 * bc + jj] = x[NR][jj];
     }
   }
   wave_order();
 }
 
-// Factor the HB x HB leaf at (o, o) of S (lower triangle, already updated) with one wavefront.
+// Factor the 16 x 16 leaf at (o, o) of S (lower triangle, already updated) with one wavefront.
 // On exit S holds L (lower, zeros above) and X holds L^-1 on that leaf; piv[o + j] = pivot^2.
-__device__ void leaf_factor(double (*S)[LP], double (*X)[LP], double* col, double* xr, double* piv,
-                            int o) {
+__device__ void leaf16(double (*S)[LP], double (*X)[LP], double* col, double* xr, double* piv,
+                       int o) {
   const int lane = threadIdx.x & 63;
   const int br = lane >> 3, bc = lane & 7;
   const bool active = br >= bc;
-  double a[4][4], x[4][4];
+  double a[2][2], x[2][2];
 #pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
+  for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int r = 4 * br + ii, c = 4 * bc + jj;
+    for (int jj = 0; jj < 2; ++jj) {
+      const int r = 2 * br + ii, c = 2 * bc + jj;
       const double v = S[o + r][o + c];
       a[ii][jj] = (r >= c) ? v : 0.0;
       x[ii][jj] = (r == c) ? 1.0 : 0.0;
     }
   if (bc == 0 && active) {
 #pragma unroll
-    for (int ii = 0; ii < 4; ++ii) col[4 * br + ii] = a[ii][0];
+    for (int ii = 0; ii < 2; ++ii) col[2 * br + ii] = a[ii][0];
   }
-  if (lane < 8) xr[4 * lane] = (lane == 0) ? 1.0 : 0.0;
+  if (lane < QB) xr[lane] = (lane == 0) ? 1.0 : 0.0;
   wave_order();
-  for (int jq = 0; jq < HB / 4; ++jq) {
+  for (int jq = 0; jq < QB / 2; ++jq) {
     leaf_step<0>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
     leaf_step<1>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
-    leaf_step<2>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
-    leaf_step<3>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
   }
 #pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
+  for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int r = 4 * br + ii, c = 4 * bc + jj;
+    for (int jj = 0; jj < 2; ++jj) {
+      const int r = 2 * br + ii, c = 2 * bc + jj;
       const bool low = active && r >= c;
       S[o + r][o + c] = low ? a[ii][jj] : 0.0;
       X[o + r][o + c] = low ? x[ii][jj] : 0.0;
     }
+  wave_order();
 }
 
-// One 16 x 16 fragment of a 32 x 32 product C = sum_k A(m, k) B(k, n), k < 32, computed by
-// the calling wavefront: lane holds C(fm + lane%16, fn + lane/16 + 4v).
+// One 16 x 16 fragment C = sum_k A(m, k) B(k, n), k < K (K a multiple of 4), computed by the
+// calling wavefront at (fm, fn): lane holds C(fm + lane%16, fn + lane/16 + 4v).
 template <class FA, class FB>
-__device__ __forceinline__ v4d frag32(FA A, FB B, int fm, int fn) {
+__device__ __forceinline__ v4d frag16(FA A, FB B, int fm, int fn, int K) {
   const int lane = threadIdx.x & 63;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kk = 0; kk < HB / 4; ++kk) {
+  for (int kk = 0; kk < K / 4; ++kk) {
     const int k = kk * 4 + (lane >> 4);
     const double av = A(fm + (lane & 15), k);
     const double bv = B(k, fn + (lane & 15));
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc, 0, 0, 0);
   }
   return acc;
+}
+
+// Factor the 32 x 32 block at (o, o) of S, with its inverse in X, by one wavefront: two serial
+// 16 x 16 leaves, the coupling L21 = A21 X11^T, the update A22 -= L21 L21^T and the inverse
+// merge X21 = -X22 (L21 X11) on the matrix cores.  The wave orders its own LDS traffic, so no
+// workgroup barrier is needed; every fragment is read completely before it is overwritten.
+__device__ void leaf32(double (*S)[LP], double (*X)[LP], double* col, double* xr, double* piv,
+                       int o) {
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, n0 = lane >> 4;
+  const int h = o + QB;
+  leaf16(S, X, col, xr, piv, o);
+  v4d t = frag16([&](int r, int k) { return S[h + r][o + k]; },
+                 [&](int k, int c) { return X[o + c][o + k]; }, 0, 0, QB);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) S[h + m][o + n0 + 4 * v] = t[v];
+  wave_order();
+  t = frag16([&](int r, int k) { return S[h + r][o + k]; },
+             [&](int k, int c) { return S[h + c][o + k]; }, 0, 0, QB);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) S[h + m][h + n0 + 4 * v] -= t[v];
+  wave_order();
+  leaf16(S, X, col, xr, piv, h);
+  t = frag16([&](int r, int k) { return S[h + r][o + k]; },
+             [&](int k, int c) { return X[o + k][o + c]; }, 0, 0, QB);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[h + m][o + n0 + 4 * v] = t[v];
+  wave_order();
+  t = frag16([&](int r, int k) { return X[h + r][h + k]; },
+             [&](int k, int c) { return X[h + k][o + c]; }, 0, 0, QB);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[h + m][o + n0 + 4 * v] = -t[v];
+  wave_order();
+}
+
+// One 16 x 16 fragment of a 32 x 32 product C = sum_k A(m, k) B(k, n), k < 32, computed by the
+// calling wavefront: lane holds C(fm + lane%16, fn + lane/16 + 4v).
+template <class FA, class FB>
+__device__ __forceinline__ v4d frag32(FA A, FB B, int fm, int fn) {
+  return frag16(A, B, fm, fn, HB);
 }
 
 __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
@@ -201,7 +242,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
     if (last) atomicExch(P.cnt + z, 0);
     writer = last ? 1 : 0;
   }
-  if (wave == 0) leaf_factor(S, X, col, xr, piv, 0);
+  if (wave == 0) leaf32(S, X, col, xr, piv, 0);
   __syncthreads();
   const int fm = (wave & 1) * 16, fn = (wave >> 1) * 16;
   // L21 = A21 X11^T
@@ -217,7 +258,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) S[HB + fm + (lane & 15)][HB + fn + (lane >> 4) + 4 * v] -= t[v];
   __syncthreads();
-  if (wave == 0) leaf_factor(S, X, col, xr, piv, HB);
+  if (wave == 0) leaf32(S, X, col, xr, piv, HB);
   __syncthreads();
   // X21 = -X22 (L21 X11)
   t = frag32([&](int m, int k) { return S[HB + m][k]; },
