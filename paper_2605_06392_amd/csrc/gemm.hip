@@ -22,7 +22,7 @@ namespace adelia {
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 32;
-constexpr int LDS_ROW = BM + 4;  // padded row (doubles); keeps 16-byte alignment
+constexpr int LDS_ROW = BM + 1;  // odd pitch (doubles): K-contiguous tiles store without bank conflicts
 
 // A view with the chain (z) and sub-problem (y) offsets applied: four quadrant bases and
 // strides, formed once per workgroup from the uniform kernel arguments.
@@ -85,18 +85,26 @@ __device__ __forceinline__ bool tri_zero(int tri, int r, int c) {
   return (tri == TRI_LOWER && c > r) || (tri == TRI_UPPER && r > c);
 }
 
-// Tile loads.  A BM x BK tile of logical A (and a BK x BN tile of logical B) goes through 8
-// registers per thread.  The eight addresses are formed first (one branch, on the tile's
-// placement) and the eight 8-byte loads are issued after it, back to back, with no use of the
-// loaded values: they stay in flight while the current K step runs on the matrix cores.  The
-// lanes of a wavefront walk the operand's contiguous dimension, so every load instruction reads
-// 256 or 512 consecutive bytes.  Addresses outside the operand are clamped onto it; bounds,
-// triangle masks and alpha are applied when the registers are written to LDS.  mode records
-// the thread -> element mapping:
-//   0: lanes along the tile's M/N dimension, 1: lanes along K.
-struct TileRegs {
+// Operand tiles.  A BM x BK tile of logical A (and a BK x BN tile of logical B) goes through 8
+// registers per thread.  The lanes of a wavefront walk the operand's contiguous dimension, so
+// every load instruction reads 256 or 512 consecutive bytes.
+//
+// Fast path: while successive K tiles stay inside one quadrant of the view, the loads are
+// buffer loads whose per-lane offsets are fixed for the whole stretch; a K step only moves the
+// scalar offset.  The buffer descriptor's record count is the quadrant's extent, so lanes of a
+// ragged tile that run past the end of the operand read zero instead of faulting; every value
+// outside the logical operand is masked when the tile is written to LDS.  Tiles that straddle a
+// quadrant boundary take the generic path (per-element addresses clamped into the operand).
+typedef const double __attribute__((address_space(1)))* gptr;
+
+struct OpPipe {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int q;            // quadrant of the current stretch (-1: none yet)
+  int mode;         // 0: lanes along M/N, 1: lanes along K
+  int kseg;         // K of the stretch's first tile
+  long long sK;     // element stride along K inside the quadrant
+  unsigned voff[8];
   double v[8];
-  int mode;
 };
 
 // (row, col) of register j of a tile; rows run along M (or N), cols along K.
@@ -108,60 +116,91 @@ __device__ __forceinline__ void tile_pos(int mode, int j, int& r, int& c) {
   c = mode ? c1 : c0;
 }
 
-// Loads the tile rows [r0, r0+64) x cols [c0, c0+32).  colsfirst: the view's first index is
-// the K coordinate (logical B(k, n) is stored as the view's (k, n)).
-__device__ __forceinline__ void load_tile(const VP& V, int R, int Cn, int r0, int c0, bool colsfirst,
-                                          TileRegs& t) {
-  const bool inb = (r0 + BM <= R) && (c0 + BK <= Cn);
-  const int q = !inb ? -1
-                     : (colsfirst ? uniform_quad(V, c0, BK, r0, BM) : uniform_quad(V, r0, BM, c0, BK));
-  // global address space: plain (flat) loads would also count against the LDS counter and
-  // make the K step's LDS waits wait for them
-  typedef const double __attribute__((address_space(1)))* gptr;
-  gptr ptr[8];
-  if (q >= 0) {
-    QuadSel s = pick(V, q);
-    const int vr0 = colsfirst ? c0 : r0, vc0 = colsfirst ? r0 : c0;
-    const int ro = (q & 1) ? vr0 - V.rs : vr0;
-    const int co = (q & 2) ? vc0 - V.cs : vc0;
-    const double* base = s.p + ro * s.sr + co * s.sc;
-    const long long sR = colsfirst ? s.sc : s.sr;  // stride along the tile's rows (M/N)
-    const long long sC = colsfirst ? s.sr : s.sc;  // stride along K
-    t.mode = (sR != 1 && sC == 1) ? 1 : 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      int r, c;
-      tile_pos(t.mode, j, r, c);
-      ptr[j] = (gptr)(base + r * sR + c * sC);
-    }
-  } else {
-    t.mode = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      int r, c;
-      tile_pos(0, j, r, c);
-      const int gr = min(r0 + r, R - 1), gc = min(c0 + c, Cn - 1);
-      ptr[j] = (gptr)(colsfirst ? elem_ptr(V, gc, gr) : elem_ptr(V, gr, gc));
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 8; ++j) t.v[j] = *ptr[j];
+// Quadrant holding the whole tile (tile rows [r0, r0+BM) clipped to R, K range [k0, k0+BK)
+// clipped to Kn), or -1 when it straddles a split.  colsfirst: the view's first index is K.
+__device__ __forceinline__ int tile_quad(const VP& V, int R, int Kn, int r0, int k0, bool colsfirst) {
+  const int r1 = min(r0 + BM, R) - 1, k1 = min(k0 + BK, Kn) - 1;
+  const int vr0 = colsfirst ? k0 : r0, vr1 = colsfirst ? k1 : r1;
+  const int vc0 = colsfirst ? r0 : k0, vc1 = colsfirst ? r1 : k1;
+  const bool rb0 = vr0 >= V.rs, rb1 = vr1 >= V.rs, cb0 = vc0 >= V.cs, cb1 = vc1 >= V.cs;
+  if (rb0 != rb1 || cb0 != cb1) return -1;
+  return (rb0 ? 1 : 0) + (cb0 ? 2 : 0);
 }
 
-// Write a tile to LDS as T[c][r] (K-major), zeroing what lies outside the operand or on the
-// zero side of a triangular operand, scaled by alpha.  tri is given in the view's own (row,
-// col) orientation: for A that is (m, k), for B it is (k, n).
-__device__ __forceinline__ void store_tile(const TileRegs& t, double (*T)[LDS_ROW], int R, int Cn,
-                                           int r0, int c0, int tri, bool colsfirst, double alpha) {
+// Issue the loads of tile (r0, k0).  Nothing reads the loaded registers before store_tile.
+__device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn, int r0, int k0,
+                                          bool colsfirst) {
+  const int q = tile_quad(V, R, Kn, r0, k0, colsfirst);
+  if (q >= 0) {
+    if (q != P.q) {  // a new stretch: descriptor and per-lane offsets
+      QuadSel s = pick(V, q);
+      const int Rv = colsfirst ? Kn : R, Cv = colsfirst ? R : Kn;
+      const int rlo = (q & 1) ? V.rs : 0, rhi = (q & 1) ? Rv : min(V.rs, Rv);
+      const int clo = (q & 2) ? V.cs : 0, chi = (q & 2) ? Cv : min(V.cs, Cv);
+      const long long last = (long long)(rhi - rlo - 1) * s.sr + (long long)(chi - clo - 1) * s.sc;
+      const long long bytes = 8 * (last + 1);
+      P.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(s.p), (short)0,
+                                                 (int)min(bytes, 0x7ffffff0LL), 0x00020000);
+      const long long sR = colsfirst ? s.sc : s.sr;
+      P.sK = colsfirst ? s.sr : s.sc;
+      P.mode = (sR != 1 && P.sK == 1) ? 1 : 0;
+      P.kseg = k0;
+      const int tr = (colsfirst ? r0 - clo : r0 - rlo), tk = (colsfirst ? k0 - rlo : k0 - clo);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        int r, c;
+        tile_pos(P.mode, j, r, c);
+        P.voff[j] = (unsigned)(8 * ((long long)(tr + r) * sR + (long long)(tk + c) * P.sK));
+      }
+      P.q = q;
+    }
+    const int soff = (int)(8 * (long long)(k0 - P.kseg) * P.sK);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+      const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(P.rsrc, (int)P.voff[j], soff, 0);
+      P.v[j] = __builtin_bit_cast(double, w);
+    }
+    return;
+  }
+  P.q = -1;
+  P.mode = 0;
+  gptr ptr[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     int r, c;
-    tile_pos(t.mode, j, r, c);
-    const int gr = r0 + r, gc = c0 + c;
-    bool ok = gr < R && gc < Cn;
+    tile_pos(0, j, r, c);
+    const int gr = min(r0 + r, R - 1), gc = min(k0 + c, Kn - 1);
+    ptr[j] = (gptr)(colsfirst ? elem_ptr(V, gc, gr) : elem_ptr(V, gr, gc));
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) P.v[j] = *ptr[j];
+}
+
+// Write a tile to LDS as T[c][r] (K-major).  Tiles inside the operand with no triangle go
+// straight through; otherwise what lies outside the operand or on the zero side of a
+// triangular operand is written as zero.  tri is in the view's own (row, col) orientation: for
+// A that is (m, k), for B it is (k, n).
+__device__ __forceinline__ void store_tile(const OpPipe& P, double (*T)[LDS_ROW], int R, int Kn,
+                                           int r0, int k0, int tri, bool colsfirst) {
+  const bool interior = (r0 + BM <= R) && (k0 + BK <= Kn) && tri == TRI_NONE;
+  if (interior) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      int r, c;
+      tile_pos(P.mode, j, r, c);
+      T[c][r] = P.v[j];
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    int r, c;
+    tile_pos(P.mode, j, r, c);
+    const int gr = r0 + r, gc = k0 + c;
+    bool ok = gr < R && gc < Kn;
     if (tri) ok = ok && !(colsfirst ? tri_zero(tri, gc, gr) : tri_zero(tri, gr, gc));
-    const double v = alpha * t.v[j];
-    T[c][r] = ok ? v : 0.0;
+    T[c][r] = ok ? P.v[j] : 0.0;
   }
 }
 
@@ -197,9 +236,9 @@ __device__ __forceinline__ void mfma_step(const double (*As)[LDS_ROW], const dou
 }
 
 // One phase as a software pipeline with a single site per stage (the kernel stays small, which
-// matters for short launches: every workgroup streams the kernel's code through the
-// instruction cache).  Iteration t issues the global loads of K tile t, runs tile t-1 from LDS
-// on the matrix cores, then writes tile t to the other LDS buffer; one barrier per iteration.
+// matters for short launches).  Iteration t issues the global loads of K tile t, runs tile t-1
+// from LDS on the matrix cores, then writes tile t to the other LDS buffer; one barrier per
+// iteration.  alpha is applied by the caller to the accumulators.
 __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
                                           double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW],
@@ -209,17 +248,19 @@ __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int
   krange(ph.kmode, K, m0, n0, klo, khi);
   const int nk = klo < khi ? (khi - klo + BK - 1) / BK : 0;
   const VP A = make_vp(ph.A, z, y), B = make_vp(ph.B, z, y);
-  TileRegs ra, rb;
+  OpPipe pa, pb;
+  pa.q = -1;
+  pb.q = -1;
   for (int t = 0; t <= nk; ++t) {
     const int k0 = klo + t * BK;
     if (t < nk) {
-      load_tile(A, M, K, m0, k0, false, ra);
-      load_tile(B, N, K, n0, k0, true, rb);
+      load_tile(pa, A, M, K, m0, k0, false);
+      load_tile(pb, B, N, K, n0, k0, true);
     }
     if (t > 0) mfma_step(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
     if (t < nk) {
-      store_tile(ra, As[t & 1], M, K, m0, k0, ph.triA, false, ph.alpha);
-      store_tile(rb, Bs[t & 1], N, K, n0, k0, ph.triB, true, 1.0);
+      store_tile(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
+      store_tile(pb, Bs[t & 1], N, K, n0, k0, ph.triB, true);
     }
     __syncthreads();
   }
@@ -270,8 +311,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
-  for (int p = 0; p < args.nph; ++p)
+  // acc collects sum_p alpha_p A_p B_p: the products of phase p are accumulated unscaled, the
+  // running sum is rescaled by alpha_{p-1} / alpha_p before phase p and by the last alpha at the
+  // end (exact for the +-1 used on the sweeps).
+  double alpha_prev = 1.0;
+  for (int p = 0; p < args.nph; ++p) {
+    const double alpha = args.ph[p].alpha;
+    if (p > 0) {
+      const double sc = alpha_prev / alpha;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] *= sc;
+    }
     run_phase(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
+    alpha_prev = alpha;
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] *= alpha_prev;
 
   // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v).  Its sixteen
   // addresses are formed once (clamped into C; out-of-range entries are never stored); with
