@@ -224,15 +224,30 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   const int b = P.b, c0 = P.c0;
   const int w = min(NB, b - c0);
   double* D = P.D + (long long)z * P.zD;
-  // diagonal tile (lower) with identity padding past w
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    double v = 0.0;
-    if (r >= c) {
-      if (r < w && c < w) v = D[(long long)(c0 + r) + (long long)(c0 + c) * b];
-      else if (r == c) v = 1.0;
+  // Every global read of the workgroup is issued here, back to back (addresses clamped into the
+  // tiles, values masked on use): the diagonal tile, and for workgroup x > 0 its 64-row tile of
+  // the panel, which stays in registers while the diagonal tile is factored.
+  const int r0 = c0 + NB * blockIdx.x;
+  const int h = blockIdx.x > 0 ? min(NB, b - r0) : 1;
+  double dv[NB * NB / 256], rv[NB * NB / 256];
+#pragma unroll
+  for (int i = 0; i < NB * NB / 256; ++i) {
+    const int e = tid + 256 * i, r = e & 63, c = e >> 6;
+    dv[i] = D[(long long)(c0 + min(r, w - 1)) + (long long)(c0 + min(c, w - 1)) * b];
+  }
+  if (blockIdx.x > 0) {
+#pragma unroll
+    for (int i = 0; i < NB * NB / 256; ++i) {
+      const int e = tid + 256 * i, m = e & 63, k = e >> 6;
+      rv[i] = D[(long long)(r0 + min(m, h - 1)) + (long long)(c0 + min(k, w - 1)) * b];
     }
-    S[r][c] = v;
+  }
+  // diagonal tile (lower) with identity padding past w
+#pragma unroll
+  for (int i = 0; i < NB * NB / 256; ++i) {
+    const int e = tid + 256 * i, r = e & 63, c = e >> 6;
+    const double v = (r < w && c < w) ? dv[i] : (r == c ? 1.0 : 0.0);
+    S[r][c] = (r >= c) ? v : 0.0;
     X[r][c] = 0.0;
   }
   __syncthreads();  // this workgroup's reads of the diagonal tile have completed
@@ -296,11 +311,11 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   }
   if (blockIdx.x == 0) return;
   // panel rows r0..r0+h: L(m, n) = sum_k A(m, k) X(n, k); the tile replaces S
-  const int r0 = c0 + NB * blockIdx.x;
-  const int h = min(NB, b - r0);
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int m = e & 63, k = e >> 6;
-    S[m][k] = (m < h && k < w) ? D[(long long)(r0 + m) + (long long)(c0 + k) * b] : 0.0;
+  __syncthreads();  // every read of S above has completed
+#pragma unroll
+  for (int i = 0; i < NB * NB / 256; ++i) {
+    const int e = tid + 256 * i, m = e & 63, k = e >> 6;
+    S[m][k] = (m < h && k < w) ? rv[i] : 0.0;
   }
   __syncthreads();
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
