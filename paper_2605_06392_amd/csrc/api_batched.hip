@@ -43,7 +43,7 @@ struct Group {
 };
 
 struct GroupWs {
-  double *D, *B, *G, *C, *LC, *T, *LB, *S, *ldpart, *zsq, *ld;
+  double *D, *B, *G, *C, *LC, *T, *LBC, *S, *ldpart, *zsq, *ld;
   int32_t *info, *cnt, *zn, *idx;
   long long zD, zB, zG, zC, zT, zLd;
   int ap, slotsB, npanel;
@@ -72,7 +72,7 @@ GroupWs group_layout(const Group& g, bool rhs, char* base) {
   w.C = take((long long)g.nmax * apa * g.b, w.zC);
   w.LC = take((long long)g.nmax * apa * g.b, dummy);
   w.T = take((long long)apa * apa, w.zT);
-  w.LB = take(bb, dummy);
+  w.LBC = take((long long)(g.b + w.ap) * g.b, dummy);
   w.S = take(bb, dummy);
   w.ldpart = take((long long)g.nmax * w.npanel + 1, w.zLd);
   w.zsq = take(1, dummy);
@@ -186,9 +186,9 @@ int bta_factor_batched(adelia_ctx ctx, int count, const adelia_bta_shape* shapes
     c.n = g.nmax; c.b = b; c.a = amax; c.ap = ap; c.nz = nz;
     c.D = w.D; c.zD = w.zD; c.slotsD = g.nmax;
     c.Bin = w.B; c.zB = w.zB; c.slotsB = w.slotsB;
-    c.LB = w.LB; c.zLB = bb; c.slotsLB = 1;
+    c.LBC = w.LBC; c.zLBC = (long long)(b + ap) * b; c.slotsLBC = 1;
+    c.invert = true;
     c.C = w.C; c.zC = w.zC;
-    c.LC = w.LC; c.zLC = w.zC;
     c.T = w.T; c.zT = w.zT;
     c.G = w.G; c.zG = w.zG; c.slotsG = g.nmax;
     c.ldpart = w.ldpart; c.zLd = w.zLd;
@@ -199,8 +199,12 @@ int bta_factor_batched(adelia_ctx ctx, int count, const adelia_bta_shape* shapes
     c.zsq = w.zsq;
     for (int i = 0; i < g.nmax; ++i) {
       if (bta_forward_block(c, i, s)) return ADELIA_E_HIP;
+      // [L_Bi; L_Ci] leave the one-block scratch for block i's slots
       if (i < g.nmax - 1 &&
-          launch_copy2d(w.LB, b, bb, w.B + (long long)i * bb, b, w.zB, b, b, nz, s))
+          launch_copy2d(w.LBC, b + ap, c.zLBC, w.B + (long long)i * bb, b, w.zB, b, b, nz, s))
+        return ADELIA_E_HIP;
+      if (ap > 0 && launch_copy2d(w.LBC + b, b + ap, c.zLBC, w.LC + (long long)i * ap * b, ap,
+                                  w.zC, ap, b, nz, s))
         return ADELIA_E_HIP;
     }
     if (bta_tip(c, s)) return ADELIA_E_HIP;

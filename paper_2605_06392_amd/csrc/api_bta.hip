@@ -78,7 +78,7 @@ int check_shape(const adelia_bta_shape& sh) {
 }
 
 struct FactorWs {
-  double *Caug, *LCaug, *Taug, *LBs, *S, *ldpart, *zsq;
+  double *Caug, *LCaug, *Taug, *LBC, *S, *ldpart, *zsq;
   int32_t* cnt;
   size_t bytes;
 };
@@ -96,7 +96,7 @@ FactorWs factor_ws_layout(const adelia_bta_shape& sh, int ap, char* base) {
   w.Caug = take(n * (size_t)(ap > 0 ? ap : 1) * b);
   w.LCaug = take(n * (size_t)(ap > 0 ? ap : 1) * b);
   w.Taug = take((size_t)(ap > 0 ? ap : 1) * (ap > 0 ? ap : 1));
-  w.LBs = take(b * b);
+  w.LBC = take((b + (size_t)(ap > 0 ? ap : 0)) * b);
   w.S = take(b * b);
   w.ldpart = take(n * npanel + 1);
   w.zsq = take(1);
@@ -239,9 +239,9 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double
   c.n = n; c.b = b; c.a = a; c.ap = ap; c.nz = 1;
   c.D = D; c.zD = 0; c.slotsD = n;
   c.Bin = B; c.zB = 0; c.slotsB = n > 1 ? n - 1 : 1;
-  c.LB = w.LBs; c.zLB = 0; c.slotsLB = 1;
   c.C = w.Caug; c.zC = 0;
-  c.LC = w.LCaug; c.zLC = 0;
+  c.LBC = w.LBC; c.zLBC = 0; c.slotsLBC = 1;
+  c.invert = true;
   c.T = w.Taug; c.zT = 0;
   c.G = Dinv; c.zG = 0; c.slotsG = n;
   c.ldpart = w.ldpart; c.zLd = 0;
@@ -252,7 +252,12 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double
   for (int i = 0; i < n; ++i) {
     int r = bta_forward_block(c, i, s);
     if (r) return ADELIA_E_HIP;
-    if (i < n - 1 && launch_copy2d(w.LBs, b, 0, B + (long long)i * bb, b, 0, b, b, 1, s))
+    // [L_Bi; L_Ci] leave the one-block scratch: L_Bi into B_i, L_Ci (and z_i) into block i of
+    // the augmented arrow
+    if (i < n - 1 && launch_copy2d(w.LBC, b + ap, 0, B + (long long)i * bb, b, 0, b, b, 1, s))
+      return ADELIA_E_HIP;
+    if (ap > 0 && launch_copy2d(w.LBC + b, b + ap, 0, w.LCaug + (long long)i * ap * b, ap, 0, ap,
+                                b, 1, s))
       return ADELIA_E_HIP;
   }
   if (bta_tip(c, s)) return ADELIA_E_HIP;
@@ -334,8 +339,8 @@ int bta_solve(adelia_ctx ctx, adelia_bta_shape sh, const double* Dinv, const dou
   SolveChains c{};
   c.n = n; c.b = b; c.a = a; c.nz = 1;
   c.G = Dinv; c.zG = 0; c.slotsG = n;
-  c.LB = LB; c.zLB = 0; c.slotsLB = n > 1 ? n - 1 : 1;
-  c.LC = LC; c.zLC = 0; c.ldLC = a > 0 ? a : 1;
+  c.LB = LB; c.zLB = 0; c.slotsLB = n > 1 ? n - 1 : 1; c.ldLB = b; c.sLB = bb;
+  c.LC = LC; c.zLC = 0; c.ldLC = a > 0 ? a : 1; c.sLC = (long long)(a > 0 ? a : 1) * b;
   c.z = x; c.zz = 0; c.sz_blk = b; c.sz_elem = 1;
   c.xT = a > 0 ? x + nb : nullptr; c.zxT = 0;
   c.x = x; c.zx = 0;
@@ -364,8 +369,9 @@ int bta_selinv(adelia_ctx ctx, adelia_bta_shape sh, const double* Dinv, const do
   SelinvChains c{};
   c.n = n; c.b = b; c.a = a; c.nz = 1;
   c.G = Dinv; c.zG = 0; c.slotsG = n;
-  c.LB = LB; c.zLB = 0; c.slotsLB = n > 1 ? n - 1 : 1;
-  c.LC = LC; c.zLC = 0; c.ldLC = a > 0 ? a : 1;
+  c.LB = LB; c.zLB = 0; c.slotsLB = n > 1 ? n - 1 : 1; c.ldLB = b;
+  c.sLB = (long long)b * b;
+  c.LC = LC; c.zLC = 0; c.ldLC = a > 0 ? a : 1; c.sLC = (long long)(a > 0 ? a : 1) * b;
   c.ZT = ZT; c.zZT = 0;
   c.ZD = ZD; c.zZD = 0; c.slotsZD = n;
   c.ZB = ZB; c.zZB = 0; c.slotsZB = n > 1 ? n - 1 : 1;

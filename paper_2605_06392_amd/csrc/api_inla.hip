@@ -32,9 +32,9 @@ namespace {
 struct InlaWs {
   int batch, nz, n, b, a, ap, k, d, npanel;
   bool grad;
-  int slotsD, slotsB, slotsLB, slotsG;
-  double *D, *Bin, *LB, *G, *C, *LC, *T, *S, *ldpart, *ld, *zsq, *ZT, *xT;
-  long long zD, zB, zLB, zG, zC, zLC, zT, zS, zLd, zZT, zXT;
+  int slotsD, slotsB, slotsLBC, slotsG;
+  double *D, *Bin, *LBC, *G, *C, *T, *S, *ldpart, *ld, *zsq, *ZT, *xT;
+  long long zD, zB, zLBC, zG, zC, zT, zS, zLd, zZT, zXT;
   int32_t* info;
   int32_t* cnt;   // panel write-back counters (nz), zero between launches
   double *phi, *dphi, *tau;
@@ -56,7 +56,7 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
   const int n = M.nt;
   w.slotsD = 2;
   w.slotsB = 1;
-  w.slotsLB = grad ? std::max(n - 1, 1) : 1;
+  w.slotsLBC = grad ? n : 1;
   w.slotsG = grad ? n : 1;
   size_t off = 0;
   auto take = [&](long long per_chain, int chains, long long& stride) {
@@ -78,10 +78,9 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
   const int nz = w.nz;
   w.D = take(w.slotsD * bb, nz, w.zD);
   w.Bin = take(w.slotsB * bb, nz, w.zB);
-  w.LB = take(w.slotsLB * bb, nz, w.zLB);
+  w.LBC = take((long long)w.slotsLBC * (M.b + w.ap) * M.b, nz, w.zLBC);
   w.G = take(w.slotsG * bb, nz, w.zG);
   w.C = take((long long)n * w.ap * M.b, nz, w.zC);
-  w.LC = take((long long)n * w.ap * M.b, nz, w.zLC);
   w.T = take((long long)w.ap * w.ap, nz, w.zT);
   w.S = take(bb, nz, w.zS);
   w.ldpart = take((long long)n * w.npanel + 1, nz, w.zLd);
@@ -123,9 +122,9 @@ BtaChains chains_of(const InlaWs& w) {
   c.n = w.n; c.b = w.b; c.a = w.a; c.ap = w.ap; c.nz = w.nz;
   c.D = w.D; c.zD = w.zD; c.slotsD = w.slotsD;
   c.Bin = w.Bin; c.zB = w.zB; c.slotsB = w.slotsB;
-  c.LB = w.LB; c.zLB = w.zLB; c.slotsLB = w.slotsLB;
   c.C = w.C; c.zC = w.zC;
-  c.LC = w.LC; c.zLC = w.zLC;
+  c.LBC = w.LBC; c.zLBC = w.zLBC; c.slotsLBC = w.slotsLBC;
+  c.invert = w.grad;
   c.T = w.T; c.zT = w.zT;
   c.G = w.G; c.zG = w.zG; c.slotsG = w.slotsG;
   c.ldpart = w.ldpart; c.zLd = w.zLd;
@@ -195,9 +194,10 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   SolveChains sc{};
   sc.n = n; sc.b = b; sc.a = a; sc.nz = nz;
   sc.G = w.G; sc.zG = w.zG; sc.slotsG = w.slotsG;
-  sc.LB = w.LB; sc.zLB = w.zLB; sc.slotsLB = w.slotsLB;
-  sc.LC = w.LC; sc.zLC = w.zLC; sc.ldLC = ap;
-  sc.z = w.LC + a; sc.zz = w.zLC; sc.sz_blk = (long long)ap * b; sc.sz_elem = ap;
+  const long long sLBC = (long long)(b + ap) * b;
+  sc.LB = w.LBC; sc.zLB = w.zLBC; sc.slotsLB = w.slotsLBC; sc.ldLB = b + ap; sc.sLB = sLBC;
+  sc.LC = w.LBC + b; sc.zLC = w.zLBC; sc.ldLC = b + ap; sc.sLC = sLBC;
+  sc.z = w.LBC + b + a; sc.zz = w.zLBC; sc.sz_blk = sLBC; sc.sz_elem = b + ap;
   sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
   sc.x = w.x; sc.zx = w.zx;
   sc.y = w.y; sc.zy = w.zy;
@@ -206,8 +206,8 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   SelinvChains si{};
   si.n = n; si.b = b; si.a = a; si.nz = nz;
   si.G = w.G; si.zG = w.zG; si.slotsG = w.slotsG;
-  si.LB = w.LB; si.zLB = w.zLB; si.slotsLB = w.slotsLB;
-  si.LC = w.LC; si.zLC = w.zLC; si.ldLC = ap;
+  si.LB = w.LBC; si.zLB = w.zLBC; si.slotsLB = w.slotsLBC; si.ldLB = b + ap; si.sLB = sLBC;
+  si.LC = w.LBC + b; si.zLC = w.zLBC; si.ldLC = b + ap; si.sLC = sLBC;
   si.ZT = w.ZT; si.zZT = w.zZT;
   si.ZD = w.ZD; si.zZD = w.zZD; si.slotsZD = 2;
   si.ZB = w.ZB; si.zZB = w.zZB; si.slotsZB = 1;

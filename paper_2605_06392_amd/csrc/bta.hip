@@ -3,13 +3,15 @@
 // runs its block steps as single launches.
 //
 // Forward (Sec. III-A-1, Alg. 1), per block i:
-//   1. chol(D_i) by 64-wide panels (potrf.hip) plus trailing GEMM updates; the panel kernels
-//      leave the 64 x 64 diagonal inverses in G_i.
-//   2. G_i = L_Di^-1 completed by recursive doubling: X21 = -X22 L21 X11 (two GEMMs per level).
-//   3. [L_Bi; L_Ci] = [B_i; C~_i] G_i^T: one triangular GEMM.  The right-hand side travels as
-//      an extra arrow row (C~_i's last row is r~_i^T), so the same product gives z_i^T as the
-//      last row of L_Ci -- the forward solve fused into the sweep.
-//   4. [[D_{i+1}], [C~_{i+1}, T~]] -= [L_Bi; L_Ci][L_Bi; L_Ci]^T: one lower-triangular GEMM
+//   1. chol(D_i) by 64-wide panels (panel.hip) plus trailing GEMM updates.  The rows [B_i; C~_i]
+//      are stacked under the block and solved with the same panels (the TRSM of Alg. 1), so
+//      every panel launch and trailing update also covers them and [L_Bi; L_Ci] comes out of
+//      the factorisation.  The right-hand side travels as an extra arrow row (C~_i's last row
+//      is r~_i^T), so L_Ci's last row is z_i^T -- the forward solve fused into the sweep.  The
+//      panel kernels leave the 64 x 64 diagonal inverses in G_i.
+//   2. When the inverse is needed (solve, selected inversion), G_i = L_Di^-1 is completed by
+//      recursive doubling: X21 = -X22 L21 X11 (two GEMMs per level).
+//   3. [[D_{i+1}], [C~_{i+1}, T~]] -= [L_Bi; L_Ci][L_Bi; L_Ci]^T: one lower-triangular GEMM
 //      updating the next diagonal block, the next arrow block (and r~_{i+1}), the tip (and
 //      v_T, and -|z_i|^2 in the tip's corner).
 // Selected inversion (Sec. III-A, Phase A; the recurrence follows from Sigma L = L^-T):
@@ -26,116 +28,105 @@ static inline long long blk_off(int t, int slots, long long bb) { return (long l
 int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
   const int b = c.b, ap = c.ap, n = c.n, nz = c.nz;
   const long long bb = (long long)b * b;
+  const int ldT = b + ap;
   const int npanel = (b + kPanel - 1) / kPanel;
   double* Dblk = c.D + blk_off(i, c.slotsD, bb);
   double* Gblk = c.G + blk_off(i, c.slotsG, bb);
-  // 1. blocked Cholesky of D_i
+  double* LBC = c.LBC + blk_off(i, c.slotsLBC, (long long)ldT * b);
+  const bool hasB = i < n - 1;
+  // 0. the rows solved with the panels of L_Di: [B_i; C~_i] (C~_i alone for the last block)
+  if (hasB && launch_copy2d(c.Bin + blk_off(i, c.slotsB, bb), b, c.zB, LBC, ldT, c.zLBC, b, b, nz, s))
+    return ADELIA_E_HIP_INTERNAL;
+  if (ap > 0 &&
+      launch_copy2d(c.C + (long long)i * ap * b, ap, c.zC, LBC + b, ldT, c.zLBC, ap, b, nz, s))
+    return ADELIA_E_HIP_INTERNAL;
+  double* Rows = hasB ? LBC : LBC + b;
+  const int mT = (hasB ? b : 0) + ap;
+  // 1. blocked Cholesky of D_i; each panel also solves its columns of [B_i; C~_i] (the fused
+  //    TRSM of Alg. 1, which with the rhs row yields z_i), and the trailing update covers the
+  //    block and those rows alike
   for (int k = 0; k < npanel; ++k) {
     const int c0 = k * kPanel;
     if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, c.ldpart + (long long)i * npanel + k, c.zLd,
-                           c.info, c.cnt, c.zn, i, b, c0, (long long)i * b, nz, s))
+                           c.info, c.cnt, c.zn, i, b, c0, (long long)i * b, mT ? Rows : nullptr,
+                           c.zLBC, ldT, mT, nz, s))
       return ADELIA_E_HIP_INTERNAL;
     const int rest = b - c0 - kPanel;
     if (rest > 0) {
       GemmArgs g{};
       g.nph = 1;
-      g.ph[0].A = view_plain(Dblk + (c0 + kPanel) + (long long)c0 * b, b, c.zD);
+      g.ph[0].A = view_rowsplit(Dblk + (c0 + kPanel) + (long long)c0 * b, b, c.zD,
+                                Rows + (long long)c0 * ldT, ldT, c.zLBC, rest);
       g.ph[0].B = view_plain(Dblk + (c0 + kPanel) + (long long)c0 * b, b, c.zD, true);
       g.ph[0].K = g.ph[0].Klast = kPanel;
       g.ph[0].kmode = KR_FULL;
       g.ph[0].alpha = -1.0;
-      g.C = view_plain(Dblk + (c0 + kPanel) + (long long)(c0 + kPanel) * b, b, c.zD);
-      g.M = g.N = g.Mlast = g.Nlast = rest;
+      g.C = view_rowsplit(Dblk + (c0 + kPanel) + (long long)(c0 + kPanel) * b, b, c.zD,
+                          Rows + (long long)(c0 + kPanel) * ldT, ldT, c.zLBC, rest);
+      g.M = g.Mlast = rest + mT;
+      g.N = g.Nlast = rest;
       g.beta = 1.0;
-      g.omode = OUT_LOWER;
+      g.omode = OUT_LOWER;  // lower for the block's own rows, every column of the rows below
       g.tag = GT_TRAIL;
       g.zn = c.zn;
       g.step = i;
       if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
-  // 2. G_i = L_Di^-1 by recursive doubling over the 64 x 64 diagonal inverses
-  for (int sz = kPanel; sz < b; sz *= 2) {
-    const int P = (b - sz + 2 * sz - 1) / (2 * sz);
-    const int s2 = b - 2 * (P - 1) * sz - sz < sz ? b - 2 * (P - 1) * sz - sz : sz;
-    const long long ystep = 2LL * sz * (b + 1);
-    double* S = c.scratch;
-    {  // T = L21 * X11  (X11 lower)
-      GemmArgs g{};
-      g.nph = 1;
-      g.ph[0].A = view_plain(Dblk + sz, b, c.zD);
-      g.ph[0].B = view_plain(Gblk, b, c.zG);
-      g.ph[0].K = g.ph[0].Klast = sz;
-      g.ph[0].kmode = KR_GE_N0;
-      g.ph[0].triB = TRI_LOWER;
-      g.ph[0].alpha = 1.0;
-      view_set_y(g.ph[0].A, ystep);
-      view_set_y(g.ph[0].B, ystep);
-      g.C = view_plain(S + sz, b, c.zS);
-      view_set_y(g.C, ystep);
-      g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
-      g.beta = 0.0;
-      g.omode = OUT_ALL;
-      g.tag = GT_TRTRI;
-      g.zn = c.zn;
-      g.step = i;
-      if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
-    }
-    {  // X21 = -X22 * T  (X22 lower)
-      GemmArgs g{};
-      g.nph = 1;
-      g.ph[0].A = view_plain(Gblk + sz + (long long)sz * b, b, c.zG);
-      g.ph[0].B = view_plain(S + sz, b, c.zS);
-      g.ph[0].K = sz; g.ph[0].Klast = s2;
-      g.ph[0].kmode = KR_LT_M1;
-      g.ph[0].triA = TRI_LOWER;
-      g.ph[0].alpha = -1.0;
-      view_set_y(g.ph[0].A, ystep);
-      view_set_y(g.ph[0].B, ystep);
-      g.C = view_plain(Gblk + sz, b, c.zG);
-      view_set_y(g.C, ystep);
-      g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
-      g.beta = 0.0;
-      g.omode = OUT_ALL;
-      g.tag = GT_TRTRI;
-      g.zn = c.zn;
-      g.step = i;
-      if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  // 2. G_i = L_Di^-1 by recursive doubling over the 64 x 64 diagonal inverses (only when the
+  //    caller needs the inverse: solve and selected inversion)
+  if (c.invert) {
+    for (int sz = kPanel; sz < b; sz *= 2) {
+      const int P = (b - sz + 2 * sz - 1) / (2 * sz);
+      const int s2 = b - 2 * (P - 1) * sz - sz < sz ? b - 2 * (P - 1) * sz - sz : sz;
+      const long long ystep = 2LL * sz * (b + 1);
+      double* S = c.scratch;
+      {  // T = L21 * X11  (X11 lower)
+        GemmArgs g{};
+        g.nph = 1;
+        g.ph[0].A = view_plain(Dblk + sz, b, c.zD);
+        g.ph[0].B = view_plain(Gblk, b, c.zG);
+        g.ph[0].K = g.ph[0].Klast = sz;
+        g.ph[0].kmode = KR_GE_N0;
+        g.ph[0].triB = TRI_LOWER;
+        g.ph[0].alpha = 1.0;
+        view_set_y(g.ph[0].A, ystep);
+        view_set_y(g.ph[0].B, ystep);
+        g.C = view_plain(S + sz, b, c.zS);
+        view_set_y(g.C, ystep);
+        g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
+        g.beta = 0.0;
+        g.omode = OUT_ALL;
+        g.tag = GT_TRTRI;
+        g.zn = c.zn;
+        g.step = i;
+        if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
+      }
+      {  // X21 = -X22 * T  (X22 lower)
+        GemmArgs g{};
+        g.nph = 1;
+        g.ph[0].A = view_plain(Gblk + sz + (long long)sz * b, b, c.zG);
+        g.ph[0].B = view_plain(S + sz, b, c.zS);
+        g.ph[0].K = sz; g.ph[0].Klast = s2;
+        g.ph[0].kmode = KR_LT_M1;
+        g.ph[0].triA = TRI_LOWER;
+        g.ph[0].alpha = -1.0;
+        view_set_y(g.ph[0].A, ystep);
+        view_set_y(g.ph[0].B, ystep);
+        g.C = view_plain(Gblk + sz, b, c.zG);
+        view_set_y(g.C, ystep);
+        g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
+        g.beta = 0.0;
+        g.omode = OUT_ALL;
+        g.tag = GT_TRTRI;
+        g.zn = c.zn;
+        g.step = i;
+        if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
+      }
     }
   }
-  // 3. [L_B; L_C] = [B_i; C~_i] G_i^T
-  const bool hasB = i < n - 1;
-  double* Cblk = c.C + (long long)i * ap * b;
-  double* LCblk = c.LC + (long long)i * ap * b;
-  double* LBblk = hasB ? c.LB + blk_off(i, c.slotsLB, bb) : nullptr;
-  {
-    GemmArgs g{};
-    g.nph = 1;
-    if (hasB) {
-      const double* Bi = c.Bin + blk_off(i, c.slotsB, bb);
-      g.ph[0].A = view_rowsplit(const_cast<double*>(Bi), b, c.zB, Cblk, ap, c.zC, b);
-      g.C = view_rowsplit(LBblk, b, c.zLB, LCblk, ap, c.zLC, b);
-      g.M = g.Mlast = b + ap;
-    } else {
-      g.ph[0].A = view_plain(Cblk, ap, c.zC);
-      g.C = view_plain(LCblk, ap, c.zLC);
-      g.M = g.Mlast = ap;
-    }
-    g.ph[0].B = view_plain(Gblk, b, c.zG, true);
-    g.ph[0].K = g.ph[0].Klast = b;
-    g.ph[0].kmode = KR_LT_N1;
-    g.ph[0].triB = TRI_UPPER;
-    g.ph[0].alpha = 1.0;
-    g.N = g.Nlast = b;
-    g.beta = 0.0;
-    g.omode = OUT_ALL;
-    g.tag = GT_TRMM;
-    g.zn = c.zn;
-    g.step = i;
-    if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
-  }
-  // 4. Schur update of the next diagonal block, next arrow block and the tip
-  {
+  // 3. Schur update of the next diagonal block, next arrow block and the tip
+  if (hasB || ap > 0) {
     GemmArgs g{};
     g.nph = 1;
     g.ph[0].alpha = -1.0;
@@ -143,27 +134,24 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
     g.ph[0].kmode = KR_FULL;
     g.beta = 1.0;
     g.omode = OUT_LOWER;
+    g.ph[0].A = view_plain(Rows, ldT, c.zLBC);
+    g.ph[0].B = view_plain(Rows, ldT, c.zLBC, true);
     if (hasB) {
       double* Dn = c.D + blk_off(i + 1, c.slotsD, bb);
       double* Cn = c.C + (long long)(i + 1) * ap * b;
-      g.ph[0].A = view_rowsplit(LBblk, b, c.zLB, LCblk, ap, c.zLC, b);
-      g.ph[0].B = view_rowsplit(LBblk, b, c.zLB, LCblk, ap, c.zLC, b, true);
       View v = view_plain(Dn, b, c.zD);
       v.rs = b; v.cs = b;
       v.p[1] = Cn; v.sr[1] = 1; v.sc[1] = ap; v.zs[1] = c.zC;
       v.p[3] = c.T; v.sr[3] = 1; v.sc[3] = ap; v.zs[3] = c.zT;
       g.C = v;
-      g.M = g.N = g.Mlast = g.Nlast = b + ap;
     } else {
-      g.ph[0].A = view_plain(LCblk, ap, c.zLC);
-      g.ph[0].B = view_plain(LCblk, ap, c.zLC, true);
       g.C = view_plain(c.T, ap, c.zT);
-      g.M = g.N = g.Mlast = g.Nlast = ap;
     }
+    g.M = g.N = g.Mlast = g.Nlast = mT;
     g.tag = GT_SYRK;
     g.zn = c.zn;
     g.step = i;
-    if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;
 }
@@ -193,13 +181,13 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
   const int b = c.b, a = c.a, n = c.n, nz = c.nz;
   const long long bb = (long long)b * b;
   const double* Gj = c.G + blk_off(j, c.slotsG, bb);
-  const double* LCj = c.LC + (long long)j * c.ldLC * b;
+  const double* LCj = c.LC + (long long)j * c.sLC;
   double* Wm = c.W;
   double* V = c.W + bb;
   double* ZDj = c.ZD + blk_off(j, c.slotsZD, bb);
   double* ZCj = a ? c.ZC + blk_off(j, c.slotsZC, (long long)a * b) : nullptr;
   const bool last = (j == n - 1);
-  const double* LBj = last ? nullptr : c.LB + blk_off(j, c.slotsLB, bb);
+  const double* LBj = last ? nullptr : c.LB + blk_off(j, c.slotsLB, c.sLB);
   double* ZBj = last ? nullptr : c.ZB + blk_off(j, c.slotsZB, bb);
   double* ZDn = last ? nullptr : c.ZD + blk_off(j + 1, c.slotsZD, bb);
   double* ZCn = (last || !a) ? nullptr : c.ZC + blk_off(j + 1, c.slotsZC, (long long)a * b);
@@ -209,7 +197,7 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     GemmArgs g{};
     g.nph = 1;
     if (!last) {
-      g.ph[0].A = view_rowsplit(const_cast<double*>(LBj), b, c.zLB, const_cast<double*>(LCj),
+      g.ph[0].A = view_rowsplit(const_cast<double*>(LBj), c.ldLB, c.zLB, const_cast<double*>(LCj),
                                 c.ldLC, c.zLC, b);
       g.C = view_rowsplit(Wm, b, zW, V, a ? a : 1, zW, b);
       g.M = g.Mlast = b + a;
@@ -306,10 +294,10 @@ int bta_upper_solve(const SolveChains& c, hipStream_t s) {
   const int b = c.b, a = c.a, n = c.n, nz = c.nz;
   const long long bb = (long long)b * b;
   for (int i = n - 1; i >= 0; --i) {
-    const double* LCi = c.LC + (long long)i * c.ldLC * b;
+    const double* LCi = c.LC + (long long)i * c.sLC;
     GemvT g{};
     if (i < n - 1) {
-      g.A = c.LB + blk_off(i, c.slotsLB, bb); g.ld = b; g.zA = c.zLB;
+      g.A = c.LB + blk_off(i, c.slotsLB, c.sLB); g.ld = c.ldLB; g.zA = c.zLB;
       g.x = c.x + (long long)(i + 1) * b; g.zx = c.zx; g.incx = 1;
       g.alpha = -1.0;
     }

@@ -89,12 +89,14 @@ int launch_zero_upper(double* p, int b, long long ld, long long blockstride, int
 struct BtaChains {
   int n, b, a, ap, nz;
   double* D; long long zD; int slotsD;      // in: D_t (lower) ; out: L_Dt
-  const double* Bin; long long zB; int slotsB; long long ldB_block;  // B_t, ld b
-  double* LB; long long zLB; int slotsLB;   // out: L_Bt
+  const double* Bin; long long zB; int slotsB;  // B_t, ld b
   double* C; long long zC;                  // n blocks ap x b (ld ap): in C_t|r_t, updated in place
-  double* LC; long long zLC;                // n blocks ap x b (ld ap): out L_Ct | z_t
+  // (b+ap) x b blocks, ld b+ap: out [L_Bt; L_Ct | z_t] (the rows solved with the panels of
+  // L_Dt); for the last block only rows b.. are used
+  double* LBC; long long zLBC; int slotsLBC;
   double* T; long long zT;                  // ap x ap (ld ap): in T|r_T, out L_T | z_T
-  double* G; long long zG; int slotsG;      // out: L_Dt^-1
+  double* G; long long zG; int slotsG;      // out: the 64 x 64 diagonal tiles of L_Dt^-1, and
+  bool invert;                              //   all of L_Dt^-1 when invert is set
   double* ldpart; long long zLd;            // logdet partials, n*npanel + 1 per chain
   int32_t* info;                            // per chain (stride 1)
   int32_t* cnt;                             // per chain (stride 1), zero: panel write-back counters
@@ -113,8 +115,8 @@ int bta_logdet_reduce(const double* ldpart, long long zLd, int nparts, double* o
 struct SelinvChains {
   int n, b, a, nz;
   const double* G; long long zG; int slotsG;
-  const double* LB; long long zLB; int slotsLB;
-  const double* LC; long long zLC; int ldLC;     // LC blocks, ld ldLC (>= a), first a rows
+  const double* LB; long long zLB; int slotsLB; int ldLB; long long sLB;  // block t at slot t % slotsLB, slot stride sLB
+  const double* LC; long long zLC; int ldLC; long long sLC;  // block t at LC + t*sLC, ld ldLC, first a rows
   const double* ZT; long long zZT;               // a x a (ld a)
   double* ZD; long long zZD; int slotsZD;        // b x b blocks (full symmetric)
   double* ZB; long long zZB; int slotsZB;
@@ -128,8 +130,8 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s);
 struct SolveChains {
   int n, b, a, nz;
   const double* G; long long zG; int slotsG;
-  const double* LB; long long zLB; int slotsLB;
-  const double* LC; long long zLC; int ldLC;
+  const double* LB; long long zLB; int slotsLB; int ldLB; long long sLB;
+  const double* LC; long long zLC; int ldLC; long long sLC;
   const double* z; long long zz; long long sz_blk; long long sz_elem;  // z_t element at z + t*sz_blk + r*sz_elem
   const double* xT; long long zxT;               // a
   double* x; long long zx;                        // length n*b + a (contiguous)

@@ -291,13 +291,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     ti = L % tilesM;
     tj = L / tilesM;
   } else {
-    const int T = tilesM * (tilesM + 1) / 2;
+    // lower trapezoid (M >= N): the triangle of the top tilesN x tilesN tiles, then full rows
+    const int T0 = tilesN * (tilesN + 1) / 2;
+    const int T = T0 + (tilesM - tilesN) * tilesN;
     if ((int)blockIdx.x >= T) return;
     const int L = (int)gridDim.x == T ? xcd_remap(blockIdx.x, T) : blockIdx.x;
-    ti = (int)((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
-    while (ti * (ti + 1) / 2 > L) --ti;
-    while ((ti + 1) * (ti + 2) / 2 <= L) ++ti;
-    tj = L - ti * (ti + 1) / 2;
+    if (L < T0) {
+      ti = (int)((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
+      while (ti * (ti + 1) / 2 > L) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= L) ++ti;
+      tj = L - ti * (ti + 1) / 2;
+    } else {
+      ti = tilesN + (L - T0) / tilesN;
+      tj = (L - T0) % tilesN;
+    }
   }
   const int m0 = ti * BM, n0 = tj * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -458,8 +465,10 @@ int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s) {
   if (a.omode == OUT_ALL) {
     gx = (long long)tM * tN;
   } else {
-    if (a.M != a.N || a.Mlast != a.Nlast) return -1;
-    gx = (long long)tM * (tM + 1) / 2;
+    // lower part of an M x N output with M >= N (a trapezoid when M > N)
+    if (a.M < a.N || a.Mlast < a.Nlast) return -1;
+    if ((a.Mlast + BM - 1) / BM > tM || (a.Nlast + BN - 1) / BN > tN) return -1;
+    gx = (long long)tN * (tN + 1) / 2 + (long long)(tM - tN) * tN;
   }
   if (gx <= 0) return 0;
   if (gx > INT_MAX) return -1;

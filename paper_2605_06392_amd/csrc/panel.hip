@@ -35,6 +35,10 @@ struct PanelArgs {
   int step;
   int b, c0;
   long long gcol0;
+  // rows below the block solved with the same panel (Alg. 1: [B_i; C_i] against L_Di^T):
+  // mT rows of T (ld ldT, chain stride zT), nullptr when none
+  double* T; long long zT;
+  int ldT, mT;
 };
 
 // Orders the LDS traffic of one wavefront: the LDS unit serves a wave's operations in issue
@@ -227,8 +231,14 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   // Every global read of the workgroup is issued here, back to back (addresses clamped into the
   // tiles, values masked on use): the diagonal tile, and for workgroup x > 0 its 64-row tile of
   // the panel, which stays in registers while the diagonal tile is factored.
-  const int r0 = c0 + NB * blockIdx.x;
-  const int h = blockIdx.x > 0 ? min(NB, b - r0) : 1;
+  // workgroup x > 0 owns a 64-row tile: first the block's own rows below the diagonal tile,
+  // then the rows of T
+  const int nd = (b - c0 + NB - 1) / NB;  // diagonal tile + block rows
+  const bool tall = (int)blockIdx.x >= nd;
+  double* R = tall ? P.T + (long long)z * P.zT : D;
+  const long long ldR = tall ? P.ldT : b;
+  const int r0 = tall ? NB * ((int)blockIdx.x - nd) : c0 + NB * blockIdx.x;
+  const int h = blockIdx.x > 0 ? min(NB, (tall ? P.mT : b) - r0) : 1;
   double dv[NB * NB / 256], rv[NB * NB / 256];
 #pragma unroll
   for (int i = 0; i < NB * NB / 256; ++i) {
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
 #pragma unroll
     for (int i = 0; i < NB * NB / 256; ++i) {
       const int e = tid + 256 * i, m = e & 63, k = e >> 6;
-      rv[i] = D[(long long)(r0 + min(m, h - 1)) + (long long)(c0 + min(k, w - 1)) * b];
+      rv[i] = R[(long long)(r0 + min(m, h - 1)) + (long long)(c0 + min(k, w - 1)) * ldR];
     }
   }
   // diagonal tile (lower) with identity padding past w
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
       for (int v = 0; v < 4; ++v) {
         const int m = wm + bi * 16 + (lane & 15);
         const int n = wn + bj * 16 + (lane >> 4) + 4 * v;
-        if (m < h && n < w) D[(long long)(r0 + m) + (long long)(c0 + n) * b] = acc[bi][bj][v];
+        if (m < h && n < w) R[(long long)(r0 + m) + (long long)(c0 + n) * ldR] = acc[bi][bj][v];
       }
 }
 
@@ -352,15 +362,18 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
 
 int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,
                        long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
-                       int b, int c0, long long gcol0, int nz, hipStream_t s) {
+                       int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
+                       int nz, hipStream_t s) {
   if (!cnt) return -1;
-  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0};
-  const int rows = (b - c0 + NB - 1) / NB;
+  if (!T) mT = 0;
+  if (mT < 0 || (mT > 0 && ldT < mT)) return -1;
+  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT, ldT, mT};
+  const int rows = (b - c0 + NB - 1) / NB + (mT + NB - 1) / NB;
   const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(potrf_panel_kernel, dim3(rows, 1, nz), dim3(256), 0, s, P);
   if (t.valid) {
     const double ww = (b - c0) < NB ? (b - c0) : NB;
-    const double below = (double)(b - c0) - ww;
+    const double below = (double)(b - c0) - ww + mT;
     prof_end(t, s, PK_PANEL, nz * (ww * ww * ww / 3.0 + below * ww * ww), 0.0);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
