@@ -155,6 +155,11 @@ int bta_selinv(adelia_ctx ctx, adelia_bta_shape shape, const double* Dinv, const
  * The model is given by HOST arrays; inla_model_create validates every index, builds the
  * per-column observation lists and the union pattern of the spatial base matrices (integer
  * work), and copies everything to device memory it owns until inla_model_destroy.
+ * A model also owns a second stream (default priority): the forward sweep of a gradient
+ * (inla_grad, inla_grad_terms, inla_objective with ADELIA_SAVE_FACTORS) forms the block
+ * inverses L_Di^-1 there while the sweep continues on the caller's stream; events order the
+ * two, so the call behaves as one stream-ordered operation on the caller's stream (and can be
+ * captured into a graph).  Calls on one model must come from one host thread at a time.
  * --------------------------------------------------------------------------------------- */
 #define ADELIA_PARAM_UNIVARIATE 1 /* theta = [log scale, range, temporal, log tau], k == 1 */
 #define ADELIA_PARAM_COREG 2      /* theta = [range(k), temporal(k), prec(k),

@@ -20,11 +20,22 @@
 
 using namespace adelia;
 
+// A second stream per model forms the block inverses L_Di^-1 of a gradient's forward sweep
+// while the sweep goes on with the next blocks (the inverses are needed only by the backward
+// pass).  Events order it against the caller's stream; the ring of three D slots in gradient
+// workspaces gives each inversion one block step of slack.
+struct SideRes {
+  hipStream_t s2;
+  hipEvent_t ready[3], done[3];
+};
+
 struct inla_model_s {
   int device;
   int param;
   ModelDev M;
   void* dev_mem;
+  SideRes side;
+  bool has_side;
 };
 
 namespace {
@@ -54,7 +65,7 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
   w.grad = grad;
   const long long bb = (long long)M.b * M.b;
   const int n = M.nt;
-  w.slotsD = 2;
+  w.slotsD = grad ? 3 : 2;
   w.slotsB = 1;
   w.slotsLBC = grad ? n : 1;
   w.slotsG = grad ? n : 1;
@@ -142,7 +153,8 @@ BtaChains chains_of(const InlaWs& w) {
 #define LAUNCH_OK() (hipGetLastError() == hipSuccess)
 
 // Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
-int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStream_t s) {
+int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStream_t s,
+                const SideRes* side) {
   const int nz = w.nz, n = w.n, b = w.b;
   hipLaunchKernelGGL(param_kernel, dim3(w.batch), dim3(256), 0, s, M, theta, w.phi, w.dphi,
                      w.tau);
@@ -158,9 +170,14 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
   const long long bb = (long long)b * b;
   const dim3 agrid(b, 1, nz);
   BtaChains c = chains_of(w);
+  const bool fork = c.invert && side && w.slotsD == 3;
+  if (fork) c.invert = false;
   hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, 0, -1, w.D, w.zD,
                      w.Bin, w.zB, w.phi, w.tau);
   for (int i = 0; i < n; ++i) {
+    // the slot about to receive D_{i+1} held D_{i-2}: its inverse must be complete
+    if (fork && i >= 2 && hipStreamWaitEvent(s, side->done[(i - 2) % 3], 0) != hipSuccess)
+      return ADELIA_E_HIP;
     const int td = i + 1 < n ? i + 1 : -1;
     const int tb = i < n - 1 ? i : -1;
     if (td >= 0 || tb >= 0) {
@@ -172,15 +189,25 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
       if (!LAUNCH_OK()) return ADELIA_E_HIP;
     }
     if (bta_forward_block(c, i, s)) return ADELIA_E_HIP;
+    if (fork) {
+      if (hipEventRecord(side->ready[i % 3], s) != hipSuccess ||
+          hipStreamWaitEvent(side->s2, side->ready[i % 3], 0) != hipSuccess)
+        return ADELIA_E_HIP;
+      if (bta_invert_block(c, i, side->s2)) return ADELIA_E_HIP;
+      if (hipEventRecord(side->done[i % 3], side->s2) != hipSuccess) return ADELIA_E_HIP;
+    }
   }
+  // the side stream runs its inversions in order: waiting for the last joins all of them
+  if (fork && hipStreamWaitEvent(s, side->done[(n - 1) % 3], 0) != hipSuccess)
+    return ADELIA_E_HIP;
   if (bta_tip(c, s)) return ADELIA_E_HIP;
   if (bta_logdet_reduce(w.ldpart, w.zLd, n * w.npanel + 1, w.ld, 1, nz, s)) return ADELIA_E_HIP;
   return 0;
 }
 
 int run_objective(const ModelDev& M, const InlaWs& w, const double* theta, double* f,
-                  int32_t* info, hipStream_t s) {
-  int r = run_forward(M, w, theta, s);
+                  int32_t* info, hipStream_t s, const SideRes* side = nullptr) {
+  int r = run_forward(M, w, theta, s, side);
   if (r) return r;
   hipLaunchKernelGGL(objective_kernel, dim3((w.batch + 63) / 64), dim3(64), 0, s, M, theta,
                      w.batch, w.tau, w.ld, w.zsq, w.info, f, info);
@@ -440,12 +467,24 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
     delete m;
     return ADELIA_E_HIP;
   }
+  m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess;
+  for (int e = 0; e < 3 && m->has_side; ++e)
+    m->has_side = hipEventCreateWithFlags(&m->side.ready[e], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&m->side.done[e], hipEventDisableTiming) == hipSuccess;
   *out = m;
   return 0;
 }
 
 int inla_model_destroy(inla_model m) {
   if (!m) return 0;
+  if (m->has_side) {
+    hipStreamSynchronize(m->side.s2);
+    for (int e = 0; e < 3; ++e) {
+      hipEventDestroy(m->side.ready[e]);
+      hipEventDestroy(m->side.done[e]);
+    }
+    hipStreamDestroy(m->side.s2);
+  }
   hipFree(m->dev_mem);
   delete m;
   return 0;
@@ -472,7 +511,8 @@ int inla_objective(inla_model m, const double* theta, int32_t batch, double* f, 
   if (save && batch != 1) return -3;
   InlaWs w = layout(m->M, batch, save, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
-  return run_objective(m->M, w, theta, f, info, (hipStream_t)stream);
+  return run_objective(m->M, w, theta, f, info, (hipStream_t)stream,
+                       m->has_side ? &m->side : nullptr);
 }
 
 int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_t* info, void* ws,
@@ -488,7 +528,7 @@ int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (!(flags & ADELIA_REUSE_FACTORS)) {
-    int r = run_forward(m->M, w, theta, s);
+    int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
   return run_backward(m->M, w, theta, f, grad, info, nullptr, s);
@@ -506,7 +546,7 @@ int inla_grad_terms(inla_model m, const double* theta, double* terms, int32_t* i
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (!(flags & ADELIA_REUSE_FACTORS)) {
-    int r = run_forward(m->M, w, theta, s);
+    int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
   const int d = m->M.d;

@@ -25,6 +25,65 @@ namespace adelia {
 
 static inline long long blk_off(int t, int slots, long long bb) { return (long long)(t % slots) * bb; }
 
+// G_i = L_Di^-1 by recursive doubling over the 64 x 64 diagonal inverses left by the panels:
+// X21 = -X22 (L21 X11), two GEMMs per level.  Reads block i's L_Di and G_i slots and the
+// scratch; may run on another stream than the sweep once block i's panels are done.
+int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
+  const int b = c.b, nz = c.nz;
+  const long long bb = (long long)b * b;
+  double* Dblk = c.D + blk_off(i, c.slotsD, bb);
+  double* Gblk = c.G + blk_off(i, c.slotsG, bb);
+  for (int sz = kPanel; sz < b; sz *= 2) {
+    const int P = (b - sz + 2 * sz - 1) / (2 * sz);
+    const int s2 = b - 2 * (P - 1) * sz - sz < sz ? b - 2 * (P - 1) * sz - sz : sz;
+    const long long ystep = 2LL * sz * (b + 1);
+    double* S = c.scratch;
+    {  // T = L21 * X11  (X11 lower)
+      GemmArgs g{};
+      g.nph = 1;
+      g.ph[0].A = view_plain(Dblk + sz, b, c.zD);
+      g.ph[0].B = view_plain(Gblk, b, c.zG);
+      g.ph[0].K = g.ph[0].Klast = sz;
+      g.ph[0].kmode = KR_GE_N0;
+      g.ph[0].triB = TRI_LOWER;
+      g.ph[0].alpha = 1.0;
+      view_set_y(g.ph[0].A, ystep);
+      view_set_y(g.ph[0].B, ystep);
+      g.C = view_plain(S + sz, b, c.zS);
+      view_set_y(g.C, ystep);
+      g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
+      g.beta = 0.0;
+      g.omode = OUT_ALL;
+      g.tag = GT_TRTRI;
+      g.zn = c.zn;
+      g.step = i;
+      if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    }
+    {  // X21 = -X22 * T  (X22 lower)
+      GemmArgs g{};
+      g.nph = 1;
+      g.ph[0].A = view_plain(Gblk + sz + (long long)sz * b, b, c.zG);
+      g.ph[0].B = view_plain(S + sz, b, c.zS);
+      g.ph[0].K = sz; g.ph[0].Klast = s2;
+      g.ph[0].kmode = KR_LT_M1;
+      g.ph[0].triA = TRI_LOWER;
+      g.ph[0].alpha = -1.0;
+      view_set_y(g.ph[0].A, ystep);
+      view_set_y(g.ph[0].B, ystep);
+      g.C = view_plain(Gblk + sz, b, c.zG);
+      view_set_y(g.C, ystep);
+      g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
+      g.beta = 0.0;
+      g.omode = OUT_ALL;
+      g.tag = GT_TRTRI;
+      g.zn = c.zn;
+      g.step = i;
+      if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    }
+  }
+  return 0;
+}
+
 int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
   const int b = c.b, ap = c.ap, n = c.n, nz = c.nz;
   const long long bb = (long long)b * b;
@@ -73,57 +132,10 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
       if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
-  // 2. G_i = L_Di^-1 by recursive doubling over the 64 x 64 diagonal inverses (only when the
-  //    caller needs the inverse: solve and selected inversion)
+  // 2. the full inverse, when the caller needs it inline
   if (c.invert) {
-    for (int sz = kPanel; sz < b; sz *= 2) {
-      const int P = (b - sz + 2 * sz - 1) / (2 * sz);
-      const int s2 = b - 2 * (P - 1) * sz - sz < sz ? b - 2 * (P - 1) * sz - sz : sz;
-      const long long ystep = 2LL * sz * (b + 1);
-      double* S = c.scratch;
-      {  // T = L21 * X11  (X11 lower)
-        GemmArgs g{};
-        g.nph = 1;
-        g.ph[0].A = view_plain(Dblk + sz, b, c.zD);
-        g.ph[0].B = view_plain(Gblk, b, c.zG);
-        g.ph[0].K = g.ph[0].Klast = sz;
-        g.ph[0].kmode = KR_GE_N0;
-        g.ph[0].triB = TRI_LOWER;
-        g.ph[0].alpha = 1.0;
-        view_set_y(g.ph[0].A, ystep);
-        view_set_y(g.ph[0].B, ystep);
-        g.C = view_plain(S + sz, b, c.zS);
-        view_set_y(g.C, ystep);
-        g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
-        g.beta = 0.0;
-        g.omode = OUT_ALL;
-        g.tag = GT_TRTRI;
-        g.zn = c.zn;
-        g.step = i;
-        if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
-      }
-      {  // X21 = -X22 * T  (X22 lower)
-        GemmArgs g{};
-        g.nph = 1;
-        g.ph[0].A = view_plain(Gblk + sz + (long long)sz * b, b, c.zG);
-        g.ph[0].B = view_plain(S + sz, b, c.zS);
-        g.ph[0].K = sz; g.ph[0].Klast = s2;
-        g.ph[0].kmode = KR_LT_M1;
-        g.ph[0].triA = TRI_LOWER;
-        g.ph[0].alpha = -1.0;
-        view_set_y(g.ph[0].A, ystep);
-        view_set_y(g.ph[0].B, ystep);
-        g.C = view_plain(Gblk + sz, b, c.zG);
-        view_set_y(g.C, ystep);
-        g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
-        g.beta = 0.0;
-        g.omode = OUT_ALL;
-        g.tag = GT_TRTRI;
-        g.zn = c.zn;
-        g.step = i;
-        if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
-      }
-    }
+    const int r = bta_invert_block(c, i, s);
+    if (r) return r;
   }
   // 3. Schur update of the next diagonal block, next arrow block and the tip
   if (hasB || ap > 0) {

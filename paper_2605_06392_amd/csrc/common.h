@@ -108,6 +108,7 @@ struct BtaChains {
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
 int bta_forward_block(const BtaChains& c, int i, hipStream_t s);  // one block step
+int bta_invert_block(const BtaChains& c, int i, hipStream_t s);   // G_i = L_Di^-1 after step i
 int bta_tip(const BtaChains& c, hipStream_t s);
 int bta_logdet_reduce(const double* ldpart, long long zLd, int nparts, double* out, long long zout,
                       int nz, hipStream_t s);
