@@ -376,7 +376,7 @@ int bta_selinv(adelia_ctx ctx, adelia_bta_shape sh, const double* Dinv, const do
   c.ZD = ZD; c.zZD = 0; c.slotsZD = n;
   c.ZB = ZB; c.zZB = 0; c.slotsZB = n > 1 ? n - 1 : 1;
   c.ZC = ZC; c.zZC = 0; c.slotsZC = n;
-  c.W = reinterpret_cast<double*>(ws); c.zW = 0;
+  c.W = reinterpret_cast<double*>(ws); c.zW = 0; c.slotsW = 1;
   for (int j = n - 1; j >= 0; --j)
     if (selinv_block(c, j, s)) return ADELIA_E_HIP;
   return 0;

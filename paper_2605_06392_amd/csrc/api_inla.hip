@@ -113,8 +113,10 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
     const long long Nlat = (long long)n * M.b + M.a;
     w.x = take(Nlat, nz, w.zx);
     w.y = take(M.b, nz, w.zy);
-    w.W = take(bb + (long long)M.a * M.b, nz, w.zW);
-    w.ZD = take(2 * bb, nz, w.zZD);
+    // [W_t; V_t] and G_t^T G_t (the Z-independent parts of the selected inversion) are formed
+    // during the forward sweep, so they get a slot per block
+    w.W = take((long long)n * (bb + (long long)M.a * M.b), nz, w.zW);
+    w.ZD = take((long long)n * bb, nz, w.zZD);
     w.ZB = take(bb, nz, w.zZB);
     w.ZC = take(std::max(1LL, 2LL * M.a * M.b), nz, w.zZC);
     w.TD = take((long long)n * 3 * M.k * M.k, nz, w.zTr);
@@ -153,6 +155,22 @@ BtaChains chains_of(const InlaWs& w) {
 #define LAUNCH_OK() (hipGetLastError() == hipSuccess)
 
 // Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
+SelinvChains selinv_of(const InlaWs& w) {
+  const int b = w.b, ap = w.ap;
+  const long long sLBC = (long long)(b + ap) * b;
+  SelinvChains si{};
+  si.n = w.n; si.b = b; si.a = w.a; si.nz = w.nz;
+  si.G = w.G; si.zG = w.zG; si.slotsG = w.slotsG;
+  si.LB = w.LBC; si.zLB = w.zLBC; si.slotsLB = w.slotsLBC; si.ldLB = b + ap; si.sLB = sLBC;
+  si.LC = w.LBC + b; si.zLC = w.zLBC; si.ldLC = b + ap; si.sLC = sLBC;
+  si.ZT = w.ZT; si.zZT = w.zZT;
+  si.ZD = w.ZD; si.zZD = w.zZD; si.slotsZD = w.n;
+  si.ZB = w.ZB; si.zZB = w.zZB; si.slotsZB = 1;
+  si.ZC = w.ZC; si.zZC = w.zZC; si.slotsZC = 2;
+  si.W = w.W; si.zW = w.zW; si.slotsW = w.n;
+  return si;
+}
+
 int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStream_t s,
                 const SideRes* side) {
   const int nz = w.nz, n = w.n, b = w.b;
@@ -170,6 +188,7 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
   const long long bb = (long long)b * b;
   const dim3 agrid(b, 1, nz);
   BtaChains c = chains_of(w);
+  const SelinvChains si = selinv_of(w);
   const bool fork = c.invert && side && w.slotsD == 3;
   if (fork) c.invert = false;
   hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, 0, -1, w.D, w.zD,
@@ -195,10 +214,14 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
         return ADELIA_E_HIP;
       if (bta_invert_block(c, i, side->s2)) return ADELIA_E_HIP;
       if (hipEventRecord(side->done[i % 3], side->s2) != hipSuccess) return ADELIA_E_HIP;
+      if (selinv_prepare(si, i, side->s2)) return ADELIA_E_HIP;
+    } else if (w.grad) {
+      if (selinv_prepare(si, i, s)) return ADELIA_E_HIP;
     }
   }
-  // the side stream runs its inversions in order: waiting for the last joins all of them
-  if (fork && hipStreamWaitEvent(s, side->done[(n - 1) % 3], 0) != hipSuccess)
+  // the side stream runs its work in order: an event after its last product joins all of it
+  if (fork && (hipEventRecord(side->done[n % 3], side->s2) != hipSuccess ||
+               hipStreamWaitEvent(s, side->done[n % 3], 0) != hipSuccess))
     return ADELIA_E_HIP;
   if (bta_tip(c, s)) return ADELIA_E_HIP;
   if (bta_logdet_reduce(w.ldpart, w.zLd, n * w.npanel + 1, w.ld, 1, nz, s)) return ADELIA_E_HIP;
@@ -229,22 +252,14 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   sc.x = w.x; sc.zx = w.zx;
   sc.y = w.y; sc.zy = w.zy;
   if (bta_upper_solve(sc, s)) return ADELIA_E_HIP;
-  // selected inversion of Qc and Qp with the trace epilogue per block (Eq. 6)
-  SelinvChains si{};
-  si.n = n; si.b = b; si.a = a; si.nz = nz;
-  si.G = w.G; si.zG = w.zG; si.slotsG = w.slotsG;
-  si.LB = w.LBC; si.zLB = w.zLBC; si.slotsLB = w.slotsLBC; si.ldLB = b + ap; si.sLB = sLBC;
-  si.LC = w.LBC + b; si.zLC = w.zLBC; si.ldLC = b + ap; si.sLC = sLBC;
-  si.ZT = w.ZT; si.zZT = w.zZT;
-  si.ZD = w.ZD; si.zZD = w.zZD; si.slotsZD = 2;
-  si.ZB = w.ZB; si.zZB = w.zZB; si.slotsZB = 1;
-  si.ZC = w.ZC; si.zZC = w.zZC; si.slotsZC = 2;
-  si.W = w.W; si.zW = w.zW;
+  // selected inversion of Qc and Qp with the trace epilogue per block (Eq. 6); the forward
+  // sweep already formed [W_j; V_j] and G_j^T G_j
+  const SelinvChains si = selinv_of(w);
   const long long bb = (long long)b * b;
   const int ntrace = 2 * M.k * M.k + M.k;
   for (int j = n - 1; j >= 0; --j) {
-    if (selinv_block(si, j, s)) return ADELIA_E_HIP;
-    const double* ZDj = w.ZD + (long long)(j % 2) * bb;
+    if (selinv_finish(si, j, s)) return ADELIA_E_HIP;
+    const double* ZDj = w.ZD + (long long)j * bb;
     const double* ZCj = w.ZC + (long long)(j % 2) * a * b;
     const ProfToken t = prof_begin(s);
     hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, s, M, j, ZDj, w.zZD,

@@ -189,36 +189,51 @@ int bta_forward(const BtaChains& c, hipStream_t s) {
   return bta_tip(c, s);
 }
 
-int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
-  const int b = c.b, a = c.a, n = c.n, nz = c.nz;
+struct SelinvPtrs {
+  const double* Gj;
+  const double* LCj;
+  const double* LBj;
+  double *Wm, *V, *ZDj, *ZCj, *ZBj, *ZDn, *ZCn;
+  bool last;
+};
+
+static SelinvPtrs selinv_ptrs(const SelinvChains& c, int j) {
+  const int b = c.b, a = c.a, n = c.n;
   const long long bb = (long long)b * b;
-  const double* Gj = c.G + blk_off(j, c.slotsG, bb);
-  const double* LCj = c.LC + (long long)j * c.sLC;
-  double* Wm = c.W;
-  double* V = c.W + bb;
-  double* ZDj = c.ZD + blk_off(j, c.slotsZD, bb);
-  double* ZCj = a ? c.ZC + blk_off(j, c.slotsZC, (long long)a * b) : nullptr;
-  const bool last = (j == n - 1);
-  const double* LBj = last ? nullptr : c.LB + blk_off(j, c.slotsLB, c.sLB);
-  double* ZBj = last ? nullptr : c.ZB + blk_off(j, c.slotsZB, bb);
-  double* ZDn = last ? nullptr : c.ZD + blk_off(j + 1, c.slotsZD, bb);
-  double* ZCn = (last || !a) ? nullptr : c.ZC + blk_off(j + 1, c.slotsZC, (long long)a * b);
+  SelinvPtrs p;
+  p.Gj = c.G + blk_off(j, c.slotsG, bb);
+  p.LCj = c.LC + (long long)j * c.sLC;
+  p.Wm = c.W + blk_off(j, c.slotsW, bb + (long long)a * b);
+  p.V = p.Wm + bb;
+  p.ZDj = c.ZD + blk_off(j, c.slotsZD, bb);
+  p.ZCj = a ? c.ZC + blk_off(j, c.slotsZC, (long long)a * b) : nullptr;
+  p.last = (j == n - 1);
+  p.LBj = p.last ? nullptr : c.LB + blk_off(j, c.slotsLB, c.sLB);
+  p.ZBj = p.last ? nullptr : c.ZB + blk_off(j, c.slotsZB, bb);
+  p.ZDn = p.last ? nullptr : c.ZD + blk_off(j + 1, c.slotsZD, bb);
+  p.ZCn = (p.last || !a) ? nullptr : c.ZC + blk_off(j + 1, c.slotsZC, (long long)a * b);
+  return p;
+}
+
+int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
+  const int b = c.b, a = c.a, nz = c.nz;
+  const SelinvPtrs p = selinv_ptrs(c, j);
   const long long zW = c.zW;
   // S1: [W; V] = [L_Bj; L_Cj] G_j
   {
     GemmArgs g{};
     g.nph = 1;
-    if (!last) {
-      g.ph[0].A = view_rowsplit(const_cast<double*>(LBj), c.ldLB, c.zLB, const_cast<double*>(LCj),
-                                c.ldLC, c.zLC, b);
-      g.C = view_rowsplit(Wm, b, zW, V, a ? a : 1, zW, b);
+    if (!p.last) {
+      g.ph[0].A = view_rowsplit(const_cast<double*>(p.LBj), c.ldLB, c.zLB,
+                                const_cast<double*>(p.LCj), c.ldLC, c.zLC, b);
+      g.C = view_rowsplit(p.Wm, b, zW, p.V, a ? a : 1, zW, b);
       g.M = g.Mlast = b + a;
     } else {
-      g.ph[0].A = view_plain(const_cast<double*>(LCj), c.ldLC, c.zLC);
-      g.C = view_plain(V, a ? a : 1, zW);
+      g.ph[0].A = view_plain(const_cast<double*>(p.LCj), c.ldLC, c.zLC);
+      g.C = view_plain(p.V, a ? a : 1, zW);
       g.M = g.Mlast = a;
     }
-    g.ph[0].B = view_plain(const_cast<double*>(Gj), b, c.zG);
+    g.ph[0].B = view_plain(const_cast<double*>(p.Gj), b, c.zG);
     g.ph[0].K = g.ph[0].Klast = b;
     g.ph[0].kmode = KR_GE_N0;
     g.ph[0].triB = TRI_LOWER;
@@ -229,23 +244,48 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     g.tag = GT_SI_W;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
-  // S2: [Z_Bj; Z_Cj] = -Zhat_{j+1} [W; V]
-  if (!last) {
+  // S3 (first term): lower triangle of Z_Dj = G_j^T G_j
+  {
     GemmArgs g{};
     g.nph = 1;
-    View A = view_plain(ZDn, b, c.zZD);
+    g.ph[0].A = view_plain(const_cast<double*>(p.Gj), b, c.zG, true);
+    g.ph[0].B = view_plain(const_cast<double*>(p.Gj), b, c.zG);
+    g.ph[0].K = g.ph[0].Klast = b;
+    g.ph[0].kmode = KR_GE_MAX;
+    g.ph[0].triA = TRI_UPPER;
+    g.ph[0].triB = TRI_LOWER;
+    g.ph[0].alpha = 1.0;
+    g.C = view_plain(p.ZDj, b, c.zZD);
+    g.M = g.N = g.Mlast = g.Nlast = b;
+    g.beta = 0.0;
+    g.omode = OUT_LOWER;
+    g.tag = GT_SI_D;
+    if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+  }
+  return 0;
+}
+
+int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
+  const int b = c.b, a = c.a, nz = c.nz;
+  const SelinvPtrs p = selinv_ptrs(c, j);
+  const long long zW = c.zW;
+  // S2: [Z_Bj; Z_Cj] = -Zhat_{j+1} [W; V]
+  if (!p.last) {
+    GemmArgs g{};
+    g.nph = 1;
+    View A = view_plain(p.ZDn, b, c.zZD);
     A.rs = b; A.cs = b;
     if (a) {
-      A.p[1] = ZCn; A.sr[1] = 1; A.sc[1] = a; A.zs[1] = c.zZC;          // Z_C(r-b, c)
-      A.p[2] = ZCn; A.sr[2] = a; A.sc[2] = 1; A.zs[2] = c.zZC;          // Z_C^T
+      A.p[1] = p.ZCn; A.sr[1] = 1; A.sc[1] = a; A.zs[1] = c.zZC;          // Z_C(r-b, c)
+      A.p[2] = p.ZCn; A.sr[2] = a; A.sc[2] = 1; A.zs[2] = c.zZC;          // Z_C^T
       A.p[3] = const_cast<double*>(c.ZT); A.sr[3] = 1; A.sc[3] = a; A.zs[3] = c.zZT;
     }
     g.ph[0].A = A;
-    g.ph[0].B = view_rowsplit(Wm, b, zW, V, a ? a : 1, zW, b);
+    g.ph[0].B = view_rowsplit(p.Wm, b, zW, p.V, a ? a : 1, zW, b);
     g.ph[0].K = g.ph[0].Klast = b + a;
     g.ph[0].kmode = KR_FULL;
     g.ph[0].alpha = -1.0;
-    g.C = view_rowsplit(ZBj, b, c.zZB, ZCj ? ZCj : ZBj, a ? a : 1, c.zZC, b);
+    g.C = view_rowsplit(p.ZBj, b, c.zZB, p.ZCj ? p.ZCj : p.ZBj, a ? a : 1, c.zZC, b);
     g.M = g.Mlast = b + a;
     g.N = g.Nlast = b;
     g.beta = 0.0;
@@ -256,11 +296,11 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     GemmArgs g{};
     g.nph = 1;
     g.ph[0].A = view_plain(const_cast<double*>(c.ZT), a, c.zZT);
-    g.ph[0].B = view_plain(V, a, zW);
+    g.ph[0].B = view_plain(p.V, a, zW);
     g.ph[0].K = g.ph[0].Klast = a;
     g.ph[0].kmode = KR_FULL;
     g.ph[0].alpha = -1.0;
-    g.C = view_plain(ZCj, a, c.zZC);
+    g.C = view_plain(p.ZCj, a, c.zZC);
     g.M = g.Mlast = a;
     g.N = g.Nlast = b;
     g.beta = 0.0;
@@ -268,33 +308,25 @@ int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
     g.tag = GT_SI_Z;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
-  // S3: Z_Dj = G^T G - [Z_Bj; Z_Cj]^T [W; V]  (lower, mirrored to a full symmetric block)
+  // S3: Z_Dj -= [Z_Bj; Z_Cj]^T [W; V] on the lower triangle holding G^T G, mirrored to a full
+  // symmetric block (the mirror is written even when there is nothing to subtract)
   {
     GemmArgs g{};
-    g.ph[0].A = view_plain(const_cast<double*>(Gj), b, c.zG, true);
-    g.ph[0].B = view_plain(const_cast<double*>(Gj), b, c.zG);
-    g.ph[0].K = g.ph[0].Klast = b;
-    g.ph[0].kmode = KR_GE_MAX;
-    g.ph[0].triA = TRI_UPPER;
-    g.ph[0].triB = TRI_LOWER;
-    g.ph[0].alpha = 1.0;
     g.nph = 1;
-    if (!last) {
-      g.ph[1].A = view_rowsplit(ZBj, b, c.zZB, ZCj ? ZCj : ZBj, a ? a : 1, c.zZC, b, true);
-      g.ph[1].B = view_rowsplit(Wm, b, zW, V, a ? a : 1, zW, b);
-      g.ph[1].K = g.ph[1].Klast = b + a;
-      g.nph = 2;
-    } else if (a) {
-      g.ph[1].A = view_plain(ZCj, a, c.zZC, true);
-      g.ph[1].B = view_plain(V, a, zW);
-      g.ph[1].K = g.ph[1].Klast = a;
-      g.nph = 2;
+    if (!p.last) {
+      g.ph[0].A = view_rowsplit(p.ZBj, b, c.zZB, p.ZCj ? p.ZCj : p.ZBj, a ? a : 1, c.zZC, b, true);
+      g.ph[0].B = view_rowsplit(p.Wm, b, zW, p.V, a ? a : 1, zW, b);
+      g.ph[0].K = g.ph[0].Klast = b + a;
+    } else {
+      g.ph[0].A = view_plain(p.ZCj ? p.ZCj : p.ZDj, a ? a : 1, c.zZC, true);
+      g.ph[0].B = view_plain(p.V, a ? a : 1, zW);
+      g.ph[0].K = g.ph[0].Klast = a;  // 0 when there is no arrow: only the mirror is written
     }
-    g.ph[1].kmode = KR_FULL;
-    g.ph[1].alpha = -1.0;
-    g.C = view_plain(ZDj, b, c.zZD);
+    g.ph[0].kmode = KR_FULL;
+    g.ph[0].alpha = -1.0;
+    g.C = view_plain(p.ZDj, b, c.zZD);
     g.M = g.N = g.Mlast = g.Nlast = b;
-    g.beta = 0.0;
+    g.beta = 1.0;
     g.omode = OUT_LOWER_MIRROR;
     g.tag = GT_SI_D;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;

@@ -122,10 +122,19 @@ struct SelinvChains {
   double* ZD; long long zZD; int slotsZD;        // b x b blocks (full symmetric)
   double* ZB; long long zZB; int slotsZB;
   double* ZC; long long zZC; int slotsZC;        // a x b (ld a)
-  double* W; long long zW;                       // scratch: b*b + a*b
+  double* W; long long zW; int slotsW;           // [W; V] of block t in slot t % slotsW, b*b + a*b each
 };
-// One backward step (block j, from n-1 down to 0).  Requires ZD/ZC of block j+1 present.
-int selinv_block(const SelinvChains& c, int j, hipStream_t s);
+// The parts of backward step j that do not depend on Z (they can run as soon as G_j exists):
+// [W_j; V_j] = [L_Bj; L_Cj] G_j, and Z_Dj's lower triangle set to G_j^T G_j.
+int selinv_prepare(const SelinvChains& c, int j, hipStream_t s);
+// The rest of backward step j (from n-1 down to 0), after selinv_prepare(j) and with Z_D/Z_C of
+// block j+1 present: [Z_Bj; Z_Cj] = -Zhat_{j+1} [W_j; V_j], Z_Dj -= [Z_Bj; Z_Cj]^T [W_j; V_j]
+// (mirrored to a full symmetric block).
+int selinv_finish(const SelinvChains& c, int j, hipStream_t s);
+inline int selinv_block(const SelinvChains& c, int j, hipStream_t s) {
+  const int r = selinv_prepare(c, j, s);
+  return r ? r : selinv_finish(c, j, s);
+}
 
 // Upper triangular solve x = L^-T z (Sec. III-A-2, Eqs. 3-5), all chains.
 struct SolveChains {
