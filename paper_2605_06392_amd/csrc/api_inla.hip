@@ -27,6 +27,7 @@ using namespace adelia;
 struct SideRes {
   hipStream_t s2;
   hipEvent_t ready[3], done[3];
+  Lookahead la;  // its own stream: trailing updates beside the panels of the sweep
 };
 
 struct inla_model_s {
@@ -207,7 +208,7 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
       if (t.valid) prof_end(t, s, PK_ASSEMBLE, 0.0, 8.0 * bb * nz * ((td >= 0) + (tb >= 0)));
       if (!LAUNCH_OK()) return ADELIA_E_HIP;
     }
-    if (bta_forward_block(c, i, s)) return ADELIA_E_HIP;
+    if (bta_forward_block(c, i, s, side ? &side->la : nullptr)) return ADELIA_E_HIP;
     if (fork) {
       if (hipEventRecord(side->ready[i % 3], s) != hipSuccess ||
           hipStreamWaitEvent(side->s2, side->ready[i % 3], 0) != hipSuccess)
@@ -482,10 +483,13 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
     delete m;
     return ADELIA_E_HIP;
   }
-  m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess;
+  m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess &&
+                hipStreamCreateWithFlags(&m->side.la.ts, hipStreamNonBlocking) == hipSuccess;
   for (int e = 0; e < 3 && m->has_side; ++e)
     m->has_side = hipEventCreateWithFlags(&m->side.ready[e], hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&m->side.done[e], hipEventDisableTiming) == hipSuccess;
+                  hipEventCreateWithFlags(&m->side.done[e], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&m->side.la.pdone[e], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&m->side.la.tdone[e], hipEventDisableTiming) == hipSuccess;
   *out = m;
   return 0;
 }
@@ -494,11 +498,15 @@ int inla_model_destroy(inla_model m) {
   if (!m) return 0;
   if (m->has_side) {
     hipStreamSynchronize(m->side.s2);
+    hipStreamSynchronize(m->side.la.ts);
     for (int e = 0; e < 3; ++e) {
       hipEventDestroy(m->side.ready[e]);
       hipEventDestroy(m->side.done[e]);
+      hipEventDestroy(m->side.la.pdone[e]);
+      hipEventDestroy(m->side.la.tdone[e]);
     }
     hipStreamDestroy(m->side.s2);
+    hipStreamDestroy(m->side.la.ts);
   }
   hipFree(m->dev_mem);
   delete m;
@@ -591,7 +599,8 @@ int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch,
     // a smaller last sub-batch uses a prefix of the same workspace; the stencil scratch sits
     // at a fixed place in front of it
     InlaWs wb = layout(m->M, bs, false, reinterpret_cast<char*>(ws));
-    int r = run_objective(m->M, wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s);
+    int r = run_objective(m->M, wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s,
+                          m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
   hipLaunchKernelGGL(fd_kernel, dim3((d + 63) / 64), dim3(64), 0, s, w.fv, d, h, f, grad);

@@ -84,7 +84,7 @@ int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
   return 0;
 }
 
-int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
+int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead* la) {
   const int b = c.b, ap = c.ap, n = c.n, nz = c.nz;
   const long long bb = (long long)b * b;
   const int ldT = b + ap;
@@ -101,35 +101,53 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s) {
     return ADELIA_E_HIP_INTERNAL;
   double* Rows = hasB ? LBC : LBC + b;
   const int mT = (hasB ? b : 0) + ap;
+  // rank-64 update of the columns from `from` on (the rows below them and the rows of
+  // [B_i; C~_i]) with panel k, on stream st
+  auto trailing = [&](int k, int from, hipStream_t st) -> int {
+    const int c0 = k * kPanel;
+    const int rest = b - from;
+    GemmArgs g{};
+    g.nph = 1;
+    g.ph[0].A = view_rowsplit(Dblk + from + (long long)c0 * b, b, c.zD,
+                              Rows + (long long)c0 * ldT, ldT, c.zLBC, rest);
+    g.ph[0].B = view_plain(Dblk + from + (long long)c0 * b, b, c.zD, true);
+    g.ph[0].K = g.ph[0].Klast = kPanel;
+    g.ph[0].kmode = KR_FULL;
+    g.ph[0].alpha = -1.0;
+    g.C = view_rowsplit(Dblk + from + (long long)from * b, b, c.zD,
+                        Rows + (long long)from * ldT, ldT, c.zLBC, rest);
+    g.M = g.Mlast = rest + mT;
+    g.N = g.Nlast = rest;
+    g.beta = 1.0;
+    g.omode = OUT_LOWER;  // lower for the block's own rows, every column of the rows below
+    g.tag = GT_TRAIL;
+    g.zn = c.zn;
+    g.step = i;
+    return launch_gemm(g, 1, nz, st) ? ADELIA_E_HIP_INTERNAL : 0;
+  };
   // 1. blocked Cholesky of D_i; each panel also solves its columns of [B_i; C~_i] (the fused
-  //    TRSM of Alg. 1, which with the rhs row yields z_i), and the trailing update covers the
+  //    TRSM of Alg. 1, which with the rhs row yields z_i), and the trailing updates cover the
   //    block and those rows alike
   for (int k = 0; k < npanel; ++k) {
     const int c0 = k * kPanel;
+    if (la && k >= 2 && hipStreamWaitEvent(s, la->tdone[(k - 2) % 3], 0) != hipSuccess)
+      return ADELIA_E_HIP_INTERNAL;
     if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, c.ldpart + (long long)i * npanel + k, c.zLd,
                            c.info, c.cnt, c.zn, i, b, c0, (long long)i * b, mT ? Rows : nullptr,
-                           c.zLBC, ldT, mT, nz, s))
+                           c.zLBC, ldT, mT, la ? 1 : 0, nz, s))
       return ADELIA_E_HIP_INTERNAL;
-    const int rest = b - c0 - kPanel;
-    if (rest > 0) {
-      GemmArgs g{};
-      g.nph = 1;
-      g.ph[0].A = view_rowsplit(Dblk + (c0 + kPanel) + (long long)c0 * b, b, c.zD,
-                                Rows + (long long)c0 * ldT, ldT, c.zLBC, rest);
-      g.ph[0].B = view_plain(Dblk + (c0 + kPanel) + (long long)c0 * b, b, c.zD, true);
-      g.ph[0].K = g.ph[0].Klast = kPanel;
-      g.ph[0].kmode = KR_FULL;
-      g.ph[0].alpha = -1.0;
-      g.C = view_rowsplit(Dblk + (c0 + kPanel) + (long long)(c0 + kPanel) * b, b, c.zD,
-                          Rows + (long long)(c0 + kPanel) * ldT, ldT, c.zLBC, rest);
-      g.M = g.Mlast = rest + mT;
-      g.N = g.Nlast = rest;
-      g.beta = 1.0;
-      g.omode = OUT_LOWER;  // lower for the block's own rows, every column of the rows below
-      g.tag = GT_TRAIL;
-      g.zn = c.zn;
-      g.step = i;
-      if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    if (la) {
+      // the next panel applies this panel's update to its own columns; the columns after it
+      // are updated on the look-ahead stream
+      if (b - c0 - 2 * kPanel > 0) {
+        if (hipEventRecord(la->pdone[k % 3], s) != hipSuccess ||
+            hipStreamWaitEvent(la->ts, la->pdone[k % 3], 0) != hipSuccess)
+          return ADELIA_E_HIP_INTERNAL;
+        if (int r = trailing(k, c0 + 2 * kPanel, la->ts)) return r;
+        if (hipEventRecord(la->tdone[k % 3], la->ts) != hipSuccess) return ADELIA_E_HIP_INTERNAL;
+      }
+    } else if (b - c0 - kPanel > 0) {
+      if (int r = trailing(k, c0 + kPanel, s)) return r;
     }
   }
   // 2. the full inverse, when the caller needs it inline

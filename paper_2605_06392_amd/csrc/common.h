@@ -107,7 +107,16 @@ struct BtaChains {
   double* xT; long long zXT;                // a per chain: L_T^-T z_T (may be null)
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
-int bta_forward_block(const BtaChains& c, int i, hipStream_t s);  // one block step
+// Look-ahead for the block Cholesky: each panel launch first applies the previous panel's
+// rank-64 update to its own columns, and the update of the remaining columns runs on stream ts
+// beside the next panel; events order the two streams (panel k waits for the update issued
+// after panel k-2).
+struct Lookahead {
+  hipStream_t ts;
+  hipEvent_t pdone[3], tdone[3];
+};
+int bta_forward_block(const BtaChains& c, int i, hipStream_t s,
+                      const Lookahead* la = nullptr);  // one block step
 int bta_invert_block(const BtaChains& c, int i, hipStream_t s);   // G_i = L_Di^-1 after step i
 int bta_tip(const BtaChains& c, hipStream_t s);
 int bta_logdet_reduce(const double* ldpart, long long zLd, int nparts, double* out, long long zout,

@@ -8,7 +8,7 @@ namespace adelia {
 int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,
                        long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
                        int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
-                       int nz, hipStream_t s);
+                       int upd, int nz, hipStream_t s);
 int launch_tip(double* T, long long zT, int a, int ap, double* ldp, long long zLd, int32_t* info,
                long long gcol0, double* zsq, double* ZT, long long zZT, double* xT,
                long long zXT, int nz, hipStream_t s);

@@ -39,6 +39,9 @@ struct PanelArgs {
   // mT rows of T (ld ldT, chain stride zT), nullptr when none
   double* T; long long zT;
   int ldT, mT;
+  // apply the previous panel's rank-64 update to this panel's columns first (the trailing
+  // update of the remaining columns then runs beside the next panels)
+  int upd;
 };
 
 // Orders the LDS traffic of one wavefront: the LDS unit serves a wave's operations in issue
@@ -217,6 +220,36 @@ __device__ __forceinline__ v4d frag32(FA A, FB B, int fm, int fn) {
   return frag16(A, B, fm, fn, HB);
 }
 
+// acc += sum_{k<64} A[m][k] B[n][k] for the calling wave's 32 x 32 quarter (wm, wn) of a 64 x 64
+// tile: lane holds (wm + bi*16 + lane%16, wn + bj*16 + lane/16 + 4v).
+__device__ __forceinline__ void mma_abt(const double (*A)[LP], const double (*B)[LP], int wm,
+                                        int wn, int lane, v4d (&acc)[2][2]) {
+#pragma unroll 4
+  for (int kk = 0; kk < NB / 4; ++kk) {
+    const int k = kk * 4 + (lane >> 4);
+    const double a0 = A[wm + (lane & 15)][k];
+    const double a1 = A[wm + 16 + (lane & 15)][k];
+    const double b0 = B[wn + (lane & 15)][k];
+    const double b1 = B[wn + 16 + (lane & 15)][k];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// T[m][n] -= acc for the calling wave's quarter
+__device__ __forceinline__ void sub_quarter(double (*T)[LP], int wm, int wn, int lane,
+                                            const v4d (&acc)[2][2]) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        T[wm + bi * 16 + (lane & 15)][wn + bj * 16 + (lane >> 4) + 4 * v] -= acc[bi][bj][v];
+}
+
 __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   __shared__ double S[NB][LP];
   __shared__ double X[NB][LP];
@@ -239,7 +272,8 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   const long long ldR = tall ? P.ldT : b;
   const int r0 = tall ? NB * ((int)blockIdx.x - nd) : c0 + NB * blockIdx.x;
   const int h = blockIdx.x > 0 ? min(NB, (tall ? P.mT : b) - r0) : 1;
-  double dv[NB * NB / 256], rv[NB * NB / 256];
+  const bool upd = P.upd && c0 >= NB;
+  double dv[NB * NB / 256], rv[NB * NB / 256], qv[NB * NB / 256], pv[NB * NB / 256];
 #pragma unroll
   for (int i = 0; i < NB * NB / 256; ++i) {
     const int e = tid + 256 * i, r = e & 63, c = e >> 6;
@@ -252,6 +286,44 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
       rv[i] = R[(long long)(r0 + min(m, h - 1)) + (long long)(c0 + min(k, w - 1)) * ldR];
     }
   }
+  if (upd) {
+    // the previous panel's columns: Q = its rows c0.. (the diagonal tile's rows), and this
+    // workgroup's own rows of it
+#pragma unroll
+    for (int i = 0; i < NB * NB / 256; ++i) {
+      const int e = tid + 256 * i, r = e & 63, k = e >> 6;
+      qv[i] = D[(long long)(c0 + min(r, w - 1)) + (long long)(c0 - NB + k) * b];
+    }
+    if (blockIdx.x > 0) {
+#pragma unroll
+      for (int i = 0; i < NB * NB / 256; ++i) {
+        const int e = tid + 256 * i, m = e & 63, k = e >> 6;
+        pv[i] = R[(long long)(r0 + min(m, h - 1)) + (long long)(c0 - NB + k) * ldR];
+      }
+    }
+  }
+  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
+  v4d uD[2][2], uR[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      uD[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+      uR[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    }
+  if (upd) {
+    // rank-64 update from the previous panel: diagonal tile -= Q Q^T, row tile -= P Q^T
+#pragma unroll
+    for (int i = 0; i < NB * NB / 256; ++i) {
+      const int e = tid + 256 * i, r = e & 63, k = e >> 6;
+      X[r][k] = (r < w) ? qv[i] : 0.0;
+      S[r][k] = (blockIdx.x > 0 && r < h) ? pv[i] : 0.0;
+    }
+    __syncthreads();
+    mma_abt(X, X, qm, qn, lane, uD);
+    if (blockIdx.x > 0) mma_abt(S, X, qm, qn, lane, uR);
+    __syncthreads();
+  }
   // diagonal tile (lower) with identity padding past w
 #pragma unroll
   for (int i = 0; i < NB * NB / 256; ++i) {
@@ -259,6 +331,10 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
     const double v = (r < w && c < w) ? dv[i] : (r == c ? 1.0 : 0.0);
     S[r][c] = (r >= c) ? v : 0.0;
     X[r][c] = 0.0;
+  }
+  if (upd) {
+    __syncthreads();
+    sub_quarter(S, qm, qn, lane, uD);  // the strictly upper part is never read
   }
   __syncthreads();  // this workgroup's reads of the diagonal tile have completed
   if (tid == 0) {
@@ -327,25 +403,18 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
     const int e = tid + 256 * i, m = e & 63, k = e >> 6;
     S[m][k] = (m < h && k < w) ? rv[i] : 0.0;
   }
+  if (upd) {
+    __syncthreads();
+    sub_quarter(S, qm, qn, lane, uR);
+  }
   __syncthreads();
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = qm, wn = qn;
   v4d acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int kk = 0; kk < NB / 4; ++kk) {
-    const int k = kk * 4 + (lane >> 4);
-    const double a0 = S[wm + (lane & 15)][k];
-    const double a1 = S[wm + 16 + (lane & 15)][k];
-    const double b0 = X[wn + (lane & 15)][k];
-    const double b1 = X[wn + 16 + (lane & 15)][k];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
-  }
+  mma_abt(S, X, wm, wn, lane, acc);
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -363,18 +432,21 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
 int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,
                        long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
                        int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
-                       int nz, hipStream_t s) {
+                       int upd, int nz, hipStream_t s) {
   if (!cnt) return -1;
   if (!T) mT = 0;
   if (mT < 0 || (mT > 0 && ldT < mT)) return -1;
-  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT, ldT, mT};
+  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT, ldT, mT, upd};
   const int rows = (b - c0 + NB - 1) / NB + (mT + NB - 1) / NB;
   const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(potrf_panel_kernel, dim3(rows, 1, nz), dim3(256), 0, s, P);
   if (t.valid) {
     const double ww = (b - c0) < NB ? (b - c0) : NB;
     const double below = (double)(b - c0) - ww + mT;
-    prof_end(t, s, PK_PANEL, nz * (ww * ww * ww / 3.0 + below * ww * ww), 0.0);
+    // with upd, the rank-64 update of the panel's columns (lower part of the diagonal tile
+    // and every row below) is part of the launch
+    const double updfl = (upd && c0 >= NB) ? 2.0 * NB * (ww * (ww + 1) / 2.0 + below * ww) : 0.0;
+    prof_end(t, s, PK_PANEL, nz * (ww * ww * ww / 3.0 + below * ww * ww + updfl), 0.0);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
