@@ -1,12 +1,19 @@
 // Panel step of the blocked Cholesky of a diagonal block (Sec. III-A-1, Alg. 1, chol()).
 //
 // The 64 x 64 diagonal tile of panel k is factored, together with its inverse, as two 32 x 32
-// leaves: each leaf is eliminated column by column by ONE wavefront (registers hold 4 x 4
+// leaves: each leaf is eliminated column by column by ONE wavefront (registers hold 2 x 2
 // sub-blocks, the current column travels through LDS; a single wave needs no workgroup
 // barrier between columns because its LDS operations complete in program order), and the
 // off-diagonal solve L21 = A21 X11^T, the update A22 -= L21 L21^T and the inverse merge
 // X21 = -X22 L21 X11 run on the matrix cores across the four waves.  Workgroup x > 0 also
 // solves its 64-row tile of the panel as A_jk L_kk^-T.
+//
+// The leaves are serial, so the other three waves work beside them: with the look-ahead
+// update (the previous panel's rank-64 contribution to this panel's columns, applied here
+// instead of by the trailing update) only the first leaf's 32 x 32 block of it precedes the
+// first leaf; the rest of the diagonal tile's update and the updated row tile are formed
+// during the first leaf, and the row tile's first 32 columns, R1 = W1 X11^T, together with
+// W2 -= R1 L21^T, during the second.  What is left after the leaves is R2 = W2 X22^T.
 //
 // Every workgroup reads the unfactored diagonal tile, so L_kk may only be written back once
 // all of them have loaded it: each workgroup bumps a per-chain counter after its load, and the
@@ -220,81 +227,66 @@ __device__ __forceinline__ v4d frag32(FA A, FB B, int fm, int fn) {
   return frag16(A, B, fm, fn, HB);
 }
 
-// acc += sum_{k<64} A[m][k] B[n][k] for the calling wave's 32 x 32 quarter (wm, wn) of a 64 x 64
-// tile: lane holds (wm + bi*16 + lane%16, wn + bj*16 + lane/16 + 4v).
-__device__ __forceinline__ void mma_abt(const double (*A)[LP], const double (*B)[LP], int wm,
-                                        int wn, int lane, v4d (&acc)[2][2]) {
+// acc[j] += sum_{k < K} A[am + m][ak + k] B[16 j + n][bk + k] for one 16-row strip (m < 16) and
+// the column fragments j < NJ: lane holds (am + lane%16, 16 j + lane/16 + 4v).
+template <int NJ, int K>
+__device__ __forceinline__ void strip_abt(const double (*A)[LP], int am, int ak,
+                                          const double (*B)[LP], int bk, int lane,
+                                          v4d (&acc)[NJ]) {
+  const int lm = lane & 15, lk = lane >> 4;
 #pragma unroll 4
-  for (int kk = 0; kk < NB / 4; ++kk) {
-    const int k = kk * 4 + (lane >> 4);
-    const double a0 = A[wm + (lane & 15)][k];
-    const double a1 = A[wm + 16 + (lane & 15)][k];
-    const double b0 = B[wn + (lane & 15)][k];
-    const double b1 = B[wn + 16 + (lane & 15)][k];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+  for (int kk = 0; kk < K / 4; ++kk) {
+    const double av = A[am + lm][ak + 4 * kk + lk];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const double bv = B[16 * j + lm][bk + 4 * kk + lk];
+      acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc[j], 0, 0, 0);
+    }
   }
 }
 
-// T[m][n] -= acc for the calling wave's quarter
-__device__ __forceinline__ void sub_quarter(double (*T)[LP], int wm, int wn, int lane,
-                                            const v4d (&acc)[2][2]) {
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        T[wm + bi * 16 + (lane & 15)][wn + bj * 16 + (lane >> 4) + 4 * v] -= acc[bi][bj][v];
-}
-
 __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
-  __shared__ double S[NB][LP];
-  __shared__ double X[NB][LP];
+  __shared__ double S[NB][LP];  // diagonal tile, factored in place into L_kk
+  __shared__ double X[NB][LP];  // L_kk^-1
+  __shared__ double Q[NB][LP];  // previous panel on the diagonal tile's rows (with the update)
+  __shared__ double W[NB][LP];  // previous panel on this tile's rows, then the updated row tile
   __shared__ double col[HB], xr[HB], piv[NB];
   __shared__ int writer;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lm = lane & 15, lk = lane >> 4;
   const int z = blockIdx.z;
   if (P.zn && P.step >= P.zn[z]) return;  // chain z has no block at this step
   const int b = P.b, c0 = P.c0;
   const int w = min(NB, b - c0);
   double* D = P.D + (long long)z * P.zD;
-  // Every global read of the workgroup is issued here, back to back (addresses clamped into the
-  // tiles, values masked on use): the diagonal tile, and for workgroup x > 0 its 64-row tile of
-  // the panel, which stays in registers while the diagonal tile is factored.
   // workgroup x > 0 owns a 64-row tile: first the block's own rows below the diagonal tile,
   // then the rows of T
   const int nd = (b - c0 + NB - 1) / NB;  // diagonal tile + block rows
+  const bool rows = blockIdx.x > 0;
   const bool tall = (int)blockIdx.x >= nd;
   double* R = tall ? P.T + (long long)z * P.zT : D;
   const long long ldR = tall ? P.ldT : b;
   const int r0 = tall ? NB * ((int)blockIdx.x - nd) : c0 + NB * blockIdx.x;
-  const int h = blockIdx.x > 0 ? min(NB, (tall ? P.mT : b) - r0) : 1;
+  const int h = rows ? min(NB, (tall ? P.mT : b) - r0) : 1;
   const bool upd = P.upd && c0 >= NB;
-  double dv[NB * NB / 256], rv[NB * NB / 256], qv[NB * NB / 256], pv[NB * NB / 256];
+  // 16-row strips of the row tile kept by waves 1..3 while wave 0 factors the leaves
+  const int s0 = wave == 1 ? 0 : wave, ns = wave == 0 ? 0 : (wave == 1 ? 2 : 1);
+  // Every global read is issued here, back to back (addresses clamped into the tiles, values
+  // masked on use): the diagonal tile, the previous panel's columns on it and on this tile's
+  // rows, and the row tile itself, which waves 1..3 load in the matrix-core accumulator layout.
+  double dv[NB * NB / 256], qv[NB * NB / 256], pv[NB * NB / 256], rt[2][4][4];
 #pragma unroll
   for (int i = 0; i < NB * NB / 256; ++i) {
     const int e = tid + 256 * i, r = e & 63, c = e >> 6;
     dv[i] = D[(long long)(c0 + min(r, w - 1)) + (long long)(c0 + min(c, w - 1)) * b];
   }
-  if (blockIdx.x > 0) {
-#pragma unroll
-    for (int i = 0; i < NB * NB / 256; ++i) {
-      const int e = tid + 256 * i, m = e & 63, k = e >> 6;
-      rv[i] = R[(long long)(r0 + min(m, h - 1)) + (long long)(c0 + min(k, w - 1)) * ldR];
-    }
-  }
   if (upd) {
-    // the previous panel's columns: Q = its rows c0.. (the diagonal tile's rows), and this
-    // workgroup's own rows of it
 #pragma unroll
     for (int i = 0; i < NB * NB / 256; ++i) {
       const int e = tid + 256 * i, r = e & 63, k = e >> 6;
       qv[i] = D[(long long)(c0 + min(r, w - 1)) + (long long)(c0 - NB + k) * b];
     }
-    if (blockIdx.x > 0) {
+    if (rows) {
 #pragma unroll
       for (int i = 0; i < NB * NB / 256; ++i) {
         const int e = tid + 256 * i, m = e & 63, k = e >> 6;
@@ -302,27 +294,17 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
       }
     }
   }
-  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
-  v4d uD[2][2], uR[2][2];
+  if (rows && wave > 0) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int s = 0; s < 2; ++s) {
+      if (s >= ns) break;
+      const int m = min(16 * (s0 + s) + lm, h - 1);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      uD[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-      uR[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          rt[s][j][v] = R[(long long)(r0 + m) + (long long)(c0 + min(16 * j + lk + 4 * v, w - 1)) * ldR];
     }
-  if (upd) {
-    // rank-64 update from the previous panel: diagonal tile -= Q Q^T, row tile -= P Q^T
-#pragma unroll
-    for (int i = 0; i < NB * NB / 256; ++i) {
-      const int e = tid + 256 * i, r = e & 63, k = e >> 6;
-      X[r][k] = (r < w) ? qv[i] : 0.0;
-      S[r][k] = (blockIdx.x > 0 && r < h) ? pv[i] : 0.0;
-    }
-    __syncthreads();
-    mma_abt(X, X, qm, qn, lane, uD);
-    if (blockIdx.x > 0) mma_abt(S, X, qm, qn, lane, uR);
-    __syncthreads();
   }
   // diagonal tile (lower) with identity padding past w
 #pragma unroll
@@ -331,10 +313,10 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
     const double v = (r < w && c < w) ? dv[i] : (r == c ? 1.0 : 0.0);
     S[r][c] = (r >= c) ? v : 0.0;
     X[r][c] = 0.0;
-  }
-  if (upd) {
-    __syncthreads();
-    sub_quarter(S, qm, qn, lane, uD);  // the strictly upper part is never read
+    if (upd) {
+      Q[r][c] = (r < w) ? qv[i] : 0.0;
+      if (rows) W[r][c] = (r < h) ? pv[i] : 0.0;
+    }
   }
   __syncthreads();  // this workgroup's reads of the diagonal tile have completed
   if (tid == 0) {
@@ -343,7 +325,52 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
     if (last) atomicExch(P.cnt + z, 0);
     writer = last ? 1 : 0;
   }
-  if (wave == 0) leaf32(S, X, col, xr, piv, 0);
+  if (upd) {
+    // rank-64 update of the first leaf's block: S -= Q Q^T on fragments (0,0), (16,0), (16,16)
+    // (the strictly upper part of S is never read)
+    if (wave < 3) {
+      const int fm = wave == 0 ? 0 : 16, fn = wave == 2 ? 16 : 0;
+      const v4d t = frag16([&](int m, int k) { return Q[m][k]; },
+                           [&](int k, int n) { return Q[n][k]; }, fm, fn, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[fm + lm][fn + lk + 4 * v] -= t[v];
+    }
+    __syncthreads();
+  }
+  if (wave == 0) {
+    leaf32(S, X, col, xr, piv, 0);
+  } else {
+    // beside the first leaf (which touches rows 0..31 of S and X only): the rest of the
+    // diagonal tile's update, rows 32..63 (waves 2 and 3), and the updated row tile
+    // W = A - P Q^T, strip by strip, each strip read and rewritten by its own wave
+    if (upd && wave >= 2) {
+      const int fm = 32 + 16 * (wave - 2);
+      for (int fn = 0; fn <= fm; fn += 16) {
+        const v4d t = frag16([&](int m, int k) { return Q[m][k]; },
+                             [&](int k, int n) { return Q[n][k]; }, fm, fn, NB);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[fm + lm][fn + lk + 4 * v] -= t[v];
+      }
+    }
+    if (rows) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (s >= ns) break;
+        const int mi = s0 + s, m = 16 * mi + lm;
+        v4d acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[j][v] = (m < h && 16 * j + lk + 4 * v < w) ? -rt[s][j][v] : 0.0;
+        if (upd) strip_abt<4, NB>(W, 16 * mi, 0, Q, 0, lane, acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) W[m][16 * j + lk + 4 * v] = -acc[j][v];
+      }
+    }
+  }
   __syncthreads();
   const int fm = (wave & 1) * 16, fn = (wave >> 1) * 16;
   // L21 = A21 X11^T
@@ -351,30 +378,64 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
                  [&](int k, int n) { return X[n][k]; }, fm, fn);
   __syncthreads();
 #pragma unroll
-  for (int v = 0; v < 4; ++v) S[HB + fm + (lane & 15)][fn + (lane >> 4) + 4 * v] = t[v];
+  for (int v = 0; v < 4; ++v) S[HB + fm + lm][fn + lk + 4 * v] = t[v];
   __syncthreads();
   // A22 -= L21 L21^T (each wave owns its fragment; the strictly upper one is never read)
   t = frag32([&](int m, int k) { return S[HB + m][k]; },
              [&](int k, int n) { return S[HB + n][k]; }, fm, fn);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) S[HB + fm + (lane & 15)][HB + fn + (lane >> 4) + 4 * v] -= t[v];
+  for (int v = 0; v < 4; ++v) S[HB + fm + lm][HB + fn + lk + 4 * v] -= t[v];
   __syncthreads();
-  if (wave == 0) leaf32(S, X, col, xr, piv, HB);
-  __syncthreads();
-  // X21 = -X22 (L21 X11)
-  t = frag32([&](int m, int k) { return S[HB + m][k]; },
-             [&](int k, int n) { return X[k][n]; }, fm, fn);
+  if (wave == 0) {
+    leaf32(S, X, col, xr, piv, HB);
+  } else if (rows) {
+    // beside the second leaf (columns 32..63 of S and X): the row tile's first half
+    // R1 = W1 X11^T, stored at once, and W2 -= R1 L21^T, so that R2 = W2 X22^T is all that
+    // waits for the leaf.  R1's accumulator layout is the A-operand layout of the second product.
 #pragma unroll
-  for (int v = 0; v < 4; ++v) X[HB + fm + (lane & 15)][fn + (lane >> 4) + 4 * v] = t[v];
-  __syncthreads();
-  t = frag32([&](int m, int k) { return X[HB + m][HB + k]; },
-             [&](int k, int n) { return X[HB + k][n]; }, fm, fn);
-  __syncthreads();
+    for (int s = 0; s < 2; ++s) {
+      if (s >= ns) break;
+      const int mi = s0 + s, m = 16 * mi + lm;
+      v4d r1[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+      strip_abt<2, HB>(W, 16 * mi, 0, X, 0, lane, r1);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) X[HB + fm + (lane & 15)][fn + (lane >> 4) + 4 * v] = -t[v];
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = 16 * j + lk + 4 * v;
+          if (m < h && n < w) R[(long long)(r0 + m) + (long long)(c0 + n) * ldR] = r1[j][v];
+        }
+      v4d u[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+      for (int kk = 0; kk < HB / 4; ++kk) {
+        const double av = r1[kk >> 2][kk & 3];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double bv = S[HB + 16 * j + lm][4 * kk + lk];
+          u[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, u[j], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) W[m][HB + 16 * j + lk + 4 * v] -= u[j][v];
+    }
+  }
   __syncthreads();
 
   if (writer) {
+    // X21 = -X22 (L21 X11), needed only for the stored inverse
+    t = frag32([&](int m, int k) { return S[HB + m][k]; },
+               [&](int k, int n) { return X[k][n]; }, fm, fn);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[HB + fm + lm][fn + lk + 4 * v] = t[v];
+    __syncthreads();
+    t = frag32([&](int m, int k) { return X[HB + m][HB + k]; },
+               [&](int k, int n) { return X[HB + k][n]; }, fm, fn);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[HB + fm + lm][fn + lk + 4 * v] = -t[v];
+    __syncthreads();
     double* G = P.G + (long long)z * P.zG;
     for (int e = tid; e < w * w; e += 256) {
       const int r = e % w, c = e / w;
@@ -395,36 +456,20 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
       }
     }
   }
-  if (blockIdx.x == 0) return;
-  // panel rows r0..r0+h: L(m, n) = sum_k A(m, k) X(n, k); the tile replaces S
-  __syncthreads();  // every read of S above has completed
+  if (!rows) return;
+  // R2 = W2 X22^T: wave q takes strip q
+  {
+    const int m = 16 * wave + lm;
+    v4d r2[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    strip_abt<2, HB>(W, 16 * wave, HB, (const double (*)[LP])(X + HB), HB, lane, r2);
 #pragma unroll
-  for (int i = 0; i < NB * NB / 256; ++i) {
-    const int e = tid + 256 * i, m = e & 63, k = e >> 6;
-    S[m][k] = (m < h && k < w) ? rv[i] : 0.0;
-  }
-  if (upd) {
-    __syncthreads();
-    sub_quarter(S, qm, qn, lane, uR);
-  }
-  __syncthreads();
-  const int wm = qm, wn = qn;
-  v4d acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-  mma_abt(S, X, wm, wn, lane, acc);
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = wm + bi * 16 + (lane & 15);
-        const int n = wn + bj * 16 + (lane >> 4) + 4 * v;
-        if (m < h && n < w) R[(long long)(r0 + m) + (long long)(c0 + n) * ldR] = acc[bi][bj][v];
+        const int n = HB + 16 * j + lk + 4 * v;
+        if (m < h && n < w) R[(long long)(r0 + m) + (long long)(c0 + n) * ldR] = r2[j][v];
       }
+  }
 }
 
 }  // namespace
