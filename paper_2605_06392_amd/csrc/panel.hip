@@ -1,9 +1,9 @@
 // Panel step of the blocked Cholesky of a diagonal block (Sec. III-A-1, Alg. 1, chol()).
 //
 // The 64 x 64 diagonal tile of panel k is factored, together with its inverse, as two 32 x 32
-// leaves: each leaf is eliminated column by column by ONE wavefront (registers hold 2 x 2
-// sub-blocks, the current column travels through LDS; a single wave needs no workgroup
-// barrier between columns because its LDS operations complete in program order), and the
+// leaves: each leaf is eliminated two columns per step by ONE wavefront (registers hold 2 x 2
+// sub-blocks, the current column pair travels through LDS; a single wave needs no workgroup
+// barrier between steps because its LDS operations complete in program order), and the
 // off-diagonal solve L21 = A21 X11^T, the update A22 -= L21 L21^T and the inverse merge
 // X21 = -X22 L21 X11 run on the matrix cores across the four waves.  Workgroup x > 0 also
 // solves its 64-row tile of the panel as A_jk L_kk^-T.
@@ -73,73 +73,101 @@ __device__ __forceinline__ void pivot(double d, double& pv, double& invs) {
 
 constexpr int QB = 16;  // edge of the serially eliminated leaves
 
-// Column j = 2 jq + JR of a 16 x 16 leaf held as 2 x 2 blocks, one per lane (36 of the 64 lanes
-// cover the lower triangle): scale the pivot column, rank-1 update of the trailing part of L and
-// of the rows of L^-1 below j, then publish column j+1 and row j+1 of L^-1.  Every LDS load is
-// unconditional (all indices lie inside the leaf) and masks are selects, so the step has no
-// divergent branch around a memory access.
-template <int JR>
-__device__ __forceinline__ void leaf_step(double (&a)[2][2], double (&x)[2][2], double* col,
-                                          double* xr, double* piv, int o, int jq, int br, int bc,
-                                          bool active, int lane) {
-  const int j = 2 * jq + JR;
-  const double djj = col[j];
-  double cr[2], cc[2], xc[2];
+// Columns j0 = 2 JQ and j1 = j0 + 1 of a 16 x 16 leaf held as 2 x 2 blocks, one per lane (lane
+// (br, bc) holds rows 2 br.., columns 2 bc..).  The column pair has been published to LDS
+// updated but unscaled (cp: column j0 then column j1; xp: rows j0 and j1 of L^-1 before their
+// scaling), so every lane factors the 2 x 2 pivot block itself, scales the entries it needs and
+// applies the rank-2 update to the trailing part of L and to the rows of L^-1 below j1; then
+// the lanes holding pair JQ + 1 publish it.  Masks are selects on the operands: lanes above the
+// diagonal compute finite values that are never read.
+template <int JQ>
+__device__ __forceinline__ void leaf_pair(double (&a)[2][2], double (&x)[2][2], double* cp,
+                                          double* xp, double* piv, int o, int br, int bc,
+                                          int lane) {
+  constexpr int j0 = 2 * JQ, j1 = j0 + 1;
+  const double* c0 = cp;
+  const double* c1 = cp + QB;
+  const double a00 = c0[j0], a10 = c0[j1], a11 = c1[j1];
+  double c0r[2], c1r[2], c0c[2], c1c[2], x0c[2], x1c[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    cr[q] = col[2 * br + q];
-    cc[q] = col[2 * bc + q];
-    xc[q] = xr[2 * bc + q];
+    c0r[q] = c0[2 * br + q];
+    c1r[q] = c1[2 * br + q];
+    c0c[q] = c0[2 * bc + q];
+    c1c[q] = c1[2 * bc + q];
+    x0c[q] = xp[2 * bc + q];
+    x1c[q] = xp[QB + 2 * bc + q];
   }
-  double pv, invs;
-  pivot(djj, pv, invs);
-  if (lane == 0) piv[o + j] = djj;
-  double lr[2], lrx[2], lc[2], xj[2];
+  double p0, r0, p1, r1;
+  pivot(a00, p0, r0);
+  const double l10 = a10 * r0;
+  const double d1 = fma(-l10, l10, a11);
+  pivot(d1, p1, r1);
+  if (lane == 0) {
+    piv[o + j0] = a00;
+    piv[o + j1] = d1;
+  }
+  const bool rowm = br > JQ, colm = bc > JQ;
+  double L0r[2], L1r[2], L0c[2], L1c[2], X0[2], X1[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    lr[q] = cr[q] * invs;
-    lrx[q] = (2 * br + q > j) ? lr[q] : 0.0;
-    lc[q] = (2 * bc + q > j) ? cc[q] * invs : 0.0;
-    xj[q] = (2 * bc + q <= j) ? xc[q] * invs : 0.0;
+    L0r[q] = c0r[q] * r0;
+    L1r[q] = fma(-L0r[q], l10, c1r[q]) * r1;
+    L0c[q] = c0c[q] * r0;
+    L1c[q] = fma(-L0c[q], l10, c1c[q]) * r1;
+    X0[q] = x0c[q] * r0;
+    X1[q] = fma(-l10, X0[q], x1c[q]) * r1;
   }
 #pragma unroll
-  for (int ii = 0; ii < 2; ++ii)
+  for (int ii = 0; ii < 2; ++ii) {
+    const double u0 = rowm ? L0r[ii] : 0.0, u1 = rowm ? L1r[ii] : 0.0;
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) {
-      a[ii][jj] = fma(-lr[ii], lc[jj], a[ii][jj]);
-      x[ii][jj] = fma(-lrx[ii], xj[jj], x[ii][jj]);
-    }
-  if (bc == jq) {
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii) a[ii][JR] = (2 * br + ii == j) ? pv : lr[ii];
-  }
-  if (br == jq) {
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) x[JR][jj] = xj[jj];
-  }
-  wave_order();  // every lane has read column j before it is replaced
-  constexpr int NR = (JR + 1) & 1;
-  const int nq = jq + (JR == 1 ? 1 : 0);
-  if (JR != 1 || nq < QB / 2) {
-    if (bc == nq && active) {
-#pragma unroll
-      for (int ii = 0; ii < 2; ++ii) col[2 * br + ii] = a[ii][NR];
-    }
-    if (br == nq && active) {
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) xr[2 * bc + jj] = x[NR][jj];
+      const double v0 = colm ? L0c[jj] : 0.0, v1 = colm ? L1c[jj] : 0.0;
+      a[ii][jj] = fma(-u0, v0, fma(-u1, v1, a[ii][jj]));
+      x[ii][jj] = fma(-u0, X0[jj], fma(-u1, X1[jj], x[ii][jj]));
     }
   }
-  wave_order();
+  if (bc == JQ) {
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) {
+      a[ii][0] = L0r[ii];
+      a[ii][1] = L1r[ii];
+    }
+  }
+  if (br == JQ) {
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      x[0][jj] = X0[jj];
+      x[1][jj] = X1[jj];
+    }
+  }
+  wave_order();  // every lane has read pair JQ before it is replaced
+  if constexpr (JQ + 1 < QB / 2) {
+    if (bc == JQ + 1) {
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii) {
+        cp[2 * br + ii] = a[ii][0];
+        cp[QB + 2 * br + ii] = a[ii][1];
+      }
+    }
+    if (br == JQ + 1) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        xp[2 * bc + jj] = x[0][jj];
+        xp[QB + 2 * bc + jj] = x[1][jj];
+      }
+    }
+    wave_order();
+  }
 }
 
 // Factor the 16 x 16 leaf at (o, o) of S (lower triangle, already updated) with one wavefront.
 // On exit S holds L (lower, zeros above) and X holds L^-1 on that leaf; piv[o + j] = pivot^2.
-__device__ void leaf16(double (*S)[LP], double (*X)[LP], double* col, double* xr, double* piv,
+__device__ void leaf16(double (*S)[LP], double (*X)[LP], double* cp, double* xp, double* piv,
                        int o) {
   const int lane = threadIdx.x & 63;
   const int br = lane >> 3, bc = lane & 7;
-  const bool active = br >= bc;
   double a[2][2], x[2][2];
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii)
@@ -150,22 +178,35 @@ __device__ void leaf16(double (*S)[LP], double (*X)[LP], double* col, double* xr
       a[ii][jj] = (r >= c) ? v : 0.0;
       x[ii][jj] = (r == c) ? 1.0 : 0.0;
     }
-  if (bc == 0 && active) {
+  if (bc == 0) {
 #pragma unroll
-    for (int ii = 0; ii < 2; ++ii) col[2 * br + ii] = a[ii][0];
+    for (int ii = 0; ii < 2; ++ii) {
+      cp[2 * br + ii] = a[ii][0];
+      cp[QB + 2 * br + ii] = a[ii][1];
+    }
   }
-  if (lane < QB) xr[lane] = (lane == 0) ? 1.0 : 0.0;
+  if (br == 0) {
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      xp[2 * bc + jj] = x[0][jj];
+      xp[QB + 2 * bc + jj] = x[1][jj];
+    }
+  }
   wave_order();
-  for (int jq = 0; jq < QB / 2; ++jq) {
-    leaf_step<0>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
-    leaf_step<1>(a, x, col, xr, piv, o, jq, br, bc, active, lane);
-  }
+  leaf_pair<0>(a, x, cp, xp, piv, o, br, bc, lane);
+  leaf_pair<1>(a, x, cp, xp, piv, o, br, bc, lane);
+  leaf_pair<2>(a, x, cp, xp, piv, o, br, bc, lane);
+  leaf_pair<3>(a, x, cp, xp, piv, o, br, bc, lane);
+  leaf_pair<4>(a, x, cp, xp, piv, o, br, bc, lane);
+  leaf_pair<5>(a, x, cp, xp, piv, o, br, bc, lane);
+  leaf_pair<6>(a, x, cp, xp, piv, o, br, bc, lane);
+  leaf_pair<7>(a, x, cp, xp, piv, o, br, bc, lane);
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) {
       const int r = 2 * br + ii, c = 2 * bc + jj;
-      const bool low = active && r >= c;
+      const bool low = r >= c;
       S[o + r][o + c] = low ? a[ii][jj] : 0.0;
       X[o + r][o + c] = low ? x[ii][jj] : 0.0;
     }
@@ -250,7 +291,7 @@ __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   __shared__ double X[NB][LP];  // L_kk^-1
   __shared__ double Q[NB][LP];  // previous panel on the diagonal tile's rows (with the update)
   __shared__ double W[NB][LP];  // previous panel on this tile's rows, then the updated row tile
-  __shared__ double col[HB], xr[HB], piv[NB];
+  __shared__ double col[2 * QB], xr[2 * QB], piv[NB];
   __shared__ int writer;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lm = lane & 15, lk = lane >> 4;
