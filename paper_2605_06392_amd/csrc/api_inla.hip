@@ -28,6 +28,7 @@ struct SideRes {
   hipStream_t s2;
   hipEvent_t ready[3], done[3];
   Lookahead la;  // its own stream: trailing updates beside the panels of the sweep
+  int side_maxwg;  // workgroup cap of the launches on s2
 };
 
 struct inla_model_s {
@@ -189,9 +190,13 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
   const long long bb = (long long)b * b;
   const dim3 agrid(b, 1, nz);
   BtaChains c = chains_of(w);
-  const SelinvChains si = selinv_of(w);
+  SelinvChains si = selinv_of(w);
   const bool fork = c.invert && side && w.slotsD == 3;
-  if (fork) c.invert = false;
+  if (fork) {
+    c.invert = false;
+    c.inv_maxwg = side->side_maxwg;
+    si.prep_maxwg = side->side_maxwg;
+  }
   hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, 0, -1, w.D, w.zD,
                      w.Bin, w.zB, w.phi, w.tau);
   for (int i = 0; i < n; ++i) {
@@ -482,6 +487,18 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
     hipFree(mem);
     delete m;
     return ADELIA_E_HIP;
+  }
+  {
+    // The side stream's products (inversion, selected-inversion preparation) run beside the
+    // panels of the sweep, whose workgroups each need a CU of their own (most of its LDS): cap
+    // them at 3/8 of the CUs (measured best on 256 CUs).  The look-ahead updates are short and
+    // stay uncapped.
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    m->side.la.maxwg = 0;
+    m->side.side_maxwg = std::max(8, (3 * cus / 8) & ~7);
   }
   m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess &&
                 hipStreamCreateWithFlags(&m->side.la.ts, hipStreamNonBlocking) == hipSuccess;

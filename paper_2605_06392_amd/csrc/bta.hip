@@ -55,6 +55,7 @@ int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
+      g.maxwg = c.inv_maxwg;
       g.zn = c.zn;
       g.step = i;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
@@ -76,6 +77,7 @@ int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
+      g.maxwg = c.inv_maxwg;
       g.zn = c.zn;
       g.step = i;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
@@ -123,6 +125,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     g.tag = GT_TRAIL;
     g.zn = c.zn;
     g.step = i;
+    g.maxwg = (la && st == la->ts) ? la->maxwg : 0;
     return launch_gemm(g, 1, nz, st) ? ADELIA_E_HIP_INTERNAL : 0;
   };
   // 1. blocked Cholesky of D_i; each panel also solves its columns of [B_i; C~_i] (the fused
@@ -260,6 +263,7 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_SI_W;
+    g.maxwg = c.prep_maxwg;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // S3 (first term): lower triangle of Z_Dj = G_j^T G_j
@@ -278,6 +282,7 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_LOWER;
     g.tag = GT_SI_D;
+    g.maxwg = c.prep_maxwg;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;

@@ -63,6 +63,9 @@ struct GemmArgs {
   // Uneven batches: chain z takes part only while step < zn[z] (zn == nullptr: always).
   const int32_t* zn;
   int step;
+  // 0: one workgroup per output tile; otherwise at most maxwg workgroups (a multiple of 8, at
+  // least 8), each walking several tiles, which leaves CUs free for work on other streams
+  int maxwg;
 };
 
 enum GemmTag { GT_OTHER = 0, GT_TRAIL, GT_TRTRI, GT_TRMM, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D, GT_COUNT };
@@ -105,6 +108,7 @@ struct BtaChains {
   double* zsq;                              // per chain: |z|^2 (if ap == a+1), may be null
   double* ZT; long long zZT;                // a x a per chain: [Q^-1]_{T,T} (may be null)
   double* xT; long long zXT;                // a per chain: L_T^-T z_T (may be null)
+  int inv_maxwg;                            // workgroup cap of bta_invert_block's launches
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
 // Look-ahead for the block Cholesky: each panel launch first applies the previous panel's
@@ -114,6 +118,7 @@ int bta_forward(const BtaChains& c, hipStream_t s);
 struct Lookahead {
   hipStream_t ts;
   hipEvent_t pdone[3], tdone[3];
+  int maxwg;  // workgroup cap of each update launch on ts (GemmArgs::maxwg)
 };
 int bta_forward_block(const BtaChains& c, int i, hipStream_t s,
                       const Lookahead* la = nullptr);  // one block step
@@ -132,6 +137,7 @@ struct SelinvChains {
   double* ZB; long long zZB; int slotsZB;
   double* ZC; long long zZC; int slotsZC;        // a x b (ld a)
   double* W; long long zW; int slotsW;           // [W; V] of block t in slot t % slotsW, b*b + a*b each
+  int prep_maxwg;                                // workgroup cap of selinv_prepare's launches
 };
 // The parts of backward step j that do not depend on Z (they can run as soon as G_j exists):
 // [W_j; V_j] = [L_Bj; L_Cj] G_j, and Z_Dj's lower triangle set to G_j^T G_j.

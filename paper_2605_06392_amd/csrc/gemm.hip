@@ -6,7 +6,7 @@
 // ([L_B; L_C], the augmented inverse [[Z_D, Z_C^T]; [Z_C, Z_T]]) without copies.
 //
 // Tiling: a 256-thread workgroup owns a 64 x 64 tile of C; each of its four wavefronts owns
-// a 32 x 32 quarter as 2 x 2 fragments of v_mfma_f64_16x16x4.  K advances 16 at a time
+// a 32 x 32 quarter as 2 x 2 fragments of v_mfma_f64_16x16x4.  K advances 32 at a time
 // through LDS with the next tile prefetched into registers.  On this instruction lane l holds
 // A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4v][l%16] (v = 0..3); the kernel feeds the
 // B-fragment as the instruction's A operand so that each lane's results lie along a column of
@@ -22,6 +22,13 @@ namespace adelia {
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 32;
+// Four wavefronts per tile (eight, with half the MFMAs per wave and K step, measured slower):
+// wave w owns rows (w % 2) * 32 .. + 32 and columns (w / 2) * WN .. + WN, as 2 x FJ fragments.
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+constexpr int WN = BN / (NW / 2);
+constexpr int FJ = WN / 16;
+constexpr int NR = BM * BK / NT;  // staging registers per thread per operand tile
 constexpr int LDS_ROW = BM + 1;  // odd pitch (doubles): K-contiguous tiles store without bank conflicts
 
 // A view with the chain (z) and sub-problem (y) offsets applied: four quadrant bases and
@@ -85,7 +92,7 @@ __device__ __forceinline__ bool tri_zero(int tri, int r, int c) {
   return (tri == TRI_LOWER && c > r) || (tri == TRI_UPPER && r > c);
 }
 
-// Operand tiles.  A BM x BK tile of logical A (and a BK x BN tile of logical B) goes through 8
+// Operand tiles.  A BM x BK tile of logical A (and a BK x BN tile of logical B) goes through NR
 // registers per thread.  The lanes of a wavefront walk the operand's contiguous dimension, so
 // every load instruction reads 256 or 512 consecutive bytes.
 //
@@ -103,15 +110,15 @@ struct OpPipe {
   int mode;         // 0: lanes along M/N, 1: lanes along K
   int kseg;         // K of the stretch's first tile
   long long sK;     // element stride along K inside the quadrant
-  unsigned voff[8];
-  double v[8];
+  unsigned voff[NR];
+  double v[NR];
 };
 
 // (row, col) of register j of a tile; rows run along M (or N), cols along K.
 __device__ __forceinline__ void tile_pos(int mode, int j, int& r, int& c) {
   const int tid = threadIdx.x;
-  const int r0 = tid & 63, c0 = (tid >> 6) + 4 * j;
-  const int r1 = (tid >> 5) + 8 * j, c1 = tid & 31;
+  const int r0 = tid & 63, c0 = (tid >> 6) + (NT / 64) * j;
+  const int r1 = (tid >> 5) + (NT / 32) * j, c1 = tid & 31;
   r = mode ? r1 : r0;
   c = mode ? c1 : c0;
 }
@@ -147,7 +154,7 @@ __device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn,
       P.kseg = k0;
       const int tr = (colsfirst ? r0 - clo : r0 - rlo), tk = (colsfirst ? k0 - rlo : k0 - clo);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < NR; ++j) {
         int r, c;
         tile_pos(P.mode, j, r, c);
         P.voff[j] = (unsigned)(8 * ((long long)(tr + r) * sR + (long long)(tk + c) * P.sK));
@@ -156,7 +163,7 @@ __device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn,
     }
     const int soff = (int)(8 * (long long)(k0 - P.kseg) * P.sK);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NR; ++j) {
       typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
       const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(P.rsrc, (int)P.voff[j], soff, 0);
       P.v[j] = __builtin_bit_cast(double, w);
@@ -165,16 +172,16 @@ __device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn,
   }
   P.q = -1;
   P.mode = 0;
-  gptr ptr[8];
+  gptr ptr[NR];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NR; ++j) {
     int r, c;
     tile_pos(0, j, r, c);
     const int gr = min(r0 + r, R - 1), gc = min(k0 + c, Kn - 1);
     ptr[j] = (gptr)(colsfirst ? elem_ptr(V, gc, gr) : elem_ptr(V, gr, gc));
   }
 #pragma unroll
-  for (int j = 0; j < 8; ++j) P.v[j] = *ptr[j];
+  for (int j = 0; j < NR; ++j) P.v[j] = *ptr[j];
 }
 
 // Write a tile to LDS as T[c][r] (K-major).  Tiles inside the operand with no triangle go
@@ -186,7 +193,7 @@ __device__ __forceinline__ void store_tile(const OpPipe& P, double (*T)[LDS_ROW]
   const bool interior = (r0 + BM <= R) && (k0 + BK <= Kn) && tri == TRI_NONE;
   if (interior) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NR; ++j) {
       int r, c;
       tile_pos(P.mode, j, r, c);
       T[c][r] = P.v[j];
@@ -194,7 +201,7 @@ __device__ __forceinline__ void store_tile(const OpPipe& P, double (*T)[LDS_ROW]
     return;
   }
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NR; ++j) {
     int r, c;
     tile_pos(P.mode, j, r, c);
     const int gr = r0 + r, gc = k0 + c;
@@ -218,20 +225,22 @@ __device__ __forceinline__ void krange(int mode, int K, int m0, int n0, int& klo
   if (klo > K) klo = K;
 }
 
-// One K step on the matrix cores: 8 x 4 MFMAs per wave over a 32-deep slice of the LDS tiles.
+// One K step on the matrix cores: 8 x 2 FJ MFMAs per wave over a 32-deep slice of the LDS tiles.
 __device__ __forceinline__ void mfma_step(const double (*As)[LDS_ROW], const double (*Bs)[LDS_ROW],
-                                          int wm, int wn, int lane, v4d (&acc)[2][2]) {
+                                          int wm, int wn, int lane, v4d (&acc)[2][FJ]) {
 #pragma unroll
   for (int kk = 0; kk < BK / 4; ++kk) {
     const int kr = kk * 4 + (lane >> 4);
     const double a0 = As[kr][wm + (lane & 15)];
     const double a1 = As[kr][wm + 16 + (lane & 15)];
-    const double b0 = Bs[kr][wn + (lane & 15)];
-    const double b1 = Bs[kr][wn + 16 + (lane & 15)];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+    double b[FJ];
+#pragma unroll
+    for (int bj = 0; bj < FJ; ++bj) b[bj] = Bs[kr][wn + 16 * bj + (lane & 15)];
+#pragma unroll
+    for (int bj = 0; bj < FJ; ++bj) {
+      acc[0][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[bj], a0, acc[0][bj], 0, 0, 0);
+      acc[1][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[bj], a1, acc[1][bj], 0, 0, 0);
+    }
   }
 }
 
@@ -242,7 +251,7 @@ __device__ __forceinline__ void mfma_step(const double (*As)[LDS_ROW], const dou
 __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
                                           double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW],
-                                          v4d (&acc)[2][2]) {
+                                          v4d (&acc)[2][FJ]) {
   const int K = lasty ? ph.Klast : ph.K;
   int klo, khi;
   krange(ph.kmode, K, m0, n0, klo, khi);
@@ -266,58 +275,18 @@ __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int
   }
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
-// a contiguous range of tiles so that neighbouring tiles, which share operand tiles, share an L2.
-__device__ __forceinline__ int xcd_remap(int L, int T) {
-  const int x = L & 7, idx = L >> 3;
-  const int per = T >> 3, rem = T & 7;
-  return x * per + min(x, rem) + idx;
-}
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemm_f64_kernel(const GemmArgs args) {
-  __shared__ double As[2][BK][LDS_ROW];
-  __shared__ double Bs[2][BK][LDS_ROW];
-  const int z = blockIdx.z, y = blockIdx.y;
-  if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
-  const bool lasty = (y == (int)gridDim.y - 1);
-  const int M = lasty ? args.Mlast : args.M;
-  const int N = lasty ? args.Nlast : args.N;
-  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
-  int ti, tj;
-  if (args.omode == OUT_ALL) {
-    const int T = tilesM * tilesN;
-    if ((int)blockIdx.x >= T) return;
-    const int L = (int)gridDim.x == T ? xcd_remap(blockIdx.x, T) : blockIdx.x;
-    ti = L % tilesM;
-    tj = L / tilesM;
-  } else {
-    // lower trapezoid (M >= N): the triangle of the top tilesN x tilesN tiles, then full rows
-    const int T0 = tilesN * (tilesN + 1) / 2;
-    const int T = T0 + (tilesM - tilesN) * tilesN;
-    if ((int)blockIdx.x >= T) return;
-    const int L = (int)gridDim.x == T ? xcd_remap(blockIdx.x, T) : blockIdx.x;
-    if (L < T0) {
-      ti = (int)((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
-      while (ti * (ti + 1) / 2 > L) --ti;
-      while ((ti + 1) * (ti + 2) / 2 <= L) ++ti;
-      tj = L - ti * (ti + 1) / 2;
-    } else {
-      ti = tilesN + (L - T0) / tilesN;
-      tj = (L - T0) % tilesN;
-    }
-  }
-  const int m0 = ti * BM, n0 = tj * BN;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-
+// One 64 x 64 output tile at (m0, n0).
+__device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, int m0, int n0,
+                                          bool lasty, int z, int y, int wm, int wn, int lane,
+                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW]) {
   const VP C = make_vp(args.C, z, y);
   const double beta = args.beta;
   const bool lowerC = args.omode != OUT_ALL;
-  v4d acc[2][2];
+  v4d acc[2][FJ];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
   // acc collects sum_p alpha_p A_p B_p: the products of phase p are accumulated unscaled, the
   // running sum is rescaled by alpha_{p-1} / alpha_p before phase p and by the last alpha at the
   // end (exact for the +-1 used on the sweeps).
@@ -329,7 +298,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] *= sc;
+        for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= sc;
     }
     run_phase(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
     alpha_prev = alpha;
@@ -337,39 +306,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] *= alpha_prev;
+    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= alpha_prev;
 
   // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v).  Its sixteen
   // addresses are formed once (clamped into C; out-of-range entries are never stored); with
   // beta != 0 all sixteen reads of C are issued before any is used.
-  double* cp[2][2][4];
+  double* cp[2][FJ][4];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < FJ; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         cp[bi][bj][v] = elem_ptr(C, min(m0 + wm + bi * 16 + (lane & 15), M - 1),
                                  min(n0 + wn + bj * 16 + (lane >> 4) + 4 * v, N - 1));
   if (beta != 0.0) {
-    double cv[2][2][4];
+    double cv[2][FJ][4];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bj = 0; bj < FJ; ++bj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bj = 0; bj < FJ; ++bj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[bi][bj][v] = fma(beta, cv[bi][bj][v], acc[bi][bj][v]);
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
+    for (int bj = 0; bj < FJ; ++bj) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm + bi * 16 + (lane & 15);
@@ -381,6 +350,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         if (args.omode == OUT_LOWER_MIRROR && m > n) *elem_ptr(C, n, m) = val;
       }
     }
+  }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
+// a contiguous range of tiles so that neighbouring tiles, which share operand tiles, share an L2.
+__device__ __forceinline__ int xcd_remap(int L, int T) {
+  const int x = L & 7, idx = L >> 3;
+  const int per = T >> 3, rem = T & 7;
+  return x * per + min(x, rem) + idx;
+}
+
+// LOOP: a capped grid (GemmArgs::maxwg) whose workgroups walk the tiles; the XCD mapping is
+// kept when the grid is a multiple of 8.
+template <bool LOOP>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemm_f64_kernel(const GemmArgs args) {
+  __shared__ double As[2][BK][LDS_ROW];
+  __shared__ double Bs[2][BK][LDS_ROW];
+  const int z = blockIdx.z, y = blockIdx.y;
+  if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
+  const bool lasty = (y == (int)gridDim.y - 1);
+  const int M = lasty ? args.Mlast : args.M;
+  const int N = lasty ? args.Nlast : args.N;
+  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * WN;
+  // lower modes: the triangle of the top tilesN x tilesN tiles, then full rows (M >= N)
+  const int T0 = args.omode == OUT_ALL ? 0 : tilesN * (tilesN + 1) / 2;
+  const int T = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
+  const bool remap = (int)gridDim.x == T || (LOOP && ((int)gridDim.x & 7) == 0);
+  auto tile_of = [&](int L, int& ti, int& tj) {
+    if (args.omode == OUT_ALL) {
+      ti = L % tilesM;
+      tj = L / tilesM;
+    } else if (L < T0) {
+      ti = (int)((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
+      while (ti * (ti + 1) / 2 > L) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= L) ++ti;
+      tj = L - ti * (ti + 1) / 2;
+    } else {
+      ti = tilesN + (L - T0) / tilesN;
+      tj = (L - T0) % tilesN;
+    }
+  };
+  if constexpr (LOOP) {
+    for (int V = blockIdx.x; V < T; V += gridDim.x) {
+      int ti, tj;
+      tile_of(remap ? xcd_remap(V, T) : V, ti, tj);
+      gemm_tile(args, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As, Bs);
+    }
+  } else {
+    if ((int)blockIdx.x >= T) return;
+    int ti, tj;
+    tile_of(remap ? xcd_remap(blockIdx.x, T) : (int)blockIdx.x, ti, tj);
+    gemm_tile(args, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As, Bs);
   }
 }
 
@@ -472,8 +495,13 @@ int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s) {
   }
   if (gx <= 0) return 0;
   if (gx > INT_MAX) return -1;
+  const bool capped = a.maxwg > 0 && gx > a.maxwg;
+  if (capped) gx = a.maxwg < 8 ? 8 : (a.maxwg & ~7);
   const ProfToken t = prof_begin(s);
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)gx, ny, nz), dim3(256), 0, s, a);
+  if (capped)
+    hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
   if (t.valid) prof_end_role(t, s, PK_GEMM, (a.tag >= 0 && a.tag < GT_COUNT) ? a.tag : 0,
                             gemm_flops(a, ny) * nz, 0.0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
