@@ -121,9 +121,9 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
     w.ZD = take((long long)n * bb, nz, w.zZD);
     w.ZB = take(bb, nz, w.zZB);
     w.ZC = take(std::max(1LL, 2LL * M.a * M.b), nz, w.zZC);
-    w.TD = take((long long)n * 3 * M.k * M.k, nz, w.zTr);
-    w.TB = take((long long)n * 3 * M.k * M.k, nz, dummy);
-    w.O = take((long long)n * M.k, nz, w.zO);
+    w.TD = take((long long)n * 3 * M.k * M.k * M.nch_rows, nz, w.zTr);
+    w.TB = take((long long)n * 3 * M.k * M.k * M.nch_rows, nz, dummy);
+    w.O = take((long long)n * M.k * M.nch_obs, nz, w.zO);
     w.qD = take((long long)n * 3 * M.k * M.k, 1, dummy);
     w.qB = take((long long)n * 3 * M.k * M.k, 1, dummy);
     w.resid = take(M.k, 1, dummy);
@@ -262,7 +262,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   // sweep already formed [W_j; V_j] and G_j^T G_j
   const SelinvChains si = selinv_of(w);
   const long long bb = (long long)b * b;
-  const int ntrace = 2 * M.k * M.k + M.k;
+  const int ntrace = 2 * M.k * M.k * M.nch_rows + M.k * M.nch_obs;
   for (int j = n - 1; j >= 0; --j) {
     if (selinv_finish(si, j, s)) return ADELIA_E_HIP;
     const double* ZDj = w.ZD + (long long)j * bb;
@@ -443,6 +443,12 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
   ModelDev& M = m->M;
   std::memset(&M, 0, sizeof(M));
   M.k = k; M.ns = ns; M.nt = nt; M.a = a; M.b = (int)b; M.n_obs = n_obs; M.nnz = nnz;
+  M.nch_rows = (ns + kTraceRows - 1) / kTraceRows;
+  {
+    int most = 0;
+    for (int i = 0; i < nt * k; ++i) most = std::max(most, obs_off[i + 1] - obs_off[i]);
+    M.nch_obs = std::max(1, (most + kTraceObs - 1) / kTraceObs);
+  }
   M.sigma = d->sigma_prior; M.tip = d->tip_prec;
   M.uptr = (const int32_t*)(mem + offsets[0]);
   M.uidx = (const int32_t*)(mem + offsets[1]);

@@ -244,8 +244,10 @@ __global__ __launch_bounds__(256) void assemble_tip_kernel(const ModelDev M, dou
 }
 
 // ---- Phase A / C traces of one selected-inverse block ------------------------------------------
-// grid.x: k*k workgroups for <Z_D^(i1,i2), base_s>, k*k for <Z_B^(i1,i2), base_s>, k for the
-// observation term sum_o a_o^T Zhat a_o per field.
+// grid.x: for each of Z_D and Z_B, k*k sub-block pairs x nch_rows slices of kTraceRows pattern
+// rows (<Z^(i1,i2), base_s> restricted to the slice), then k fields x nch_obs slices of
+// kTraceObs observations (sum_o a_o^T Zhat a_o).  Every workgroup writes one partial sum per
+// quantity; grad_kernel adds the slices in order.
 __global__ __launch_bounds__(256) void trace_kernel(const ModelDev M, int j, const double* ZD,
                                                     long long zZD, const double* ZB,
                                                     long long zZB, const double* ZC,
@@ -256,58 +258,64 @@ __global__ __launch_bounds__(256) void trace_kernel(const ModelDev M, int j, con
   const int z = blockIdx.z;
   const int k = M.k, ns = M.ns, b = M.b, a = M.a;
   const int w = blockIdx.x;
-  const int kk = k * k;
-  if (w < 2 * kk) {
-    const bool isB = w >= kk;
-    const int i1 = (w % kk) / k, i2 = (w % kk) % k;
+  const int kk = k * k, nr = M.nch_rows;
+  if (w < 2 * kk * nr) {
+    const bool isB = w >= kk * nr;
+    const int pair = (w % (kk * nr)) / nr, ch = w % nr;
+    const int i1 = pair / k, i2 = pair % k;
     const double* Z = isB ? ZB : ZD;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (!isB || j < M.nt - 1) {
+    const int pr = ch * kTraceRows + (threadIdx.x >> 2);
+    if ((!isB || j < M.nt - 1) && pr < ns) {
       Z += (long long)z * (isB ? zZB : zZD);
-      for (int pr = threadIdx.x; pr < ns; pr += 256) {
-        const long long row = (long long)i1 * ns + pr;
-        for (int e = M.uptr[pr]; e < M.uptr[pr + 1]; ++e) {
-          const double v = Z[row + ((long long)i2 * ns + M.uidx[e]) * b];
-          s0 += v * M.uval[e];
-          s1 += v * M.uval[M.nnz + e];
-          s2 += v * M.uval[2 * M.nnz + e];
-        }
+      const long long row = (long long)i1 * ns + pr;
+      for (int e = M.uptr[pr] + (threadIdx.x & 3); e < M.uptr[pr + 1]; e += 4) {
+        const double v = Z[row + ((long long)i2 * ns + M.uidx[e]) * b];
+        s0 += v * M.uval[e];
+        s1 += v * M.uval[M.nnz + e];
+        s2 += v * M.uval[2 * M.nnz + e];
       }
     }
     s0 = block_sum(s0, red);
     s1 = block_sum(s1, red);
     s2 = block_sum(s2, red);
     if (threadIdx.x == 0) {
-      double* out = (isB ? TB : TD) + (long long)z * zTr + ((long long)j * kk + i1 * k + i2) * 3;
-      out[0] = s0; out[1] = s1; out[2] = s2;
+      double* out = (isB ? TB : TD) + (long long)z * zTr + ((long long)j * kk + pair) * 3 * nr + ch;
+      out[0] = s0;
+      out[nr] = s1;
+      out[2 * nr] = s2;
     }
     return;
   }
-  const int m = w - 2 * kk;
+  const int no = M.nch_obs;
+  const int m = (w - 2 * kk * nr) / no, ch = (w - 2 * kk * nr) % no;
   const double* Zd = ZD + (long long)z * zZD;
   const double* Zc = a ? ZC + (long long)z * zZC : nullptr;
   const double* Zt = a ? ZT + (long long)z * zZT : nullptr;
   double s = 0.0;
-  const int o0 = M.obs_off[j * k + m], o1 = M.obs_off[j * k + m + 1];
-  for (int o = o0 + threadIdx.x; o < o1; o += 256) {
-    long long gidx[4];
-    double wv[4];
-    for (int e = 0; e < 4; ++e) {
-      gidx[e] = (long long)m * ns + M.obs_node[4 * o + e];
-      wv[e] = M.obs_w[4 * o + e];
-    }
-    double v = 0.0;
-    for (int e = 0; e < 4; ++e)
-      for (int e2 = 0; e2 < 4; ++e2) v += wv[e] * wv[e2] * Zd[gidx[e] + gidx[e2] * b];
+  const int o = M.obs_off[j * k + m] + ch * kTraceObs + (threadIdx.x >> 4);
+  if (o < M.obs_off[j * k + m + 1]) {
+    // the 16 + 4a + a^2 products of a_o^T Zhat a_o, spread over the observation's 16 lanes
     const double* xo = M.X + (long long)o * a;
-    for (int e = 0; e < 4; ++e)
-      for (int c = 0; c < a; ++c) v += 2.0 * wv[e] * xo[c] * Zc[c + gidx[e] * a];
-    for (int c = 0; c < a; ++c)
-      for (int c2 = 0; c2 < a; ++c2) v += xo[c] * xo[c2] * Zt[c + (long long)c2 * a];
-    s += v;
+    const int nterm = 16 + 4 * a + a * a;
+    for (int q = threadIdx.x & 15; q < nterm; q += 16) {
+      if (q < 16) {
+        const int e = q >> 2, e2 = q & 3;
+        const long long g = (long long)m * ns + M.obs_node[4 * o + e];
+        const long long g2 = (long long)m * ns + M.obs_node[4 * o + e2];
+        s += M.obs_w[4 * o + e] * M.obs_w[4 * o + e2] * Zd[g + g2 * b];
+      } else if (q < 16 + 4 * a) {
+        const int r = q - 16, e = r / a, c = r % a;
+        const long long g = (long long)m * ns + M.obs_node[4 * o + e];
+        s += 2.0 * M.obs_w[4 * o + e] * xo[c] * Zc[c + g * a];
+      } else {
+        const int r = q - 16 - 4 * a, c = r / a, c2 = r % a;
+        s += xo[c] * xo[c2] * Zt[c + (long long)c2 * a];
+      }
+    }
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) O[(long long)z * zO + (long long)j * k + m] = s;
+  if (threadIdx.x == 0) O[(long long)z * zO + ((long long)j * k + m) * no + ch] = s;
 }
 
 // ---- Phase B: quadratic forms of the mode (Eq. 8) and the data residual -----------------------
@@ -417,17 +425,24 @@ __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const doubl
     const int r = e / (3 * kk);
     const int rest = e % (3 * kk);  // (i1*k + i2)*3 + s
     double a = 0.0, bq = 0.0, c = 0.0;
+    const int nr = M.nch_rows;
+    // the trace of quantity o summed over its row slices, in slice order
+    auto slices = [nr](const double* T, long long o) {
+      double v = 0.0;
+      for (int c = 0; c < nr; ++c) v += T[o * nr + c];
+      return v;
+    };
     for (int t = 0; t < nt; ++t) {
       const long long o = (long long)t * kk * 3 + rest;
       const double md = tmat(M, r, t, 0);
-      a -= 0.5 * md * TD[o];
+      a -= 0.5 * md * slices(TD, o);
       bq -= 0.5 * md * qD[o];
-      c += 0.5 * md * TD[zTr + o];
+      c += 0.5 * md * slices(TD + zTr, o);
       if (t < nt - 1) {
         const double mo = tmat(M, r, t, 1);
-        a -= mo * TB[o];
+        a -= mo * slices(TB, o);
         bq -= mo * qB[o];
-        c += mo * TB[zTr + o];
+        c += mo * slices(TB + zTr, o);
       }
     }
     SA[e] = a;
@@ -447,7 +462,8 @@ __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const doubl
     if (M.role_kind[q] == ROLE_TAU) {
       const int m = M.role_idx[q];
       double so = 0.0;
-      for (int t = 0; t < nt; ++t) so += O[(long long)t * k + m];
+      for (int t = 0; t < nt; ++t)
+        for (int c = 0; c < M.nch_obs; ++c) so += O[((long long)t * k + m) * M.nch_obs + c];
       pa += -0.5 * tau[m] * so;
       dl = 0.5 * M.nobs_field[m] - 0.5 * tau[m] * resid[m];
     }
