@@ -126,7 +126,7 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
     w.O = take((long long)n * M.k * M.nch_obs, nz, w.zO);
     w.qD = take((long long)n * 3 * M.k * M.k, 1, dummy);
     w.qB = take((long long)n * 3 * M.k * M.k, 1, dummy);
-    w.resid = take(M.k, 1, dummy);
+    w.resid = take((long long)M.k * M.nch_resid, 1, dummy);
   }
   w.bytes = off + 256;
   return w;
@@ -276,7 +276,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   }
   // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 0)
   hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k), dim3(256), 0, s, M, w.x, w.qD, w.qB);
-  hipLaunchKernelGGL(resid_kernel, dim3(M.k), dim3(256), 0, s, M, w.x, w.resid);
+  hipLaunchKernelGGL(resid_kernel, dim3(M.k * M.nch_resid), dim3(256), 0, s, M, w.x, w.resid);
   hipLaunchKernelGGL(grad_kernel, dim3(1), dim3(256), 0, s, M, theta, w.phi, w.dphi, w.tau, w.TD,
                      w.TB, w.zTr, w.O, w.qD, w.qB, w.resid, w.ld, w.zsq, w.ZT, w.info, f, grad,
                      info, terms);
@@ -444,6 +444,7 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
   std::memset(&M, 0, sizeof(M));
   M.k = k; M.ns = ns; M.nt = nt; M.a = a; M.b = (int)b; M.n_obs = n_obs; M.nnz = nnz;
   M.nch_rows = (ns + kTraceRows - 1) / kTraceRows;
+  M.nch_resid = std::max(1, (n_obs + kResidObs - 1) / kResidObs);
   {
     int most = 0;
     for (int i = 0; i < nt * k; ++i) most = std::max(most, obs_off[i + 1] - obs_off[i]);

@@ -8,12 +8,14 @@ enum Role { ROLE_RANGE = 0, ROLE_TEMPORAL = 1, ROLE_COUPLING = 2, ROLE_TAU = 3 }
 
 constexpr int kTraceRows = 64;  // pattern rows per trace workgroup (four lanes per row)
 constexpr int kTraceObs = 16;   // observations per trace workgroup (sixteen lanes each)
+constexpr int kResidObs = 1024;  // observations per residual workgroup
 
 struct ModelDev {
   int k, ns, nt, a, b, n_obs, d, nnz;
   // the traces of one block are summed in slices (kTraceRows pattern rows, kTraceObs
   // observations per workgroup) whose partial sums are added in slice order at the end
   int nch_rows, nch_obs;
+  int nch_resid;  // slices of kResidObs observations of the data residual
   double sigma, tip;
   const int32_t* uptr;   // union pattern of c0, g1, g2 (CSR, ns + 1)
   const int32_t* uidx;   // nnz

@@ -361,11 +361,13 @@ __global__ __launch_bounds__(256) void phaseb_kernel(const ModelDev M, const dou
 __global__ __launch_bounds__(256) void resid_kernel(const ModelDev M, const double* x,
                                                     double* resid) {
   __shared__ double red[256];
-  const int m = blockIdx.x;
+  // grid.x = k fields x nch_resid slices of kResidObs observations; one partial sum each
+  const int m = blockIdx.x / M.nch_resid, ch = blockIdx.x % M.nch_resid;
   const int a = M.a, b = M.b, ns = M.ns;
   const double* xT = x + (long long)M.nt * b;
   double s = 0.0;
-  for (int o = threadIdx.x; o < M.n_obs; o += 256) {
+  const int oend = min(M.n_obs, (ch + 1) * kResidObs);
+  for (int o = ch * kResidObs + threadIdx.x; o < oend; o += 256) {
     if (M.obs_f[o] != m) continue;
     const long long base = (long long)M.obs_t[o] * b + (long long)m * ns;
     double yh = 0.0;
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void resid_kernel(const ModelDev M, const doub
     s += rr * rr;
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) resid[m] = s;
+  if (threadIdx.x == 0) resid[blockIdx.x] = s;
 }
 
 __device__ double objective_value(const ModelDev& M, const double* th, const double* tau,
@@ -421,33 +423,45 @@ __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const doubl
   __shared__ double SC[9 * kMaxFields * kMaxFields];
   const int k = M.k, kk = k * k, nt = M.nt, d = M.d;
   const int NE = 9 * kk;
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+  // Per element e = (r, i1, i2, s): sums over the time steps and the trace slices, spread over
+  // the workgroup (each thread takes time steps t = tid, tid + 256, ...; block sums in a fixed
+  // order)
+  __shared__ double red[256];
+  const int nr = M.nch_rows;
+  for (int e = 0; e < NE; ++e) {
     const int r = e / (3 * kk);
     const int rest = e % (3 * kk);  // (i1*k + i2)*3 + s
     double a = 0.0, bq = 0.0, c = 0.0;
-    const int nr = M.nch_rows;
-    // the trace of quantity o summed over its row slices, in slice order
-    auto slices = [nr](const double* T, long long o) {
-      double v = 0.0;
-      for (int c = 0; c < nr; ++c) v += T[o * nr + c];
-      return v;
-    };
-    for (int t = 0; t < nt; ++t) {
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
       const long long o = (long long)t * kk * 3 + rest;
+      double td0 = 0.0, td1 = 0.0, tb0 = 0.0, tb1 = 0.0;
+      for (int q = 0; q < nr; ++q) {
+        td0 += TD[o * nr + q];
+        td1 += TD[zTr + o * nr + q];
+      }
       const double md = tmat(M, r, t, 0);
-      a -= 0.5 * md * slices(TD, o);
+      a -= 0.5 * md * td0;
       bq -= 0.5 * md * qD[o];
-      c += 0.5 * md * slices(TD + zTr, o);
+      c += 0.5 * md * td1;
       if (t < nt - 1) {
+        for (int q = 0; q < nr; ++q) {
+          tb0 += TB[o * nr + q];
+          tb1 += TB[zTr + o * nr + q];
+        }
         const double mo = tmat(M, r, t, 1);
-        a -= mo * slices(TB, o);
+        a -= mo * tb0;
         bq -= mo * qB[o];
-        c += mo * slices(TB + zTr, o);
+        c += mo * tb1;
       }
     }
-    SA[e] = a;
-    SB[e] = bq;
-    SC[e] = c;
+    a = block_sum(a, red);
+    bq = block_sum(bq, red);
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) {
+      SA[e] = a;
+      SB[e] = bq;
+      SC[e] = c;
+    }
   }
   __syncthreads();
   const double fval = objective_value(M, theta, tau, ld[0], ld[1], zsq[0]);
@@ -465,7 +479,9 @@ __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const doubl
       for (int t = 0; t < nt; ++t)
         for (int c = 0; c < M.nch_obs; ++c) so += O[((long long)t * k + m) * M.nch_obs + c];
       pa += -0.5 * tau[m] * so;
-      dl = 0.5 * M.nobs_field[m] - 0.5 * tau[m] * resid[m];
+      double rs = 0.0;
+      for (int c = 0; c < M.nch_resid; ++c) rs += resid[m * M.nch_resid + c];
+      dl = 0.5 * M.nobs_field[m] - 0.5 * tau[m] * rs;
     }
     const double dp = -theta[q] / (M.sigma * M.sigma);
     const double g = pa + pb + pc + dl + dp;
