@@ -27,7 +27,7 @@ PEAK_HBM_GBS = 8000.0
 # profiler names of the library's kernel groups -> device kernel symbols (as rocprofv3 lists them)
 KERNEL_SYMBOLS = {"gemm_f64": "gemm_f64_kernel", "potrf_panel": "potrf_panel_kernel",
                   "gemv": "gemv_t_kernel", "assemble": "assemble_blocks_kernel",
-                  "trace": "trace_kernel", "tip": "tip_kernel"}
+                  "trace": "trace_kernel", "tip": "tip_kernel", "panel_step": "panel_step_kernel"}
 
 
 def parse():

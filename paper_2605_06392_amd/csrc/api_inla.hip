@@ -27,7 +27,7 @@ using namespace adelia;
 struct SideRes {
   hipStream_t s2;
   hipEvent_t ready[3], done[3];
-  Lookahead la;  // its own stream: trailing updates beside the panels of the sweep
+  Lookahead la;  // look-ahead of the sweep: fused steps, or its own stream for large batches
   int side_maxwg;  // workgroup cap of the launches on s2
 };
 
@@ -498,13 +498,13 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
   {
     // The side stream's products (inversion, selected-inversion preparation) run beside the
     // panels of the sweep, whose workgroups each need a CU of their own (most of its LDS): cap
-    // them at 3/8 of the CUs (measured best on 256 CUs).  The look-ahead updates are short and
-    // stay uncapped.
+    // them at 3/8 of the CUs (measured best on 256 CUs).
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
         cus <= 0)
       cus = 256;
     m->side.la.maxwg = 0;
+    m->side.la.cus = cus;
     m->side.side_maxwg = std::max(8, (3 * cus / 8) & ~7);
   }
   m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess &&

@@ -104,8 +104,8 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
   double* Rows = hasB ? LBC : LBC + b;
   const int mT = (hasB ? b : 0) + ap;
   // rank-64 update of the columns from `from` on (the rows below them and the rows of
-  // [B_i; C~_i]) with panel k, on stream st
-  auto trailing = [&](int k, int from, hipStream_t st) -> int {
+  // [B_i; C~_i]) with panel k
+  auto trailing_args = [&](int k, int from) -> GemmArgs {
     const int c0 = k * kPanel;
     const int rest = b - from;
     GemmArgs g{};
@@ -125,32 +125,47 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     g.tag = GT_TRAIL;
     g.zn = c.zn;
     g.step = i;
-    g.maxwg = (la && st == la->ts) ? la->maxwg : 0;
-    return launch_gemm(g, 1, nz, st) ? ADELIA_E_HIP_INTERNAL : 0;
+    return g;
   };
   // 1. blocked Cholesky of D_i; each panel also solves its columns of [B_i; C~_i] (the fused
   //    TRSM of Alg. 1, which with the rhs row yields z_i), and the trailing updates cover the
-  //    block and those rows alike
+  //    block and those rows alike.  With the look-ahead, panel k applies panel k-1's update to
+  //    its own columns, and the update of the columns from c0 + 64 on runs beside it: in the
+  //    same launch (batches whose panels leave most CUs idle) or on the look-ahead stream.
+  const bool fuse = la && 2LL * nz * panel_workgroups(b, 0, mT) <= la->cus;
   for (int k = 0; k < npanel; ++k) {
     const int c0 = k * kPanel;
+    double* ldp = c.ldpart + (long long)i * npanel + k;
+    if (fuse) {
+      const bool upd = k >= 1 && b - (c0 + kPanel) > 0;
+      const GemmArgs u = upd ? trailing_args(k - 1, c0 + kPanel) : GemmArgs{};
+      if (launch_panel_step(Dblk, c.zD, Gblk, c.zG, ldp, c.zLd, c.info, c.cnt, c.zn, i, b, c0,
+                            (long long)i * b, mT ? Rows : nullptr, c.zLBC, ldT, mT, 1, nz,
+                            upd ? &u : nullptr, la->maxwg, s))
+        return ADELIA_E_HIP_INTERNAL;
+      continue;
+    }
+    // panel k waits for the update the look-ahead stream issued after panel k-2
     if (la && k >= 2 && hipStreamWaitEvent(s, la->tdone[(k - 2) % 3], 0) != hipSuccess)
       return ADELIA_E_HIP_INTERNAL;
-    if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, c.ldpart + (long long)i * npanel + k, c.zLd,
-                           c.info, c.cnt, c.zn, i, b, c0, (long long)i * b, mT ? Rows : nullptr,
-                           c.zLBC, ldT, mT, la ? 1 : 0, nz, s))
+    if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, ldp, c.zLd, c.info, c.cnt, c.zn, i, b, c0,
+                           (long long)i * b, mT ? Rows : nullptr, c.zLBC, ldT, mT, la ? 1 : 0, nz,
+                           s))
       return ADELIA_E_HIP_INTERNAL;
     if (la) {
-      // the next panel applies this panel's update to its own columns; the columns after it
-      // are updated on the look-ahead stream
+      // panel k+1 applies this panel's update to its own columns; the columns after it are
+      // updated on the look-ahead stream
       if (b - c0 - 2 * kPanel > 0) {
         if (hipEventRecord(la->pdone[k % 3], s) != hipSuccess ||
             hipStreamWaitEvent(la->ts, la->pdone[k % 3], 0) != hipSuccess)
           return ADELIA_E_HIP_INTERNAL;
-        if (int r = trailing(k, c0 + 2 * kPanel, la->ts)) return r;
+        const GemmArgs g = trailing_args(k, c0 + 2 * kPanel);
+        if (launch_gemm(g, 1, nz, la->ts)) return ADELIA_E_HIP_INTERNAL;
         if (hipEventRecord(la->tdone[k % 3], la->ts) != hipSuccess) return ADELIA_E_HIP_INTERNAL;
       }
     } else if (b - c0 - kPanel > 0) {
-      if (int r = trailing(k, c0 + kPanel, s)) return r;
+      const GemmArgs g = trailing_args(k, c0 + kPanel);
+      if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
   // 2. the full inverse, when the caller needs it inline

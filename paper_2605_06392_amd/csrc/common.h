@@ -76,6 +76,7 @@ View view_rowsplit(double* p0, long long ld0, long long zs0, double* p1, long lo
                    long long zs1, int rsplit, bool trans = false);
 void view_set_y(View& v, long long ystride);
 int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s);
+double gemm_flops(const GemmArgs& a, int ny);  // algorithmic flops of one chain
 
 // ---- small kernels (util.hip) -------------------------------------------------------------
 int launch_fill(double* p, long long n, double v, hipStream_t s);
@@ -112,13 +113,15 @@ struct BtaChains {
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
 // Look-ahead for the block Cholesky: each panel launch first applies the previous panel's
-// rank-64 update to its own columns, and the update of the remaining columns runs on stream ts
-// beside the next panel; events order the two streams (panel k waits for the update issued
-// after panel k-2).
+// rank-64 update to its own columns, and the update of the columns after them runs beside the
+// next panel.  Batches whose panel launches leave most CUs idle get it in the same launch
+// (launch_panel_step, consecutive steps in stream order); larger batches run it on stream ts,
+// ordered by events (panel k waits for the update issued after panel k-2).
 struct Lookahead {
+  int maxwg;  // workgroup cap of the update part of a fused step (0: one per tile)
+  int cus;    // CUs of the device: fused steps while 2 x (panel workgroups) <= cus
   hipStream_t ts;
   hipEvent_t pdone[3], tdone[3];
-  int maxwg;  // workgroup cap of each update launch on ts (GemmArgs::maxwg)
 };
 int bta_forward_block(const BtaChains& c, int i, hipStream_t s,
                       const Lookahead* la = nullptr);  // one block step

@@ -1,17 +1,7 @@
-// FP64 matrix-core GEMM for gfx950.
-//
-// C = beta*C + sum_ph alpha_ph * op(A_ph) * op(B_ph) over one or two "phases", batched over
-// grid.z (independent chains) and grid.y (sub-problems).  Operands are strided quadrant views
-// (common.h), which lets one kernel read the block-plus-arrow operands of the BTA sweeps
-// ([L_B; L_C], the augmented inverse [[Z_D, Z_C^T]; [Z_C, Z_T]]) without copies.
-//
-// Tiling: a 256-thread workgroup owns a 64 x 64 tile of C; each of its four wavefronts owns
-// a 32 x 32 quarter as 2 x 2 fragments of v_mfma_f64_16x16x4.  K advances 32 at a time
-// through LDS with the next tile prefetched into registers.  On this instruction lane l holds
-// A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4v][l%16] (v = 0..3); the kernel feeds the
-// B-fragment as the instruction's A operand so that each lane's results lie along a column of
-// C and 16 consecutive lanes write 16 consecutive doubles.
+// Device code of the GEMM (tiles, operand staging, pipeline) is in gemm_dev.h; the FP64 GEMM
+// kernel and its host launcher are here.
 #include "common.h"
+#include "gemm_dev.h"
 #include "profile.h"
 #include <climits>
 #include <cmath>
@@ -19,350 +9,11 @@
 
 namespace adelia {
 
+using namespace gemm_dev;
+
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 32;
-// Four wavefronts per tile (eight, with half the MFMAs per wave and K step, measured slower):
-// wave w owns rows (w % 2) * 32 .. + 32 and columns (w / 2) * WN .. + WN, as 2 x FJ fragments.
-constexpr int NT = 256;
-constexpr int NW = NT / 64;
-constexpr int WN = BN / (NW / 2);
-constexpr int FJ = WN / 16;
-constexpr int NR = BM * BK / NT;  // staging registers per thread per operand tile
-constexpr int LDS_ROW = BM + 1;  // odd pitch (doubles): K-contiguous tiles store without bank conflicts
-
-// A view with the chain (z) and sub-problem (y) offsets applied: four quadrant bases and
-// strides, formed once per workgroup from the uniform kernel arguments.
-struct VP {
-  const double* b[4];
-  long long sr[4], sc[4];
-  int rs, cs;
-};
-
-__device__ __forceinline__ VP make_vp(const View& v, int z, int y) {
-  VP o;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    o.b[q] = v.p[q] + (long long)z * v.zs[q] + (long long)y * v.ys[q];
-    o.sr[q] = v.sr[q];
-    o.sc[q] = v.sc[q];
-  }
-  o.rs = v.rs;
-  o.cs = v.cs;
-  return o;
-}
-
-struct QuadSel {
-  const double* p;
-  long long sr, sc;
-};
-
-// Quadrant q of a view; q may differ between lanes, so the four candidates are selected
-// rather than indexed (an indexed access would put the argument block in scratch).
-__device__ __forceinline__ QuadSel pick(const VP& v, int q) {
-  const bool hi = (q & 1) != 0, right = (q & 2) != 0;
-  QuadSel s;
-  const double* p01 = hi ? v.b[1] : v.b[0];
-  const double* p23 = hi ? v.b[3] : v.b[2];
-  const long long sr01 = hi ? v.sr[1] : v.sr[0], sr23 = hi ? v.sr[3] : v.sr[2];
-  const long long sc01 = hi ? v.sc[1] : v.sc[0], sc23 = hi ? v.sc[3] : v.sc[2];
-  s.p = right ? p23 : p01;
-  s.sr = right ? sr23 : sr01;
-  s.sc = right ? sc23 : sc01;
-  return s;
-}
-
-__device__ __forceinline__ double* elem_ptr(const VP& v, int r, int c) {
-  const bool rb = r >= v.rs, cb = c >= v.cs;
-  QuadSel s = pick(v, (rb ? 1 : 0) + (cb ? 2 : 0));
-  const int rr = rb ? r - v.rs : r;
-  const int cc = cb ? c - v.cs : c;
-  return const_cast<double*>(s.p + rr * s.sr + cc * s.sc);
-}
-
-// Whole region [r0, r0+R) x [c0, c0+Cn) inside one quadrant?  Returns quadrant or -1.
-__device__ __forceinline__ int uniform_quad(const VP& v, int r0, int R, int c0, int Cn) {
-  const bool rb0 = r0 >= v.rs, rb1 = (r0 + R - 1) >= v.rs;
-  const bool cb0 = c0 >= v.cs, cb1 = (c0 + Cn - 1) >= v.cs;
-  if (rb0 != rb1 || cb0 != cb1) return -1;
-  return (rb0 ? 1 : 0) + (cb0 ? 2 : 0);
-}
-
-__device__ __forceinline__ bool tri_zero(int tri, int r, int c) {
-  return (tri == TRI_LOWER && c > r) || (tri == TRI_UPPER && r > c);
-}
-
-// Operand tiles.  A BM x BK tile of logical A (and a BK x BN tile of logical B) goes through NR
-// registers per thread.  The lanes of a wavefront walk the operand's contiguous dimension, so
-// every load instruction reads 256 or 512 consecutive bytes.
-//
-// Fast path: while successive K tiles stay inside one quadrant of the view, the loads are
-// buffer loads whose per-lane offsets are fixed for the whole stretch; a K step only moves the
-// scalar offset.  The buffer descriptor's record count is the quadrant's extent, so lanes of a
-// ragged tile that run past the end of the operand read zero instead of faulting; every value
-// outside the logical operand is masked when the tile is written to LDS.  Tiles that straddle a
-// quadrant boundary take the generic path (per-element addresses clamped into the operand).
-typedef const double __attribute__((address_space(1)))* gptr;
-
-struct OpPipe {
-  __amdgpu_buffer_rsrc_t rsrc;
-  int q;            // quadrant of the current stretch (-1: none yet)
-  int mode;         // 0: lanes along M/N, 1: lanes along K
-  int kseg;         // K of the stretch's first tile
-  long long sK;     // element stride along K inside the quadrant
-  unsigned voff[NR];
-  double v[NR];
-};
-
-// (row, col) of register j of a tile; rows run along M (or N), cols along K.
-__device__ __forceinline__ void tile_pos(int mode, int j, int& r, int& c) {
-  const int tid = threadIdx.x;
-  const int r0 = tid & 63, c0 = (tid >> 6) + (NT / 64) * j;
-  const int r1 = (tid >> 5) + (NT / 32) * j, c1 = tid & 31;
-  r = mode ? r1 : r0;
-  c = mode ? c1 : c0;
-}
-
-// Quadrant holding the whole tile (tile rows [r0, r0+BM) clipped to R, K range [k0, k0+BK)
-// clipped to Kn), or -1 when it straddles a split.  colsfirst: the view's first index is K.
-__device__ __forceinline__ int tile_quad(const VP& V, int R, int Kn, int r0, int k0, bool colsfirst) {
-  const int r1 = min(r0 + BM, R) - 1, k1 = min(k0 + BK, Kn) - 1;
-  const int vr0 = colsfirst ? k0 : r0, vr1 = colsfirst ? k1 : r1;
-  const int vc0 = colsfirst ? r0 : k0, vc1 = colsfirst ? r1 : k1;
-  const bool rb0 = vr0 >= V.rs, rb1 = vr1 >= V.rs, cb0 = vc0 >= V.cs, cb1 = vc1 >= V.cs;
-  if (rb0 != rb1 || cb0 != cb1) return -1;
-  return (rb0 ? 1 : 0) + (cb0 ? 2 : 0);
-}
-
-// Issue the loads of tile (r0, k0).  Nothing reads the loaded registers before store_tile.
-__device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn, int r0, int k0,
-                                          bool colsfirst) {
-  const int q = tile_quad(V, R, Kn, r0, k0, colsfirst);
-  if (q >= 0) {
-    if (q != P.q) {  // a new stretch: descriptor and per-lane offsets
-      QuadSel s = pick(V, q);
-      const int Rv = colsfirst ? Kn : R, Cv = colsfirst ? R : Kn;
-      const int rlo = (q & 1) ? V.rs : 0, rhi = (q & 1) ? Rv : min(V.rs, Rv);
-      const int clo = (q & 2) ? V.cs : 0, chi = (q & 2) ? Cv : min(V.cs, Cv);
-      const long long last = (long long)(rhi - rlo - 1) * s.sr + (long long)(chi - clo - 1) * s.sc;
-      const long long bytes = 8 * (last + 1);
-      P.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(s.p), (short)0,
-                                                 (int)min(bytes, 0x7ffffff0LL), 0x00020000);
-      const long long sR = colsfirst ? s.sc : s.sr;
-      P.sK = colsfirst ? s.sr : s.sc;
-      P.mode = (sR != 1 && P.sK == 1) ? 1 : 0;
-      P.kseg = k0;
-      const int tr = (colsfirst ? r0 - clo : r0 - rlo), tk = (colsfirst ? k0 - rlo : k0 - clo);
-#pragma unroll
-      for (int j = 0; j < NR; ++j) {
-        int r, c;
-        tile_pos(P.mode, j, r, c);
-        P.voff[j] = (unsigned)(8 * ((long long)(tr + r) * sR + (long long)(tk + c) * P.sK));
-      }
-      P.q = q;
-    }
-    const int soff = (int)(8 * (long long)(k0 - P.kseg) * P.sK);
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-      const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(P.rsrc, (int)P.voff[j], soff, 0);
-      P.v[j] = __builtin_bit_cast(double, w);
-    }
-    return;
-  }
-  P.q = -1;
-  P.mode = 0;
-  gptr ptr[NR];
-#pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    int r, c;
-    tile_pos(0, j, r, c);
-    const int gr = min(r0 + r, R - 1), gc = min(k0 + c, Kn - 1);
-    ptr[j] = (gptr)(colsfirst ? elem_ptr(V, gc, gr) : elem_ptr(V, gr, gc));
-  }
-#pragma unroll
-  for (int j = 0; j < NR; ++j) P.v[j] = *ptr[j];
-}
-
-// Write a tile to LDS as T[c][r] (K-major).  Tiles inside the operand with no triangle go
-// straight through; otherwise what lies outside the operand or on the zero side of a
-// triangular operand is written as zero.  tri is in the view's own (row, col) orientation: for
-// A that is (m, k), for B it is (k, n).
-__device__ __forceinline__ void store_tile(const OpPipe& P, double (*T)[LDS_ROW], int R, int Kn,
-                                           int r0, int k0, int tri, bool colsfirst) {
-  const bool interior = (r0 + BM <= R) && (k0 + BK <= Kn) && tri == TRI_NONE;
-  if (interior) {
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      int r, c;
-      tile_pos(P.mode, j, r, c);
-      T[c][r] = P.v[j];
-    }
-    return;
-  }
-#pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    int r, c;
-    tile_pos(P.mode, j, r, c);
-    const int gr = r0 + r, gc = k0 + c;
-    bool ok = gr < R && gc < Kn;
-    if (tri) ok = ok && !(colsfirst ? tri_zero(tri, gc, gr) : tri_zero(tri, gr, gc));
-    T[c][r] = ok ? P.v[j] : 0.0;
-  }
-}
-
-__device__ __forceinline__ void krange(int mode, int K, int m0, int n0, int& klo, int& khi) {
-  klo = 0;
-  khi = K;
-  switch (mode) {
-    case KR_GE_N0: klo = n0; break;
-    case KR_LT_N1: khi = min(K, n0 + BN); break;
-    case KR_LT_M1: khi = min(K, m0 + BM); break;
-    case KR_GE_MAX: klo = max(m0, n0); break;
-    default: break;
-  }
-  klo = (klo / BK) * BK;
-  if (klo > K) klo = K;
-}
-
-// One K step on the matrix cores: 8 x 2 FJ MFMAs per wave over a 32-deep slice of the LDS tiles.
-__device__ __forceinline__ void mfma_step(const double (*As)[LDS_ROW], const double (*Bs)[LDS_ROW],
-                                          int wm, int wn, int lane, v4d (&acc)[2][FJ]) {
-#pragma unroll
-  for (int kk = 0; kk < BK / 4; ++kk) {
-    const int kr = kk * 4 + (lane >> 4);
-    const double a0 = As[kr][wm + (lane & 15)];
-    const double a1 = As[kr][wm + 16 + (lane & 15)];
-    double b[FJ];
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) b[bj] = Bs[kr][wn + 16 * bj + (lane & 15)];
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) {
-      acc[0][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[bj], a0, acc[0][bj], 0, 0, 0);
-      acc[1][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[bj], a1, acc[1][bj], 0, 0, 0);
-    }
-  }
-}
-
-// One phase as a software pipeline with a single site per stage (the kernel stays small, which
-// matters for short launches).  Iteration t issues the global loads of K tile t, runs tile t-1
-// from LDS on the matrix cores, then writes tile t to the other LDS buffer; one barrier per
-// iteration.  alpha is applied by the caller to the accumulators.
-__device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
-                                          bool lasty, int z, int y, int wm, int wn, int lane,
-                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW],
-                                          v4d (&acc)[2][FJ]) {
-  const int K = lasty ? ph.Klast : ph.K;
-  int klo, khi;
-  krange(ph.kmode, K, m0, n0, klo, khi);
-  const int nk = klo < khi ? (khi - klo + BK - 1) / BK : 0;
-  const VP A = make_vp(ph.A, z, y), B = make_vp(ph.B, z, y);
-  OpPipe pa, pb;
-  pa.q = -1;
-  pb.q = -1;
-  for (int t = 0; t <= nk; ++t) {
-    const int k0 = klo + t * BK;
-    if (t < nk) {
-      load_tile(pa, A, M, K, m0, k0, false);
-      load_tile(pb, B, N, K, n0, k0, true);
-    }
-    if (t > 0) mfma_step(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
-    if (t < nk) {
-      store_tile(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
-      store_tile(pb, Bs[t & 1], N, K, n0, k0, ph.triB, true);
-    }
-    __syncthreads();
-  }
-}
-
-// One 64 x 64 output tile at (m0, n0).
-__device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, int m0, int n0,
-                                          bool lasty, int z, int y, int wm, int wn, int lane,
-                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW]) {
-  const VP C = make_vp(args.C, z, y);
-  const double beta = args.beta;
-  const bool lowerC = args.omode != OUT_ALL;
-  v4d acc[2][FJ];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
-  // acc collects sum_p alpha_p A_p B_p: the products of phase p are accumulated unscaled, the
-  // running sum is rescaled by alpha_{p-1} / alpha_p before phase p and by the last alpha at the
-  // end (exact for the +-1 used on the sweeps).
-  double alpha_prev = 1.0;
-  for (int p = 0; p < args.nph; ++p) {
-    const double alpha = args.ph[p].alpha;
-    if (p > 0) {
-      const double sc = alpha_prev / alpha;
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= sc;
-    }
-    run_phase(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
-    alpha_prev = alpha;
-  }
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= alpha_prev;
-
-  // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v).  Its sixteen
-  // addresses are formed once (clamped into C; out-of-range entries are never stored); with
-  // beta != 0 all sixteen reads of C are issued before any is used.
-  double* cp[2][FJ][4];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        cp[bi][bj][v] = elem_ptr(C, min(m0 + wm + bi * 16 + (lane & 15), M - 1),
-                                 min(n0 + wn + bj * 16 + (lane >> 4) + 4 * v, N - 1));
-  if (beta != 0.0) {
-    double cv[2][FJ][4];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < FJ; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < FJ; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[bi][bj][v] = fma(beta, cv[bi][bj][v], acc[bi][bj][v]);
-  }
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi) {
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm + bi * 16 + (lane & 15);
-        const int n = n0 + wn + bj * 16 + (lane >> 4) + 4 * v;
-        if (m >= M || n >= N) continue;
-        if (lowerC && m < n) continue;
-        const double val = acc[bi][bj][v];
-        *cp[bi][bj][v] = val;
-        if (args.omode == OUT_LOWER_MIRROR && m > n) *elem_ptr(C, n, m) = val;
-      }
-    }
-  }
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
-// a contiguous range of tiles so that neighbouring tiles, which share operand tiles, share an L2.
-__device__ __forceinline__ int xcd_remap(int L, int T) {
-  const int x = L & 7, idx = L >> 3;
-  const int per = T >> 3, rem = T & 7;
-  return x * per + min(x, rem) + idx;
-}
-
-// LOOP: a capped grid (GemmArgs::maxwg) whose workgroups walk the tiles; the XCD mapping is
-// kept when the grid is a multiple of 8.
+// LOOP: a capped grid (GemmArgs::maxwg) whose workgroups walk the tiles.
 template <bool LOOP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemm_f64_kernel(const GemmArgs args) {
   __shared__ double As[2][BK][LDS_ROW];
@@ -370,41 +21,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   const int z = blockIdx.z, y = blockIdx.y;
   if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
   const bool lasty = (y == (int)gridDim.y - 1);
-  const int M = lasty ? args.Mlast : args.M;
-  const int N = lasty ? args.Nlast : args.N;
-  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * WN;
-  // lower modes: the triangle of the top tilesN x tilesN tiles, then full rows (M >= N)
-  const int T0 = args.omode == OUT_ALL ? 0 : tilesN * (tilesN + 1) / 2;
-  const int T = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
-  const bool remap = (int)gridDim.x == T || (LOOP && ((int)gridDim.x & 7) == 0);
-  auto tile_of = [&](int L, int& ti, int& tj) {
-    if (args.omode == OUT_ALL) {
-      ti = L % tilesM;
-      tj = L / tilesM;
-    } else if (L < T0) {
-      ti = (int)((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
-      while (ti * (ti + 1) / 2 > L) --ti;
-      while ((ti + 1) * (ti + 2) / 2 <= L) ++ti;
-      tj = L - ti * (ti + 1) / 2;
-    } else {
-      ti = tilesN + (L - T0) / tilesN;
-      tj = (L - T0) % tilesN;
-    }
-  };
-  if constexpr (LOOP) {
-    for (int V = blockIdx.x; V < T; V += gridDim.x) {
-      int ti, tj;
-      tile_of(remap ? xcd_remap(V, T) : V, ti, tj);
-      gemm_tile(args, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As, Bs);
-    }
-  } else {
-    if ((int)blockIdx.x >= T) return;
-    int ti, tj;
-    tile_of(remap ? xcd_remap(blockIdx.x, T) : (int)blockIdx.x, ti, tj);
-    gemm_tile(args, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As, Bs);
-  }
+  gemm_walk<LOOP>(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
 }
 
 }  // namespace

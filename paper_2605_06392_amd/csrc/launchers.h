@@ -1,4 +1,4 @@
-// Launch wrappers implemented in potrf.hip / util.hip (host side).
+// Launch wrappers implemented in panel.hip / step.hip / potrf.hip / util.hip (host side).
 #pragma once
 #include "common.h"
 
@@ -9,6 +9,15 @@ int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double*
                        long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
                        int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
                        int upd, int nz, hipStream_t s);
+// Workgroups of one panel launch per chain, and its algorithmic flops per chain.
+int panel_workgroups(int b, int c0, int mT);
+double panel_flops(int b, int c0, int mT, int upd);
+// Panel launch fused with the trailing update U of the previous panel (step.hip); U == nullptr
+// or an empty U: the panel alone.  At most maxw workgroups (0: one per tile) walk U's tiles.
+int launch_panel_step(double* D, long long zD, double* G, long long zG, double* ldp,
+                      long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
+                      int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
+                      int upd, int nz, const GemmArgs* U, int maxw, hipStream_t s);
 int launch_tip(double* T, long long zT, int a, int ap, double* ldp, long long zLd, int32_t* info,
                long long gcol0, double* zsq, double* ZT, long long zZT, double* xT,
                long long zXT, int nz, hipStream_t s);

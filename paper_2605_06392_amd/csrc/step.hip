@@ -1,0 +1,76 @@
+// One step of the look-ahead blocked Cholesky of a diagonal block as a single launch
+// (Sec. III-A-1, Alg. 1, chol()): the workgroups of panel k+1 come first in the grid, so they
+// are placed before any others, and the remaining workgroups apply panel k's rank-64 update to
+// the columns from c0_k + 128 on (and to the rows of [B_i; C~_i] below them).  Panel k+1 applies
+// panel k's update to its own columns itself, so the two parts touch disjoint columns: the
+// update writes columns >= c0_{k+1} + 64 and reads those of panel k, which panel k+1 only reads.
+// Consecutive steps run in stream order, with no events between them.
+#include "common.h"
+#include "gemm_dev.h"
+#include "launchers.h"
+#include "panel_dev.h"
+#include "profile.h"
+
+namespace adelia {
+
+namespace {
+
+struct GemmSmem {
+  double As[2][gemm_dev::BK][gemm_dev::LDS_ROW];
+  double Bs[2][gemm_dev::BK][gemm_dev::LDS_ROW];
+};
+
+union StepSmem {
+  panel_dev::PanelSmem p;
+  GemmSmem g;
+};
+
+__global__ __launch_bounds__(256) void panel_step_kernel(const panel_dev::PanelArgs P, int npw,
+                                                         const GemmArgs U, int ntw) {
+  static_assert(gemm_dev::NT == 256, "the panel and the tile GEMM share the workgroup shape");
+  __shared__ StepSmem sm;
+  const int bx = blockIdx.x;
+  if (bx < npw) {
+    panel_dev::panel_body(P, bx, npw, sm.p);
+    return;
+  }
+  const int z = blockIdx.z;
+  if (U.zn && U.step >= U.zn[z]) return;  // chain z has no block at this step
+  gemm_dev::gemm_walk<true>(U, z, 0, true, bx - npw, ntw, sm.g.As, sm.g.Bs);
+}
+
+}  // namespace
+
+int launch_panel_step(double* D, long long zD, double* G, long long zG, double* ldp,
+                      long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
+                      int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
+                      int upd, int nz, const GemmArgs* U, int maxw, hipStream_t s) {
+  long long tiles = 0;
+  if (U) {
+    // one sub-problem, one phase, lower output (the trailing update)
+    if (U->nph != 1 || U->omode == OUT_ALL || U->M != U->Mlast || U->N != U->Nlast ||
+        U->M < U->N)
+      return -1;
+    const long long tM = (U->M + gemm_dev::BM - 1) / gemm_dev::BM;
+    const long long tN = (U->N + gemm_dev::BN - 1) / gemm_dev::BN;
+    tiles = U->N > 0 ? tN * (tN + 1) / 2 + (tM - tN) * tN : 0;
+  }
+  if (tiles == 0)
+    return launch_potrf_panel(D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT,
+                              ldT, mT, upd, nz, s);
+  if (!cnt) return -1;
+  if (!T) mT = 0;
+  if (mT < 0 || (mT > 0 && ldT < mT) || nz > 65535) return -1;
+  panel_dev::PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT, ldT,
+                         mT, upd};
+  const int npw = panel_workgroups(b, c0, mT);
+  int ntw = (int)tiles;
+  if (maxw > 0 && ntw > maxw) ntw = maxw < 8 ? 8 : (maxw & ~7);
+  const ProfToken t = prof_begin(s);
+  hipLaunchKernelGGL(panel_step_kernel, dim3(npw + ntw, 1, nz), dim3(256), 0, s, P, npw, *U, ntw);
+  if (t.valid)
+    prof_end(t, s, PK_STEP, nz * panel_flops(b, c0, mT, upd) + gemm_flops(*U, 1) * nz, 0.0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace adelia
