@@ -498,14 +498,16 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
   {
     // The side stream's products (inversion, selected-inversion preparation) run beside the
     // panels of the sweep, whose workgroups each need a CU of their own (most of its LDS): cap
-    // them at 3/8 of the CUs (measured best on 256 CUs).
+    // them at 5/8 of the CUs in tile slots, two tiles per workgroup (gemm_f64_dual_kernel), i.e.
+    // on 5/16 of the CUs (measured on 256 CUs: 144-168 slots all best, 128 and 176 clearly
+    // worse).
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
         cus <= 0)
       cus = 256;
     m->side.la.maxwg = 0;
     m->side.la.cus = cus;
-    m->side.side_maxwg = std::max(8, (3 * cus / 8) & ~7);
+    m->side.side_maxwg = std::max(16, (5 * cus / 8) & ~15);
   }
   m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess &&
                 hipStreamCreateWithFlags(&m->side.la.ts, hipStreamNonBlocking) == hipSuccess;

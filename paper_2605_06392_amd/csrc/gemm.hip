@@ -24,6 +24,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   gemm_walk<LOOP>(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
 }
 
+// Capped one-phase launches: two tiles per 512-thread workgroup (gemm_walk_dual).
+__global__ __launch_bounds__(2 * NT) void gemm_f64_dual_kernel(const GemmArgs args) {
+  __shared__ double As[2][2][BK][LDS_ROW];
+  __shared__ double Bs[2][2][BK][LDS_ROW];
+  const int z = blockIdx.z, y = blockIdx.y;
+  if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
+  const bool lasty = (y == (int)gridDim.y - 1);
+  gemm_walk_dual(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
+}
+
 }  // namespace
 
 
@@ -114,8 +124,13 @@ int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s) {
   if (gx > INT_MAX) return -1;
   const bool capped = a.maxwg > 0 && gx > a.maxwg;
   if (capped) gx = a.maxwg < 8 ? 8 : (a.maxwg & ~7);
+  // a capped one-phase launch takes two tiles per workgroup: maxwg tile slots on maxwg / 2 CUs
+  const bool dual = capped && a.nph == 1 && gx >= 16;
   const ProfToken t = prof_begin(s);
-  if (capped)
+  if (dual)
+    hipLaunchKernelGGL(gemm_f64_dual_kernel, dim3((unsigned)(gx / 16 * 8), ny, nz), dim3(2 * NT), 0,
+                       s, a);
+  else if (capped)
     hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
   else
     hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);

@@ -114,7 +114,7 @@ struct OpPipe {
 
 // (row, col) of register j of a tile; rows run along M (or N), cols along K.
 __device__ __forceinline__ void tile_pos(int mode, int j, int& r, int& c) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x & (NT - 1);  // thread within the tile's wavefronts
   const int r0 = tid & 63, c0 = (tid >> 6) + (NT / 64) * j;
   const int r1 = (tid >> 5) + (NT / 32) * j, c1 = tid & 31;
   r = mode ? r1 : r0;
@@ -273,39 +273,13 @@ __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int
   }
 }
 
-// One 64 x 64 output tile at (m0, n0).
-__device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, int m0, int n0,
-                                          bool lasty, int z, int y, int wm, int wn, int lane,
-                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW]) {
+// C = beta C + acc on the tile at (m0, n0) (its written part).
+__device__ __forceinline__ void tile_store(const GemmArgs& args, int M, int N, int m0, int n0,
+                                           int z, int y, int wm, int wn, int lane,
+                                           v4d (&acc)[2][FJ]) {
   const VP C = make_vp(args.C, z, y);
   const double beta = args.beta;
   const bool lowerC = args.omode != OUT_ALL;
-  v4d acc[2][FJ];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
-  // acc collects sum_p alpha_p A_p B_p: the products of phase p are accumulated unscaled, the
-  // running sum is rescaled by alpha_{p-1} / alpha_p before phase p and by the last alpha at the
-  // end (exact for the +-1 used on the sweeps).
-  double alpha_prev = 1.0;
-  for (int p = 0; p < args.nph; ++p) {
-    const double alpha = args.ph[p].alpha;
-    if (p > 0) {
-      const double sc = alpha_prev / alpha;
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= sc;
-    }
-    run_phase(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
-    alpha_prev = alpha;
-  }
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= alpha_prev;
-
   // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v).  Its sixteen
   // addresses are formed once (clamped into C; out-of-range entries are never stored); with
   // beta != 0 all sixteen reads of C are issued before any is used.
@@ -351,12 +325,82 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, in
   }
 }
 
+// One 64 x 64 output tile at (m0, n0).
+__device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, int m0, int n0,
+                                          bool lasty, int z, int y, int wm, int wn, int lane,
+                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW]) {
+  v4d acc[2][FJ];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // acc collects sum_p alpha_p A_p B_p: the products of phase p are accumulated unscaled, the
+  // running sum is rescaled by alpha_{p-1} / alpha_p before phase p and by the last alpha at the
+  // end (exact for the +-1 used on the sweeps).
+  double alpha_prev = 1.0;
+  for (int p = 0; p < args.nph; ++p) {
+    const double alpha = args.ph[p].alpha;
+    if (p > 0) {
+      const double sc = alpha_prev / alpha;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= sc;
+    }
+    run_phase(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
+    alpha_prev = alpha;
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= alpha_prev;
+
+  tile_store(args, M, N, m0, n0, z, y, wm, wn, lane, acc);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
 // a contiguous range of tiles so that neighbouring tiles, which share operand tiles, share an L2.
 __device__ __forceinline__ int xcd_remap(int L, int T) {
   const int x = L & 7, idx = L >> 3;
   const int per = T >> 3, rem = T & 7;
   return x * per + min(x, rem) + idx;
+}
+
+// K steps of the tile at (m0, n0) in phase ph.
+__device__ __forceinline__ int tile_nk(const GemmPhase& ph, bool lasty, int m0, int n0) {
+  int klo, khi;
+  krange(ph.kmode, lasty ? ph.Klast : ph.K, m0, n0, klo, khi);
+  return klo < khi ? (khi - klo + BK - 1) / BK : 0;
+}
+
+// run_phase for two tiles in one workgroup: both halves run nkr + 1 pipeline iterations (one
+// barrier each), a half whose tile has fewer K steps (or no tile) idles through the rest.
+__device__ __forceinline__ void run_phase_locked(const GemmPhase& ph, int M, int N, int m0, int n0,
+                                                 bool lasty, int z, int y, int wm, int wn,
+                                                 int lane, double (*As)[BK][LDS_ROW],
+                                                 double (*Bs)[BK][LDS_ROW], v4d (&acc)[2][FJ],
+                                                 bool has, int nkr) {
+  const int K = lasty ? ph.Klast : ph.K;
+  int klo, khi;
+  krange(ph.kmode, K, m0, n0, klo, khi);
+  const int nk = has && klo < khi ? (khi - klo + BK - 1) / BK : 0;
+  const VP A = make_vp(ph.A, z, y), B = make_vp(ph.B, z, y);
+  OpPipe pa, pb;
+  pa.q = -1;
+  pb.q = -1;
+  for (int t = 0; t <= nkr; ++t) {
+    const int k0 = klo + t * BK;
+    if (t < nk) {
+      load_tile(pa, A, M, K, m0, k0, false);
+      load_tile(pb, B, N, K, n0, k0, true);
+    }
+    if (t > 0 && t <= nk) mfma_step(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
+    if (t < nk) {
+      store_tile(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
+      store_tile(pb, Bs[t & 1], N, K, n0, k0, ph.triB, true);
+    }
+    __syncthreads();
+  }
 }
 
 // Tile (ti, tj) of linear index L: column-major over all tiles, or for the lower modes the
@@ -374,6 +418,56 @@ __device__ __forceinline__ void tile_of(int omode, int L, int tilesM, int tilesN
   } else {
     ti = tilesN + (L - T0) / tilesN;
     tj = (L - T0) % tilesN;
+  }
+}
+
+// Two tiles per 512-thread workgroup (waves 0-3 and 4-7, each half with its own LDS buffers), so
+// that every SIMD holds two waves: a capped launch of one-phase products reaches the matrix
+// cores' two-wave rate on half as many CUs.  Workgroup b of G takes tile slots b and b + G, then
+// b + 2G and b + 3G, ...; with G a multiple of 8 every slot stays on its workgroup's XCD range.
+__device__ __forceinline__ void gemm_walk_dual(const GemmArgs& args, int z, int y, bool lasty,
+                                               int b, int G, double (*As)[2][BK][LDS_ROW],
+                                               double (*Bs)[2][BK][LDS_ROW]) {
+  const int M = lasty ? args.Mlast : args.M;
+  const int N = lasty ? args.Nlast : args.N;
+  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  const int h = threadIdx.x >> 8;
+  const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) & 3;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * WN;
+  const int T0 = args.omode == OUT_ALL ? 0 : tilesN * (tilesN + 1) / 2;
+  const int T = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
+  const bool remap = (G & 7) == 0;
+  const GemmPhase& ph = args.ph[0];
+  for (int base = b; base < T; base += 2 * G) {
+    int nkr = 0, ti = 0, tj = 0;
+    bool has = false;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int V = base + q * G;
+      if (V >= T) continue;
+      int qi, qj;
+      tile_of(args.omode, remap ? xcd_remap(V, T) : V, tilesM, tilesN, T0, qi, qj);
+      nkr = max(nkr, tile_nk(ph, lasty, qi * BM, qj * BN));
+      if (q == h) {
+        has = true;
+        ti = qi;
+        tj = qj;
+      }
+    }
+    v4d acc[2][FJ];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+    run_phase_locked(ph, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As[h], Bs[h], acc,
+                     has, nkr);
+    if (has) {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= ph.alpha;
+      tile_store(args, M, N, ti * BM, tj * BN, z, y, wm, wn, lane, acc);
+    }
   }
 }
 
