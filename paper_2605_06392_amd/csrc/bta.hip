@@ -324,12 +324,27 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.ph[0].kmode = KR_FULL;
     g.ph[0].alpha = -1.0;
     g.C = view_rowsplit(p.ZBj, b, c.zZB, p.ZCj ? p.ZCj : p.ZBj, a ? a : 1, c.zZC, b);
-    g.M = g.Mlast = b + a;
+    // a few arrow rows would add a row of mostly empty 64-row tiles to the product (a second
+    // round of workgroups when the tiles exactly fill the device): they go through the short
+    // product kernel instead
+    const bool skinny = a > 0 && a <= kSkinnyRows;
+    g.M = g.Mlast = skinny ? b : b + a;
     g.N = g.Nlast = b;
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_SI_Z;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    if (skinny) {  // Z_Cj = -(Z_C,j+1 W + Z_T V)
+      Skinny k{};
+      k.m = a; k.N = b; k.K1 = b; k.K2 = a;
+      k.A1 = p.ZCn; k.lda1 = a; k.zA1 = c.zZC;
+      k.B1 = p.Wm; k.ldb1 = b; k.zB1 = zW;
+      k.A2 = c.ZT; k.lda2 = a; k.zA2 = c.zZT;
+      k.B2 = p.V; k.ldb2 = a; k.zB2 = zW;
+      k.C = p.ZCj; k.ldc = a; k.zC = c.zZC;
+      k.alpha = -1.0; k.beta = 0.0;
+      if (launch_skinny(k, nz, s)) return ADELIA_E_HIP_INTERNAL;
+    }
   } else if (a) {
     GemmArgs g{};
     g.nph = 1;

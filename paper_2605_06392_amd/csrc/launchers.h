@@ -30,4 +30,16 @@ int launch_tri_small(const double* L, long long ld, long long zL, double* v, lon
 int launch_logdiag(const double* L, int b, long long ld, long long bs, int nblk, double* part,
                    long long zL, long long zp, int nz, hipStream_t s);
 int launch_fill_strided(double* p, long long stride, int count, double v, hipStream_t s);
+// C = alpha (A1 B1 + A2 B2) + beta C for m <= kSkinnyRows rows (util.hip); A2 may be null
+constexpr int kSkinnyRows = 8, kSkinnyCols = 8;
+struct Skinny {
+  int m, N, K1, K2;
+  const double* A1; long long lda1, zA1;
+  const double* B1; long long ldb1, zB1;
+  const double* A2; long long lda2, zA2;
+  const double* B2; long long ldb2, zB2;
+  double* C; long long ldc, zC;
+  double alpha, beta;
+};
+int launch_skinny(const Skinny& g, int nz, hipStream_t s);
 }  // namespace adelia

@@ -2,6 +2,7 @@
 // the triangular solves (Sec. III-A-2, Eqs. 3-5).  Reductions use a fixed order (no atomics)
 // so that repeated runs are bitwise identical.
 #include "common.h"
+#include "launchers.h"
 #include "profile.h"
 #include <climits>
 
@@ -163,6 +164,54 @@ inline unsigned grid_for(long long n) {
 
 }  // namespace
 
+// C(r, n) = alpha * (sum_k A1(r, k) B1(k, n) + sum_k A2(r, k) B2(k, n)) + beta * C(r, n) for the
+// m <= kSkinnyRows rows of a short, wide product (column-major operands; A2/B2 may be absent).
+// Each wavefront takes kSkinnyCols columns; its lanes walk K (coalesced reads of B's columns),
+// each lane reads the m values of A at its k once for all its columns, and the 64 partial sums
+// are combined by a fixed-order reduce-scatter butterfly that leaves sum i on lane i.
+__global__ __launch_bounds__(256) void skinny_kernel(const Skinny g) {
+  const int z = blockIdx.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n0 = (blockIdx.x * 4 + wave) * kSkinnyCols;
+  if (n0 >= g.N) return;
+  double v[kSkinnyRows * kSkinnyCols];
+#pragma unroll
+  for (int i = 0; i < kSkinnyRows * kSkinnyCols; ++i) v[i] = 0.0;
+  auto part = [&](const double* A, long long lda, const double* B, long long ldb, int K) {
+    for (int k = lane; k < K; k += 64) {
+      double av[kSkinnyRows];
+#pragma unroll
+      for (int r = 0; r < kSkinnyRows; ++r) av[r] = r < g.m ? A[r + (long long)k * lda] : 0.0;
+#pragma unroll
+      for (int j = 0; j < kSkinnyCols; ++j) {
+        const double bv = B[k + (long long)min(n0 + j, g.N - 1) * ldb];
+#pragma unroll
+        for (int r = 0; r < kSkinnyRows; ++r) v[r * kSkinnyCols + j] = fma(av[r], bv, v[r * kSkinnyCols + j]);
+      }
+    }
+  };
+  part(g.A1 + (long long)z * g.zA1, g.lda1, g.B1 + (long long)z * g.zB1, g.ldb1, g.K1);
+  if (g.A2 && g.K2 > 0)
+    part(g.A2 + (long long)z * g.zA2, g.lda2, g.B2 + (long long)z * g.zB2, g.ldb2, g.K2);
+  // reduce-scatter: at offset o a lane keeps half of its current values (the upper half if bit
+  // o of its lane id is set) and adds the partner's copy of that half
+#pragma unroll
+  for (int o = 32, cnt = 64; o >= 1; o >>= 1, cnt >>= 1) {
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < cnt / 2; ++i) {
+      const double send = up ? v[i] : v[i + cnt / 2];
+      const double keep = up ? v[i + cnt / 2] : v[i];
+      v[i] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  const int r = lane / kSkinnyCols, n = n0 + lane % kSkinnyCols;
+  if (r < g.m && n < g.N) {
+    double* c = g.C + (long long)z * g.zC + r + (long long)n * g.ldc;
+    *c = g.alpha * v[0] + (g.beta != 0.0 ? g.beta * *c : 0.0);
+  }
+}
+
 int launch_fill(double* p, long long n, double v, hipStream_t s) {
   if (n <= 0) return 0;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
@@ -244,4 +293,17 @@ int launch_fill_strided(double* p, long long stride, int count, double v, hipStr
                      count, v);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+int launch_skinny(const Skinny& g, int nz, hipStream_t s) {
+  if (g.m < 1 || g.m > kSkinnyRows || g.N < 0 || g.K1 < 0 || g.K2 < 0 || nz < 1 || nz > 65535)
+    return -1;
+  if (g.N == 0) return 0;
+  const ProfToken t = prof_begin(s);
+  hipLaunchKernelGGL(skinny_kernel, dim3((g.N + 4 * kSkinnyCols - 1) / (4 * kSkinnyCols), 1, nz),
+                     dim3(256), 0, s, g);
+  if (t.valid)
+    prof_end(t, s, PK_GEMV, nz * 2.0 * g.m * (double)g.N * (g.K1 + g.K2),
+             nz * 8.0 * ((double)g.N * (g.K1 + g.K2) + (double)g.m * (g.K1 + g.K2) + g.m * g.N));
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 }  // namespace adelia
