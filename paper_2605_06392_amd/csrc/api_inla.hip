@@ -198,7 +198,11 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
     si.prep_maxwg = side->side_maxwg;
   }
   hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, 0, -1, w.D, w.zD,
-                     w.Bin, w.zB, w.phi, w.tau);
+                     w.Bin, w.zB, (long long)b, w.phi, w.tau);
+  // With the side stream (a gradient: every block keeps its [L_B; L_C] slot), B_i is assembled
+  // straight into the rows of [L_B; L_C] of block i instead of a separate slot.
+  c.b_in_place = fork;
+  const long long ldT = (long long)b + w.ap;
   for (int i = 0; i < n; ++i) {
     // the slot about to receive D_{i+1} held D_{i-2}: its inverse must be complete
     if (fork && i >= 2 && hipStreamWaitEvent(s, side->done[(i - 2) % 3], 0) != hipSuccess)
@@ -207,9 +211,11 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
     const int tb = i < n - 1 ? i : -1;
     if (td >= 0 || tb >= 0) {
       double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * bb;
+      double* Bslot = fork ? w.LBC + (long long)(i % w.slotsLBC) * ldT * b : w.Bin;
       const ProfToken t = prof_begin(s);
       hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, td, tb, Dslot,
-                         w.zD, w.Bin, w.zB, w.phi, w.tau);
+                         w.zD, Bslot, fork ? w.zLBC : w.zB, fork ? ldT : (long long)b, w.phi,
+                         w.tau);
       if (t.valid) prof_end(t, s, PK_ASSEMBLE, 0.0, 8.0 * bb * nz * ((td >= 0) + (tb >= 0)));
       if (!LAUNCH_OK()) return ADELIA_E_HIP;
     }

@@ -96,7 +96,8 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
   double* LBC = c.LBC + blk_off(i, c.slotsLBC, (long long)ldT * b);
   const bool hasB = i < n - 1;
   // 0. the rows solved with the panels of L_Di: [B_i; C~_i] (C~_i alone for the last block)
-  if (hasB && launch_copy2d(c.Bin + blk_off(i, c.slotsB, bb), b, c.zB, LBC, ldT, c.zLBC, b, b, nz, s))
+  if (hasB && !c.b_in_place &&
+      launch_copy2d(c.Bin + blk_off(i, c.slotsB, bb), b, c.zB, LBC, ldT, c.zLBC, b, b, nz, s))
     return ADELIA_E_HIP_INTERNAL;
   if (ap > 0 &&
       launch_copy2d(c.C + (long long)i * ap * b, ap, c.zC, LBC + b, ldT, c.zLBC, ap, b, nz, s))

@@ -110,6 +110,7 @@ struct BtaChains {
   double* ZT; long long zZT;                // a x a per chain: [Q^-1]_{T,T} (may be null)
   double* xT; long long zXT;                // a per chain: L_T^-T z_T (may be null)
   int inv_maxwg;                            // workgroup cap of bta_invert_block's launches
+  bool b_in_place;                          // B_t already assembled into the rows of [L_B; L_C]
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
 // Look-ahead for the block Cholesky: each panel launch first applies the previous panel's

@@ -41,7 +41,7 @@ struct ModelDev {
 __global__ void param_kernel(const ModelDev M, const double* theta, double* phi, double* dphi,
                              double* tau);
 __global__ void assemble_blocks_kernel(const ModelDev M, int td, int tb, double* D, long long zD,
-                                       double* B, long long zB, const double* phi,
+                                       double* B, long long zB, long long ldB, const double* phi,
                                        const double* tau);
 __global__ void assemble_arrow_kernel(const ModelDev M, double* C, long long zC, int ap,
                                       const double* tau);

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void param_kernel(const ModelDev M, const doub
 __global__ __launch_bounds__(64) void assemble_blocks_kernel(const ModelDev M, int td, int tb,
                                                              double* D, long long zD,
                                                              double* B, long long zB,
-                                                             const double* phi,
+                                                             long long ldB, const double* phi,
                                                              const double* tau) {
   const int z = blockIdx.z;
   const int p = z >> 1;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(64) void assemble_blocks_kernel(const ModelDev M, i
   const int q = blockIdx.x;
   const int lane = threadIdx.x;
   double* Dc = td >= 0 ? D + (long long)z * zD + (long long)q * b : nullptr;
-  double* Bc = tb >= 0 ? B + (long long)z * zB + (long long)q * b : nullptr;
+  double* Bc = tb >= 0 ? B + (long long)z * zB + (long long)q * ldB : nullptr;
   for (int r = lane; r < b; r += 64) {
     if (Dc) Dc[r] = 0.0;
     if (Bc) Bc[r] = 0.0;
