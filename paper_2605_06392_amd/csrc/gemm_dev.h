@@ -273,17 +273,11 @@ __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int
   }
 }
 
-// C = beta C + acc on the tile at (m0, n0) (its written part).
-__device__ __forceinline__ void tile_store(const GemmArgs& args, int M, int N, int m0, int n0,
-                                           int z, int y, int wm, int wn, int lane,
-                                           v4d (&acc)[2][FJ]) {
-  const VP C = make_vp(args.C, z, y);
-  const double beta = args.beta;
-  const bool lowerC = args.omode != OUT_ALL;
-  // epilogue: lane holds C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v).  Its sixteen
-  // addresses are formed once (clamped into C; out-of-range entries are never stored); with
-  // beta != 0 all sixteen reads of C are issued before any is used.
-  double* cp[2][FJ][4];
+// Addresses of the sixteen C entries of the calling lane: lane holds
+// C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v), clamped into C (out-of-range entries are
+// never stored).
+__device__ __forceinline__ void tile_c_addr(const VP& C, int M, int N, int m0, int n0, int wm,
+                                            int wn, int lane, double* (&cp)[2][FJ][4]) {
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -292,14 +286,17 @@ __device__ __forceinline__ void tile_store(const GemmArgs& args, int M, int N, i
       for (int v = 0; v < 4; ++v)
         cp[bi][bj][v] = elem_ptr(C, min(m0 + wm + bi * 16 + (lane & 15), M - 1),
                                  min(n0 + wn + bj * 16 + (lane >> 4) + 4 * v, N - 1));
+}
+
+// C = beta C + acc on the tile (its written part), with cv the values of C read earlier (only
+// used when beta != 0; every tile's C is read and written by its own workgroup alone).
+__device__ __forceinline__ void tile_finish(const GemmArgs& args, const VP& C, int M, int N,
+                                            int m0, int n0, int wm, int wn, int lane,
+                                            double* (&cp)[2][FJ][4], const double (&cv)[2][FJ][4],
+                                            v4d (&acc)[2][FJ]) {
+  const double beta = args.beta;
+  const bool lowerC = args.omode != OUT_ALL;
   if (beta != 0.0) {
-    double cv[2][FJ][4];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < FJ; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -325,10 +322,43 @@ __device__ __forceinline__ void tile_store(const GemmArgs& args, int M, int N, i
   }
 }
 
+// C = beta C + acc on the tile at (m0, n0) (its written part), C read now.
+__device__ __forceinline__ void tile_store(const GemmArgs& args, int M, int N, int m0, int n0,
+                                           int z, int y, int wm, int wn, int lane,
+                                           v4d (&acc)[2][FJ]) {
+  const VP C = make_vp(args.C, z, y);
+  double* cp[2][FJ][4];
+  tile_c_addr(C, M, N, m0, n0, wm, wn, lane, cp);
+  double cv[2][FJ][4];
+  if (args.beta != 0.0) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < FJ; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
+  }
+  tile_finish(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc);
+}
+
 // One 64 x 64 output tile at (m0, n0).
 __device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
                                           double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW]) {
+  // with beta != 0 the reads of C are issued first, so that their latency overlaps the K loop
+  // (short-K tiles, such as the rank-64 updates, would otherwise wait for them at the end)
+  const VP C = make_vp(args.C, z, y);
+  double* cp[2][FJ][4];
+  tile_c_addr(C, M, N, m0, n0, wm, wn, lane, cp);
+  double cv[2][FJ][4];
+  if (args.beta != 0.0) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < FJ; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
+  }
   v4d acc[2][FJ];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -354,8 +384,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, in
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= alpha_prev;
-
-  tile_store(args, M, N, m0, n0, z, y, wm, wn, lane, acc);
+  tile_finish(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
