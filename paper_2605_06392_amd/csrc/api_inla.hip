@@ -219,14 +219,32 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
       if (t.valid) prof_end(t, s, PK_ASSEMBLE, 0.0, 8.0 * bb * nz * ((td >= 0) + (tb >= 0)));
       if (!LAUNCH_OK()) return ADELIA_E_HIP;
     }
-    if (bta_forward_block(c, i, s, side ? &side->la : nullptr)) return ADELIA_E_HIP;
-    if (fork) {
-      if (hipEventRecord(side->ready[i % 3], s) != hipSuccess ||
-          hipStreamWaitEvent(side->s2, side->ready[i % 3], 0) != hipSuccess)
+    // The side work of block i-1 (its inversion and the selected-inversion preparation) is
+    // forked after the first step of block i rather than right after block i-1: the first steps
+    // of a block carry most of its update tiles and run faster without the side stream's
+    // products beside them (measured 47.7 against 48.6 ms per gradient; forking after later
+    // steps lets the side stream fall behind).
+    Lookahead la{};
+    if (side) la = side->la;
+    la.mark = nullptr;
+    const bool late = fork && i >= 1;
+    if (late) {
+      la.mark = side->ready[(i - 1) % 3];
+      la.mark_step = 0;
+    }
+    if (bta_forward_block(c, i, s, side ? &la : nullptr)) return ADELIA_E_HIP;
+    auto fork_block = [&](int j, bool recorded) -> int {
+      if ((!recorded && hipEventRecord(side->ready[j % 3], s) != hipSuccess) ||
+          hipStreamWaitEvent(side->s2, side->ready[j % 3], 0) != hipSuccess)
         return ADELIA_E_HIP;
-      if (bta_invert_block(c, i, side->s2)) return ADELIA_E_HIP;
-      if (hipEventRecord(side->done[i % 3], side->s2) != hipSuccess) return ADELIA_E_HIP;
-      if (selinv_prepare(si, i, side->s2)) return ADELIA_E_HIP;
+      if (bta_invert_block(c, j, side->s2)) return ADELIA_E_HIP;
+      if (hipEventRecord(side->done[j % 3], side->s2) != hipSuccess) return ADELIA_E_HIP;
+      if (selinv_prepare(si, j, side->s2)) return ADELIA_E_HIP;
+      return 0;
+    };
+    if (fork) {
+      if (late && fork_block(i - 1, true)) return ADELIA_E_HIP;
+      if (i == n - 1 && fork_block(i, false)) return ADELIA_E_HIP;
     } else if (w.grad) {
       if (selinv_prepare(si, i, s)) return ADELIA_E_HIP;
     }
@@ -442,7 +460,7 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
       hipFree(mem);
       return ADELIA_E_HIP;
     }
-  inla_model m = new inla_model_s;
+  inla_model m = new inla_model_s();  // value-initialised: every handle starts null
   m->device = ctx->device;
   m->param = d->param;
   m->dev_mem = mem;
@@ -513,6 +531,8 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
       cus = 256;
     m->side.la.maxwg = 0;
     m->side.la.cus = cus;
+    m->side.la.mark = nullptr;
+    m->side.la.mark_step = 0;
     m->side.side_maxwg = std::max(16, (5 * cus / 8) & ~15);
   }
   m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess &&

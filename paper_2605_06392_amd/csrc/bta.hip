@@ -20,6 +20,7 @@
 //   Z_Dj = G_j^T G_j - [Z_Bj; Z_Cj]^T [W; V].
 #include "common.h"
 #include "launchers.h"
+#include <algorithm>
 
 namespace adelia {
 
@@ -144,6 +145,9 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
                             (long long)i * b, mT ? Rows : nullptr, c.zLBC, ldT, mT, 1, nz,
                             upd ? &u : nullptr, la->maxwg, s))
         return ADELIA_E_HIP_INTERNAL;
+      if (la->mark && k == std::min(la->mark_step, npanel - 1) &&
+          hipEventRecord(la->mark, s) != hipSuccess)
+        return ADELIA_E_HIP_INTERNAL;
       continue;
     }
     // panel k waits for the update the look-ahead stream issued after panel k-2
@@ -152,6 +156,9 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, ldp, c.zLd, c.info, c.cnt, c.zn, i, b, c0,
                            (long long)i * b, mT ? Rows : nullptr, c.zLBC, ldT, mT, la ? 1 : 0, nz,
                            s))
+      return ADELIA_E_HIP_INTERNAL;
+    if (la && la->mark && k == std::min(la->mark_step, npanel - 1) &&
+        hipEventRecord(la->mark, s) != hipSuccess)
       return ADELIA_E_HIP_INTERNAL;
     if (la) {
       // panel k+1 applies this panel's update to its own columns; the columns after it are

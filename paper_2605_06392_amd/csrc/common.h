@@ -121,6 +121,8 @@ int bta_forward(const BtaChains& c, hipStream_t s);
 struct Lookahead {
   int maxwg;  // workgroup cap of the update part of a fused step (0: one per tile)
   int cus;    // CUs of the device: fused steps while 2 x (panel workgroups) <= cus
+  hipEvent_t mark;  // if not null: recorded on the sweep's stream after step (panel) mark_step
+  int mark_step;
   hipStream_t ts;
   hipEvent_t pdone[3], tdone[3];
 };
