@@ -14,6 +14,7 @@ sample of the same workload as the CPU baseline.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -87,14 +88,32 @@ def timed(fn, steps, warmup, use_graph, torch):
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for t in range(steps):
         run()
-    e1.record()
+        ev[t + 1].record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    per_call = [ev[t].elapsed_time(ev[t + 1]) for t in range(steps)]
+    TIMES[id(fn)] = per_call
+    return ev[0].elapsed_time(ev[steps]) / steps
+
+
+TIMES = {}
+
+
+def median_ci(xs):
+    """Median and a distribution-free 95% confidence interval for it (order statistics of the
+    binomial(n, 1/2) ranks, normal approximation)."""
+    v = sorted(xs)
+    n = len(v)
+    if n == 0:
+        return None
+    med = v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+    half = 0.98 * math.sqrt(n)
+    lo = v[max(0, int(math.floor(n / 2 - half)))]
+    hi = v[min(n - 1, int(math.ceil(n / 2 + half)) - 1)]
+    return {"median": med, "ci95": [lo, hi], "n": n}
 
 
 def algorithmic_flops(b, n, a):
@@ -193,6 +212,97 @@ def cpu_baseline(spec_name, seed, nt_sample):
     }
 
 
+UNEVEN_COUNT = 64
+
+
+def uneven_shapes(seed, count=UNEVEN_COUNT):
+    """An uneven batch: b in {128, 256, 512, 1024}, n in [8, 64], a in [2, 8], drawn from seed."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(8, 65)), int(rng.choice([128, 256, 512, 1024])),
+             int(rng.integers(2, 9))) for _ in range(count)]
+
+
+def bench_uneven(args, torch):
+    """Batched factorisation (with the fused lower solve) of an uneven batch of BTA matrices in
+    one call: every launch of the sweep covers all matrices of a block size at once."""
+    from paper_2605_06392_amd import bta
+    from workloads.bta import random_bta_device
+
+    dev = torch.device("cuda:0")
+    shapes = uneven_shapes(args.seed)
+    keys = ("D", "B", "C", "T")
+    pristine, work = [], []
+    for i, (n, b, a) in enumerate(shapes):
+        blk = random_bta_device(n, b, a, args.seed * 1000 + i, dev)
+        m = {"D": bta.to_cm(blk["D"]), "B": bta.to_cm(blk["B"]) if n > 1 else None,
+             "C": bta.to_cm(blk["C"]), "T": bta.to_cm(blk["T"][None])[0], "rhs": blk["rhs"]}
+        del blk
+        pristine.append(m)
+        work.append({k: (v.clone() if v is not None else None) for k, v in m.items()})
+
+    def restore():
+        for w, p in zip(work, pristine):
+            for k in keys + ("rhs",):
+                if p[k] is not None:
+                    w[k].copy_(p[k])
+
+    # the factorisation's algorithmic work (App. B, one matrix): POTRF b^3/3 per block, TRSM and
+    # the Schur update b^3 each for every block but the last
+    flops = sum(((n - 1) * 7.0 / 3.0 + 1.0 / 3.0) * b ** 3 for n, b, _ in shapes)
+    for _ in range(max(1, args.warmup)):
+        restore()
+        bta.bta_factor_batched(work, with_rhs=True)
+    torch.cuda.synchronize()
+    per_call = []
+    infos_ok = True
+    for _ in range(args.steps):
+        restore()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, logdet, info = bta.bta_factor_batched(work, with_rhs=True)
+        e1.record()
+        torch.cuda.synchronize()
+        per_call.append(e0.elapsed_time(e1))
+        infos_ok = infos_ok and bool((info == 0).all().item())
+    # consistency: the smallest matrices factorised one at a time give the same log-determinants
+    order = sorted(range(len(shapes)), key=lambda i: shapes[i][0] * shapes[i][1] ** 2)[:3]
+    rel = 0.0
+    for i in order:
+        m = {k: (v.clone() if v is not None else None) for k, v in pristine[i].items()}
+        _, ld1, inf1 = bta.bta_factor(m["D"], m["B"], m["C"], m["T"], m["rhs"])
+        rel = max(rel, abs(ld1.item() - logdet[i].item()) / abs(ld1.item()))
+        infos_ok = infos_ok and int(inf1.item()) == 0
+    mean = sum(per_call) / len(per_call)
+    line = {
+        "metric": "BTA factorisations/s, uneven batch in one call",
+        "value": len(shapes) * 1000.0 / mean,
+        "unit": "matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mean,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uneven64", "count": len(shapes), "seed": args.seed,
+                   "b_counts": {str(bb): sum(1 for _, b, _ in shapes if b == bb)
+                                for bb in (128, 256, 512, 1024)},
+                   "n_range": [min(n for n, _, _ in shapes), max(n for n, _, _ in shapes)],
+                   "a_range": [min(a for _, _, a in shapes), max(a for _, _, a in shapes)],
+                   "rhs": True},
+        "ms_per_call": median_ci(per_call),
+        "tflops_paper_flop_model": flops / (mean * 1e-3) / 1e12,
+        "algorithmic_flops_per_call": flops,
+        "check": {"info_ok": infos_ok, "logdet_vs_single_rel": rel},
+        "peak_device_memory_gb": torch.cuda.max_memory_allocated() / 1e9,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -202,6 +312,10 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.workload == "uneven64":
+        torch.cuda.set_device(0)
+        bench_uneven(args, torch)
+        return
     from workloads import NAMED_CONFIGS, named_config
     from paper_2605_06392_amd import bta, inla
 
@@ -237,7 +351,11 @@ def main():
         return
 
     # accuracy at full size: AD vs GPU central differences with h = 1e-4
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
     model.grad(theta, f=f_ad, g=g_ad, info=i_ad)
+    torch.cuda.synchronize()
+    peak_ad = torch.cuda.max_memory_allocated()
     model.fd_grad(theta, h=1e-4, f=f_fd, g=g_fd, info=i_fd)
     torch.cuda.synchronize()
     gad = g_ad.cpu().numpy()
@@ -285,7 +403,13 @@ def main():
         "beta_bwd_over_fwd": ms_bwd / ms_fwd,
         "c_AD": ms_ad / (ms_fd / npts),
         "ad_tflops_paper_flop_model": (fwd_fl + si_fl) / (ms_ad * 1e-3) / 1e12,
+        "objectives_per_s_fd_batch": npts * 1000.0 / ms_fd,
         "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": ad_fd_rel, "info_ok": ok},
+        "ms_ad_per_call": median_ci(TIMES.get(id(ad_step), [])),
+        "ms_fd_per_call": median_ci(TIMES.get(id(fd_step), [])),
+        # torch-owned device memory (every workspace; the model's own upload is a few MB)
+        "peak_device_memory_gb": {"ad": peak_ad / 1e9,
+                                  "with_fd_batch": torch.cuda.max_memory_allocated() / 1e9},
         "kernels": {kname: {"launches_per_step": v["launches"] / args.profile_steps,
                             "ms_per_step": v["ms"] / args.profile_steps,
                             "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None}
