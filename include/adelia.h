@@ -231,7 +231,7 @@ int inla_grad(inla_model model, const double* theta, double* f, double* grad, in
 int inla_grad_terms(inla_model model, const double* theta, double* terms, int32_t* info,
                     void* ws, size_t ws_bytes, int flags, void* stream);
 
-/* Central finite-difference gradient (Sec. II-C, Eq. 2) on the GPU: the 2d+1 points
+/* Central finite-difference gradient (Sec. II-D, Eq. 2) on the GPU: the 2d+1 points
  * theta, theta +- h e_j are evaluated as batched objectives (in sub-batches of at most
  * `max_batch` points, sized by the caller's workspace = inla_workspace_bytes(model,
  * max_batch, OBJECTIVE)); grad_j = (f(theta+h e_j) - f(theta-h e_j)) / 2h, f = f(theta).

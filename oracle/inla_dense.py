@@ -33,7 +33,10 @@ What is computed (paper references are to sections, equations and tables):
   ``dQp/dtheta_k`` is assembled analytically.  This formula is pinned in the tests against
   the complex-step derivative of ``objective(..., factor="lu")`` and against central
   differences.
-* Central differences, Sec. II-C, Eq. 2, with 2d+1 evaluations.
+* Central differences, Sec. II-D, Eq. 2, with 2d+1 evaluations.
+* The posterior Hessian, Sec. III-D, Eq. 12: column j is the central difference of the exact
+  gradient along e_j (2d+1 gradient evaluations), not symmetrised; and the FD baseline it
+  replaces, second-order central differences of f over 2d^2+1 points (Sec. II-D).
 * The selected inverse (Sec. III-A, Phase A): the dense inverse read at the BTA pattern.
 """
 from __future__ import annotations
@@ -44,7 +47,8 @@ import scipy.linalg as sla
 __all__ = [
     "dense_bases", "temporal_dense", "theta_layout", "prior_precision",
     "prior_precision_jacobian", "observation_matrix", "obs_tau", "objective", "gradient",
-    "fd_gradient", "bta_dense", "bta_split", "dense_cholesky", "selected_inverse",
+    "fd_gradient", "hessian_from_gradients", "hessian_fd_of_grad", "second_differences",
+    "fd_hessian", "bta_dense", "bta_split", "dense_cholesky", "selected_inverse",
 ]
 
 
@@ -296,6 +300,52 @@ def fd_gradient(model, theta, h=1e-3):
         e[j] = h
         g[j] = (objective(model, theta + e)["f"] - objective(model, theta - e)["f"]) / (2 * h)
     return g, f0
+
+
+def hessian_from_gradients(grad_fun, theta, h):
+    """Eq. 12 for any gradient routine: H[:, j] = (g(theta + h e_j) - g(theta - h e_j)) / (2h).
+    Returns (H, g(theta)); H is returned as the equation defines it (not symmetrised)."""
+    theta = np.asarray(theta, dtype=float)
+    d = theta.size
+    g0 = np.asarray(grad_fun(theta), dtype=float)
+    H = np.zeros((d, d))
+    for j in range(d):
+        e = np.zeros(d)
+        e[j] = h
+        H[:, j] = (np.asarray(grad_fun(theta + e)) - np.asarray(grad_fun(theta - e))) / (2 * h)
+    return H, g0
+
+
+def hessian_fd_of_grad(model, theta, h=5e-3):
+    """Sec. III-D, Eq. 12 with the exact gradient (Eq. 5): 2d+1 gradient evaluations, the centre
+    one giving f and the gradient at theta.  Returns (H, g, f)."""
+    theta = np.asarray(theta, dtype=float)
+    H, g0 = hessian_from_gradients(lambda t: gradient(model, t)["grad"], theta, h)
+    return H, g0, objective(model, theta)["f"]
+
+
+def second_differences(fun, theta, h):
+    """Second-order central differences of a scalar function over 2d^2+1 points:
+    H_jj = (f(+e_j) - 2 f(0) + f(-e_j)) / h^2 and, for j != k,
+    H_jk = (f(+e_j+e_k) - f(+e_j-e_k) - f(-e_j+e_k) + f(-e_j-e_k)) / (4 h^2), steps of size h.
+    Returns (H, f(theta))."""
+    theta = np.asarray(theta, dtype=float)
+    d = theta.size
+    E = np.eye(d) * h
+    f0 = float(fun(theta))
+    H = np.zeros((d, d))
+    for j in range(d):
+        H[j, j] = (fun(theta + E[j]) - 2.0 * f0 + fun(theta - E[j])) / h ** 2
+        for k in range(j + 1, d):
+            v = (fun(theta + E[j] + E[k]) - fun(theta + E[j] - E[k])
+                 - fun(theta - E[j] + E[k]) + fun(theta - E[j] - E[k])) / (4.0 * h ** 2)
+            H[j, k] = H[k, j] = v
+    return H, f0
+
+
+def fd_hessian(model, theta, h=5e-3):
+    """The FD Hessian that Eq. 12 replaces (Sec. II-D): 2d^2+1 objective evaluations."""
+    return second_differences(lambda t: objective(model, t)["f"], theta, h)
 
 
 # ---- BTA helpers (Sec. II-B layout) -------------------------------------------------------

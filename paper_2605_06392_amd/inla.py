@@ -2,7 +2,7 @@
 
 ``InlaModel`` uploads a model once (``inla_model_create``); ``objective`` evaluates f for a
 batch of theta points, ``grad`` returns f and the exact gradient (Sec. III-A-3, Eq. 5),
-``fd_grad`` the (2d+1)-point central-difference gradient on the GPU (Sec. II-C, Eq. 2), and
+``fd_grad`` the (2d+1)-point central-difference gradient on the GPU (Sec. II-D, Eq. 2), and
 ``InlaObjective`` is the torch.autograd.Function whose forward keeps the Cholesky factors of
 Qc and Qp in the model's workspace and whose backward runs the hand-written reverse pass
 (selected inversion + traces) from them.

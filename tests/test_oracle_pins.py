@@ -288,3 +288,69 @@ def test_bta_cholesky_no_fill_and_leibniz():
 def test_neumann_second_difference():
     d, o = neumann_second_difference(4)
     assert np.array_equal(d, [1, 2, 2, 1]) and np.array_equal(o, [-1, -1, -1])
+
+
+# ---- posterior Hessian (Sec. III-D, Eq. 12) and its FD baseline ----------------------------
+
+def test_hessian_from_gradients_column_orientation_and_scale():
+    # a linear gradient field g(t) = J t + c (J not symmetric): Eq. 12 returns J exactly, column
+    # j being the difference along e_j; a transposed or mis-scaled difference fails
+    rng = np.random.default_rng(4)
+    d = 5
+    J = rng.standard_normal((d, d))
+    c = rng.standard_normal(d)
+    t0 = rng.standard_normal(d)
+    H, g0 = oracle.hessian_from_gradients(lambda t: J @ t + c, t0, 5e-3)
+    assert np.allclose(g0, J @ t0 + c, rtol=0, atol=1e-14)
+    assert np.abs(H - J).max() <= 1e-12
+
+
+def test_difference_hessians_on_a_quartic_closed_form():
+    # f = sum t_i^4 / 12 + t_0^2 t_1^2 / 4.  Central differences of the exact gradient give
+    # t_i^2 + h^2/3 (+ the coupling terms), second differences of f give t_i^2 + h^2/6; the
+    # mixed second difference of t_0^2 t_1^2 / 4 is t_0 t_1 exactly.
+    h = 5e-3
+    t0 = np.array([0.7, -0.4, 0.3])
+
+    def f(t):
+        return np.sum(t ** 4) / 12 + t[0] ** 2 * t[1] ** 2 / 4
+
+    def g(t):
+        out = t ** 3 / 3
+        out[0] += t[0] * t[1] ** 2 / 2
+        out[1] += t[0] ** 2 * t[1] / 2
+        return out
+
+    exact = np.diag(t0 ** 2)
+    exact[0, 0] += t0[1] ** 2 / 2
+    exact[1, 1] += t0[0] ** 2 / 2
+    exact[0, 1] = exact[1, 0] = t0[0] * t0[1]
+    Hg, _ = oracle.hessian_from_gradients(g, t0, h)
+    Hf, f0 = oracle.second_differences(f, t0, h)
+    assert np.isclose(f0, f(t0), rtol=1e-15)
+    assert np.abs(Hg - (exact + np.eye(3) * h * h / 3)).max() <= 1e-12
+    assert np.abs(Hf - (exact + np.eye(3) * h * h / 6)).max() <= 1e-9
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_hessian_without_observations_is_prior_curvature(k):
+    # no observations: f = log p(theta), whose Hessian is -I / sigma^2
+    m = make_model(k, 4, 3, 3, 2, 0, seed=11)
+    s2 = m.sigma_prior ** 2
+    H, g, f = oracle.hessian_fd_of_grad(m, m.theta, h=5e-3)
+    assert np.abs(H + np.eye(m.d) / s2).max() <= 1e-9
+    assert np.allclose(g, -m.theta / s2, rtol=1e-10, atol=1e-10)
+    Hf, f0 = oracle.fd_hessian(m, m.theta, h=5e-3)
+    assert np.isclose(f0, f, rtol=1e-13)
+    assert np.abs(Hf + np.eye(m.d) / s2).max() <= 1e-6
+
+
+def test_hessian_of_gradients_agrees_with_second_differences():
+    # two independent routes to the same Hessian (exact gradients vs f alone) agree to their
+    # O(h^2) truncation, and Eq. 12's H is symmetric to the same order
+    m = named_config("uni_6x5_nt5", seed=7)
+    H, _, _ = oracle.hessian_fd_of_grad(m, m.theta, h=5e-3)
+    Hf, _ = oracle.fd_hessian(m, m.theta, h=5e-3)
+    scale = np.abs(H).max()
+    assert np.abs(H - Hf).max() <= 1e-5 * scale
+    assert np.abs(H - H.T).max() <= 1e-5 * scale
