@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nt", type=int, default=5)
     ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--hessian", action="store_true",
+                    help="time the posterior Hessian of Eq. 12 (2d+1 exact gradients) against "
+                         "the 2d^2+1-point finite-difference Hessian instead")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the event-profiled gradient steps (the command rocprofv3 traces)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -303,6 +306,82 @@ def bench_uneven(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_hessian(args, model, theta, spec, torch, np):
+    """Posterior Hessian at theta: Eq. 12 (2d+1 exact gradients, one graph) against the
+    second-order FD Hessian (2d^2+1 objectives: the faster of one batched call and sub-batches
+    of 2d+1 points)."""
+    d = model.d
+    dev = theta.device
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(d, dtype=torch.float64, device=dev)
+    H = torch.empty((d, d), dtype=torch.float64, device=dev)
+    info = torch.empty(2 * d + 1, dtype=torch.int32, device=dev)
+    nfd = 2 * d * d + 1
+    Hf = torch.empty((d, d), dtype=torch.float64, device=dev)
+    ff = torch.empty(1, dtype=torch.float64, device=dev)
+    info_f = torch.empty(nfd, dtype=torch.int32, device=dev)
+    use_graph = not args.no_graph
+    # Eq. 12: the 2d+1 gradients in as few passes as the memory allows (and one at a time)
+    total = torch.cuda.get_device_properties(dev).total_memory
+    ad_batches = sorted({1, model.fitting_batch(2 * d + 1, 1)})
+    ad_ms, ad_calls = {}, {}
+    for mb in ad_batches:
+        ad = lambda: model.hessian(theta, h=5e-3, max_batch=mb, f=f, g=g, H=H, info=info)  # noqa: E731,B023
+        ad_ms[mb] = timed(ad, args.steps, args.warmup, use_graph, torch)
+        ad_calls[mb] = TIMES[id(ad)]
+    best_ad = min(ad_ms, key=ad_ms.get)
+    ms_ad = ad_ms[best_ad]
+    torch.cuda.synchronize()
+    peak_ad = torch.cuda.max_memory_allocated()
+    fd_ms = {}
+    fd_calls = {}
+    # batch sizes whose objective workspace fits in half of the device memory
+    sizes = [mb for mb in sorted({nfd, 2 * d + 1})
+             if model.workspace_bytes(mb, 0) <= total // 2] or [2 * d + 1]
+    for mb in sizes:
+        fd = lambda: model.fd_hessian(theta, h=5e-3, max_batch=mb, f=ff, H=Hf, info=info_f)  # noqa: E731,B023
+        fd_ms[mb] = timed(fd, max(1, args.steps // 2), min(1, args.warmup), use_graph, torch)
+        fd_calls[mb] = TIMES[id(fd)]
+    best = min(fd_ms, key=fd_ms.get)
+    torch.cuda.synchronize()
+    Hn, Hfn = H.cpu().numpy(), Hf.cpu().numpy()
+    scale = np.abs(Hn).max()
+    k, nx, ny, nt, a, obs = NAMED_CONFIGS_REF[args.workload]
+    line = {
+        "metric": "posterior Hessians/s: Eq. 12 (2d+1 exact gradients) vs 2d^2+1-point FD",
+        "value": 1000.0 / ms_ad,
+        "unit": "hessians/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_ad,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "b": k * nx * ny, "n": nt, "a": a, "d": d,
+                   "h": 5e-3, "seed": args.seed, "graph": use_graph},
+        "ad_hessian_max_batch": best_ad,
+        "ms_ad_hessian_by_batch": {str(mb_): v for mb_, v in ad_ms.items()},
+        "ms_per_fd_hessian": fd_ms[best],
+        "fd_hessian_max_batch": best,
+        "ms_fd_hessian_by_batch": {str(mb_): v for mb_, v in fd_ms.items()},
+        "ad_over_fd_speedup": fd_ms[best] / ms_ad,
+        "ms_ad_per_call": median_ci(ad_calls[best_ad]),
+        "ms_fd_per_call": median_ci(fd_calls[best]),
+        "check": {"info_ok": bool((info == 0).all().item()) and bool((info_f == 0).all().item()),
+                  "asymmetry_rel": float(np.abs(Hn - Hn.T).max() / scale),
+                  "ad_vs_fd_hessian_rel": float(np.abs(Hn - Hfn).max() / scale)},
+        "peak_device_memory_gb": {"ad": peak_ad / 1e9,
+                                  "with_fd_batch": torch.cuda.max_memory_allocated() / 1e9},
+    }
+    print(json.dumps(line), flush=True)
+
+
+NAMED_CONFIGS_REF = {}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -317,6 +396,7 @@ def main():
         bench_uneven(args, torch)
         return
     from workloads import NAMED_CONFIGS, named_config
+    NAMED_CONFIGS_REF.update(NAMED_CONFIGS)
     from paper_2605_06392_amd import bta, inla
 
     dev = torch.device("cuda:0")
@@ -332,6 +412,10 @@ def main():
     f_fd = torch.empty(1, dtype=torch.float64, device=dev)
     g_fd = torch.empty(d, dtype=torch.float64, device=dev)
     i_fd = torch.empty(npts, dtype=torch.int32, device=dev)
+
+    if args.hessian:
+        bench_hessian(args, model, theta, spec, torch, np)
+        return
 
     if args.roofline_only:
         ad_only = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731

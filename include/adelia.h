@@ -199,9 +199,10 @@ int inla_model_dim(inla_model model);
 /* Thread-local text of the last validation failure (set-up calls only). */
 const char* adelia_last_error(void);
 
-/* Workspace for evaluating `batch` theta points (mode = ADELIA_MODE_OBJECTIVE), or for a
- * gradient (mode = ADELIA_MODE_GRAD; batch must be 1): the forward factors of Qc and Qp are
- * kept in it between inla_objective(SAVE) and inla_grad(REUSE). */
+/* Workspace for evaluating `batch` theta points (mode = ADELIA_MODE_OBJECTIVE), or for the
+ * gradients of `batch` points (mode = ADELIA_MODE_GRAD): the forward factors of Qc and Qp are
+ * kept in it between inla_objective(SAVE) and inla_grad(REUSE).  A gradient workspace keeps
+ * every block's factor, W and G^T G: about (4n + 6) b^2 doubles per matrix and point. */
 #define ADELIA_MODE_OBJECTIVE 0
 #define ADELIA_MODE_GRAD 1
 size_t inla_workspace_bytes(inla_model model, int batch, int mode);
@@ -223,6 +224,15 @@ int inla_objective(inla_model model, const double* theta, int32_t batch, double*
 int inla_grad(inla_model model, const double* theta, double* f, double* grad, int32_t* info,
               void* ws, size_t ws_bytes, int flags, void* stream);
 
+/* f and the exact gradient at `batch` points (theta: device, batch x d, row-major; f, info:
+ * batch; grad: batch x d, row-major) in one pass: every launch of the forward sweeps and of
+ * the reverse pass covers the 2 * batch chains (Qc and Qp of each point) at once.  Workspace:
+ * inla_workspace_bytes(model, batch, GRAD) or larger.  The saved factors are not reusable
+ * with REUSE afterwards unless batch == 1.  Errors: -k for argument k, ADELIA_E_WORKSPACE,
+ * ADELIA_E_HIP. */
+int inla_grad_batched(inla_model model, const double* theta, int32_t batch, double* f,
+                      double* grad, int32_t* info, void* ws, size_t ws_bytes, void* stream);
+
 /* inla_grad with its decomposition, for diagnostics and identities: terms (device,
  * 5 + 6d doubles) = [f, log|Qp|, log|Qc|, |z|^2 (z = L_c^-1 r), tr([Qc^-1]_{T,T}),
  * PhaseA(d), PhaseB(d), PhaseC(d), dlog l/dtheta(d), dlog p/dtheta(d), grad(d)], where
@@ -239,6 +249,30 @@ int inla_grad_terms(inla_model model, const double* theta, double* terms, int32_
 int inla_fd_grad(inla_model model, const double* theta, double h, int32_t max_batch,
                  double* f, double* grad, int32_t* info, void* ws, size_t ws_bytes,
                  void* stream);
+
+/* Posterior Hessian from exact gradients (Sec. III-D, Eq. 12): the exact gradients at the 2d+1
+ * points theta, theta +- h e_j (in that order: +e_j at 1+2j, -e_j at 2+2j) are computed as in
+ * inla_grad_batched, at most `max_batch` points per pass, and column j of H is
+ * (grad f(theta + h e_j) - grad f(theta - h e_j)) / 2h, as the equation defines it (not
+ * symmetrised).  The paper's step is h = 5e-3.  H: device, d x d, column-major.  f, grad:
+ * device, f and its gradient at theta.  info: device int32, 2d+1 entries (one per gradient).
+ * Workspace: inla_workspace_bytes(model, max_batch, GRAD) or larger.  Errors: -k for argument
+ * k (h must be positive), ADELIA_E_WORKSPACE, ADELIA_E_HIP. */
+int inla_hessian(inla_model model, const double* theta, double h, int32_t max_batch, double* f,
+                 double* grad, double* H, int32_t* info, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/* The finite-difference Hessian that Eq. 12 replaces (Sec. II-D): second-order central
+ * differences over 2d^2+1 objective evaluations, batched in sub-batches of at most `max_batch`
+ * points (workspace = inla_workspace_bytes(model, max_batch, OBJECTIVE)):
+ *   H_jj = (f(theta + h e_j) - 2 f(theta) + f(theta - h e_j)) / h^2,
+ *   H_jk = (f(+e_j+e_k) - f(+e_j-e_k) - f(-e_j+e_k) + f(-e_j-e_k)) / 4h^2  (steps of size h).
+ * H: device, d x d, column-major (symmetric).  f: device, f(theta).  info: device int32,
+ * 2d^2+1 entries: the centre, theta +- h e_j at 1+2j and 2+2j, then four points per pair
+ * j < k in the order above.  Errors as inla_fd_grad. */
+int inla_fd_hessian(inla_model model, const double* theta, double h, int32_t max_batch,
+                    double* f, double* H, int32_t* info, void* ws, size_t ws_bytes,
+                    void* stream);
 
 
 /* ---------------------------------------------------------------------------------------

@@ -70,6 +70,9 @@ SIGNATURES = {
     "inla_grad": (c_int, [vp, vp, vp, vp, vp, vp, c_size_t, c_int, vp]),
     "inla_grad_terms": (c_int, [vp, vp, vp, vp, vp, c_size_t, c_int, vp]),
     "inla_fd_grad": (c_int, [vp, vp, c_double, c_int32, vp, vp, vp, vp, c_size_t, vp]),
+    "inla_grad_batched": (c_int, [vp, vp, c_int32, vp, vp, vp, vp, c_size_t, vp]),
+    "inla_hessian": (c_int, [vp, vp, c_double, c_int32, vp, vp, vp, vp, vp, c_size_t, vp]),
+    "inla_fd_hessian": (c_int, [vp, vp, c_double, c_int32, vp, vp, vp, vp, c_size_t, vp]),
     "adelia_profile_start": (c_int, [vp, c_int]),
     "adelia_profile_stop": (c_int, [vp, C.POINTER(KernelStats), c_int, C.POINTER(c_int)]),
 }

@@ -53,6 +53,8 @@ struct InlaWs {
   double *phi, *dphi, *tau;
   double *Th, *fv;
   int32_t* finfo;
+  long long zq, zr;  // per-point strides of qD/qB and resid
+  double* gv;
   double *x, *y, *W, *ZD, *ZB, *ZC, *TD, *TB, *O, *qD, *qB, *resid;
   long long zx, zy, zW, zZD, zZB, zZC, zTr, zO;
   size_t bytes;
@@ -79,10 +81,13 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
     return p;
   };
   long long dummy;
-  // finite-difference stencil scratch first: its place does not depend on the batch size
-  const int npts = 2 * M.d + 1;
+  // finite-difference stencil scratch first: its place does not depend on the batch size.  It
+  // holds the largest stencil (the 2d^2 + 1 points of the FD Hessian) and the 2d + 1 gradients
+  // of the Hessian of Eq. 12.
+  const int npts = 2 * M.d * M.d + 1;
   w.Th = take((long long)npts * M.d, 1, dummy);
   w.fv = take(npts, 1, dummy);
+  w.gv = take((long long)(2 * M.d + 1) * M.d, 1, dummy);
   {
     double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
     w.finfo = reinterpret_cast<int32_t*>(p);
@@ -124,9 +129,9 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
     w.TD = take((long long)n * 3 * M.k * M.k * M.nch_rows, nz, w.zTr);
     w.TB = take((long long)n * 3 * M.k * M.k * M.nch_rows, nz, dummy);
     w.O = take((long long)n * M.k * M.nch_obs, nz, w.zO);
-    w.qD = take((long long)n * 3 * M.k * M.k, 1, dummy);
-    w.qB = take((long long)n * 3 * M.k * M.k, 1, dummy);
-    w.resid = take((long long)M.k * M.nch_resid, 1, dummy);
+    w.qD = take((long long)n * 3 * M.k * M.k, batch, w.zq);
+    w.qB = take((long long)n * 3 * M.k * M.k, batch, dummy);
+    w.resid = take((long long)M.k * M.nch_resid, batch, w.zr);
   }
   w.bytes = off + 256;
   return w;
@@ -298,12 +303,15 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
       prof_end(t, s, PK_TRACE, 0.0, 8.0 * nz * 2.0 * M.k * M.k * M.nnz);
     if (!LAUNCH_OK()) return ADELIA_E_HIP;
   }
-  // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 0)
-  hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k), dim3(256), 0, s, M, w.x, w.qD, w.qB);
-  hipLaunchKernelGGL(resid_kernel, dim3(M.k * M.nch_resid), dim3(256), 0, s, M, w.x, w.resid);
-  hipLaunchKernelGGL(grad_kernel, dim3(1), dim3(256), 0, s, M, theta, w.phi, w.dphi, w.tau, w.TD,
-                     w.TB, w.zTr, w.O, w.qD, w.qB, w.resid, w.ld, w.zsq, w.ZT, w.info, f, grad,
-                     info, terms);
+  // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 2p of point p)
+  const int B = w.batch;
+  hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k, 1, B), dim3(256), 0, s, M, w.x, 2 * w.zx,
+                     w.qD, w.qB, w.zq);
+  hipLaunchKernelGGL(resid_kernel, dim3(M.k * M.nch_resid, 1, B), dim3(256), 0, s, M, w.x,
+                     2 * w.zx, w.resid, w.zr);
+  hipLaunchKernelGGL(grad_kernel, dim3(B), dim3(256), 0, s, M, theta, w.dphi, w.tau, w.TD, w.TB,
+                     w.zTr, w.O, w.zO, w.qD, w.qB, w.zq, w.resid, w.zr, w.ld, w.zsq, w.ZT, w.zZT,
+                     w.info, f, grad, info, B == 1 ? terms : nullptr);
   return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
 }
 
@@ -569,7 +577,7 @@ int inla_model_dim(inla_model m) { return m ? m->M.d : 0; }
 
 size_t inla_workspace_bytes(inla_model m, int batch, int mode) {
   if (!m || batch < 1 || batch > 32767) return 0;
-  if (mode == ADELIA_MODE_GRAD && batch != 1) return 0;
+  if (mode != ADELIA_MODE_OBJECTIVE && mode != ADELIA_MODE_GRAD) return 0;
   return layout(m->M, batch, mode == ADELIA_MODE_GRAD, nullptr).bytes;
 }
 
@@ -606,6 +614,23 @@ int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_
     int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
+  return run_backward(m->M, w, theta, f, grad, info, nullptr, s);
+}
+
+int inla_grad_batched(inla_model m, const double* theta, int32_t batch, double* f, double* grad,
+                      int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (batch < 1 || batch > 32767) return -3;
+  if (!f || !aligned(f, 8)) return -4;
+  if (!grad || !aligned(grad, 8)) return -5;
+  if (!info || !aligned(info, 4)) return -6;
+  if (!ws || !aligned(ws, 256)) return -7;
+  InlaWs w = layout(m->M, batch, true, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
+  if (r) return r;
   return run_backward(m->M, w, theta, f, grad, info, nullptr, s);
 }
 
@@ -656,6 +681,71 @@ int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch,
     if (r) return r;
   }
   hipLaunchKernelGGL(fd_kernel, dim3((d + 63) / 64), dim3(64), 0, s, w.fv, d, h, f, grad);
+  return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+}
+
+int inla_hessian(inla_model m, const double* theta, double h, int32_t max_batch, double* f,
+                 double* grad, double* H, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (!(h > 0.0)) return -3;
+  if (max_batch < 1 || max_batch > 32767) return -4;
+  if (!f || !aligned(f, 8)) return -5;
+  if (!grad || !aligned(grad, 8)) return -6;
+  if (!H || !aligned(H, 8)) return -7;
+  if (!info || !aligned(info, 4)) return -8;
+  if (!ws || !aligned(ws, 256)) return -9;
+  const int d = m->M.d, npts = 2 * d + 1;
+  const int bmax = std::min<int>(max_batch, npts);
+  InlaWs w = layout(m->M, bmax, true, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d, h,
+                     w.Th);
+  if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  // exact gradients of the points, `bmax` at a time (a smaller last sub-batch uses a prefix of
+  // the same workspace; the stencil scratch sits at a fixed place in front of it)
+  for (int p0 = 0; p0 < npts; p0 += bmax) {
+    const int bs = std::min(bmax, npts - p0);
+    InlaWs wb = layout(m->M, bs, true, reinterpret_cast<char*>(ws));
+    const double* th = w.Th + (long long)p0 * d;
+    int r = run_forward(m->M, wb, th, s, m->has_side ? &m->side : nullptr);
+    if (r) return r;
+    r = run_backward(m->M, wb, th, w.fv + p0, w.gv + (long long)p0 * d, info + p0, nullptr, s);
+    if (r) return r;
+  }
+  hipLaunchKernelGGL(grad_hessian_kernel, dim3((d * d + 63) / 64), dim3(64), 0, s, w.fv, w.gv, d,
+                     h, f, grad, H);
+  return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+}
+
+int inla_fd_hessian(inla_model m, const double* theta, double h, int32_t max_batch, double* f,
+                    double* H, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (!(h > 0.0)) return -3;
+  if (max_batch < 1 || max_batch > 32767) return -4;
+  if (!f || !aligned(f, 8)) return -5;
+  if (!H || !aligned(H, 8)) return -6;
+  if (!info || !aligned(info, 4)) return -7;
+  if (!ws || !aligned(ws, 256)) return -8;
+  const int d = m->M.d, npts = 2 * d * d + 1;
+  const int bmax = std::min<int>(max_batch, npts);
+  InlaWs w = layout(m->M, bmax, false, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(hess_stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d,
+                     h, w.Th);
+  if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  for (int p0 = 0; p0 < npts; p0 += bmax) {
+    const int bs = std::min(bmax, npts - p0);
+    InlaWs wb = layout(m->M, bs, false, reinterpret_cast<char*>(ws));
+    int r = run_objective(m->M, wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s,
+                          m->has_side ? &m->side : nullptr);
+    if (r) return r;
+  }
+  hipLaunchKernelGGL(fd_hessian_kernel, dim3((d * d + 63) / 64), dim3(64), 0, s, w.fv, d, h, f,
+                     H);
   return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
 }
 

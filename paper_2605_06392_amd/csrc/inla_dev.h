@@ -51,19 +51,26 @@ __global__ void trace_kernel(const ModelDev M, int j, const double* ZD, long lon
                              const double* ZB, long long zZB, const double* ZC, long long zZC,
                              const double* ZT, long long zZT, double* TD, double* TB, double* O,
                              long long zTr, long long zO);
-__global__ void phaseb_kernel(const ModelDev M, const double* x, double* qD, double* qB);
-__global__ void resid_kernel(const ModelDev M, const double* x, double* resid);
+__global__ void phaseb_kernel(const ModelDev M, const double* x, long long zxp, double* qD,
+                              double* qB, long long zq);
+__global__ void resid_kernel(const ModelDev M, const double* x, long long zxp, double* resid,
+                             long long zr);
 __global__ void objective_kernel(const ModelDev M, const double* theta, int batch,
                                  const double* tau, const double* ld, const double* zsq,
                                  const int32_t* info, double* f, int32_t* info_out);
-__global__ void grad_kernel(const ModelDev M, const double* theta, const double* phi,
-                            const double* dphi, const double* tau, const double* TD,
-                            const double* TB, long long zTr, const double* O, const double* qD,
-                            const double* qB, const double* resid, const double* ld,
-                            const double* zsq, const double* ZTc, const int32_t* info, double* f,
-                            double* grad, int32_t* info_out, double* terms);
+__global__ void grad_kernel(const ModelDev M, const double* theta, const double* dphi,
+                            const double* tau, const double* TD, const double* TB, long long zTr,
+                            const double* O, long long zO, const double* qD, const double* qB,
+                            long long zq, const double* resid, long long zr, const double* ld,
+                            const double* zsq, const double* ZTc, long long zZT,
+                            const int32_t* info, double* f, double* grad, int32_t* info_out,
+                            double* terms);
 __global__ void yy_kernel(const ModelDev M, double* yy);
 __global__ void stencil_kernel(const double* theta, int d, double h, double* Th);
 __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad);
+__global__ void hess_stencil_kernel(const double* theta, int d, double h, double* Th);
+__global__ void fd_hessian_kernel(const double* fv, int d, double h, double* f, double* H);
+__global__ void grad_hessian_kernel(const double* fv, const double* gv, int d, double h,
+                                    double* f, double* grad, double* H);
 
 }  // namespace adelia

@@ -320,8 +320,13 @@ __global__ __launch_bounds__(256) void trace_kernel(const ModelDev M, int j, con
 
 // ---- Phase B: quadratic forms of the mode (Eq. 8) and the data residual -----------------------
 __global__ __launch_bounds__(256) void phaseb_kernel(const ModelDev M, const double* x,
-                                                     double* qD, double* qB) {
+                                                     long long zxp, double* qD, double* qB,
+                                                     long long zq) {
   __shared__ double red[256];
+  // grid.z: theta point (x of its Qc chain at x + z * zxp; outputs at z * zq)
+  x += blockIdx.z * zxp;
+  qD += blockIdx.z * zq;
+  qB += blockIdx.z * zq;
   const int k = M.k, ns = M.ns, b = M.b;
   const int t = blockIdx.x / k, i2 = blockIdx.x % k;
   const bool hasB = t < M.nt - 1;
@@ -359,8 +364,11 @@ __global__ __launch_bounds__(256) void phaseb_kernel(const ModelDev M, const dou
 }
 
 __global__ __launch_bounds__(256) void resid_kernel(const ModelDev M, const double* x,
-                                                    double* resid) {
+                                                    long long zxp, double* resid, long long zr) {
   __shared__ double red[256];
+  // grid.z: theta point (x of its Qc chain at x + z * zxp; partial sums at z * zr)
+  x += blockIdx.z * zxp;
+  resid += blockIdx.z * zr;
   // grid.x = k fields x nch_resid slices of kResidObs observations; one partial sum each
   const int m = blockIdx.x / M.nch_resid, ch = blockIdx.x % M.nch_resid;
   const int a = M.a, b = M.b, ns = M.ns;
@@ -405,17 +413,18 @@ __global__ void objective_kernel(const ModelDev M, const double* theta, int batc
   info_out[p] = (ic != 0 && ic != INT32_MAX) ? ic : ((ip != INT32_MAX) ? ip : 0);
 }
 
-// Gradient assembly for one theta point (chains 0 = Qc, 1 = Qp).  Optionally writes the
-// decomposition terms = [f, log|Qp|, log|Qc|, |z|^2, tr(Z_T of Qc), PhaseA(d), PhaseB(d),
-// PhaseC(d), dlog l(d), dlog p(d), grad(d)].
+// Gradient assembly, one workgroup per theta point p (chains 2p = Qc, 2p + 1 = Qp).  Optionally
+// (one point) writes the decomposition terms = [f, log|Qp|, log|Qc|, |z|^2, tr(Z_T of Qc),
+// PhaseA(d), PhaseB(d), PhaseC(d), dlog l(d), dlog p(d), grad(d)].
 __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const double* theta,
-                                                   const double* phi, const double* dphi,
-                                                   const double* tau, const double* TD,
-                                                   const double* TB, long long zTr,
-                                                   const double* O, const double* qD,
-                                                   const double* qB, const double* resid,
-                                                   const double* ld, const double* zsq,
-                                                   const double* ZTc, const int32_t* info,
+                                                   const double* dphi, const double* tau,
+                                                   const double* TD, const double* TB,
+                                                   long long zTr, const double* O, long long zO,
+                                                   const double* qD, const double* qB,
+                                                   long long zq, const double* resid,
+                                                   long long zr, const double* ld,
+                                                   const double* zsq, const double* ZTc,
+                                                   long long zZT, const int32_t* info,
                                                    double* f, double* grad, int32_t* info_out,
                                                    double* terms) {
   __shared__ double SA[9 * kMaxFields * kMaxFields];
@@ -423,6 +432,23 @@ __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const doubl
   __shared__ double SC[9 * kMaxFields * kMaxFields];
   const int k = M.k, kk = k * k, nt = M.nt, d = M.d;
   const int NE = 9 * kk;
+  const int p = blockIdx.x;
+  theta += (long long)p * d;
+  dphi += (long long)p * NE * d;
+  tau += (long long)p * k;
+  TD += 2LL * p * zTr;
+  TB += 2LL * p * zTr;
+  O += 2LL * p * zO;
+  qD += p * zq;
+  qB += p * zq;
+  resid += p * zr;
+  ld += 2 * p;
+  zsq += 2 * p;
+  ZTc += 2LL * p * zZT;
+  info += 2 * p;
+  f += p;
+  grad += (long long)p * d;
+  info_out += p;
   // Per element e = (r, i1, i2, s): sums over the time steps and the trace slices, spread over
   // the workgroup (each thread takes time steps t = tid, tid + 256, ...; block sums in a fixed
   // order)
@@ -538,6 +564,61 @@ __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* 
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j == 0) f[0] = fv[0];
   if (j < d) grad[j] = (fv[1 + 2 * j] - fv[2 + 2 * j]) / (2.0 * h);
+}
+
+// Points of the second-order central-difference Hessian (2d^2 + 1): 0 the centre; 1 + 2j and
+// 2 + 2j the steps +h e_j and -h e_j; then, for each pair j < k in order, four points
+// (+e_j + e_k, +e_j - e_k, -e_j + e_k, -e_j - e_k) times h.
+__global__ void hess_stencil_kernel(const double* theta, int d, double h, double* Th) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int npts = 2 * d * d + 1;
+  if (i >= npts * d) return;
+  const int p = i / d, c = i % d;
+  double v = theta[c];
+  if (p >= 1 && p <= 2 * d) {
+    if ((p - 1) / 2 == c) v += ((p - 1) % 2 == 0) ? h : -h;
+  } else if (p > 2 * d) {
+    int q = (p - 1 - 2 * d) / 4;
+    const int r = (p - 1 - 2 * d) % 4;
+    int j = 0;
+    while (q >= d - 1 - j) {
+      q -= d - 1 - j;
+      ++j;
+    }
+    const int k = j + 1 + q;
+    if (c == j) v += (r < 2) ? h : -h;
+    if (c == k) v += (r % 2 == 0) ? h : -h;
+  }
+  Th[i] = v;
+}
+
+// H (d x d, column-major) from the objective values at hess_stencil_kernel's points.
+__global__ void fd_hessian_kernel(const double* fv, int d, double h, double* f, double* H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) f[0] = fv[0];
+  if (i >= d * d) return;
+  const int r = i % d, c = i / d;
+  double v;
+  if (r == c) {
+    v = (fv[1 + 2 * r] - 2.0 * fv[0] + fv[2 + 2 * r]) / (h * h);
+  } else {
+    const int a = r < c ? r : c, b = r < c ? c : r;
+    const int base = 1 + 2 * d + 4 * (a * (2 * d - a - 1) / 2 + (b - a - 1));
+    v = (fv[base] - fv[base + 1] - fv[base + 2] + fv[base + 3]) / (4.0 * h * h);
+  }
+  H[i] = v;
+}
+
+// Eq. 12: column j of H (d x d, column-major) from the gradients at stencil_kernel's points
+// theta + h e_j (point 1 + 2j) and theta - h e_j (point 2 + 2j); f and grad at the centre.
+__global__ void grad_hessian_kernel(const double* fv, const double* gv, int d, double h,
+                                    double* f, double* grad, double* H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) f[0] = fv[0];
+  if (i < d) grad[i] = gv[i];
+  if (i >= d * d) return;
+  const int r = i % d, j = i / d;
+  H[i] = (gv[(long long)(1 + 2 * j) * d + r] - gv[(long long)(2 + 2 * j) * d + r]) / (2.0 * h);
 }
 
 }  // namespace adelia

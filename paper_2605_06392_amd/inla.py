@@ -2,7 +2,9 @@
 
 ``InlaModel`` uploads a model once (``inla_model_create``); ``objective`` evaluates f for a
 batch of theta points, ``grad`` returns f and the exact gradient (Sec. III-A-3, Eq. 5),
-``fd_grad`` the (2d+1)-point central-difference gradient on the GPU (Sec. II-D, Eq. 2), and
+``fd_grad`` the (2d+1)-point central-difference gradient on the GPU (Sec. II-D, Eq. 2),
+``hessian`` the posterior Hessian from 2d+1 exact gradients (Sec. III-D, Eq. 12) and
+``fd_hessian`` its (2d^2+1)-point finite-difference counterpart, and
 ``InlaObjective`` is the torch.autograd.Function whose forward keeps the Cholesky factors of
 Qc and Qp in the model's workspace and whose backward runs the hand-written reverse pass
 (selected inversion + traces) from them.
@@ -190,6 +192,69 @@ class InlaModel:
                                  C.c_void_p(inf.data_ptr()), ws, nb, self._stream()),
               "inla_fd_grad")
         return f, g, inf
+
+    def grad_batched(self, theta, f=None, g=None, info=None):
+        """f and the exact gradient at a batch of theta points (batch x d) in one pass."""
+        th = self._theta(theta).reshape(-1, self.d).contiguous()
+        B = th.shape[0]
+        f = f if f is not None else torch.empty(B, dtype=torch.float64, device=self.device)
+        g = g if g is not None else torch.empty((B, self.d), dtype=torch.float64, device=self.device)
+        inf = info if info is not None else torch.empty(B, dtype=torch.int32, device=self.device)
+        ws, nb = self.workspace(B, MODE_GRAD)
+        check(lib().inla_grad_batched(self._h, C.c_void_p(th.data_ptr()), B,
+                                      C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()),
+                                      C.c_void_p(inf.data_ptr()), ws, nb, self._stream()),
+              "inla_grad_batched")
+        return f, g, inf
+
+    def fitting_batch(self, npts, mode, fraction=0.5):
+        """The largest batch (<= npts) whose workspace fits in `fraction` of the free memory."""
+        free, _ = torch.cuda.mem_get_info(self.device)
+        for mb in range(npts, 0, -1):
+            if self.workspace_bytes(mb, mode) <= fraction * free:
+                return mb
+        return 1
+
+    def hessian(self, theta, h=5e-3, max_batch=None, f=None, g=None, H=None, info=None):
+        """Posterior Hessian from 2d+1 exact gradients (Sec. III-D, Eq. 12), max_batch points per
+        pass (default: as many as fit); H[:, j] is the central difference of the gradient along
+        e_j (not symmetrised)."""
+        th = self._theta(theta).reshape(self.d)
+        d = self.d
+        if max_batch is None:
+            key = ("hessian_batch", d)
+            if key not in self._ws:
+                self._ws[key] = self.fitting_batch(2 * d + 1, MODE_GRAD)
+            max_batch = self._ws[key]
+        mb = min(int(max_batch), 2 * d + 1)
+        f = f if f is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        g = g if g is not None else torch.empty(d, dtype=torch.float64, device=self.device)
+        H = H if H is not None else torch.empty((d, d), dtype=torch.float64, device=self.device)
+        inf = info if info is not None else torch.empty(2 * d + 1, dtype=torch.int32,
+                                                        device=self.device)
+        ws, nb = self.workspace(mb, MODE_GRAD)
+        # the library writes H column-major: the storage of H.T
+        check(lib().inla_hessian(self._h, C.c_void_p(th.data_ptr()), float(h), mb,
+                                 C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()),
+                                 C.c_void_p(H.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb,
+                                 self._stream()), "inla_hessian")
+        return f, g, H.T, inf
+
+    def fd_hessian(self, theta, h=5e-3, max_batch=None, f=None, H=None, info=None):
+        """Second-order central-difference Hessian over 2d^2+1 batched objective evaluations."""
+        th = self._theta(theta).reshape(self.d)
+        d = self.d
+        npts = 2 * d * d + 1
+        mb = npts if max_batch is None else min(int(max_batch), npts)
+        f = f if f is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        H = H if H is not None else torch.empty((d, d), dtype=torch.float64, device=self.device)
+        inf = info if info is not None else torch.empty(npts, dtype=torch.int32, device=self.device)
+        ws, nb = self.workspace(mb, MODE_OBJECTIVE)
+        check(lib().inla_fd_hessian(self._h, C.c_void_p(th.data_ptr()), float(h), mb,
+                                    C.c_void_p(f.data_ptr()), C.c_void_p(H.data_ptr()),
+                                    C.c_void_p(inf.data_ptr()), ws, nb, self._stream()),
+              "inla_fd_hessian")
+        return f, H.T, inf
 
 
 class InlaObjective(torch.autograd.Function):

@@ -12,7 +12,9 @@ Pins that hold at any size (no dense matrix needed):
   + sum(tau); the coupling terms of Phase C vanish because |Qp| depends on Lambda's diagonal
   only (Eq. 9-11);
 * the no-observation model gives f = log p(theta) and grad = -theta/sigma^2 exactly;
-* the exact gradient agrees with the GPU's central differences (h = 1e-4) to 1e-5.
+* the exact gradient agrees with the GPU's central differences (h = 1e-4) to 1e-5;
+* the Hessian of Eq. 12 is symmetric to its O(h^2) truncation, and -I/sigma^2 without
+  observations.
 The gradient here runs in the same launch configuration the benchmark times.
 """
 import numpy as np
@@ -70,6 +72,14 @@ def test_bench_size_identities_and_fd(name):
     assert np.all(info.cpu().numpy() == 0)
     g = t["grad"]
     assert np.abs(g_fd.cpu().numpy() - g).max() <= 1e-5 * np.abs(g).max()
+    # the Hessian of Eq. 12 in the benchmark's launch configuration: symmetric to its O(h^2)
+    # truncation, and its centre gradient is the gradient above
+    _, g_c, H, info = m.hessian(torch.tensor(spec.theta), h=5e-3)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    H = H.cpu().numpy()
+    assert np.array_equal(g_c.cpu().numpy(), g)
+    assert np.abs(H - H.T).max() <= 1e-5 * np.abs(H).max()
 
 
 def test_bench_size_without_observations():
@@ -85,6 +95,12 @@ def test_bench_size_without_observations():
     ref = spectral.prior_logdet(spec, spec.theta)
     assert abs(t["logdet_p"] - ref) <= 1e-11 * abs(ref)
     assert abs(t["logdet_c"] - t["logdet_p"]) <= 1e-11 * abs(ref)
+    # Eq. 12 on this model is the prior's curvature -I/sigma^2: each stencil gradient is held to
+    # rtol = atol = 1e-8 above (|g| <= 4 (|theta| + h) here), so an entry is within about 1e-5
+    _, _, H, info = m.hessian(torch.tensor(spec.theta), h=5e-3)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    assert np.abs(H.cpu().numpy() + np.eye(spec.d) / s2).max() <= 1e-5
 
 
 def test_coregional_d15_identities_and_fd():
