@@ -212,7 +212,29 @@ def cpu_baseline(spec_name, seed, nt_sample):
                    f"nt={nt_sample} (N={sample.N}) took {ts:.2f} s on {threads} BLAS threads; "
                    f"scaled by (N/N_sample)^3 = {scale:.4g} to the full N={N_full}"),
         "sample_seconds": ts,
+        "cpu_count": os.cpu_count(),
+        "single_thread": single_thread_oracle(k, nx, ny, nt, a, obs, seed, N_full),
     }
+
+
+def single_thread_oracle(k, nx, ny, nt, a, obs, seed, N_full, nt_sample=2):
+    """The same oracle gradient with the BLAS limited to one thread, on a smaller sample."""
+    import oracle
+    from workloads import make_model
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        return None
+    sample = make_model(k, nx, ny, nt_sample, a, obs, seed)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.gradient(sample, sample.theta)
+        ts = time.perf_counter() - t0
+    scale = (N_full / sample.N) ** 3
+    return {"value": 1.0 / (ts * scale), "unit": "gradients/s", "cores": 1,
+            "sample": (f"nt={nt_sample} (N={sample.N}) took {ts:.2f} s on 1 BLAS thread; "
+                       f"scaled by (N/N_sample)^3 = {scale:.4g}"),
+            "sample_seconds": ts}
 
 
 UNEVEN_COUNT = 64
