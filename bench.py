@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--hessian", action="store_true",
                     help="time the posterior Hessian of Eq. 12 (2d+1 exact gradients) against "
                          "the 2d^2+1-point finite-difference Hessian instead")
+    ap.add_argument("--sweep", choices=["time", "space"], default=None,
+                    help="problem-size sweep of c_AD = T_AD / T_f and beta = t_bwd / t_fwd: "
+                         "n = 2..256 steps on the 32x32 univariate grid (time), or three "
+                         "coregionalised fields on ns = 72..1122 nodes, n = 16 (space)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the event-profiled gradient steps (the command rocprofv3 traces)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -403,6 +407,61 @@ def bench_hessian(args, model, theta, spec, torch, np):
 
 NAMED_CONFIGS_REF = {}
 
+SWEEPS = {
+    # (k, nx, ny, nt, a, obs per step and field)
+    "time": [(1, 32, 32, n, 6, 200) for n in (2, 4, 8, 16, 32, 64, 128, 256)],
+    "space": [(3, nx, ny, 16, 6, max(nx * ny // 4, 8))
+              for nx, ny in ((9, 8), (12, 12), (18, 16), (24, 24), (30, 30), (34, 33))],
+}
+
+
+def bench_sweep(args, torch, np):
+    """c_AD = T_AD / T_f (one exact gradient against one objective evaluation), beta =
+    t_bwd / t_fwd, and the AD speed-up over the batched (2d+1)-point FD gradient, over a family
+    of problem sizes; one JSON line per size, then a summary line."""
+    from paper_2605_06392_amd import inla
+    from workloads import make_model
+    dev = torch.device("cuda:0")
+    use_graph = not args.no_graph
+    rows = []
+    for k, nx, ny, nt, a, obs in SWEEPS[args.sweep]:
+        spec = make_model(k, nx, ny, nt, a, obs, args.seed)
+        model = inla.InlaModel(spec, device=dev)
+        d = model.d
+        npts = 2 * d + 1
+        theta = torch.tensor(spec.theta, dtype=torch.float64, device=dev)
+        f1 = torch.empty(1, dtype=torch.float64, device=dev)
+        i1 = torch.empty(1, dtype=torch.int32, device=dev)
+        g = torch.empty(d, dtype=torch.float64, device=dev)
+        gf = torch.empty(d, dtype=torch.float64, device=dev)
+        ifd = torch.empty(npts, dtype=torch.int32, device=dev)
+        th1 = theta[None].contiguous()
+        steps, warm = args.steps, args.warmup
+        ms_f = timed(lambda: model.objective(th1, out=f1, info=i1), steps, warm, use_graph, torch)
+        ms_ad = timed(lambda: model.grad(theta, f=f1, g=g, info=i1), steps, warm, use_graph, torch)
+        ms_fwd = timed(lambda: model.forward_saved(theta), steps, warm, use_graph, torch)
+        ms_bwd = timed(lambda: model.grad(theta, reuse=True, f=f1, g=g, info=i1), steps, warm,
+                       use_graph, torch)
+        mb = model.fitting_batch(npts, 0)
+        ms_fd = timed(lambda: model.fd_grad(theta, h=1e-3, max_batch=mb, f=f1, g=gf, info=ifd),
+                      steps, warm, use_graph, torch)
+        torch.cuda.synchronize()
+        ok = bool((i1 == 0).all().item()) and bool((ifd == 0).all().item())
+        row = {"k": k, "nx": nx, "ny": ny, "ns": nx * ny, "b": k * nx * ny, "n": nt, "a": a,
+               "d": d, "ms_f": ms_f, "ms_ad": ms_ad, "ms_fwd": ms_fwd, "ms_bwd": ms_bwd,
+               "ms_fd_gradient": ms_fd, "fd_max_batch": mb, "c_AD": ms_ad / ms_f,
+               "beta": ms_bwd / ms_fwd, "ad_over_fd": ms_fd / ms_ad,
+               "ad_over_sequential_fd": npts * ms_f / ms_ad, "info_ok": ok}
+        rows.append(row)
+        print(json.dumps({"sweep": args.sweep, **row}), flush=True)
+        del model
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": f"problem-size sweep ({args.sweep})", "unit": "c_AD, beta",
+                      "c_AD": [r["c_AD"] for r in rows], "beta": [r["beta"] for r in rows],
+                      "ad_over_fd": [r["ad_over_fd"] for r in rows],
+                      "sizes": [(r["b"], r["n"]) for r in rows], "dtype": "f64",
+                      "data": "synthetic", "graph": use_graph, "seed": args.seed}), flush=True)
+
 
 def main():
     args = parse()
@@ -413,6 +472,10 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.sweep:
+        torch.cuda.set_device(0)
+        bench_sweep(args, torch, np)
+        return
     if args.workload == "uneven64":
         torch.cuda.set_device(0)
         bench_uneven(args, torch)
