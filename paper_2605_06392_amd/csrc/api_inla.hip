@@ -55,6 +55,8 @@ struct InlaWs {
   int32_t* finfo;
   long long zq, zr;  // per-point strides of qD/qB and resid
   double* gv;
+  double* Vp;
+  long long zVp;
   double *x, *y, *W, *ZD, *ZB, *ZC, *TD, *TB, *O, *qD, *qB, *resid;
   long long zx, zy, zW, zZD, zZB, zZC, zTr, zO;
   size_t bytes;
@@ -106,6 +108,7 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
   w.zsq = take(1, nz, dummy);
   w.ZT = take(std::max(1, w.a * w.a), nz, w.zZT);
   w.xT = take(std::max(1, w.a), nz, w.zXT);
+  w.Vp = take((long long)kPanel * kPanel, nz, w.zVp);
   {
     double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
     w.info = reinterpret_cast<int32_t*>(p);
@@ -156,6 +159,7 @@ BtaChains chains_of(const InlaWs& w) {
     c.ZT = w.ZT; c.zZT = w.zZT;
     c.xT = w.xT; c.zXT = w.zXT;
   }
+  c.Vp = w.Vp; c.zVp = w.zVp;
   return c;
 }
 

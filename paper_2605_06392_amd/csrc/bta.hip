@@ -29,6 +29,20 @@ static inline long long blk_off(int t, int slots, long long bb) { return (long l
 // G_i = L_Di^-1 by recursive doubling over the 64 x 64 diagonal inverses left by the panels:
 // X21 = -X22 (L21 X11), two GEMMs per level.  Reads block i's L_Di and G_i slots and the
 // scratch; may run on another stream than the sweep once block i's panels are done.
+// CUs of the current device (cached per device)
+static int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] <= 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cache[dev] = v;
+  }
+  return cache[dev];
+}
+
 int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
   const int b = c.b, nz = c.nz;
   const long long bb = (long long)b * b;
@@ -135,6 +149,55 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
   //    its own columns, and the update of the columns from c0 + 64 on runs beside it: in the
   //    same launch (batches whose panels leave most CUs idle) or on the look-ahead stream.
   const bool fuse = la && 2LL * nz * panel_workgroups(b, 0, mT) <= la->cus;
+  // Batches whose panel workgroups outnumber the CUs split each panel: one workgroup per chain
+  // factors the diagonal tile, then one GEMM launch solves the panel's rows in place,
+  // R = A L_kk^-T - P V^T with V = L_kk^-1 Q (P, Q: the previous panel's columns on the rows and
+  // on the diagonal tile; that term is the look-ahead update (A - P Q^T) L_kk^-T), instead of
+  // every row workgroup factoring the diagonal tile again.
+  const int cus = la ? la->cus : device_cus();
+  const bool split = !fuse && (long long)nz * panel_workgroups(b, 0, mT) > cus &&
+                     (!la || c.Vp);
+  auto panel = [&](int k, int upd) -> int {
+    const int c0 = k * kPanel;
+    double* ldp = c.ldpart + (long long)i * npanel + k;
+    if (!split)
+      return launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, ldp, c.zLd, c.info, c.cnt, c.zn, i, b, c0,
+                                (long long)i * b, mT ? Rows : nullptr, c.zLBC, ldT, mT, upd, nz,
+                                s);
+    const bool u = upd && c0 >= kPanel;
+    if (launch_panel_diag(Dblk, c.zD, Gblk, c.zG, ldp, c.zLd, c.info, c.cnt, c.zn, i, b, c0,
+                          (long long)i * b, u ? 1 : 0, u ? c.Vp : nullptr, c.zVp, nz, s))
+      return -1;
+    const int w = std::min(kPanel, b - c0);
+    const int rest = b - c0 - w;
+    if (rest + mT <= 0) return 0;
+    GemmArgs g{};
+    g.nph = u ? 2 : 1;
+    g.ph[0].A = view_rowsplit(Dblk + c0 + w + (long long)c0 * b, b, c.zD,
+                              Rows + (long long)c0 * ldT, ldT, c.zLBC, rest);
+    g.ph[0].B = view_plain(Gblk + c0 + (long long)c0 * b, b, c.zG, true);
+    g.ph[0].K = g.ph[0].Klast = w;
+    g.ph[0].kmode = KR_LT_N1;
+    g.ph[0].triB = TRI_UPPER;
+    g.ph[0].alpha = 1.0;
+    if (u) {
+      g.ph[1].A = view_rowsplit(Dblk + c0 + w + (long long)(c0 - kPanel) * b, b, c.zD,
+                                Rows + (long long)(c0 - kPanel) * ldT, ldT, c.zLBC, rest);
+      g.ph[1].B = view_plain(c.Vp, kPanel, c.zVp, true);
+      g.ph[1].K = g.ph[1].Klast = kPanel;
+      g.ph[1].kmode = KR_FULL;
+      g.ph[1].alpha = -1.0;
+    }
+    g.C = g.ph[0].A;  // in place: each tile reads its own rows of A before it stores them
+    g.M = g.Mlast = rest + mT;
+    g.N = g.Nlast = w;
+    g.beta = 0.0;
+    g.omode = OUT_ALL;
+    g.tag = GT_PROWS;
+    g.zn = c.zn;
+    g.step = i;
+    return launch_gemm(g, 1, nz, s);
+  };
   for (int k = 0; k < npanel; ++k) {
     const int c0 = k * kPanel;
     double* ldp = c.ldpart + (long long)i * npanel + k;
@@ -153,10 +216,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     // panel k waits for the update the look-ahead stream issued after panel k-2
     if (la && k >= 2 && hipStreamWaitEvent(s, la->tdone[(k - 2) % 3], 0) != hipSuccess)
       return ADELIA_E_HIP_INTERNAL;
-    if (launch_potrf_panel(Dblk, c.zD, Gblk, c.zG, ldp, c.zLd, c.info, c.cnt, c.zn, i, b, c0,
-                           (long long)i * b, mT ? Rows : nullptr, c.zLBC, ldT, mT, la ? 1 : 0, nz,
-                           s))
-      return ADELIA_E_HIP_INTERNAL;
+    if (panel(k, la ? 1 : 0)) return ADELIA_E_HIP_INTERNAL;
     if (la && la->mark && k == std::min(la->mark_step, npanel - 1) &&
         hipEventRecord(la->mark, s) != hipSuccess)
       return ADELIA_E_HIP_INTERNAL;

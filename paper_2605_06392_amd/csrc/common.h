@@ -68,7 +68,7 @@ struct GemmArgs {
   int maxwg;
 };
 
-enum GemmTag { GT_OTHER = 0, GT_TRAIL, GT_TRTRI, GT_TRMM, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D, GT_COUNT };
+enum GemmTag { GT_OTHER = 0, GT_TRAIL, GT_TRTRI, GT_PROWS, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D, GT_COUNT };
 
 // ---- host helpers (gemm.hip) --------------------------------------------------------------
 View view_plain(double* p, long long ld, long long zstride, bool trans = false);
@@ -111,6 +111,7 @@ struct BtaChains {
   double* xT; long long zXT;                // a per chain: L_T^-T z_T (may be null)
   int inv_maxwg;                            // workgroup cap of bta_invert_block's launches
   bool b_in_place;                          // B_t already assembled into the rows of [L_B; L_C]
+  double* Vp; long long zVp;                // 64 x 64 per chain (split panels with look-ahead)
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
 // Look-ahead for the block Cholesky: each panel launch first applies the previous panel's

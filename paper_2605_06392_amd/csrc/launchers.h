@@ -5,6 +5,12 @@
 #define ADELIA_E_HIP_INTERNAL (-102)
 
 namespace adelia {
+// The diagonal tile of a panel alone (one workgroup per chain): L_kk, L_kk^-1, the log-diagonal
+// partial and the pivot check, and with upd and V the product V = L_kk^-1 Q (panel_dev.h).
+int launch_panel_diag(double* D, long long zD, double* G, long long zG, double* ldp,
+                      long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
+                      int b, int c0, long long gcol0, int upd, double* V, long long zV, int nz,
+                      hipStream_t s);
 int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,
                        long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
                        int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,

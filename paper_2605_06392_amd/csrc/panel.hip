@@ -3,6 +3,7 @@
 #include "common.h"
 #include "panel_dev.h"
 #include "profile.h"
+#include <algorithm>
 #include <cmath>
 
 namespace adelia {
@@ -29,6 +30,19 @@ double panel_flops(int b, int c0, int mT, int upd) {
   // every row below) is part of the launch
   const double updfl = (upd && c0 >= NB) ? 2.0 * NB * (ww * (ww + 1) / 2.0 + below * ww) : 0.0;
   return ww * ww * ww / 3.0 + below * ww * ww + updfl;
+}
+
+int launch_panel_diag(double* D, long long zD, double* G, long long zG, double* ldp,
+                      long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
+                      int b, int c0, long long gcol0, int upd, double* V, long long zV, int nz,
+                      hipStream_t s) {
+  if (!cnt) return -1;
+  PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, nullptr, 0, 0, 0, upd,
+              V, zV};
+  const ProfToken t = prof_begin(s);
+  hipLaunchKernelGGL(potrf_panel_kernel, dim3(1, 1, nz), dim3(256), 0, s, P);
+  if (t.valid) prof_end(t, s, PK_PANEL, nz * panel_flops(std::min(b, c0 + NB), c0, 0, upd), 0.0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double* ldp,

@@ -48,6 +48,10 @@ struct PanelArgs {
   // apply the previous panel's rank-64 update to this panel's columns first (the trailing
   // update of the remaining columns then runs beside the next panels)
   int upd;
+  // if not null (and upd): the writer also stores V = L_kk^-1 Q (64 x 64, column-major, chain
+  // stride zV), Q the previous panel's columns on the diagonal rows, so that rows solved
+  // elsewhere get R = A L_kk^-T - P V^T without the updated diagonal tile
+  double* V; long long zV;
 };
 
 // Orders the LDS traffic of one wavefront: the LDS unit serves a wave's operations in issue
@@ -495,6 +499,17 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
       const long long off = (long long)(c0 + r) + (long long)(c0 + c) * b;
       D[off] = (r >= c) ? S[r][c] : 0.0;
       G[off] = (r >= c) ? X[r][c] : 0.0;
+    }
+    if (P.V && upd) {
+      // V = X Q: wave q takes rows 16q..16q+15 (X is zero past w and above the diagonal)
+      double* V = P.V + (long long)z * P.zV;
+#pragma unroll
+      for (int fn = 0; fn < NB; fn += 16) {
+        const v4d t = frag16([&](int m, int k) { return X[m][k]; },
+                             [&](int k, int n) { return Q[k][n]; }, 16 * wave, fn, NB);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) V[(16 * wave + lm) + (long long)(fn + lk + 4 * v) * NB] = t[v];
+      }
     }
     if (wave == 0) {
       const double dj = piv[lane];

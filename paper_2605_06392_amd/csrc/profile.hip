@@ -49,7 +49,7 @@ const char* kind_name(int k) {
     case PK_GEMM_ROLE0 + 0: return "gemm_f64:other";
     case PK_GEMM_ROLE0 + 1: return "gemm_f64:trailing";
     case PK_GEMM_ROLE0 + 2: return "gemm_f64:trtri";
-    case PK_GEMM_ROLE0 + 3: return "gemm_f64:trmm_LB_LC";
+    case PK_GEMM_ROLE0 + 3: return "gemm_f64:panel_rows";
     case PK_GEMM_ROLE0 + 4: return "gemm_f64:schur_update";
     case PK_GEMM_ROLE0 + 5: return "gemm_f64:si_W";
     case PK_GEMM_ROLE0 + 6: return "gemm_f64:si_ZB";

@@ -72,13 +72,14 @@ def test_bench_size_identities_and_fd(name):
     assert np.all(info.cpu().numpy() == 0)
     g = t["grad"]
     assert np.abs(g_fd.cpu().numpy() - g).max() <= 1e-5 * np.abs(g).max()
-    # the Hessian of Eq. 12 in the benchmark's launch configuration: symmetric to its O(h^2)
-    # truncation, and its centre gradient is the gradient above
+    # the Hessian of Eq. 12 in the benchmark's launch configuration (all 2d+1 gradients in one
+    # pass, split panels): symmetric to its O(h^2) truncation, and its centre gradient is the
+    # gradient above up to the rounding of the other schedule
     _, g_c, H, info = m.hessian(torch.tensor(spec.theta), h=5e-3)
     torch.cuda.synchronize()
     assert np.all(info.cpu().numpy() == 0)
     H = H.cpu().numpy()
-    assert np.array_equal(g_c.cpu().numpy(), g)
+    assert np.abs(g_c.cpu().numpy() - g).max() <= 1e-10 * np.abs(g).max()
     assert np.abs(H - H.T).max() <= 1e-5 * np.abs(H).max()
 
 

@@ -188,3 +188,35 @@ def test_gradient_phases_match_oracle(name, seed):
     assert abs(t["logdet_c"] - ev["logdet_c"]) <= 1e-11 * abs(ev["logdet_c"])
     nb = spec.nt * spec.b
     assert abs(t["trZT"] - np.trace(ref["Zc"][nb:, nb:])) <= 1e-10 * abs(t["trZT"])
+
+
+def test_large_batches_split_panels_match_oracle():
+    """Batches whose panel workgroups outnumber the CUs factor each panel's diagonal tile once
+    per chain and solve its rows with a GEMM: objectives of 150 points and gradients of 60
+    points (300 and 120 chains) against the oracle at a few points and against one-point
+    evaluations everywhere."""
+    spec, m = gpu_model("uni_8x8_nt8", 0)
+    rng = np.random.default_rng(17)
+    pts = spec.theta + 0.2 * rng.standard_normal((150, spec.d))
+    f, info = m.objective(torch.tensor(pts))
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    f = f.cpu().numpy()
+    for p in (0, 77, 149):
+        ref = oracle.objective(spec, pts[p])["f"]
+        assert abs(f[p] - ref) <= 1e-10 * abs(ref)
+    for p in range(0, 150, 10):
+        f1, _ = m.objective(torch.tensor(pts[p])[None])
+        assert abs(f[p] - f1.item()) <= 1e-12 * abs(f1.item())
+    gp = pts[:60]
+    fg, g, info = m.grad_batched(torch.tensor(gp))
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    g = g.cpu().numpy()
+    for p in (0, 31, 59):
+        ref = oracle.gradient(spec, gp[p])
+        assert np.abs(g[p] - ref["grad"]).max() <= 1e-8 * np.abs(ref["grad"]).max()
+    for p in range(0, 60, 6):
+        _, g1, _ = m.grad(torch.tensor(gp[p]))
+        g1 = g1.cpu().numpy()
+        assert np.abs(g[p] - g1).max() <= 1e-10 * np.abs(g1).max()
