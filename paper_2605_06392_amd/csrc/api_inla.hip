@@ -277,7 +277,7 @@ int run_objective(const ModelDev& M, const InlaWs& w, const double* theta, doubl
 }
 
 int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double* f, double* grad,
-                 int32_t* info, double* terms, hipStream_t s) {
+                 int32_t* info, double* terms, hipStream_t s, const SideRes* side) {
   const int n = w.n, b = w.b, a = w.a, ap = w.ap, nz = w.nz;
   // x* = Qc^-1 r by the upper sweep (Eqs. 3-5); z_t is the rhs row of L_C
   SolveChains sc{};
@@ -290,7 +290,17 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
   sc.x = w.x; sc.zx = w.zx;
   sc.y = w.y; sc.zy = w.zy;
-  if (bta_upper_solve(sc, s)) return ADELIA_E_HIP;
+  // x* is read only by Phase B and the residual at the end: with the side stream (idle after
+  // the forward sweep's join) the upper sweep runs there, beside the selected inversion
+  if (side) {
+    if (hipEventRecord(side->ready[0], s) != hipSuccess ||
+        hipStreamWaitEvent(side->s2, side->ready[0], 0) != hipSuccess ||
+        bta_upper_solve(sc, side->s2) ||
+        hipEventRecord(side->done[0], side->s2) != hipSuccess)
+      return ADELIA_E_HIP;
+  } else if (bta_upper_solve(sc, s)) {
+    return ADELIA_E_HIP;
+  }
   // selected inversion of Qc and Qp with the trace epilogue per block (Eq. 6); the forward
   // sweep already formed [W_j; V_j] and G_j^T G_j
   const SelinvChains si = selinv_of(w);
@@ -307,6 +317,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
       prof_end(t, s, PK_TRACE, 0.0, 8.0 * nz * 2.0 * M.k * M.k * M.nnz);
     if (!LAUNCH_OK()) return ADELIA_E_HIP;
   }
+  if (side && hipStreamWaitEvent(s, side->done[0], 0) != hipSuccess) return ADELIA_E_HIP;
   // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 2p of point p)
   const int B = w.batch;
   hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k, 1, B), dim3(256), 0, s, M, w.x, 2 * w.zx,
@@ -618,7 +629,8 @@ int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_
     int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
-  return run_backward(m->M, w, theta, f, grad, info, nullptr, s);
+  return run_backward(m->M, w, theta, f, grad, info, nullptr, s,
+                      m->has_side ? &m->side : nullptr);
 }
 
 int inla_grad_batched(inla_model m, const double* theta, int32_t batch, double* f, double* grad,
@@ -635,7 +647,8 @@ int inla_grad_batched(inla_model m, const double* theta, int32_t batch, double* 
   hipStream_t s = (hipStream_t)stream;
   int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
   if (r) return r;
-  return run_backward(m->M, w, theta, f, grad, info, nullptr, s);
+  return run_backward(m->M, w, theta, f, grad, info, nullptr, s,
+                      m->has_side ? &m->side : nullptr);
 }
 
 int inla_grad_terms(inla_model m, const double* theta, double* terms, int32_t* info, void* ws,
@@ -654,7 +667,8 @@ int inla_grad_terms(inla_model m, const double* theta, double* terms, int32_t* i
     if (r) return r;
   }
   const int d = m->M.d;
-  return run_backward(m->M, w, theta, terms, terms + 5 + 5 * d, info, terms, s);
+  return run_backward(m->M, w, theta, terms, terms + 5 + 5 * d, info, terms, s,
+                      m->has_side ? &m->side : nullptr);
 }
 
 int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch, double* f,
@@ -715,7 +729,8 @@ int inla_hessian(inla_model m, const double* theta, double h, int32_t max_batch,
     const double* th = w.Th + (long long)p0 * d;
     int r = run_forward(m->M, wb, th, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
-    r = run_backward(m->M, wb, th, w.fv + p0, w.gv + (long long)p0 * d, info + p0, nullptr, s);
+    r = run_backward(m->M, wb, th, w.fv + p0, w.gv + (long long)p0 * d, info + p0, nullptr, s,
+                     m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
   hipLaunchKernelGGL(grad_hessian_kernel, dim3((d * d + 63) / 64), dim3(64), 0, s, w.fv, w.gv, d,
