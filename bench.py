@@ -109,6 +109,42 @@ def timed(fn, steps, warmup, use_graph, torch):
 TIMES = {}
 
 
+def timed_backward(model, theta, f, g, info, steps, warmup, use_graph, torch):
+    """Mean ms of the reverse pass alone: each step replays the forward pass that saves the
+    factors (untimed) and then the gradient that reuses them (timed with its own events), since
+    a reuse consumes the saved factors."""
+    fwd = lambda: model.forward_saved(theta)  # noqa: E731
+    bwd = lambda: model.grad(theta, reuse=True, f=f, g=g, info=info)  # noqa: E731
+    fwd()
+    bwd()
+    torch.cuda.synchronize()
+    if use_graph:
+        ga = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(ga):
+            fwd()
+        gb = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gb):
+            bwd()
+        run_f, run_b = ga.replay, gb.replay
+    else:
+        run_f, run_b = fwd, bwd
+    for _ in range(warmup):
+        run_f()
+        run_b()
+    torch.cuda.synchronize()
+    total = 0.0
+    for _ in range(steps):
+        run_f()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run_b()
+        e1.record()
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1)
+    return total / steps
+
+
 def median_ci(xs):
     """Median and a distribution-free 95% confidence interval for it (order statistics of the
     binomial(n, 1/2) ranks, normal approximation)."""
@@ -440,8 +476,7 @@ def bench_sweep(args, torch, np):
         ms_f = timed(lambda: model.objective(th1, out=f1, info=i1), steps, warm, use_graph, torch)
         ms_ad = timed(lambda: model.grad(theta, f=f1, g=g, info=i1), steps, warm, use_graph, torch)
         ms_fwd = timed(lambda: model.forward_saved(theta), steps, warm, use_graph, torch)
-        ms_bwd = timed(lambda: model.grad(theta, reuse=True, f=f1, g=g, info=i1), steps, warm,
-                       use_graph, torch)
+        ms_bwd = timed_backward(model, theta, f1, g, i1, steps, warm, use_graph, torch)
         mb = model.fitting_batch(npts, 0)
         ms_fd = timed(lambda: model.fd_grad(theta, h=1e-3, max_batch=mb, f=f1, g=gf, info=ifd),
                       steps, warm, use_graph, torch)
@@ -537,10 +572,18 @@ def main():
     fd_step = lambda: model.fd_grad(theta, h=1e-3, max_batch=npts, f=f_fd, g=g_fd, info=i_fd)  # noqa: E731
     fwd_step = lambda: model.forward_saved(theta)  # noqa: E731
     ms_ad = timed(ad_step, args.steps, args.warmup, use_graph, torch)
+    g_ref = g_ad.clone()  # every replay of the full gradient recomputes it
     ms_fd = timed(fd_step, args.steps, args.warmup, use_graph, torch)
     ms_fwd = timed(fwd_step, max(3, args.steps // 2), 1, use_graph, torch)
-    ms_bwd = timed(lambda: model.grad(theta, reuse=True, f=f_ad, g=g_ad, info=i_ad),
-                   max(3, args.steps // 2), 1, use_graph, torch)
+    ms_bwd = timed_backward(model, theta, f_ad, g_ad, i_ad, max(3, args.steps // 2), 1, use_graph,
+                            torch)
+
+    # the carry-only memory mode (factors rebuilt in the backward pass)
+    g_c = torch.empty(d, dtype=torch.float64, device=dev)
+    ms_carry = timed(lambda: model.grad(theta, f=f_ad, g=g_c, info=i_ad, carry=True),
+                     max(3, args.steps // 2), 1, use_graph, torch)
+    torch.cuda.synchronize()
+    carry_rel = float((g_c - g_ref).abs().max().item() / g_ref.abs().max().item())
 
     stats, roof = profiled_pass(args, ad_step, bta, torch)
     roof["traffic"] = measured_traffic(roof["kernel_symbol"], args.workload)
@@ -576,6 +619,10 @@ def main():
         "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": ad_fd_rel, "info_ok": ok},
         "ms_ad_per_call": median_ci(TIMES.get(id(ad_step), [])),
         "ms_fd_per_call": median_ci(TIMES.get(id(fd_step), [])),
+        "carry_only": {"ms_per_gradient": ms_carry,
+                       "workspace_gb": model.workspace_bytes(1, 2) / 1e9,
+                       "stored_factor_workspace_gb": model.workspace_bytes(1, 1) / 1e9,
+                       "grad_rel_vs_stored": carry_rel},
         # torch-owned device memory (every workspace; the model's own upload is a few MB)
         "peak_device_memory_gb": {"ad": peak_ad / 1e9,
                                   "with_fd_batch": torch.cuda.max_memory_allocated() / 1e9},

@@ -205,6 +205,9 @@ const char* adelia_last_error(void);
  * every block's factor, W and G^T G: about (4n + 6) b^2 doubles per matrix and point. */
 #define ADELIA_MODE_OBJECTIVE 0
 #define ADELIA_MODE_GRAD 1
+/* A carry-only gradient workspace (see ADELIA_CARRY_ONLY): about n b^2 + 10 b^2 doubles per
+ * matrix and point instead of (4n + 6) b^2. */
+#define ADELIA_MODE_GRAD_CARRY 2
 size_t inla_workspace_bytes(inla_model model, int batch, int mode);
 
 /* f(theta) of Eq. 1 for `batch` points theta (device, batch x d, row-major):
@@ -219,8 +222,17 @@ int inla_objective(inla_model model, const double* theta, int32_t batch, double*
 /* f and its exact gradient (Sec. III-A-3, Eq. 5: Phases A, B, C plus the likelihood and
  * prior terms; Eqs. 10-11 for the coregional parameters).  theta, grad: device, d.
  * flags & ADELIA_REUSE_FACTORS: skip the forward pass and use the factors saved by the
- * preceding inla_objective(SAVE_FACTORS) on the same workspace and theta. */
+ * preceding inla_objective(SAVE_FACTORS) on the same workspace and theta.  The reverse pass
+ * consumes them (it overwrites G^T G with Z_D): a second REUSE call, or a REUSE call after any
+ * other call on that workspace, returns ADELIA_E_STATE.  (A captured graph that replays a
+ * REUSE call must replay the SAVE call before it.) */
 #define ADELIA_REUSE_FACTORS 1
+/* flags & ADELIA_CARRY_ONLY (workspace of mode ADELIA_MODE_GRAD_CARRY; not with REUSE): the
+ * memory mode of Sec. III-A-1/2.  The forward keeps only each block's Schur-updated diagonal
+ * block D_i - S_{i-1} (the carry, b x b) and its arrow rows [L_C | z]; the backward rebuilds
+ * L_D and L_B block by block (one more block Cholesky per block), with G, W and G^T G in rings
+ * of two blocks.  The result equals the stored-factor gradient up to rounding. */
+#define ADELIA_CARRY_ONLY 2
 int inla_grad(inla_model model, const double* theta, double* f, double* grad, int32_t* info,
               void* ws, size_t ws_bytes, int flags, void* stream);
 

@@ -38,6 +38,10 @@ struct inla_model_s {
   void* dev_mem;
   SideRes side;
   bool has_side;
+  // the workspace holding the factors of the last inla_objective(SAVE_FACTORS): one
+  // inla_grad(REUSE_FACTORS) on it consumes them (the reverse pass overwrites G^T G with Z_D);
+  // any other call on that workspace discards them
+  const void* saved_ws;
 };
 
 namespace {
@@ -45,6 +49,13 @@ namespace {
 struct InlaWs {
   int batch, nz, n, b, a, ap, k, d, npanel;
   bool grad;
+  // carry-only gradient: the forward keeps each block's Schur-updated diagonal block (Dc) and
+  // its arrow rows [L_C | z] (LCz, ld ap) instead of the factors; the backward rebuilds
+  // L_D, L_B, G, W and G^T G block by block in small rings
+  bool carry;
+  double *Dc, *LCz;
+  long long zDc, zLCz;
+  int slotsW, slotsZD;
   int slotsD, slotsB, slotsLBC, slotsG;
   double *D, *Bin, *LBC, *G, *C, *T, *S, *ldpart, *ld, *zsq, *ZT, *xT;
   long long zD, zB, zLBC, zG, zC, zT, zS, zLd, zZT, zXT;
@@ -62,19 +73,23 @@ struct InlaWs {
   size_t bytes;
 };
 
-InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
+InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = false) {
   InlaWs w{};
   w.batch = batch;
+  w.carry = grad && carry;
   w.nz = 2 * batch;
   w.n = M.nt; w.b = M.b; w.a = M.a; w.ap = M.a + 1; w.k = M.k; w.d = M.d;
   w.npanel = (M.b + kPanel - 1) / kPanel;
   w.grad = grad;
   const long long bb = (long long)M.b * M.b;
   const int n = M.nt;
-  w.slotsD = grad ? 3 : 2;
+  const bool stored = grad && !w.carry;  // every block's factor kept
+  w.slotsD = stored ? 3 : 2;
   w.slotsB = 1;
-  w.slotsLBC = grad ? n : 1;
-  w.slotsG = grad ? n : 1;
+  w.slotsLBC = stored ? n : (w.carry ? 2 : 1);
+  w.slotsG = stored ? n : (w.carry ? 2 : 1);
+  w.slotsW = stored ? n : 2;
+  w.slotsZD = stored ? n : 2;
   size_t off = 0;
   auto take = [&](long long per_chain, int chains, long long& stride) {
     stride = per_chain;
@@ -125,8 +140,12 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base) {
     w.y = take(M.b, nz, w.zy);
     // [W_t; V_t] and G_t^T G_t (the Z-independent parts of the selected inversion) are formed
     // during the forward sweep, so they get a slot per block
-    w.W = take((long long)n * (bb + (long long)M.a * M.b), nz, w.zW);
-    w.ZD = take((long long)n * bb, nz, w.zZD);
+    w.W = take((long long)w.slotsW * (bb + (long long)M.a * M.b), nz, w.zW);
+    w.ZD = take((long long)w.slotsZD * bb, nz, w.zZD);
+    if (w.carry) {
+      w.Dc = take((long long)n * bb, nz, w.zDc);
+      w.LCz = take(std::max(1LL, (long long)n * w.ap * M.b), nz, w.zLCz);
+    }
     w.ZB = take(bb, nz, w.zZB);
     w.ZC = take(std::max(1LL, 2LL * M.a * M.b), nz, w.zZC);
     w.TD = take((long long)n * 3 * M.k * M.k * M.nch_rows, nz, w.zTr);
@@ -147,7 +166,7 @@ BtaChains chains_of(const InlaWs& w) {
   c.Bin = w.Bin; c.zB = w.zB; c.slotsB = w.slotsB;
   c.C = w.C; c.zC = w.zC;
   c.LBC = w.LBC; c.zLBC = w.zLBC; c.slotsLBC = w.slotsLBC;
-  c.invert = w.grad;
+  c.invert = w.grad && !w.carry;
   c.T = w.T; c.zT = w.zT;
   c.G = w.G; c.zG = w.zG; c.slotsG = w.slotsG;
   c.ldpart = w.ldpart; c.zLd = w.zLd;
@@ -175,10 +194,13 @@ SelinvChains selinv_of(const InlaWs& w) {
   si.LB = w.LBC; si.zLB = w.zLBC; si.slotsLB = w.slotsLBC; si.ldLB = b + ap; si.sLB = sLBC;
   si.LC = w.LBC + b; si.zLC = w.zLBC; si.ldLC = b + ap; si.sLC = sLBC;
   si.ZT = w.ZT; si.zZT = w.zZT;
-  si.ZD = w.ZD; si.zZD = w.zZD; si.slotsZD = w.n;
+  si.ZD = w.ZD; si.zZD = w.zZD; si.slotsZD = w.slotsZD;
   si.ZB = w.ZB; si.zZB = w.zZB; si.slotsZB = 1;
   si.ZC = w.ZC; si.zZC = w.zZC; si.slotsZC = 2;
-  si.W = w.W; si.zW = w.zW; si.slotsW = w.n;
+  si.W = w.W; si.zW = w.zW; si.slotsW = w.slotsW;
+  if (w.carry) {  // the arrow rows of every block, ld ap
+    si.LC = w.LCz; si.zLC = w.zLCz; si.ldLC = ap; si.sLC = (long long)ap * b;
+  }
   return si;
 }
 
@@ -241,7 +263,15 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
       la.mark = side->ready[(i - 1) % 3];
       la.mark_step = 0;
     }
+    // carry-only: the diagonal block about to be factored is D_i - S_{i-1}
+    if (w.carry && launch_copy2d(w.D + (long long)(i % w.slotsD) * bb, b, w.zD,
+                                 w.Dc + (long long)i * bb, b, w.zDc, b, b, nz, s))
+      return ADELIA_E_HIP;
     if (bta_forward_block(c, i, s, side ? &la : nullptr)) return ADELIA_E_HIP;
+    if (w.carry && w.ap > 0 &&
+        launch_copy2d(w.LBC + (long long)(i % w.slotsLBC) * ldT * b + b, ldT, w.zLBC,
+                      w.LCz + (long long)i * w.ap * b, w.ap, w.zLCz, w.ap, b, nz, s))
+      return ADELIA_E_HIP;
     auto fork_block = [&](int j, bool recorded) -> int {
       if ((!recorded && hipEventRecord(side->ready[j % 3], s) != hipSuccess) ||
           hipStreamWaitEvent(side->s2, side->ready[j % 3], 0) != hipSuccess)
@@ -254,7 +284,7 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
     if (fork) {
       if (late && fork_block(i - 1, true)) return ADELIA_E_HIP;
       if (i == n - 1 && fork_block(i, false)) return ADELIA_E_HIP;
-    } else if (w.grad) {
+    } else if (w.grad && !w.carry) {
       if (selinv_prepare(si, i, s)) return ADELIA_E_HIP;
     }
   }
@@ -290,34 +320,77 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
   sc.x = w.x; sc.zx = w.zx;
   sc.y = w.y; sc.zy = w.zy;
-  // x* is read only by Phase B and the residual at the end: with the side stream (idle after
-  // the forward sweep's join) the upper sweep runs there, beside the selected inversion
-  if (side) {
-    if (hipEventRecord(side->ready[0], s) != hipSuccess ||
-        hipStreamWaitEvent(side->s2, side->ready[0], 0) != hipSuccess ||
-        bta_upper_solve(sc, side->s2) ||
-        hipEventRecord(side->done[0], side->s2) != hipSuccess)
-      return ADELIA_E_HIP;
-  } else if (bta_upper_solve(sc, s)) {
-    return ADELIA_E_HIP;
-  }
-  // selected inversion of Qc and Qp with the trace epilogue per block (Eq. 6); the forward
-  // sweep already formed [W_j; V_j] and G_j^T G_j
   const SelinvChains si = selinv_of(w);
   const long long bb = (long long)b * b;
   const int ntrace = 2 * M.k * M.k * M.nch_rows + M.k * M.nch_obs;
-  for (int j = n - 1; j >= 0; --j) {
-    if (selinv_finish(si, j, s)) return ADELIA_E_HIP;
-    const double* ZDj = w.ZD + (long long)j * bb;
+  auto trace = [&](int j) -> int {
+    const double* ZDj = w.ZD + (long long)(j % w.slotsZD) * bb;
     const double* ZCj = w.ZC + (long long)(j % 2) * a * b;
     const ProfToken t = prof_begin(s);
     hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, s, M, j, ZDj, w.zZD,
                        w.ZB, w.zZB, ZCj, w.zZC, w.ZT, w.zZT, w.TD, w.TB, w.O, w.zTr, w.zO);
     if (t.valid)  // the band of Z_D and Z_B at the base-matrix pattern, per sub-block pair
       prof_end(t, s, PK_TRACE, 0.0, 8.0 * nz * 2.0 * M.k * M.k * M.nnz);
-    if (!LAUNCH_OK()) return ADELIA_E_HIP;
+    return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+  };
+  bool forked = false;
+  if (w.carry) {
+    // Carry-only (Sec. III-A-2, L reconstruction): block j's factor is rebuilt from its stored
+    // Schur-updated diagonal block D_j - S_{j-1} and B_j (assembled again from theta): the
+    // panels solve B_j only (the arrow rows [L_C | z] are stored), then G_j, [W_j; V_j] and
+    // G_j^T G_j, the upper-solve step for x_j and the selected-inversion step, all in one pass
+    // from the last block down.
+    sc.LC = w.LCz; sc.zLC = w.zLCz; sc.ldLC = ap; sc.sLC = (long long)ap * b;
+    sc.z = w.LCz + a; sc.zz = w.zLCz; sc.sz_blk = (long long)ap * b; sc.sz_elem = ap;
+    BtaChains c = chains_of(w);
+    c.refactor = true;
+    c.b_in_place = true;
+    c.invert = false;
+    Lookahead la{};
+    if (side) {
+      la = side->la;
+      la.mark = nullptr;
+    }
+    const long long ldT = (long long)b + ap;
+    const dim3 agrid(b, 1, nz);
+    for (int j = n - 1; j >= 0; --j) {
+      double* Dslot = w.D + (long long)(j % w.slotsD) * bb;
+      if (launch_copy2d(w.Dc + (long long)j * bb, b, w.zDc, Dslot, b, w.zD, b, b, nz, s))
+        return ADELIA_E_HIP;
+      if (j < n - 1) {
+        hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, -1, j, Dslot, w.zD,
+                           w.LBC + (long long)(j % w.slotsLBC) * ldT * b, w.zLBC, ldT, w.phi,
+                           w.tau);
+        if (!LAUNCH_OK()) return ADELIA_E_HIP;
+      }
+      if (bta_forward_block(c, j, s, side ? &la : nullptr) || bta_invert_block(c, j, s) ||
+          selinv_prepare(si, j, s) || bta_upper_solve_block(sc, j, s) ||
+          selinv_finish(si, j, s))
+        return ADELIA_E_HIP;
+      if (int r = trace(j)) return r;
+    }
+    if (bta_upper_solve_tip(sc, s)) return ADELIA_E_HIP;
+  } else {
+    // x* is read only by Phase B and the residual at the end: with the side stream (idle after
+    // the forward sweep's join) the upper sweep runs there, beside the selected inversion
+    if (side) {
+      if (hipEventRecord(side->ready[0], s) != hipSuccess ||
+          hipStreamWaitEvent(side->s2, side->ready[0], 0) != hipSuccess ||
+          bta_upper_solve(sc, side->s2) ||
+          hipEventRecord(side->done[0], side->s2) != hipSuccess)
+        return ADELIA_E_HIP;
+      forked = true;
+    } else if (bta_upper_solve(sc, s)) {
+      return ADELIA_E_HIP;
+    }
+    // selected inversion of Qc and Qp with the trace epilogue per block (Eq. 6); the forward
+    // sweep already formed [W_j; V_j] and G_j^T G_j
+    for (int j = n - 1; j >= 0; --j) {
+      if (selinv_finish(si, j, s)) return ADELIA_E_HIP;
+      if (int r = trace(j)) return r;
+    }
   }
-  if (side && hipStreamWaitEvent(s, side->done[0], 0) != hipSuccess) return ADELIA_E_HIP;
+  if (forked && hipStreamWaitEvent(s, side->done[0], 0) != hipSuccess) return ADELIA_E_HIP;
   // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 2p of point p)
   const int B = w.batch;
   hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k, 1, B), dim3(256), 0, s, M, w.x, 2 * w.zx,
@@ -592,8 +665,10 @@ int inla_model_dim(inla_model m) { return m ? m->M.d : 0; }
 
 size_t inla_workspace_bytes(inla_model m, int batch, int mode) {
   if (!m || batch < 1 || batch > 32767) return 0;
-  if (mode != ADELIA_MODE_OBJECTIVE && mode != ADELIA_MODE_GRAD) return 0;
-  return layout(m->M, batch, mode == ADELIA_MODE_GRAD, nullptr).bytes;
+  if (mode != ADELIA_MODE_OBJECTIVE && mode != ADELIA_MODE_GRAD && mode != ADELIA_MODE_GRAD_CARRY)
+    return 0;
+  return layout(m->M, batch, mode != ADELIA_MODE_OBJECTIVE, nullptr,
+                mode == ADELIA_MODE_GRAD_CARRY).bytes;
 }
 
 int inla_objective(inla_model m, const double* theta, int32_t batch, double* f, int32_t* info,
@@ -609,6 +684,7 @@ int inla_objective(inla_model m, const double* theta, int32_t batch, double* f, 
   if (save && batch != 1) return -3;
   InlaWs w = layout(m->M, batch, save, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  m->saved_ws = save ? ws : (m->saved_ws == ws ? nullptr : m->saved_ws);
   return run_objective(m->M, w, theta, f, info, (hipStream_t)stream,
                        m->has_side ? &m->side : nullptr);
 }
@@ -621,9 +697,13 @@ int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_
   if (!grad || !aligned(grad, 8)) return -4;
   if (!info || !aligned(info, 4)) return -5;
   if (!ws || !aligned(ws, 256)) return -6;
-  if (flags & ~ADELIA_REUSE_FACTORS) return -8;
-  InlaWs w = layout(m->M, 1, true, reinterpret_cast<char*>(ws));
+  if (flags & ~(ADELIA_REUSE_FACTORS | ADELIA_CARRY_ONLY)) return -8;
+  const bool carry = flags & ADELIA_CARRY_ONLY;
+  if (carry && (flags & ADELIA_REUSE_FACTORS)) return -8;
+  InlaWs w = layout(m->M, 1, true, reinterpret_cast<char*>(ws), carry);
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  if ((flags & ADELIA_REUSE_FACTORS) && m->saved_ws != ws) return ADELIA_E_STATE;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   if (!(flags & ADELIA_REUSE_FACTORS)) {
     int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
@@ -644,6 +724,7 @@ int inla_grad_batched(inla_model m, const double* theta, int32_t batch, double* 
   if (!ws || !aligned(ws, 256)) return -7;
   InlaWs w = layout(m->M, batch, true, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
   if (r) return r;
@@ -658,9 +739,13 @@ int inla_grad_terms(inla_model m, const double* theta, double* terms, int32_t* i
   if (!terms || !aligned(terms, 8)) return -3;
   if (!info || !aligned(info, 4)) return -4;
   if (!ws || !aligned(ws, 256)) return -5;
-  if (flags & ~ADELIA_REUSE_FACTORS) return -7;
-  InlaWs w = layout(m->M, 1, true, reinterpret_cast<char*>(ws));
+  if (flags & ~(ADELIA_REUSE_FACTORS | ADELIA_CARRY_ONLY)) return -7;
+  const bool carry = flags & ADELIA_CARRY_ONLY;
+  if (carry && (flags & ADELIA_REUSE_FACTORS)) return -7;
+  InlaWs w = layout(m->M, 1, true, reinterpret_cast<char*>(ws), carry);
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  if ((flags & ADELIA_REUSE_FACTORS) && m->saved_ws != ws) return ADELIA_E_STATE;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   if (!(flags & ADELIA_REUSE_FACTORS)) {
     int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
@@ -685,6 +770,7 @@ int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch,
   const int bmax = std::min<int>(max_batch, npts);
   InlaWs w = layout(m->M, bmax, false, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d, h,
                      w.Th);
@@ -717,6 +803,7 @@ int inla_hessian(inla_model m, const double* theta, double h, int32_t max_batch,
   const int bmax = std::min<int>(max_batch, npts);
   InlaWs w = layout(m->M, bmax, true, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d, h,
                      w.Th);
@@ -752,6 +839,7 @@ int inla_fd_hessian(inla_model m, const double* theta, double h, int32_t max_bat
   const int bmax = std::min<int>(max_batch, npts);
   InlaWs w = layout(m->M, bmax, false, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(hess_stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d,
                      h, w.Th);

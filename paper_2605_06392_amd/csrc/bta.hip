@@ -114,11 +114,11 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
   if (hasB && !c.b_in_place &&
       launch_copy2d(c.Bin + blk_off(i, c.slotsB, bb), b, c.zB, LBC, ldT, c.zLBC, b, b, nz, s))
     return ADELIA_E_HIP_INTERNAL;
-  if (ap > 0 &&
+  if (ap > 0 && !c.refactor &&
       launch_copy2d(c.C + (long long)i * ap * b, ap, c.zC, LBC + b, ldT, c.zLBC, ap, b, nz, s))
     return ADELIA_E_HIP_INTERNAL;
   double* Rows = hasB ? LBC : LBC + b;
-  const int mT = (hasB ? b : 0) + ap;
+  const int mT = (hasB ? b : 0) + (c.refactor ? 0 : ap);
   // rank-64 update of the columns from `from` on (the rows below them and the rows of
   // [B_i; C~_i]) with panel k
   auto trailing_args = [&](int k, int from) -> GemmArgs {
@@ -241,8 +241,9 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     const int r = bta_invert_block(c, i, s);
     if (r) return r;
   }
-  // 3. Schur update of the next diagonal block, next arrow block and the tip
-  if (hasB || ap > 0) {
+  // 3. Schur update of the next diagonal block, next arrow block and the tip (a rebuilt block
+  //    has its successor's carry stored already)
+  if (!c.refactor && (hasB || ap > 0)) {
     GemmArgs g{};
     g.nph = 1;
     g.ph[0].alpha = -1.0;
@@ -456,9 +457,15 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
 }
 
 int bta_upper_solve(const SolveChains& c, hipStream_t s) {
+  for (int i = c.n - 1; i >= 0; --i)
+    if (bta_upper_solve_block(c, i, s)) return ADELIA_E_HIP_INTERNAL;
+  return bta_upper_solve_tip(c, s);
+}
+
+int bta_upper_solve_block(const SolveChains& c, int i, hipStream_t s) {
   const int b = c.b, a = c.a, n = c.n, nz = c.nz;
   const long long bb = (long long)b * b;
-  for (int i = n - 1; i >= 0; --i) {
+  {
     const double* LCi = c.LC + (long long)i * c.sLC;
     GemvT g{};
     if (i < n - 1) {
@@ -484,6 +491,11 @@ int bta_upper_solve(const SolveChains& c, hipStream_t s) {
     h.M = b; h.K = b; h.lowerA = 1;
     if (launch_gemv_t(h, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
+  return 0;
+}
+
+int bta_upper_solve_tip(const SolveChains& c, hipStream_t s) {
+  const int b = c.b, a = c.a, n = c.n, nz = c.nz;
   // the tip part of x
   if (a && c.xT) {
     if (launch_copy2d(c.xT, a, c.zxT, c.x + (long long)n * b, a, c.zx, a, 1, nz, s))

@@ -112,6 +112,9 @@ struct BtaChains {
   int inv_maxwg;                            // workgroup cap of bta_invert_block's launches
   bool b_in_place;                          // B_t already assembled into the rows of [L_B; L_C]
   double* Vp; long long zVp;                // 64 x 64 per chain (split panels with look-ahead)
+  // rebuild a block's factor from its stored Schur-updated diagonal block: B_i already in the
+  // rows of [L_B; L_C], the arrow rows stored elsewhere (not solved again), no Schur update
+  bool refactor;
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
 // Look-ahead for the block Cholesky: each panel launch first applies the previous panel's
@@ -170,6 +173,9 @@ struct SolveChains {
   double* y; long long zy;                        // scratch b
 };
 int bta_upper_solve(const SolveChains& c, hipStream_t s);
+// One block of it (x_i from x_{i+1} and x_T), and the tip part of x (after block 0).
+int bta_upper_solve_block(const SolveChains& c, int i, hipStream_t s);
+int bta_upper_solve_tip(const SolveChains& c, hipStream_t s);
 
 // y(m) = beta*y0(m) + alpha * sum_k A(k, m) x(k) over k in [klo(m), K), A column-major (ld),
 // plus optional alpha2 * sum_c A2(c, m) x2(c) (A2 is r2 x M, ld2).  klo(m) = m if lowerA.

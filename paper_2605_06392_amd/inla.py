@@ -23,8 +23,10 @@ PARAM_UNIVARIATE = 1
 PARAM_COREG = 2
 MODE_OBJECTIVE = 0
 MODE_GRAD = 1
+MODE_GRAD_CARRY = 2
 SAVE_FACTORS = 1
 REUSE_FACTORS = 1
+CARRY_ONLY = 2
 
 _token = itertools.count(1)
 
@@ -150,28 +152,33 @@ class InlaModel:
         self.saved_token = next(_token)
         return f, inf, self.saved_token
 
-    def grad(self, theta, reuse=False, f=None, g=None, info=None):
+    def grad(self, theta, reuse=False, f=None, g=None, info=None, carry=False):
+        """f and the exact gradient; carry=True keeps only the per-block carries and rebuilds
+        the factors in the backward pass (less memory, one more block Cholesky per block)."""
         th = self._theta(theta).reshape(self.d)
         f = f if f is not None else torch.empty(1, dtype=torch.float64, device=self.device)
         g = g if g is not None else torch.empty(self.d, dtype=torch.float64, device=self.device)
         inf = info if info is not None else torch.empty(1, dtype=torch.int32, device=self.device)
-        ws, nb = self.workspace(1, MODE_GRAD)
+        ws, nb = self.workspace(1, MODE_GRAD_CARRY if carry else MODE_GRAD)
+        flags = (REUSE_FACTORS if reuse else 0) | (CARRY_ONLY if carry else 0)
         check(lib().inla_grad(self._h, C.c_void_p(th.data_ptr()), C.c_void_p(f.data_ptr()),
                               C.c_void_p(g.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb,
-                              REUSE_FACTORS if reuse else 0, self._stream()), "inla_grad")
+                              flags, self._stream()), "inla_grad")
+        self.saved_token = 0  # a reuse consumes the saved factors, a new pass overwrites them
         return f, g, inf
 
-    def grad_terms(self, theta, reuse=False):
+    def grad_terms(self, theta, reuse=False, carry=False):
         """f, gradient and its decomposition as a dict of host numpy values."""
         th = self._theta(theta).reshape(self.d)
         d = self.d
         terms = torch.empty(5 + 6 * d, dtype=torch.float64, device=self.device)
         inf = torch.empty(1, dtype=torch.int32, device=self.device)
-        ws, nb = self.workspace(1, MODE_GRAD)
+        ws, nb = self.workspace(1, MODE_GRAD_CARRY if carry else MODE_GRAD)
+        flags = (REUSE_FACTORS if reuse else 0) | (CARRY_ONLY if carry else 0)
         check(lib().inla_grad_terms(self._h, C.c_void_p(th.data_ptr()), C.c_void_p(terms.data_ptr()),
-                                    C.c_void_p(inf.data_ptr()), ws, nb,
-                                    REUSE_FACTORS if reuse else 0, self._stream()),
+                                    C.c_void_p(inf.data_ptr()), ws, nb, flags, self._stream()),
               "inla_grad_terms")
+        self.saved_token = 0
         t = terms.cpu().numpy()
         return {"f": t[0], "logdet_p": t[1], "logdet_c": t[2], "zsq": t[3], "trZT": t[4],
                 "phaseA": t[5:5 + d], "phaseB": t[5 + d:5 + 2 * d], "phaseC": t[5 + 2 * d:5 + 3 * d],
@@ -205,6 +212,7 @@ class InlaModel:
                                       C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()),
                                       C.c_void_p(inf.data_ptr()), ws, nb, self._stream()),
               "inla_grad_batched")
+        self.saved_token = 0
         return f, g, inf
 
     def fitting_batch(self, npts, mode, fraction=0.5):
@@ -238,6 +246,7 @@ class InlaModel:
                                  C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()),
                                  C.c_void_p(H.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb,
                                  self._stream()), "inla_hessian")
+        self.saved_token = 0
         return f, g, H.T, inf
 
     def fd_hessian(self, theta, h=5e-3, max_batch=None, f=None, H=None, info=None):

@@ -83,6 +83,22 @@ def test_bench_size_identities_and_fd(name):
     assert np.abs(H - H.T).max() <= 1e-5 * np.abs(H).max()
 
 
+def test_bench_size_carry_only_gradient():
+    """The carry-only memory mode at the benchmark size: the same gradient as the stored-factor
+    mode (up to rounding) in under half the workspace."""
+    from paper_2605_06392_amd.inla import InlaModel, MODE_GRAD, MODE_GRAD_CARRY
+    spec = named_config("uni_32x32_nt50", seed=0)
+    m = InlaModel(spec, device=_dev())
+    assert m.workspace_bytes(1, MODE_GRAD_CARRY) * 2 < m.workspace_bytes(1, MODE_GRAD)
+    t_s = m.grad_terms(torch.tensor(spec.theta))
+    t_c = m.grad_terms(torch.tensor(spec.theta), carry=True)
+    assert t_c["info"] == 0
+    _identities(spec, t_c)
+    scale = np.abs(t_s["grad"]).max()
+    assert abs(t_c["f"] - t_s["f"]) <= 1e-12 * abs(t_s["f"])
+    assert np.abs(t_c["grad"] - t_s["grad"]).max() <= 1e-10 * scale
+
+
 def test_bench_size_without_observations():
     from paper_2605_06392_amd.inla import InlaModel
     k, nx, ny, nt, a, _ = NAMED_CONFIGS["uni_32x32_nt50"]
