@@ -43,7 +43,7 @@ struct Group {
 };
 
 struct GroupWs {
-  double *D, *B, *G, *C, *LC, *T, *LBC, *S, *ldpart, *zsq, *ld;
+  double *D, *B, *G, *C, *LC, *T, *LBC, *S, *ldpart, *zsq, *ld, *Vp;
   int32_t *info, *cnt, *zn, *idx;
   long long zD, zB, zG, zC, zT, zLd;
   int ap, slotsB, npanel;
@@ -77,6 +77,7 @@ GroupWs group_layout(const Group& g, bool rhs, char* base) {
   w.ldpart = take((long long)g.nmax * w.npanel + 1, w.zLd);
   w.zsq = take(1, dummy);
   w.ld = take(1, dummy);
+  w.Vp = take((long long)kPanel * kPanel, dummy);
   int32_t* ints = base ? reinterpret_cast<int32_t*>(base + off) : nullptr;
   off = align_up(off + (size_t)4 * nz * sizeof(int32_t));
   w.info = ints;
@@ -187,7 +188,6 @@ int bta_factor_batched(adelia_ctx ctx, int count, const adelia_bta_shape* shapes
     c.D = w.D; c.zD = w.zD; c.slotsD = g.nmax;
     c.Bin = w.B; c.zB = w.zB; c.slotsB = w.slotsB;
     c.LBC = w.LBC; c.zLBC = (long long)(b + ap) * b; c.slotsLBC = 1;
-    c.invert = true;
     c.C = w.C; c.zC = w.zC;
     c.T = w.T; c.zT = w.zT;
     c.G = w.G; c.zG = w.zG; c.slotsG = g.nmax;
@@ -197,8 +197,19 @@ int bta_factor_batched(adelia_ctx ctx, int count, const adelia_bta_shape* shapes
     c.zn = w.zn;
     c.scratch = w.S; c.zS = bb;
     c.zsq = w.zsq;
+    c.Vp = w.Vp; c.zVp = (long long)kPanel * kPanel;
+    // with the context's streams: look-ahead steps, and each block's inverse on the side stream
+    // (every block keeps its L_D and G slot), joined before the results are unpacked
+    const bool side = ctx->has_streams;
+    c.invert = !side;
+    c.inv_maxwg = side ? ctx->side_maxwg : 0;
+    Lookahead la = ctx->la;
     for (int i = 0; i < g.nmax; ++i) {
-      if (bta_forward_block(c, i, s)) return ADELIA_E_HIP;
+      if (bta_forward_block(c, i, s, side ? &la : nullptr)) return ADELIA_E_HIP;
+      if (side && (hipEventRecord(ctx->fork[i % 3], s) != hipSuccess ||
+                   hipStreamWaitEvent(ctx->s2, ctx->fork[i % 3], 0) != hipSuccess ||
+                   bta_invert_block(c, i, ctx->s2)))
+        return ADELIA_E_HIP;
       // [L_Bi; L_Ci] leave the one-block scratch for block i's slots
       if (i < g.nmax - 1 &&
           launch_copy2d(w.LBC, b + ap, c.zLBC, w.B + (long long)i * bb, b, w.zB, b, b, nz, s))
@@ -207,6 +218,9 @@ int bta_factor_batched(adelia_ctx ctx, int count, const adelia_bta_shape* shapes
                                   w.zC, ap, b, nz, s))
         return ADELIA_E_HIP;
     }
+    if (side && (hipEventRecord(ctx->join, ctx->s2) != hipSuccess ||
+                 hipStreamWaitEvent(s, ctx->join, 0) != hipSuccess))
+      return ADELIA_E_HIP;
     if (bta_tip(c, s)) return ADELIA_E_HIP;
     e |= bta_logdet_reduce(w.ldpart, w.zLd, g.nmax * w.npanel + 1, w.ld, 1, nz, s);
     // ---- unpack

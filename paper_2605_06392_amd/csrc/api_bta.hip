@@ -5,6 +5,7 @@
 #include "launchers.h"
 #include "internal_api.h"
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstring>
@@ -114,13 +115,38 @@ int adelia_create(adelia_ctx* ctx, int device) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return -2;
   if (hipSetDevice(device) != hipSuccess) return ADELIA_E_HIP;
-  adelia_ctx c = new adelia_ctx_s;
+  adelia_ctx c = new adelia_ctx_s();  // value-initialised: every handle starts null
   c->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  c->la.cus = cus;
+  c->side_maxwg = std::max(16, (5 * cus / 8) & ~15);
+  bool ok = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->la.ts, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;
+  for (int e = 0; e < 3 && ok; ++e)
+    ok = hipEventCreateWithFlags(&c->fork[e], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->la.pdone[e], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->la.tdone[e], hipEventDisableTiming) == hipSuccess;
+  c->has_streams = ok;
   *ctx = c;
   return 0;
 }
 
 int adelia_destroy(adelia_ctx ctx) {
+  if (!ctx) return 0;
+  if (ctx->s2) hipStreamSynchronize(ctx->s2);
+  if (ctx->la.ts) hipStreamSynchronize(ctx->la.ts);
+  for (int e = 0; e < 3; ++e) {
+    if (ctx->fork[e]) hipEventDestroy(ctx->fork[e]);
+    if (ctx->la.pdone[e]) hipEventDestroy(ctx->la.pdone[e]);
+    if (ctx->la.tdone[e]) hipEventDestroy(ctx->la.tdone[e]);
+  }
+  if (ctx->join) hipEventDestroy(ctx->join);
+  if (ctx->s2) hipStreamDestroy(ctx->s2);
+  if (ctx->la.ts) hipStreamDestroy(ctx->la.ts);
   delete ctx;
   return 0;
 }
@@ -241,7 +267,6 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double
   c.Bin = B; c.zB = 0; c.slotsB = n > 1 ? n - 1 : 1;
   c.C = w.Caug; c.zC = 0;
   c.LBC = w.LBC; c.zLBC = 0; c.slotsLBC = 1;
-  c.invert = true;
   c.T = w.Taug; c.zT = 0;
   c.G = Dinv; c.zG = 0; c.slotsG = n;
   c.ldpart = w.ldpart; c.zLd = 0;
@@ -249,9 +274,19 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double
   c.cnt = w.cnt;
   c.scratch = w.S; c.zS = 0;
   c.zsq = w.zsq;
+  // with the context's streams: look-ahead steps, and each block's inverse on the side stream
+  // (every block keeps its L_D and G slot), joined before returning
+  const bool side = ctx->has_streams;
+  c.invert = !side;
+  c.inv_maxwg = side ? ctx->side_maxwg : 0;
+  adelia::Lookahead la = ctx->la;
   for (int i = 0; i < n; ++i) {
-    int r = bta_forward_block(c, i, s);
+    int r = bta_forward_block(c, i, s, side ? &la : nullptr);
     if (r) return ADELIA_E_HIP;
+    if (side && (hipEventRecord(ctx->fork[i % 3], s) != hipSuccess ||
+                 hipStreamWaitEvent(ctx->s2, ctx->fork[i % 3], 0) != hipSuccess ||
+                 bta_invert_block(c, i, ctx->s2)))
+      return ADELIA_E_HIP;
     // [L_Bi; L_Ci] leave the one-block scratch: L_Bi into B_i, L_Ci (and z_i) into block i of
     // the augmented arrow
     if (i < n - 1 && launch_copy2d(w.LBC, b + ap, 0, B + (long long)i * bb, b, 0, b, b, 1, s))
@@ -260,6 +295,9 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double
                                 b, 1, s))
       return ADELIA_E_HIP;
   }
+  if (side && (hipEventRecord(ctx->join, ctx->s2) != hipSuccess ||
+               hipStreamWaitEvent(s, ctx->join, 0) != hipSuccess))
+    return ADELIA_E_HIP;
   if (bta_tip(c, s)) return ADELIA_E_HIP;
   if (ap > 0) {
     if (a > 0) {

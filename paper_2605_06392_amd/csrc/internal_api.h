@@ -5,6 +5,13 @@
 
 struct adelia_ctx_s {
   int device;
+  // streams of the batched sweep (default priority), created with the context: the inversions
+  // G_i = L_Di^-1 run on s2 beside the sweep, and the look-ahead updates on la.ts
+  bool has_streams;
+  hipStream_t s2;
+  hipEvent_t fork[3], join;
+  adelia::Lookahead la;
+  int side_maxwg;
 };
 
 namespace adelia {
