@@ -84,12 +84,13 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = 
   const long long bb = (long long)M.b * M.b;
   const int n = M.nt;
   const bool stored = grad && !w.carry;  // every block's factor kept
-  w.slotsD = stored ? 3 : 2;
+  // carry-only: rings of three blocks for the pipelined reverse pass
+  w.slotsD = (stored || w.carry) ? 3 : 2;
   w.slotsB = 1;
-  w.slotsLBC = stored ? n : (w.carry ? 2 : 1);
-  w.slotsG = stored ? n : (w.carry ? 2 : 1);
-  w.slotsW = stored ? n : 2;
-  w.slotsZD = stored ? n : 2;
+  w.slotsLBC = stored ? n : (w.carry ? 3 : 1);
+  w.slotsG = stored ? n : (w.carry ? 3 : 1);
+  w.slotsW = stored ? n : 3;
+  w.slotsZD = stored ? n : 3;
   size_t off = 0;
   auto take = [&](long long per_chain, int chains, long long& stride) {
     stride = per_chain;
@@ -323,14 +324,14 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   const SelinvChains si = selinv_of(w);
   const long long bb = (long long)b * b;
   const int ntrace = 2 * M.k * M.k * M.nch_rows + M.k * M.nch_obs;
-  auto trace = [&](int j) -> int {
+  auto trace = [&](int j, hipStream_t ts) -> int {
     const double* ZDj = w.ZD + (long long)(j % w.slotsZD) * bb;
     const double* ZCj = w.ZC + (long long)(j % 2) * a * b;
-    const ProfToken t = prof_begin(s);
-    hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, s, M, j, ZDj, w.zZD,
+    const ProfToken t = prof_begin(ts);
+    hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, ts, M, j, ZDj, w.zZD,
                        w.ZB, w.zZB, ZCj, w.zZC, w.ZT, w.zZT, w.TD, w.TB, w.O, w.zTr, w.zO);
     if (t.valid)  // the band of Z_D and Z_B at the base-matrix pattern, per sub-block pair
-      prof_end(t, s, PK_TRACE, 0.0, 8.0 * nz * 2.0 * M.k * M.k * M.nnz);
+      prof_end(t, ts, PK_TRACE, 0.0, 8.0 * nz * 2.0 * M.k * M.k * M.nnz);
     return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
   };
   bool forked = false;
@@ -353,7 +354,23 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
     }
     const long long ldT = (long long)b + ap;
     const dim3 agrid(b, 1, nz);
+    // Pipelined over three streams when the rebuild takes the single-launch steps (the
+    // look-ahead stream is then free): rebuilding block j (main stream), its inverse and
+    // [W_j; V_j], G_j^T G_j (side stream), and the upper-solve, selected-inversion and trace
+    // steps (look-ahead stream) overlap for consecutive blocks.  The rebuild of block j reuses
+    // the ring slots of block j+3, whose last reader is block j+2's selected-inversion step.
+    const bool pipe = side && 2LL * nz * panel_workgroups(b, 0, b) <= side->la.cus;
+    hipStream_t s2 = pipe ? side->s2 : s, s3 = pipe ? side->la.ts : s;
+    const hipEvent_t* built = pipe ? side->ready : nullptr;
+    const hipEvent_t* prepared = pipe ? side->la.pdone : nullptr;
+    const hipEvent_t* finished = pipe ? side->la.tdone : nullptr;
+    if (pipe && (hipEventRecord(side->done[0], s) != hipSuccess ||
+                 hipStreamWaitEvent(s2, side->done[0], 0) != hipSuccess ||
+                 hipStreamWaitEvent(s3, side->done[0], 0) != hipSuccess))
+      return ADELIA_E_HIP;
     for (int j = n - 1; j >= 0; --j) {
+      if (pipe && j + 2 <= n - 1 && hipStreamWaitEvent(s, finished[(j + 2) % 3], 0) != hipSuccess)
+        return ADELIA_E_HIP;
       double* Dslot = w.D + (long long)(j % w.slotsD) * bb;
       if (launch_copy2d(w.Dc + (long long)j * bb, b, w.zDc, Dslot, b, w.zD, b, b, nz, s))
         return ADELIA_E_HIP;
@@ -363,12 +380,19 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
                            w.tau);
         if (!LAUNCH_OK()) return ADELIA_E_HIP;
       }
-      if (bta_forward_block(c, j, s, side ? &la : nullptr) || bta_invert_block(c, j, s) ||
-          selinv_prepare(si, j, s) || bta_upper_solve_block(sc, j, s) ||
-          selinv_finish(si, j, s))
+      if (bta_forward_block(c, j, s, side ? &la : nullptr)) return ADELIA_E_HIP;
+      if (pipe && (hipEventRecord(built[j % 3], s) != hipSuccess ||
+                   hipStreamWaitEvent(s2, built[j % 3], 0) != hipSuccess))
         return ADELIA_E_HIP;
-      if (int r = trace(j)) return r;
+      if (bta_invert_block(c, j, s2) || selinv_prepare(si, j, s2)) return ADELIA_E_HIP;
+      if (pipe && (hipEventRecord(prepared[j % 3], s2) != hipSuccess ||
+                   hipStreamWaitEvent(s3, prepared[j % 3], 0) != hipSuccess))
+        return ADELIA_E_HIP;
+      if (bta_upper_solve_block(sc, j, s3) || selinv_finish(si, j, s3)) return ADELIA_E_HIP;
+      if (int r = trace(j, s3)) return r;
+      if (pipe && hipEventRecord(finished[j % 3], s3) != hipSuccess) return ADELIA_E_HIP;
     }
+    if (pipe && hipStreamWaitEvent(s, finished[0], 0) != hipSuccess) return ADELIA_E_HIP;
     if (bta_upper_solve_tip(sc, s)) return ADELIA_E_HIP;
   } else {
     // x* is read only by Phase B and the residual at the end: with the side stream (idle after
@@ -387,7 +411,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
     // sweep already formed [W_j; V_j] and G_j^T G_j
     for (int j = n - 1; j >= 0; --j) {
       if (selinv_finish(si, j, s)) return ADELIA_E_HIP;
-      if (int r = trace(j)) return r;
+      if (int r = trace(j, s)) return r;
     }
   }
   if (forked && hipStreamWaitEvent(s, side->done[0], 0) != hipSuccess) return ADELIA_E_HIP;
