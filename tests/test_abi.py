@@ -20,7 +20,9 @@ def declared_functions():
 
 def test_header_declares_hot_path_calls():
     names = declared_functions()
-    for n in ["bta_factor", "bta_logdet", "bta_solve", "bta_selinv", "inla_objective", "inla_grad"]:
+    for n in ["bta_factor", "bta_factor_batched", "bta_logdet", "bta_solve", "bta_selinv",
+              "inla_objective", "inla_grad", "inla_grad_batched", "inla_fd_grad", "inla_hessian",
+              "inla_fd_hessian"]:
         assert n in names
 
 

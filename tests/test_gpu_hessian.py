@@ -132,3 +132,38 @@ def test_hessian_graph_replay_matches_eager():
         assert np.array_equal(H.cpu().numpy(), ref[2])
         m.grad(other)
         torch.cuda.synchronize()
+
+
+def test_entry_points_reject_bad_arguments():
+    """Argument checks of the Hessian, batched-gradient and carry-only entry points (each
+    returns before anything is enqueued)."""
+    import ctypes as C
+    from paper_2605_06392_amd._lib import lib
+    from paper_2605_06392_amd.inla import (CARRY_ONLY, MODE_GRAD, MODE_OBJECTIVE,
+                                           REUSE_FACTORS)
+    spec, m = gpu_model("uni_8x8_nt8", 0)
+    d = spec.d
+    dev = "cuda:0"
+    th = torch.tensor(spec.theta, device=dev)
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(d, dtype=torch.float64, device=dev)
+    H = torch.empty((d, d), dtype=torch.float64, device=dev)
+    info = torch.empty(2 * d * d + 1, dtype=torch.int32, device=dev)
+    ws, nb = m.workspace(1, MODE_GRAD)
+    wso, nbo = m.workspace(1, MODE_OBJECTIVE)
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def p(t):
+        return C.c_void_p(t.data_ptr())
+
+    L = lib()
+    assert L.inla_hessian(m._h, p(th), 0.0, 1, p(f), p(g), p(H), p(info), ws, nb, s) == -3
+    assert L.inla_hessian(m._h, p(th), 5e-3, 0, p(f), p(g), p(H), p(info), ws, nb, s) == -4
+    assert L.inla_hessian(m._h, p(th), 5e-3, 1, p(f), p(g), p(H), p(info), ws, 256, s) == -101
+    assert L.inla_fd_hessian(m._h, p(th), -1.0, 1, p(f), p(H), p(info), wso, nbo, s) == -3
+    assert L.inla_grad(m._h, p(th), p(f), p(g), p(info), ws, nb, REUSE_FACTORS | CARRY_ONLY,
+                       s) == -8
+    assert L.inla_grad_batched(m._h, p(th), 0, p(f), p(g), p(info), ws, nb, s) == -3
+    assert L.inla_workspace_bytes(m._h, 1, 7) == 0
+    assert L.inla_workspace_bytes(m._h, 1, 2) < L.inla_workspace_bytes(m._h, 1, 1)
+    torch.cuda.synchronize()
