@@ -278,3 +278,29 @@ def test_saved_factors_are_consumed_once():
     with pytest.raises(AdeliaError, match="-104"):
         m.grad(torch.tensor(spec.theta), reuse=True)
     torch.cuda.synchronize()
+
+
+def test_carry_only_graph_replay_matches_eager():
+    """A captured carry-only gradient (three streams in its reverse pass) replays to the eager
+    result, with other work on the model in between."""
+    spec, m = gpu_model("uni_12x12_nt6", 4)
+    theta = torch.tensor(spec.theta, device="cuda:0")
+    f = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    g = torch.empty(spec.d, dtype=torch.float64, device="cuda:0")
+    info = torch.empty(1, dtype=torch.int32, device="cuda:0")
+    m.grad(theta, f=f, g=g, info=info, carry=True)
+    torch.cuda.synchronize()
+    f_ref, g_ref = f.item(), g.cpu().numpy().copy()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        m.grad(theta, f=f, g=g, info=info, carry=True)
+    other = torch.tensor(spec.theta[::-1].copy(), device="cuda:0")
+    for _ in range(3):
+        f.zero_()
+        g.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert f.item() == f_ref and np.array_equal(g.cpu().numpy(), g_ref)
+        m.grad(other, carry=True)
+        m.grad(other)
+        torch.cuda.synchronize()
