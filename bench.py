@@ -49,6 +49,8 @@ def parse():
                     help="problem-size sweep of c_AD = T_AD / T_f and beta = t_bwd / t_fwd: "
                          "n = 2..256 steps on the 32x32 univariate grid (time), or three "
                          "coregionalised fields on ns = 72..1122 nodes, n = 16 (space)")
+    ap.add_argument("--progress", action="store_true",
+                    help="print a line to stderr after every timed step (long workloads)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the event-profiled gradient steps (the command rocprofv3 traces)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -86,6 +88,8 @@ def timed(fn, steps, warmup, use_graph, torch):
     if use_graph:
         fn()  # allocations (workspaces) happen outside the capture
         torch.cuda.synchronize()
+        if PROGRESS:
+            print("first call done", file=sys.stderr, flush=True)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             fn()
@@ -94,12 +98,18 @@ def timed(fn, steps, warmup, use_graph, torch):
         run = fn
     for _ in range(warmup):
         run()
+        if PROGRESS:
+            torch.cuda.synchronize()
+            print("warm-up step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record()
     for t in range(steps):
         run()
         ev[t + 1].record()
+        if PROGRESS:  # long calls: a line per finished step
+            ev[t + 1].synchronize()
+            print(f"step {t + 1}/{steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     per_call = [ev[t].elapsed_time(ev[t + 1]) for t in range(steps)]
     TIMES[id(fn)] = per_call
@@ -107,6 +117,7 @@ def timed(fn, steps, warmup, use_graph, torch):
 
 
 TIMES = {}
+PROGRESS = False
 
 
 def timed_backward(model, theta, f, g, info, steps, warmup, use_graph, torch):
@@ -402,7 +413,10 @@ def bench_hessian(args, model, theta, spec, torch, np):
              if model.workspace_bytes(mb, 0) <= total // 2] or [2 * d + 1]
     for mb in sizes:
         fd = lambda: model.fd_hessian(theta, h=5e-3, max_batch=mb, f=ff, H=Hf, info=info_f)  # noqa: E731,B023
-        fd_ms[mb] = timed(fd, max(1, args.steps // 2), min(1, args.warmup), use_graph, torch)
+        # an FD Hessian in several passes is timed eagerly: capturing one (about 2e5 launches at
+        # b = 2700, d = 15) ended the process during capture or replay
+        fd_ms[mb] = timed(fd, max(1, args.steps // 2), min(1, args.warmup),
+                          use_graph and mb >= nfd, torch)
         fd_calls[mb] = TIMES[id(fd)]
     best = min(fd_ms, key=fd_ms.get)
     torch.cuda.synchronize()
@@ -500,6 +514,8 @@ def bench_sweep(args, torch, np):
 
 def main():
     args = parse()
+    global PROGRESS
+    PROGRESS = args.progress
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: there is no multi-GPU path; "
