@@ -5,13 +5,19 @@ The computation lives in ``libadelia.so`` (HIP kernels behind a C ABI, see inclu
 this package only marshals arguments.  Submodules:
 
 * ``bta``  -- bta_factor / bta_logdet / bta_solve / bta_selinv and a batched FP64 GEMM;
-* ``inla`` -- InlaModel, objective, gradient, GPU finite differences, the autograd Function.
+* ``inla`` -- InlaModel, objective, gradient, GPU finite differences, the posterior Hessian,
+  the autograd Function and BatchRunner (graph-captured batched evaluation); the package
+  re-exports InlaModel, InlaObjective, BatchRunner, fd_grad and hessian.
 """
-__all__ = ["bta", "inla"]
+__all__ = ["bta", "inla", "InlaModel", "InlaObjective", "BatchRunner", "fd_grad", "hessian"]
+
+_FROM_INLA = ("InlaModel", "InlaObjective", "BatchRunner", "fd_grad", "hessian")
 
 
 def __getattr__(name):
+    import importlib
     if name in ("bta", "inla"):
-        import importlib
         return importlib.import_module(f".{name}", __name__)
+    if name in _FROM_INLA:
+        return getattr(importlib.import_module(".inla", __name__), name)
     raise AttributeError(name)

@@ -266,6 +266,55 @@ class InlaModel:
         return f, H.T, inf
 
 
+class BatchRunner:
+    """f (kind="objective") or f and the exact gradient (kind="grad") at a fixed number of theta
+    points per call: the first call captures one batched evaluation (every launch covers all
+    points' chains) into a hipGraph, later calls copy the points in and replay it."""
+
+    def __init__(self, model, batch, kind="objective"):
+        if kind not in ("objective", "grad"):
+            raise ValueError("kind must be 'objective' or 'grad'")
+        self.model, self.batch, self.kind = model, int(batch), kind
+        dev, d = model.device, model.d
+        self.theta = torch.zeros((self.batch, d), dtype=torch.float64, device=dev)
+        self.f = torch.empty(self.batch, dtype=torch.float64, device=dev)
+        self.info = torch.empty(self.batch, dtype=torch.int32, device=dev)
+        self.g = (torch.empty((self.batch, d), dtype=torch.float64, device=dev)
+                  if kind == "grad" else None)
+        self._graph = None
+
+    def _evaluate(self):
+        if self.kind == "objective":
+            self.model.objective(self.theta, out=self.f, info=self.info)
+        else:
+            self.model.grad_batched(self.theta, f=self.f, g=self.g, info=self.info)
+
+    def __call__(self, theta):
+        th = torch.as_tensor(theta, dtype=torch.float64, device=self.model.device)
+        self.theta.copy_(th.reshape(self.batch, self.model.d))
+        if self._graph is None:
+            self._evaluate()  # workspaces are allocated outside the capture
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                self._evaluate()
+            self._graph = graph
+        self._graph.replay()
+        if self.kind == "objective":
+            return self.f, self.info
+        return self.f, self.g, self.info
+
+
+def fd_grad(model, theta, h=1e-3, max_batch=None):
+    """The GPU's (2d+1)-point central-difference gradient (Sec. II-D, Eq. 2): (f, grad, info)."""
+    return model.fd_grad(theta, h=h, max_batch=max_batch)
+
+
+def hessian(model, theta, h=5e-3, max_batch=None):
+    """The posterior Hessian from exact gradients (Sec. III-D, Eq. 12): (f, grad, H, info)."""
+    return model.hessian(theta, h=h, max_batch=max_batch)
+
+
 class InlaObjective(torch.autograd.Function):
     """f = InlaObjective.apply(theta, model); f.backward() fills theta.grad.
 
