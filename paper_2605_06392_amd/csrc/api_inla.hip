@@ -205,6 +205,32 @@ SelinvChains selinv_of(const InlaWs& w) {
   return si;
 }
 
+// The Z-independent part of the selected inversion of block j: V_j, G_j^T G_j and then
+// W_j = L_Bj G_j = B_j (L_Dj L_Dj^T)^-1 = B_j G_j^T G_j from the sparse B_j (the dense product
+// [L_Bj; L_Cj] G_j would cost b^3 flops per block), when a column of G_j^T G_j fits in LDS.
+// The W_j product is bound by reading G_j^T G_j and writing W_j; about 512 workgroups over all
+// chains keep HBM busy without crowding the work that runs beside it.
+constexpr int kWGroups = 512;
+
+int prepare_block(const ModelDev& M, const InlaWs& w, SelinvChains si, int j, hipStream_t s) {
+  const int b = w.b;
+  // as many columns of G_j^T G_j per pass as fit in 64 KB of LDS (at most kWBatch)
+  const int cb = std::min<int>(kWBatch, (int)((64 * 1024) / ((size_t)b * sizeof(double))));
+  const bool sparse_w = j < w.n - 1 && cb >= 1;
+  si.w_external = sparse_w;
+  if (selinv_prepare(si, j, s)) return ADELIA_E_HIP;
+  if (sparse_w) {
+    const long long bb = (long long)b * b;
+    const double* Y = w.ZD + (long long)(j % w.slotsZD) * bb;
+    double* Wm = w.W + (long long)(j % w.slotsW) * (bb + (long long)w.a * b);
+    const int wg = std::max(1, std::min((b + cb - 1) / cb, kWGroups / w.nz));
+    hipLaunchKernelGGL(w_from_gtg_kernel, dim3(wg, 1, w.nz), dim3(256),
+                       (size_t)cb * b * sizeof(double), s, M, j, Y, w.zZD, Wm, w.zW, w.phi, cb);
+    if (hipGetLastError() != hipSuccess) return ADELIA_E_HIP;
+  }
+  return 0;
+}
+
 int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStream_t s,
                 const SideRes* side) {
   const int nz = w.nz, n = w.n, b = w.b;
@@ -279,14 +305,14 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
         return ADELIA_E_HIP;
       if (bta_invert_block(c, j, side->s2)) return ADELIA_E_HIP;
       if (hipEventRecord(side->done[j % 3], side->s2) != hipSuccess) return ADELIA_E_HIP;
-      if (selinv_prepare(si, j, side->s2)) return ADELIA_E_HIP;
+      if (prepare_block(M, w, si, j, side->s2)) return ADELIA_E_HIP;
       return 0;
     };
     if (fork) {
       if (late && fork_block(i - 1, true)) return ADELIA_E_HIP;
       if (i == n - 1 && fork_block(i, false)) return ADELIA_E_HIP;
     } else if (w.grad && !w.carry) {
-      if (selinv_prepare(si, i, s)) return ADELIA_E_HIP;
+      if (prepare_block(M, w, si, i, s)) return ADELIA_E_HIP;
     }
   }
   // the side stream runs its work in order: an event after its last product joins all of it
@@ -384,7 +410,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
       if (pipe && (hipEventRecord(built[j % 3], s) != hipSuccess ||
                    hipStreamWaitEvent(s2, built[j % 3], 0) != hipSuccess))
         return ADELIA_E_HIP;
-      if (bta_invert_block(c, j, s2) || selinv_prepare(si, j, s2)) return ADELIA_E_HIP;
+      if (bta_invert_block(c, j, s2) || prepare_block(M, w, si, j, s2)) return ADELIA_E_HIP;
       if (pipe && (hipEventRecord(prepared[j % 3], s2) != hipSuccess ||
                    hipStreamWaitEvent(s3, prepared[j % 3], 0) != hipSuccess))
         return ADELIA_E_HIP;

@@ -328,7 +328,7 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
   {
     GemmArgs g{};
     g.nph = 1;
-    if (!p.last) {
+    if (!p.last && !c.w_external) {
       g.ph[0].A = view_rowsplit(const_cast<double*>(p.LBj), c.ldLB, c.zLB,
                                 const_cast<double*>(p.LCj), c.ldLC, c.zLC, b);
       g.C = view_rowsplit(p.Wm, b, zW, p.V, a ? a : 1, zW, b);
@@ -364,7 +364,7 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
     g.C = view_plain(p.ZDj, b, c.zZD);
     g.M = g.N = g.Mlast = g.Nlast = b;
     g.beta = 0.0;
-    g.omode = OUT_LOWER;
+    g.omode = c.w_external ? OUT_LOWER_MIRROR : OUT_LOWER;  // W_j reads its full columns
     g.tag = GT_SI_D;
     g.maxwg = c.prep_maxwg;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;

@@ -69,6 +69,9 @@ __global__ void yy_kernel(const ModelDev M, double* yy);
 __global__ void stencil_kernel(const double* theta, int d, double h, double* Th);
 __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad);
 __global__ void hess_stencil_kernel(const double* theta, int d, double h, double* Th);
+constexpr int kWBatch = 8;  // columns of W_t per pass of w_from_gtg_kernel (at most)
+__global__ void w_from_gtg_kernel(const ModelDev M, int t, const double* Y, long long zY,
+                                  double* W, long long zW, const double* phi, int cb);
 __global__ void fd_hessian_kernel(const double* fv, int d, double h, double* f, double* H);
 __global__ void grad_hessian_kernel(const double* fv, const double* gv, int d, double h,
                                     double* f, double* grad, double* H);

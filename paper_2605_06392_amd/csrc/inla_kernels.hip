@@ -566,6 +566,56 @@ __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* 
   if (j < d) grad[j] = (fv[1 + 2 * j] - fv[2 + 2 * j]) / (2.0 * h);
 }
 
+// W_t = B_t Y with Y = G_t^T G_t = (L_Dt L_Dt^T)^-1 (so W_t = L_Bt G_t, the b rows of [W; V] in
+// the selected inversion), B_t = Q[t+1, t] sparse (the base-matrix pattern for every field
+// pair, as assembled).  For each column c of W (the workgroups of a chain walk them): column c
+// of Y (stored in full) is loaded into LDS, then every row of B_t is applied to it.
+__global__ __launch_bounds__(256) void w_from_gtg_kernel(const ModelDev M, int t, const double* Y,
+                                                         long long zY, double* W, long long zW,
+                                                         const double* phi, int cb) {
+  extern __shared__ double ys[];  // cb columns of Y, b each
+  __shared__ double cB[kMaxFields][kMaxFields][3];
+  const int z = blockIdx.z, p = z >> 1;
+  const int b = M.b, ns = M.ns, k = M.k;
+  const double* Yz = Y + (long long)z * zY;
+  if (threadIdx.x < k * k * 3) {
+    const int s = threadIdx.x % 3, i2 = (threadIdx.x / 3) % k, i1 = threadIdx.x / (3 * k);
+    const double* ph = phi + (long long)p * 9 * k * k;
+    double v = 0.0;
+    for (int r = 0; r < 3; ++r) v += tmat(M, r, t, 1) * ph[((r * k + i1) * k + i2) * 3 + s];
+    cB[i1][i2][s] = v;
+  }
+  // the workgroups of a chain walk batches of cb columns; each row of B_t (its pattern read
+  // once per batch) is applied to all of them
+  for (int c0 = blockIdx.x * cb; c0 < b; c0 += gridDim.x * cb) {
+    const int nc = min(cb, b - c0);
+    __syncthreads();  // the previous batch's reads of ys are done (and cB is written)
+    for (int e = threadIdx.x; e < nc * b; e += 256) ys[e] = Yz[(long long)c0 * b + e];
+    __syncthreads();
+    double* Wc = W + (long long)z * zW + (long long)c0 * b;
+    for (int row = threadIdx.x; row < b; row += 256) {
+      const int i1 = row / ns, rr = row % ns;
+      double acc[kWBatch];
+#pragma unroll
+      for (int cc = 0; cc < kWBatch; ++cc) acc[cc] = 0.0;
+      for (int e = M.uptr[rr]; e < M.uptr[rr + 1]; ++e) {
+        const int qq = M.uidx[e];
+        const double v0 = M.uval[e], v1 = M.uval[M.nnz + e], v2 = M.uval[2 * M.nnz + e];
+        for (int i2 = 0; i2 < k; ++i2) {
+          const double bv = cB[i1][i2][0] * v0 + cB[i1][i2][1] * v1 + cB[i1][i2][2] * v2;
+          const double* yq = ys + i2 * ns + qq;
+#pragma unroll
+          for (int cc = 0; cc < kWBatch; ++cc)
+            if (cc < nc) acc[cc] += bv * yq[(long long)cc * b];
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < kWBatch; ++cc)
+        if (cc < nc) Wc[(long long)cc * b + row] = acc[cc];
+    }
+  }
+}
+
 // Points of the second-order central-difference Hessian (2d^2 + 1): 0 the centre; 1 + 2j and
 // 2 + 2j the steps +h e_j and -h e_j; then, for each pair j < k in order, four points
 // (+e_j + e_k, +e_j - e_k, -e_j + e_k, -e_j - e_k) times h.
