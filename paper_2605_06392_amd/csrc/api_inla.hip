@@ -347,7 +347,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
   sc.x = w.x; sc.zx = w.zx;
   sc.y = w.y; sc.zy = w.zy;
-  const SelinvChains si = selinv_of(w);
+  SelinvChains si = selinv_of(w);
   const long long bb = (long long)b * b;
   const int ntrace = 2 * M.k * M.k * M.nch_rows + M.k * M.nch_obs;
   auto trace = [&](int j, hipStream_t ts) -> int {
@@ -387,6 +387,15 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
     // the ring slots of block j+3, whose last reader is block j+2's selected-inversion step.
     const bool pipe = side && 2LL * nz * panel_workgroups(b, 0, b) <= side->la.cus;
     hipStream_t s2 = pipe ? side->s2 : s, s3 = pipe ? side->la.ts : s;
+    // The selected-inversion stage runs beside the rebuild's latency-bound panel steps.  While
+    // its Z_B product has at most two tiles per CU, its grids are capped at 3/8 of the CUs
+    // (b = 1024: 88.4 -> 84.4 ms per gradient; caps of 72-104 workgroups measure alike, 112-128
+    // less well).  Larger products set the pace themselves and stay uncapped (a cap of 144 at
+    // b = 1200: 78.4 -> 81.0 ms; of 96 at b = 2700: 671 -> 996 ms).
+    if (pipe) {
+      const long long tiles = (long long)nz * ((b + 63) / 64) * ((b + 63) / 64);
+      if (tiles <= 2LL * side->la.cus) si.fin_maxwg = std::max(8, (3 * side->la.cus / 8) & ~7);
+    }
     const hipEvent_t* built = pipe ? side->ready : nullptr;
     const hipEvent_t* prepared = pipe ? side->la.pdone : nullptr;
     const hipEvent_t* finished = pipe ? side->la.tdone : nullptr;

@@ -402,6 +402,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_SI_Z;
+    g.maxwg = c.fin_maxwg;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     if (skinny) {  // Z_Cj = -(Z_C,j+1 W + Z_T V)
       Skinny k{};
@@ -428,6 +429,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_SI_Z;
+    g.maxwg = c.fin_maxwg;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // S3: Z_Dj -= [Z_Bj; Z_Cj]^T [W; V] on the lower triangle holding G^T G, mirrored to a full
@@ -451,6 +453,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 1.0;
     g.omode = OUT_LOWER_MIRROR;
     g.tag = GT_SI_D;
+    g.maxwg = c.fin_maxwg;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;

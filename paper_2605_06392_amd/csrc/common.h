@@ -148,6 +148,7 @@ struct SelinvChains {
   double* ZC; long long zZC; int slotsZC;        // a x b (ld a)
   double* W; long long zW; int slotsW;           // [W; V] of block t in slot t % slotsW, b*b + a*b each
   int prep_maxwg;                                // workgroup cap of selinv_prepare's launches
+  int fin_maxwg;                                 // workgroup cap of selinv_finish's launches
   // W_j (the b rows of [W_j; V_j]) is formed by the caller after selinv_prepare, from
   // G_j^T G_j (W_j = L_Bj G_j = B_j D~_j^-1 = B_j G_j^T G_j, for a sparse B_j); selinv_prepare
   // then forms V_j and G_j^T G_j only
