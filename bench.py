@@ -28,7 +28,8 @@ PEAK_HBM_GBS = 8000.0
 # profiler names of the library's kernel groups -> device kernel symbols (as rocprofv3 lists them)
 KERNEL_SYMBOLS = {"gemm_f64": "gemm_f64_kernel", "potrf_panel": "potrf_panel_kernel",
                   "gemv": "gemv_t_kernel", "assemble": "assemble_blocks_kernel",
-                  "trace": "trace_kernel", "tip": "tip_kernel", "panel_step": "panel_step_kernel"}
+                  "trace": "trace_kernel", "tip": "tip_kernel", "panel_step": "panel_step_kernel",
+                  "w_sparse": "w_from_gtg_kernel"}
 
 
 def parse():
@@ -220,7 +221,7 @@ def profiled_pass(args, ad_step, bta, torch):
     raw_ms = st["ms"]
     kern_ms = max(raw_ms - launches * ovh_ms, 1e-9)
     per_launch_ms = kern_ms / launches
-    if st["flops"] > 0 and name not in ("gemv", "assemble", "trace"):
+    if st["flops"] > 0 and name not in ("gemv", "assemble", "trace", "w_sparse"):
         achieved = st["flops"] / (kern_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}

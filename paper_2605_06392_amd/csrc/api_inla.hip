@@ -224,8 +224,11 @@ int prepare_block(const ModelDev& M, const InlaWs& w, SelinvChains si, int j, hi
     const double* Y = w.ZD + (long long)(j % w.slotsZD) * bb;
     double* Wm = w.W + (long long)(j % w.slotsW) * (bb + (long long)w.a * b);
     const int wg = std::max(1, std::min((b + cb - 1) / cb, kWGroups / w.nz));
+    const ProfToken t = prof_begin(s);
     hipLaunchKernelGGL(w_from_gtg_kernel, dim3(wg, 1, w.nz), dim3(256),
                        (size_t)cb * b * sizeof(double), s, M, j, Y, w.zZD, Wm, w.zW, w.phi, cb);
+    if (t.valid)  // G_j^T G_j read and W_j written once per chain
+      prof_end(t, s, PK_WSPARSE, 0.0, 16.0 * w.nz * (double)bb);
     if (hipGetLastError() != hipSuccess) return ADELIA_E_HIP;
   }
   return 0;

@@ -7,6 +7,7 @@ namespace adelia {
 enum ProfKind {
   PK_GEMM = 0, PK_PANEL, PK_GEMV, PK_ASSEMBLE, PK_TRACE, PK_TIP,
   PK_STEP,  // panel k+1 and the trailing update of panel k in one launch
+  PK_WSPARSE,  // W_t = B_t (G_t^T G_t) from the sparse B_t
   PK_GEMM_ROLE0,  // + GemmTag: per-role copies of the GEMM statistics
   PK_COUNT = PK_GEMM_ROLE0 + 8
 };

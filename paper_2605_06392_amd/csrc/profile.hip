@@ -46,6 +46,7 @@ const char* kind_name(int k) {
     case PK_TRACE: return "trace";
     case PK_TIP: return "tip";
     case PK_STEP: return "panel_step";
+    case PK_WSPARSE: return "w_sparse";
     case PK_GEMM_ROLE0 + 0: return "gemm_f64:other";
     case PK_GEMM_ROLE0 + 1: return "gemm_f64:trailing";
     case PK_GEMM_ROLE0 + 2: return "gemm_f64:trtri";
