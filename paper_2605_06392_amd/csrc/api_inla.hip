@@ -185,7 +185,7 @@ BtaChains chains_of(const InlaWs& w) {
 
 #define LAUNCH_OK() (hipGetLastError() == hipSuccess)
 
-// Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
+// The selected-inversion view of the workspace (factors, [W; V] and Z blocks per chain).
 SelinvChains selinv_of(const InlaWs& w) {
   const int b = w.b, ap = w.ap;
   const long long sLBC = (long long)(b + ap) * b;
@@ -234,6 +234,7 @@ int prepare_block(const ModelDev& M, const InlaWs& w, SelinvChains si, int j, hi
   return 0;
 }
 
+// Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
 int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStream_t s,
                 const SideRes* side) {
   const int nz = w.nz, n = w.n, b = w.b;

@@ -568,8 +568,10 @@ __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* 
 
 // W_t = B_t Y with Y = G_t^T G_t = (L_Dt L_Dt^T)^-1 (so W_t = L_Bt G_t, the b rows of [W; V] in
 // the selected inversion), B_t = Q[t+1, t] sparse (the base-matrix pattern for every field
-// pair, as assembled).  For each column c of W (the workgroups of a chain walk them): column c
-// of Y (stored in full) is loaded into LDS, then every row of B_t is applied to it.
+// pair, as assembled).  The workgroups of a chain walk batches of cb columns: the batch's
+// columns of Y (stored in full) are loaded into LDS, then each row of B_t, its pattern and
+// values read once per batch, is applied to all of them.  Bound by the pattern reads (b/cb
+// passes over B_t) and by reading Y and writing W once: 16 b^2 bytes per chain.
 __global__ __launch_bounds__(256) void w_from_gtg_kernel(const ModelDev M, int t, const double* Y,
                                                          long long zY, double* W, long long zW,
                                                          const double* phi, int cb) {
