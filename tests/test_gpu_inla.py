@@ -126,6 +126,25 @@ def test_golden_values():
         assert rel_inf(g.cpu().numpy(), val["grad"]) <= 1e-8
 
 
+# k = 2 and k = 4 coregionalised fields (d = 9 and 22): every field pair of the sub-diagonal
+# blocks, whose coefficients the selected inversion rebuilds from theta for W_t = B_t G^T G,
+# and b = 80 spanning a full and a ragged 64-wide panel
+@pytest.mark.parametrize("k,nx,ny,nt,a,obs", [(2, 6, 5, 4, 3, 8), (4, 4, 3, 3, 2, 6),
+                                              (4, 5, 4, 3, 3, 8)])
+def test_two_and_four_fields_match_oracle(k, nx, ny, nt, a, obs):
+    from paper_2605_06392_amd.inla import InlaModel
+    spec = make_model(k, nx, ny, nt, a, obs, seed=21)
+    m = InlaModel(spec, device=_dev())
+    print(f"k={k} b={k * nx * ny} n={nt} a={a} d={spec.d}", flush=True)
+    ref = oracle.gradient(spec, spec.theta)
+    for carry in (False, True):
+        f, g, info = m.grad(torch.tensor(spec.theta), carry=carry)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        assert abs(f.item() - ref["f"]) <= 1e-10 * abs(ref["f"]), carry
+        assert rel_inf(g.cpu().numpy(), ref["grad"]) <= 1e-8, carry
+
+
 @pytest.mark.parametrize("k", [1, 3])
 def test_no_observations_gives_prior(k):
     from paper_2605_06392_amd.inla import InlaModel
