@@ -17,7 +17,11 @@
  * - Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).  Every call
  *   only enqueues work on that stream and returns without synchronising, allocating or
  *   printing, so calls may be captured into a hipGraph.  Exceptions: adelia_create,
- *   inla_model_create/destroy (set-up time).
+ *   inla_model_create/destroy (set-up time).  Bound on captures: an INLA call whose estimated
+ *   number of kernel launches exceeds 60,000 (e.g. an FD Hessian of many passes) returns
+ *   ADELIA_E_UNSUPPORTED, before enqueueing anything, when its stream is capturing: a capture
+ *   of about 96,000 launches ended the process on the host, one of 44,000 ran normally, and the
+ *   cause is not established.  Called eagerly, such calls run normally.
  * - Return codes: 0 = enqueued.  -k = argument k (1-based) is invalid.  ADELIA_E_* below.
  *   Numerical failure is reported asynchronously through a device int `info`: 0 = success,
  *   j > 0 = the leading minor of global order j is not positive definite (LAPACK POTRF
@@ -47,10 +51,16 @@ extern "C" {
 typedef struct adelia_ctx_s* adelia_ctx;
 typedef struct inla_model_s* inla_model;
 
+/* Largest block size b (also k * ns of an INLA model).  The matrix cores read every operand of
+ * the sweeps (up to a b x (b + 65) block) through 32-bit buffer descriptors, so a block of 2 GiB
+ * or more could not be addressed; larger shapes are rejected with ADELIA_E_SHAPE (workspace
+ * queries return 0) rather than computed wrongly. */
+#define ADELIA_MAX_BLOCK 16320
+
 typedef struct {
-  int32_t n; /* number of diagonal blocks, >= 1 */
-  int32_t b; /* block size, >= 1                */
-  int32_t a; /* arrowhead width, 0..64          */
+  int32_t n; /* number of diagonal blocks, >= 1        */
+  int32_t b; /* block size, 1..ADELIA_MAX_BLOCK         */
+  int32_t a; /* arrowhead width, 0..64                  */
 } adelia_bta_shape;
 
 /* Context bound to one HIP device (made current by the call).  Returns 0 or ADELIA_E_HIP. */
@@ -67,7 +77,9 @@ const char* adelia_version(void);
  * with A_z = A + z*strideA etc.  C is M x N (ld ldc); op(A) is M x K; op(B) is K x N.
  * `uplo` = 0 writes all of C, 1 writes only the lower triangle (r >= c) of C.
  * A helper entry point used by the factorisations; exported for testing and for callers
- * that want the same tile kernel.  beta == 0 never reads C.
+ * that want the same tile kernel.  beta == 0 never reads C.  Errors: -k for argument k;
+ * ADELIA_E_SHAPE when uplo == 1 and M != N, or when one operand (of one batch entry) spans
+ * 2 GiB or more (the tile kernel addresses each operand through a 32-bit buffer range).
  * --------------------------------------------------------------------------------------- */
 int adelia_dgemm(adelia_ctx ctx, int transA, int transB, int M, int N, int K, double alpha,
                  const double* A, int lda, long long strideA, const double* B, int ldb,
@@ -167,7 +179,7 @@ int bta_selinv(adelia_ctx ctx, adelia_bta_shape shape, const double* Dinv, const
 typedef struct {
   int32_t param;   /* ADELIA_PARAM_*                                                     */
   int32_t k;       /* fields, 1..4                                                        */
-  int32_t ns;      /* spatial nodes per field; b = k*ns                                    */
+  int32_t ns;      /* spatial nodes per field; b = k*ns <= ADELIA_MAX_BLOCK                */
   int32_t nt;      /* time steps (n)                                                       */
   int32_t a;       /* fixed effects (arrowhead width), 0..64                               */
   int32_t n_obs;   /* observations                                                         */

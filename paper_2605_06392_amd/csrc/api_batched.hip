@@ -89,7 +89,7 @@ GroupWs group_layout(const Group& g, bool rhs, char* base) {
 }
 
 bool shape_ok(const adelia_bta_shape& sh) {
-  if (sh.n < 1 || sh.b < 1 || sh.a < 0 || sh.a > 63) return false;
+  if (sh.n < 1 || sh.b < 1 || sh.a < 0 || sh.a > 63 || sh.b > kMaxBlock) return false;
   const long long N = (long long)sh.n * sh.b + sh.a;
   return N <= INT_MAX && (long long)sh.n * sh.b <= INT_MAX;
 }

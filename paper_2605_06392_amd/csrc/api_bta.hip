@@ -74,7 +74,7 @@ int check_shape(const adelia_bta_shape& sh) {
   if (sh.n < 1 || sh.b < 1 || sh.a < 0 || sh.a > 64) return ADELIA_E_SHAPE;
   const long long N = (long long)sh.n * sh.b + sh.a;
   if (N > (1LL << 31) - 1) return ADELIA_E_SHAPE;
-  if ((long long)sh.b * sh.b > (1LL << 40)) return ADELIA_E_SHAPE;
+  if (sh.b > kMaxBlock) return ADELIA_E_SHAPE;  // an operand quadrant would pass 2 GiB
   return 0;
 }
 
@@ -187,6 +187,15 @@ int adelia_dgemm(adelia_ctx ctx, int transA, int transB, int M, int N, int K, do
   if (batch < 0 || batch > 65535) return -18;
   if (uplo != 0 && uplo != 1) return -19;
   if (uplo == 1 && M != N) return ADELIA_E_SHAPE;
+  // each operand is one quadrant of the tile kernel's views: its byte extent must fit the
+  // 32-bit buffer range
+  auto extent = [](long long rows, long long cols, long long ld) {
+    return 8 * ((rows - 1) + (cols - 1) * ld + 1);
+  };
+  if ((K > 0 && (extent(transA ? K : M, transA ? M : K, lda) > kMaxOperandBytes ||
+                 extent(transB ? N : K, transB ? K : N, ldb) > kMaxOperandBytes)) ||
+      extent(M, N, ldc) > kMaxOperandBytes)
+    return ADELIA_E_SHAPE;
   GemmArgs g{};
   g.nph = 1;
   g.ph[0].A = view_plain(const_cast<double*>(A), lda, strideA, transA == 1);

@@ -468,6 +468,44 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
 
 bool aligned(const void* p, size_t al) { return ((uintptr_t)p % al) == 0; }
 
+// Kernel launches of one batched pass (objective, or gradient with its reverse pass) over
+// `batch` points, from the schedule rules of the sweeps: per block the assembly and arrow copy,
+// the panel launches (fused steps: one per panel; split panels: the diagonal tile, its rows'
+// GEMM and the trailing update; otherwise panel plus trailing update), the Schur update, and for
+// a gradient the inversion (two GEMMs per doubling level), the selected-inversion preparation
+// (three), its finish with the trace (four) and the upper solve (two).
+long long launches_per_pass(const ModelDev& M, const SideRes* side, int batch, bool grad) {
+  const int b = M.b, ap = M.a + 1, nz = 2 * batch;
+  const int npanel = (b + kPanel - 1) / kPanel;
+  const int cus = side ? side->la.cus : 256;
+  const long long wg = (long long)nz * panel_workgroups(b, 0, b + ap);
+  const int per_panel = side && 2 * wg <= cus ? 1 : (wg > cus ? 3 : 2);
+  int levels = 0;
+  for (int sz = kPanel; sz < b; sz *= 2) ++levels;
+  long long per_block = 4 + (long long)per_panel * npanel;
+  if (grad) per_block += 2 * levels + 3 + 6 + 2;
+  return 16 + (long long)M.nt * per_block;
+}
+
+// Capturing very long calls into one graph: an FD Hessian at b = 2700, d = 15 (15 passes of 31
+// points, about 96,000 launches by the estimate above) ended the process with a host
+// segmentation fault during the capture or its first replay, while captures of up to about
+// 44,000 estimated launches (the Eq. 12 Hessian at the same size) run normally.  The cause has
+// not been established (no GPU fault was reported; the same calls run eagerly).  Until it is,
+// a call whose estimated launch count exceeds this bound returns ADELIA_E_UNSUPPORTED when
+// its stream is capturing, before anything is enqueued.
+constexpr long long kCaptureLaunchLimit = 60000;
+
+int capture_guard(hipStream_t s, long long planned) {
+  if (planned <= kCaptureLaunchLimit) return 0;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();  // a failed query must not read as a failed launch later
+    return 0;
+  }
+  return st == hipStreamCaptureStatusNone ? 0 : ADELIA_E_UNSUPPORTED;
+}
+
 int fail(const std::string& msg) {
   set_last_error(msg);
   return ADELIA_E_SHAPE;
@@ -496,6 +534,14 @@ std::string check_csr(const char* name, const int32_t* ptr, const int32_t* idx, 
 
 }  // namespace
 
+// Estimated launches of `npts` points evaluated in passes of at most `bmax` points.
+static long long planned_passes(inla_model m, int npts, int bmax, bool grad) {
+  const SideRes* side = m->has_side ? &m->side : nullptr;
+  const long long full = npts / bmax, rest = npts % bmax;
+  return full * launches_per_pass(m->M, side, bmax, grad) +
+         (rest ? launches_per_pass(m->M, side, (int)rest, grad) : 0);
+}
+
 extern "C" {
 
 int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out) {
@@ -510,7 +556,8 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
   if (d->param == ADELIA_PARAM_UNIVARIATE && k != 1) return fail("univariate model needs k == 1");
   if (ns < 1 || nt < 1 || a < 0 || a > 64 || n_obs < 0) return fail("bad sizes");
   const long long b = (long long)k * ns;
-  if (b * nt + a > INT_MAX || b * b > (1LL << 40)) return fail("model too large");
+  if (b * nt + a > INT_MAX) return fail("model too large");
+  if (b > kMaxBlock) return fail("block size k*ns above 16320 (a GEMM operand would pass 2 GiB)");
   if (!(d->sigma_prior > 0.0) || !(d->tip_prec > 0.0)) return fail("sigma and tip_prec must be > 0");
   std::string e;
   if (!(e = check_csr("c0", d->c0_ptr, d->c0_idx, d->c0_val, ns)).empty()) return fail(e);
@@ -747,6 +794,9 @@ int inla_objective(inla_model m, const double* theta, int32_t batch, double* f, 
   if (save && batch != 1) return -3;
   InlaWs w = layout(m->M, batch, save, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  if (int r = capture_guard((hipStream_t)stream,
+                            launches_per_pass(m->M, m->has_side ? &m->side : nullptr, batch, save)))
+    return r;
   m->saved_ws = save ? ws : (m->saved_ws == ws ? nullptr : m->saved_ws);
   return run_objective(m->M, w, theta, f, info, (hipStream_t)stream,
                        m->has_side ? &m->side : nullptr);
@@ -787,8 +837,11 @@ int inla_grad_batched(inla_model m, const double* theta, int32_t batch, double* 
   if (!ws || !aligned(ws, 256)) return -7;
   InlaWs w = layout(m->M, batch, true, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
-  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  if (int r = capture_guard(s, launches_per_pass(m->M, m->has_side ? &m->side : nullptr, batch,
+                                                 true)))
+    return r;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
   if (r) return r;
   return run_backward(m->M, w, theta, f, grad, info, nullptr, s,
@@ -833,8 +886,9 @@ int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch,
   const int bmax = std::min<int>(max_batch, npts);
   InlaWs w = layout(m->M, bmax, false, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
-  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  if (int r = capture_guard(s, planned_passes(m, npts, bmax, false))) return r;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipLaunchKernelGGL(stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d, h,
                      w.Th);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
@@ -866,8 +920,9 @@ int inla_hessian(inla_model m, const double* theta, double h, int32_t max_batch,
   const int bmax = std::min<int>(max_batch, npts);
   InlaWs w = layout(m->M, bmax, true, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
-  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  if (int r = capture_guard(s, planned_passes(m, npts, bmax, true))) return r;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipLaunchKernelGGL(stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d, h,
                      w.Th);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
@@ -902,8 +957,9 @@ int inla_fd_hessian(inla_model m, const double* theta, double h, int32_t max_bat
   const int bmax = std::min<int>(max_batch, npts);
   InlaWs w = layout(m->M, bmax, false, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
-  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  if (int r = capture_guard(s, planned_passes(m, npts, bmax, false))) return r;
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipLaunchKernelGGL(hess_stencil_kernel, dim3((npts * d + 255) / 256), dim3(256), 0, s, theta, d,
                      h, w.Th);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;

@@ -17,6 +17,14 @@ namespace adelia {
 constexpr int kMaxFields = 4;
 constexpr int kMaxTheta = 4 * kMaxFields + kMaxFields * (kMaxFields - 1) / 2;
 constexpr int kPanel = 64;  // POTRF panel width == GEMM tile edge
+// The GEMM reads each quadrant of an operand view through a buffer descriptor whose record
+// count and per-lane byte offsets are 32-bit (at most kMaxOperandBytes): every operand a sweep
+// forms, up to a b x (b + 65) block, must stay inside that range.  kMaxBlock is the largest
+// block size for which it does (8 b (b + 65) <= kMaxOperandBytes); larger shapes are rejected
+// at the entry points instead of reading zeros past the range.
+constexpr long long kMaxOperandBytes = 0x7ffffff0LL;
+constexpr int kMaxBlock = 16320;
+static_assert(8LL * kMaxBlock * (kMaxBlock + 65) <= kMaxOperandBytes, "block limit");
 
 // A strided view of a logical matrix split into up to four quadrants at (rs, cs):
 // q = (r >= rs) + 2 * (c >= cs).  Element (r, c) of quadrant q lives at

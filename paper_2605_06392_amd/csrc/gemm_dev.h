@@ -145,7 +145,7 @@ __device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn,
       const long long last = (long long)(rhi - rlo - 1) * s.sr + (long long)(chi - clo - 1) * s.sc;
       const long long bytes = 8 * (last + 1);
       P.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(s.p), (short)0,
-                                                 (int)min(bytes, 0x7ffffff0LL), 0x00020000);
+                                                 (int)min(bytes, kMaxOperandBytes), 0x00020000);
       const long long sR = colsfirst ? s.sc : s.sr;
       P.sK = colsfirst ? s.sr : s.sc;
       P.mode = (sR != 1 && P.sK == 1) ? 1 : 0;

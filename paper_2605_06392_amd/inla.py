@@ -105,17 +105,26 @@ class InlaModel:
             pass
 
     # -- workspaces (torch-owned device memory, kept per (batch, mode)) -----------------------
-    def workspace(self, batch, mode):
-        key = (batch, mode)
-        if key not in self._ws:
-            nbytes = lib().inla_workspace_bytes(self._h, batch, mode)
-            if nbytes == 0:
-                raise ValueError("invalid workspace request")
-            buf = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=self.device)
-            self._ws[key] = (buf, nbytes)
-        buf, nbytes = self._ws[key]
+    def new_workspace(self, batch, mode):
+        """A fresh torch-owned workspace buffer for `batch` points in `mode`: (buffer, bytes)."""
+        nbytes = lib().inla_workspace_bytes(self._h, batch, mode)
+        if nbytes == 0:
+            raise ValueError("invalid workspace request")
+        return torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=self.device), nbytes
+
+    @staticmethod
+    def _aligned(buf, nbytes):
         p = buf.data_ptr()
         return C.c_void_p(p + ((-p) % 256)), nbytes
+
+    def workspace(self, batch, mode, private=None):
+        """The model's shared workspace for (batch, mode), or `private` = (buffer, bytes)."""
+        if private is not None:
+            return self._aligned(*private)
+        key = (batch, mode)
+        if key not in self._ws:
+            self._ws[key] = self.new_workspace(batch, mode)
+        return self._aligned(*self._ws[key])
 
     def workspace_bytes(self, batch, mode):
         return int(lib().inla_workspace_bytes(self._h, batch, mode))
@@ -129,13 +138,13 @@ class InlaModel:
         return t.contiguous()
 
     # -- evaluations ---------------------------------------------------------------------------
-    def objective(self, theta, out=None, info=None):
+    def objective(self, theta, out=None, info=None, ws=None):
         th = self._theta(theta)
         th2 = th.reshape(-1, self.d)
         batch = th2.shape[0]
         f = out if out is not None else torch.empty(batch, dtype=torch.float64, device=self.device)
         inf = info if info is not None else torch.empty(batch, dtype=torch.int32, device=self.device)
-        ws, nb = self.workspace(batch, MODE_OBJECTIVE)
+        ws, nb = self.workspace(batch, MODE_OBJECTIVE, ws)
         check(lib().inla_objective(self._h, C.c_void_p(th2.data_ptr()), batch,
                                    C.c_void_p(f.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb, 0,
                                    self._stream()), "inla_objective")
@@ -200,19 +209,22 @@ class InlaModel:
               "inla_fd_grad")
         return f, g, inf
 
-    def grad_batched(self, theta, f=None, g=None, info=None):
-        """f and the exact gradient at a batch of theta points (batch x d) in one pass."""
+    def grad_batched(self, theta, f=None, g=None, info=None, ws=None):
+        """f and the exact gradient at a batch of theta points (batch x d) in one pass.  With
+        `ws` (a private workspace from new_workspace) the model's shared workspaces, and any
+        factors saved in them, are left alone."""
         th = self._theta(theta).reshape(-1, self.d).contiguous()
         B = th.shape[0]
         f = f if f is not None else torch.empty(B, dtype=torch.float64, device=self.device)
         g = g if g is not None else torch.empty((B, self.d), dtype=torch.float64, device=self.device)
         inf = info if info is not None else torch.empty(B, dtype=torch.int32, device=self.device)
-        ws, nb = self.workspace(B, MODE_GRAD)
+        wsp, nb = self.workspace(B, MODE_GRAD, ws)
         check(lib().inla_grad_batched(self._h, C.c_void_p(th.data_ptr()), B,
                                       C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()),
-                                      C.c_void_p(inf.data_ptr()), ws, nb, self._stream()),
+                                      C.c_void_p(inf.data_ptr()), wsp, nb, self._stream()),
               "inla_grad_batched")
-        self.saved_token = 0
+        if ws is None:
+            self.saved_token = 0
         return f, g, inf
 
     def fitting_batch(self, npts, mode, fraction=0.5):
@@ -269,7 +281,9 @@ class InlaModel:
 class BatchRunner:
     """f (kind="objective") or f and the exact gradient (kind="grad") at a fixed number of theta
     points per call: the first call captures one batched evaluation (every launch covers all
-    points' chains) into a hipGraph, later calls copy the points in and replay it."""
+    points' chains) into a hipGraph, later calls copy the points in and replay it.  The runner
+    owns its workspace: a replay runs no host code, so it must not write into a workspace that
+    holds factors saved by InlaObjective.forward for a later backward."""
 
     def __init__(self, model, batch, kind="objective"):
         if kind not in ("objective", "grad"):
@@ -281,13 +295,14 @@ class BatchRunner:
         self.info = torch.empty(self.batch, dtype=torch.int32, device=dev)
         self.g = (torch.empty((self.batch, d), dtype=torch.float64, device=dev)
                   if kind == "grad" else None)
+        self._ws = model.new_workspace(self.batch, MODE_GRAD if kind == "grad" else MODE_OBJECTIVE)
         self._graph = None
 
     def _evaluate(self):
         if self.kind == "objective":
-            self.model.objective(self.theta, out=self.f, info=self.info)
+            self.model.objective(self.theta, out=self.f, info=self.info, ws=self._ws)
         else:
-            self.model.grad_batched(self.theta, f=self.f, g=self.g, info=self.info)
+            self.model.grad_batched(self.theta, f=self.f, g=self.g, info=self.info, ws=self._ws)
 
     def __call__(self, theta):
         th = torch.as_tensor(theta, dtype=torch.float64, device=self.model.device)

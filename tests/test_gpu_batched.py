@@ -159,3 +159,29 @@ def test_many_matrices_split_panels_match_dense_cholesky():
     torch.cuda.synchronize()
     assert int(info1.item()) == 0
     assert abs(ld1.item() - logdet[45].item()) <= 1e-12 * abs(ld1.item())
+
+
+def test_uneven_batch_large_blocks_match_dense_cholesky():
+    """The block sizes of the uneven benchmark batch (b = 128, 512, 1024; several 64-wide panels,
+    fused look-ahead steps for the small groups) with n <= 8, against the dense oracle."""
+    from paper_2605_06392_amd import bta
+    dev = _dev()
+    shapes = [(3, 128, 2), (5, 128, 0), (6, 512, 5), (2, 512, 8), (4, 1024, 8), (2, 1024, 3)]
+    print("shapes", shapes, flush=True)
+    blks, mats = _mats(shapes, 1300, dev, True)
+    _, logdet, info = bta.bta_factor_batched(mats, with_rhs=True)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    for i, ((n, b, a), blk, m) in enumerate(zip(shapes, blks, mats)):
+        Q = oracle.bta_dense(blk["D"], blk["B"], blk["C"], blk["T"])
+        ref = oracle.dense_cholesky(Q, blk["rhs"])
+        Lb = oracle.bta_split(ref["L"], n, b, a)
+        scale = np.abs(ref["L"]).max()
+        assert np.abs(_cm_to_np(m["D"]) - Lb["D"]).max() <= 1e-12 * scale, i
+        if n > 1:
+            assert np.abs(_cm_to_np(m["B"]) - Lb["B"]).max() <= 1e-12 * scale, i
+        if a:
+            assert np.abs(_cm_to_np(m["C"]) - Lb["C"]).max() <= 1e-12 * scale, i
+        assert abs(logdet[i].item() - ref["logdet"]) <= 1e-12 * abs(ref["logdet"]), i
+        z = m["rhs"].cpu().numpy()
+        assert np.abs(z - ref["z"]).max() <= 1e-11 * np.abs(ref["z"]).max(), i

@@ -138,3 +138,47 @@ def test_bta_factor_reports_first_failing_column():
     torch.cuda.synchronize()
     assert lapack_info > 0
     assert int(info.item()) == lapack_info
+
+
+def _random_shapes(count, seed):
+    """Seeded random BTA shapes: n in [1, 8], b in [1, 130], a in [0, 8]."""
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(1, 9)), int(rng.integers(1, 131)), int(rng.integers(0, 9)))
+            for _ in range(count)]
+
+
+@pytest.mark.parametrize("n,b,a", _random_shapes(12, 2024))
+def test_random_shapes_factor_solve_selinv(n, b, a):
+    """A seeded sweep of shapes (ragged tiles, single blocks, no arrow, one-row blocks): the
+    factor, the fused forward solve, log|Q|, the solve and the selected inverse against the
+    dense oracle."""
+    from paper_2605_06392_amd import bta
+    print(f"shape n={n} b={b} a={a}", flush=True)
+    seed = 31 * n + 7 * b + a
+    blk, Q, out = _factor_case(n, b, a, seed=seed)
+    ref = oracle.dense_cholesky(Q, blk["rhs"])
+    Lb = oracle.bta_split(ref["L"], n, b, a)
+    assert int(out["info"].item()) == 0
+    scale = np.abs(ref["L"]).max()
+    assert np.abs(_cm_to_np(out["D"]) - Lb["D"]).max() <= 1e-12 * scale
+    if n > 1:
+        assert np.abs(_cm_to_np(out["B"]) - Lb["B"]).max() <= 1e-12 * scale
+    if a:
+        assert np.abs(_cm_to_np(out["C"]) - Lb["C"]).max() <= 1e-12 * scale
+    assert abs(out["logdet"].item() - ref["logdet"]) <= 1e-12 * abs(ref["logdet"]) + 1e-12
+    z = out["rhs"].cpu().numpy()
+    assert np.abs(z - ref["z"]).max() <= 1e-11 * np.abs(ref["z"]).max()
+    x = torch.from_numpy(z.copy()).to(out["D"].device)
+    bta.bta_solve(out["Dinv"], out["B"], out["C"], out["T"], x, z_input=True)
+    ZD, ZB, ZC, ZT = bta.bta_selinv(out["Dinv"], out["B"], out["C"], out["T"])
+    torch.cuda.synchronize()
+    xref = np.linalg.solve(Q, blk["rhs"])
+    assert np.abs(x.cpu().numpy() - xref).max() <= 1e-11 * np.abs(xref).max()
+    Zr = oracle.selected_inverse(Q, n, b, a)
+    sc = np.abs(Zr["D"]).max()
+    assert np.abs(_cm_to_np(ZD) - Zr["D"]).max() <= 1e-11 * sc
+    if n > 1:
+        assert np.abs(_cm_to_np(ZB)[: n - 1] - Zr["B"]).max() <= 1e-11 * sc
+    if a:
+        assert np.abs(_cm_to_np(ZC) - Zr["C"]).max() <= 1e-11 * sc
+        assert np.abs(_cm_to_np(ZT[None])[0] - Zr["T"]).max() <= 1e-11 * sc

@@ -167,3 +167,30 @@ def test_entry_points_reject_bad_arguments():
     assert L.inla_workspace_bytes(m._h, 1, 7) == 0
     assert L.inla_workspace_bytes(m._h, 1, 2) < L.inla_workspace_bytes(m._h, 1, 1)
     torch.cuda.synchronize()
+
+
+def test_capture_of_very_long_call_is_refused_before_enqueueing():
+    """Capturing a call whose estimated launch count passes the library's capture bound (here an
+    FD Hessian of 451 points one at a time, about 3.4e5 launches) returns ADELIA_E_UNSUPPORTED
+    before anything is enqueued; the model keeps working eagerly afterwards."""
+    from paper_2605_06392_amd._lib import AdeliaError
+    from paper_2605_06392_amd.inla import InlaModel, MODE_OBJECTIVE
+    spec = named_config("coreg3_20x20_nt32", seed=0)
+    m = InlaModel(spec, device="cuda:0")
+    theta = torch.tensor(spec.theta, device="cuda:0")
+    d = spec.d
+    f = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    H = torch.empty((d, d), dtype=torch.float64, device="cuda:0")
+    info = torch.empty(2 * d * d + 1, dtype=torch.int32, device="cuda:0")
+    m.workspace(1, MODE_OBJECTIVE)  # allocated outside the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with pytest.raises(AdeliaError, match="-103"):
+        with torch.cuda.graph(graph):
+            m.fd_hessian(theta, h=5e-3, max_batch=1, f=f, H=H, info=info)
+    torch.cuda.synchronize()
+    fo, io = m.objective(theta[None])
+    torch.cuda.synchronize()
+    assert int(io.item()) == 0 and np.isfinite(fo.item())
+    del m
+    torch.cuda.empty_cache()

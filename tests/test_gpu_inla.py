@@ -347,3 +347,84 @@ def test_batch_runner_replays_batched_evaluations():
         assert np.array_equal(g3, ge.cpu().numpy())
     f0, g0, _ = adelia.fd_grad(m, torch.tensor(spec.theta), h=1e-4)
     assert np.isfinite(g0.cpu().numpy()).all()
+
+
+def test_lookahead_stream_schedule_matches_oracle():
+    """Objectives and gradients of 16 points of uni_12x12_nt6 in one pass: 32 chains with 6
+    panel workgroups each (192 <= 256 CUs, so no split panels; 384 > 256, so no fused steps) run
+    each panel's trailing update on the look-ahead stream, the schedule of a single b = 2700
+    gradient.  Against the oracle at three points, and bitwise repeatable."""
+    spec, m = gpu_model("uni_12x12_nt6", 4)
+    rng = np.random.default_rng(23)
+    pts = spec.theta + 0.2 * rng.standard_normal((16, spec.d))
+    fo, info_o = m.objective(torch.tensor(pts))
+    f, g, info = m.grad_batched(torch.tensor(pts))
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all() and (info_o.cpu().numpy() == 0).all()
+    f, g, fo = f.cpu().numpy().copy(), g.cpu().numpy().copy(), fo.cpu().numpy().copy()
+    for p in (0, 7, 15):
+        ref = oracle.gradient(spec, pts[p])
+        assert abs(f[p] - ref["f"]) <= 1e-10 * abs(ref["f"]), p
+        assert abs(fo[p] - ref["f"]) <= 1e-10 * abs(ref["f"]), p
+        assert rel_inf(g[p], ref["grad"]) <= 1e-8, p
+    f2, g2, _ = m.grad_batched(torch.tensor(pts))
+    torch.cuda.synchronize()
+    assert np.array_equal(f2.cpu().numpy(), f) and np.array_equal(g2.cpu().numpy(), g)
+
+
+def test_nan_theta_reports_failure():
+    """A NaN hyperparameter makes every pivot NaN: the pivot check reports the first column
+    (info = 1) for the objective, the gradient and every FD stencil point, and the call itself
+    still returns 0 (numerical failure is asynchronous)."""
+    spec, m = gpu_model("uni_8x8_nt8", 0)
+    th = spec.theta.copy()
+    th[1] = np.nan
+    _, info = m.objective(torch.tensor(th)[None])
+    _, _, ginfo = m.grad(torch.tensor(th))
+    _, _, finfo = m.fd_grad(torch.tensor(th), h=1e-4)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 1
+    assert int(ginfo.item()) == 1
+    assert (finfo.cpu().numpy() == 1).all()
+    # the model is unharmed: the next evaluation is correct
+    f, _ = m.objective(torch.tensor(spec.theta)[None])
+    torch.cuda.synchronize()
+    ref = oracle.objective(spec, spec.theta)["f"]
+    assert abs(f.item() - ref) <= 1e-10 * abs(ref)
+
+
+def test_double_backward_raises():
+    """The hand-written reverse pass is not itself differentiable: asking for a second-order
+    derivative through it raises instead of returning a wrong one."""
+    from paper_2605_06392_amd.inla import InlaObjective
+    spec, m = gpu_model("uni_8x8_nt8", 0)
+    theta = torch.tensor(spec.theta, device="cuda:0", requires_grad=True)
+    f = InlaObjective.apply(theta, m)
+    (g,) = torch.autograd.grad(f, theta, create_graph=True)
+    ref = oracle.gradient(spec, spec.theta)
+    assert rel_inf(g.detach().cpu().numpy(), ref["grad"]) <= 1e-8
+    with pytest.raises(RuntimeError, match="twice"):
+        g.sum().backward()
+
+
+def test_batch_runner_replay_keeps_saved_factors():
+    """A one-point gradient runner replayed between InlaObjective.forward and backward works in
+    its own workspace: the backward still reuses the factors of its own forward pass and gives
+    the oracle's gradient."""
+    import paper_2605_06392_amd as adelia
+    from paper_2605_06392_amd.inla import InlaObjective
+    spec, m = gpu_model("uni_8x8_nt8", 1)
+    runner = adelia.BatchRunner(m, 1, "grad")
+    other = spec.theta[::-1].copy()
+    runner(other[None])  # captures
+    theta = torch.tensor(spec.theta, device="cuda:0", requires_grad=True)
+    f = InlaObjective.apply(theta, m)
+    token = m.saved_token
+    _, g_other, _ = runner(other[None])  # replay on another point
+    assert m.saved_token == token
+    f.backward()
+    torch.cuda.synchronize()
+    ref = oracle.gradient(spec, spec.theta)
+    assert rel_inf(theta.grad.cpu().numpy(), ref["grad"]) <= 1e-8
+    ref_o = oracle.gradient(spec, other)
+    assert rel_inf(g_other[0].cpu().numpy(), ref_o["grad"]) <= 1e-8

@@ -354,3 +354,34 @@ def test_hessian_of_gradients_agrees_with_second_differences():
     scale = np.abs(H).max()
     assert np.abs(H - Hf).max() <= 1e-5 * scale
     assert np.abs(H - H.T).max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("k,nx,ny,nt,a,obs", [(1, 6, 5, 4, 3, 7), (3, 5, 4, 3, 6, 4),
+                                              (2, 1, 6, 3, 2, 5), (1, 7, 1, 2, 0, 6)])
+def test_observation_matrix_interpolates_linear_fields(k, nx, ny, nt, a, obs):
+    """Bilinear interpolation reproduces a linear field exactly: placing alpha*ix + beta*iy +
+    gamma on the nodes of time block t and field m, row r of A returns alpha*u + beta*v + gamma
+    at the observation's location for the observations of (t, m) and 0 for all others; the
+    covariates sit on the fixed-effect columns.  A wrong time or field offset, a swapped weight or
+    a transposed node id fails this."""
+    spec = make_model(k, nx, ny, nt, a, obs, seed=4)
+    A = oracle.observation_matrix(spec)
+    uv = spec.extra["obs_uv"]
+    assert A.shape == (spec.n_obs, spec.N)
+    ns, b, nb = spec.ns, spec.b, spec.nt * spec.b
+    ix, iy = np.arange(ns) % nx, np.arange(ns) // nx
+    alpha, beta, gamma = 0.37, -1.21, 2.5
+    lin = alpha * ix + beta * iy + gamma
+    for t in range(nt):
+        for m in range(k):
+            x = np.zeros(spec.N)
+            x[t * b + m * ns:t * b + (m + 1) * ns] = lin
+            sel = (spec.obs_t == t) & (spec.obs_field == m)
+            expect = np.where(sel, alpha * uv[:, 0] + beta * uv[:, 1] + gamma, 0.0)
+            assert np.allclose(A @ x, expect, rtol=0, atol=1e-12)
+    for r in range(spec.n_obs):
+        lo = spec.obs_t[r] * b + spec.obs_field[r] * ns
+        nzc = np.nonzero(A[r, :nb])[0]
+        assert nzc.size > 0 and nzc.min() >= lo and nzc.max() < lo + ns
+        assert abs(A[r, :nb].sum() - 1.0) <= 1e-14
+    assert np.array_equal(A[:, nb:], spec.X)

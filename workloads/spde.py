@@ -216,7 +216,7 @@ def make_model(k: int, nx: int, ny: int, nt: int, a: int, obs_per_step: int, see
     m1 = neumann_second_difference(nt)
     m2 = (np.full(nt, 2.0), np.full(max(nt - 1, 0), -1.0))
     ns = nx * ny
-    obs_t, obs_f, obs_node, obs_w, xs = [], [], [], [], []
+    obs_t, obs_f, obs_node, obs_w, xs, locs = [], [], [], [], [], []
     if with_obs and obs_per_step > 0:
         for t in range(nt):
             for m in range(k):
@@ -230,6 +230,7 @@ def make_model(k: int, nx: int, ny: int, nt: int, a: int, obs_per_step: int, see
                         cov[:, (2 * m) % a] += vals[:, 0]
                         cov[:, (2 * m + 1) % a] += vals[:, 1]
                 nodes, w = _bilinear(nx, ny, u, v)
+                locs.append(np.stack([u, v], axis=1))
                 obs_t.append(np.full(obs_per_step, t, dtype=np.int32))
                 obs_f.append(np.full(obs_per_step, m, dtype=np.int32))
                 obs_node.append(nodes)
@@ -241,12 +242,14 @@ def make_model(k: int, nx: int, ny: int, nt: int, a: int, obs_per_step: int, see
         obs_node = np.concatenate(obs_node)
         obs_w = np.concatenate(obs_w)
         X = np.concatenate(xs)
+        obs_uv = np.concatenate(locs)
     else:
         obs_t = np.zeros(0, np.int32)
         obs_f = np.zeros(0, np.int32)
         obs_node = np.zeros((0, 4), np.int32)
         obs_w = np.zeros((0, 4))
         X = np.zeros((0, a))
+        obs_uv = np.zeros((0, 2))
     xi = rng.standard_normal(k * ns * nt)
     fields = [_sample_field(nx, ny, nt, xi[m * ns * nt:(m + 1) * ns * nt]) for m in range(k)]
     # latent x ordered (t, field, node); at theta_true = 0 the coregional mixing is identity
@@ -265,7 +268,9 @@ def make_model(k: int, nx: int, ny: int, nt: int, a: int, obs_per_step: int, see
     return SpdeModel(kind=kind, k=k, nx=nx, ny=ny, nt=nt, a=a, c0=c0, g1=g1, g2=g2,
                      m0=m0, m1=m1, m2=m2, obs_t=obs_t, obs_field=obs_f,
                      obs_node=obs_node.astype(np.int32), obs_w=obs_w, X=X, y=y, theta=theta,
-                     extra={"seed": seed, "obs_per_step": obs_per_step})
+                     extra={"seed": seed, "obs_per_step": obs_per_step,
+                            # grid coordinates (u, v) of each observation's location
+                            "obs_uv": obs_uv})
 
 
 # name -> (k, nx, ny, nt, a, obs_per_step)
