@@ -400,8 +400,16 @@ def test_double_backward_raises():
     spec, m = gpu_model("uni_8x8_nt8", 0)
     theta = torch.tensor(spec.theta, device="cuda:0", requires_grad=True)
     f = InlaObjective.apply(theta, m)
+    # with a constant output gradient the result carries no graph at all: there is nothing to
+    # differentiate, so no second derivative can come back silently
     (g,) = torch.autograd.grad(f, theta, create_graph=True)
     ref = oracle.gradient(spec, spec.theta)
+    assert rel_inf(g.detach().cpu().numpy(), ref["grad"]) <= 1e-8
+    assert not g.requires_grad
+    # with an output gradient that itself requires grad, differentiating again raises
+    f = InlaObjective.apply(theta, m)
+    seed = torch.ones((), dtype=torch.float64, device="cuda:0", requires_grad=True)
+    (g,) = torch.autograd.grad(f, theta, grad_outputs=seed, create_graph=True)
     assert rel_inf(g.detach().cpu().numpy(), ref["grad"]) <= 1e-8
     with pytest.raises(RuntimeError, match="twice"):
         g.sum().backward()
