@@ -115,6 +115,26 @@ int bta_factor(adelia_ctx ctx, adelia_bta_shape shape, double* D, double* B, dou
                size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * bta_factor without a workspace argument, for callers that cannot allocate device memory
+ * (code under hipGraph capture, serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, in/out contract, numbering of argument errors and results as bta_factor, minus
+ * `ws` and `ws_bytes`: the call allocates nothing and works in a static device array of
+ * ADELIA_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on until the
+ * process ends (its address is taken by adelia_create, with the context's device current).
+ * Shapes whose factor workspace, adelia_bta_workspace_bytes(shape, ADELIA_WS_FACTOR), exceeds
+ * that size return ADELIA_E_WORKSPACE before anything is enqueued (adelia_last_error says
+ * how much the shape needs); ADELIA_E_HIP if the array's address could not be obtained.
+ * Every call on a device shares that device's array: calls that overlap in time on one device
+ * (other streams, other contexts or threads) race and give undefined results; calls in order
+ * on one stream are safe.  The array keeps the last call's contents; everything a call reads
+ * from it is written by that call first.
+ * --------------------------------------------------------------------------------------- */
+#define ADELIA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int bta_factor_noalloc(adelia_ctx ctx, adelia_bta_shape shape, double* D, double* B, double* C,
+                       double* T, double* Dinv, double* rhs, double* logdet, int32_t* info,
+                       void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Uneven batch (Sec. III-A-1, Alg. 1, applied to many independent matrices at once; the
  * batched evaluation of many instances is the setting of Sec. IV): factorises `count`
  * independent BTA matrices whose (n, b, a) differ, with the same in/out contract per matrix

@@ -55,6 +55,7 @@ SIGNATURES = {
                              vp, c_int, c_ll, c_double, vp, c_int, c_ll, c_int, c_int, vp]),
     "adelia_bta_workspace_bytes": (c_size_t, [BtaShape, c_int]),
     "bta_factor": (c_int, [vp, BtaShape, vp, vp, vp, vp, vp, vp, vp, vp, vp, c_size_t, vp]),
+    "bta_factor_noalloc": (c_int, [vp, BtaShape, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     "adelia_bta_batched_workspace_bytes": (c_size_t, [c_int, C.POINTER(BtaShape), c_int]),
     "bta_factor_batched": (c_int, [vp, c_int, C.POINTER(BtaShape), C.POINTER(vp), C.POINTER(vp),
                                    C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),

@@ -9,6 +9,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 namespace adelia {
@@ -106,6 +107,128 @@ FactorWs factor_ws_layout(const adelia_bta_shape& sh, int ap, char* base) {
   return w;
 }
 
+// bta_factor_noalloc works in this array instead of a caller workspace.  Host code never
+// passes its name to a kernel (on the host it names a stand-in, not device memory): the
+// device address comes from hipGetSymbolAddress, once per device, and is kept per device.
+constexpr size_t kNoAllocBytes = ADELIA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device (nullptr if the
+// query failed).
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+      g_scratch_ptr[device] = p;
+    else
+      (void)hipGetLastError();  // a failed query must not read as a failed launch later
+  }
+  return g_scratch_ptr[device];
+}
+
+// Arguments 1..10 of bta_factor / bta_factor_noalloc (same numbering).
+int check_factor_args(adelia_ctx ctx, const adelia_bta_shape& sh, const double* D,
+                      const double* B, const double* C, const double* T, const double* Dinv,
+                      const double* rhs, const double* logdet, const int32_t* info) {
+  if (!ctx) return -1;
+  if (check_shape(sh)) return -2;
+  if (!D || !aligned8(D)) return -3;
+  if (sh.n > 1 && (!B || !aligned8(B))) return -4;
+  if (sh.a > 0 && (!C || !aligned8(C))) return -5;
+  if (sh.a > 0 && (!T || !aligned8(T))) return -6;
+  if (!Dinv || !aligned8(Dinv)) return -7;
+  if (rhs && !aligned8(rhs)) return -8;
+  if (!logdet || !aligned8(logdet)) return -9;
+  if (!info || ((uintptr_t)info & 3)) return -10;
+  if ((long long)sh.n * sh.b > INT_MAX) return ADELIA_E_SHAPE;
+  return 0;
+}
+
+// The body of bta_factor, on a workspace laid out by factor_ws_layout (checked by the caller).
+int factor_enqueue(adelia_ctx ctx, const adelia_bta_shape& sh, double* D, double* B, double* C,
+                   double* T, double* Dinv, double* rhs, double* logdet, int32_t* info,
+                   const FactorWs& w, hipStream_t s) {
+  const int n = sh.n, b = sh.b, a = sh.a;
+  const int ap = a + (rhs ? 1 : 0);
+  const long long bb = (long long)b * b;
+  const long long nb = (long long)n * b;
+  int e = 0;
+  e |= launch_fill_i32(info, 1, INT32_MAX, s);
+  e |= launch_fill_i32(w.cnt, 1, 0, s);
+  if (ap > 0) {
+    if (a > 0) {
+      e |= launch_copy2d(C, a, 0, w.Caug, ap, 0, a, (int)nb, 1, s);
+      e |= launch_copy2d(T, a, 0, w.Taug, ap, 0, a, a, 1, s);
+    }
+    if (rhs) {
+      e |= launch_copy2d(rhs, 1, 0, w.Caug + a, ap, 0, 1, (int)nb, 1, s);
+      if (a > 0) e |= launch_copy2d(rhs + nb, 1, 0, w.Taug + a, ap, 0, 1, a, 1, s);
+      e |= launch_fill(w.Taug + a + (long long)a * ap, 1, 0.0, s);
+    }
+  }
+  if (e) return ADELIA_E_HIP;
+  BtaChains c{};
+  c.n = n; c.b = b; c.a = a; c.ap = ap; c.nz = 1;
+  c.D = D; c.zD = 0; c.slotsD = n;
+  c.Bin = B; c.zB = 0; c.slotsB = n > 1 ? n - 1 : 1;
+  c.C = w.Caug; c.zC = 0;
+  c.LBC = w.LBC; c.zLBC = 0; c.slotsLBC = 1;
+  c.T = w.Taug; c.zT = 0;
+  c.G = Dinv; c.zG = 0; c.slotsG = n;
+  c.ldpart = w.ldpart; c.zLd = 0;
+  c.info = info;
+  c.cnt = w.cnt;
+  c.scratch = w.S; c.zS = 0;
+  c.zsq = w.zsq;
+  // with the context's streams: look-ahead steps, and each block's inverse on the side stream
+  // (every block keeps its L_D and G slot), joined before returning
+  const bool side = ctx->has_streams;
+  c.invert = !side;
+  c.inv_maxwg = side ? ctx->side_maxwg : 0;
+  adelia::Lookahead la = ctx->la;
+  for (int i = 0; i < n; ++i) {
+    int r = bta_forward_block(c, i, s, side ? &la : nullptr);
+    if (r) return ADELIA_E_HIP;
+    if (side && (hipEventRecord(ctx->fork[i % 3], s) != hipSuccess ||
+                 hipStreamWaitEvent(ctx->s2, ctx->fork[i % 3], 0) != hipSuccess ||
+                 bta_invert_block(c, i, ctx->s2)))
+      return ADELIA_E_HIP;
+    // [L_Bi; L_Ci] leave the one-block scratch: L_Bi into B_i, L_Ci (and z_i) into block i of
+    // the augmented arrow
+    if (i < n - 1 && launch_copy2d(w.LBC, b + ap, 0, B + (long long)i * bb, b, 0, b, b, 1, s))
+      return ADELIA_E_HIP;
+    if (ap > 0 && launch_copy2d(w.LBC + b, b + ap, 0, w.LCaug + (long long)i * ap * b, ap, 0, ap,
+                                b, 1, s))
+      return ADELIA_E_HIP;
+  }
+  if (side && (hipEventRecord(ctx->join, ctx->s2) != hipSuccess ||
+               hipStreamWaitEvent(s, ctx->join, 0) != hipSuccess))
+    return ADELIA_E_HIP;
+  if (bta_tip(c, s)) return ADELIA_E_HIP;
+  if (ap > 0) {
+    if (a > 0) {
+      e |= launch_copy2d(w.LCaug, ap, 0, C, a, 0, a, (int)nb, 1, s);
+      e |= launch_copy2d(w.Taug, ap, 0, T, a, 0, a, a, 1, s);
+    }
+    if (rhs) {
+      e |= launch_copy2d(w.LCaug + a, ap, 0, rhs, 1, 0, 1, (int)nb, 1, s);
+      if (a > 0) e |= launch_copy2d(w.Taug + a, ap, 0, rhs + nb, 1, 0, 1, a, 1, s);
+    }
+  }
+  const int npanel = (b + kPanel - 1) / kPanel;
+  e |= bta_logdet_reduce(w.ldpart, 0, n * npanel + 1, logdet, 0, 1, s);
+  e |= launch_zero_upper(D, b, b, bb, n, 0, 1, s);
+  e |= launch_zero_upper(Dinv, b, b, bb, n, 0, 1, s);
+  e |= launch_finalize_info(info, 1, s);
+  return e ? ADELIA_E_HIP : 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -123,6 +246,9 @@ int adelia_create(adelia_ctx* ctx, int device) {
     cus = 256;
   c->la.cus = cus;
   c->side_maxwg = std::max(16, (5 * cus / 8) & ~15);
+  // the device address of bta_factor_noalloc's static scratch, taken here with the device
+  // current (null if the query fails: that entry point then returns ADELIA_E_HIP)
+  c->noalloc_scratch = scratch_address(device);
   bool ok = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&c->la.ts, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;
@@ -236,94 +362,29 @@ size_t adelia_bta_workspace_bytes(adelia_bta_shape sh, int which) {
 int bta_factor(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double* C, double* T,
                double* Dinv, double* rhs, double* logdet, int32_t* info, void* ws,
                size_t ws_bytes, void* stream) {
-  if (!ctx) return -1;
-  if (check_shape(sh)) return -2;
-  const int n = sh.n, b = sh.b, a = sh.a;
-  if (!D || !aligned8(D)) return -3;
-  if (n > 1 && (!B || !aligned8(B))) return -4;
-  if (a > 0 && (!C || !aligned8(C))) return -5;
-  if (a > 0 && (!T || !aligned8(T))) return -6;
-  if (!Dinv || !aligned8(Dinv)) return -7;
-  if (rhs && !aligned8(rhs)) return -8;
-  if (!logdet || !aligned8(logdet)) return -9;
-  if (!info || ((uintptr_t)info & 3)) return -10;
-  const int ap = a + (rhs ? 1 : 0);
-  FactorWs w = factor_ws_layout(sh, ap, reinterpret_cast<char*>(ws));
+  if (int r = check_factor_args(ctx, sh, D, B, C, T, Dinv, rhs, logdet, info)) return r;
   if (!ws || ((uintptr_t)ws & 255)) return -11;
+  const FactorWs w = factor_ws_layout(sh, sh.a + (rhs ? 1 : 0), reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  const long long bb = (long long)b * b;
-  const long long nb = (long long)n * b;
-  if (nb > INT_MAX) return ADELIA_E_SHAPE;
-  int e = 0;
-  e |= launch_fill_i32(info, 1, INT32_MAX, s);
-  e |= launch_fill_i32(w.cnt, 1, 0, s);
-  if (ap > 0) {
-    if (a > 0) {
-      e |= launch_copy2d(C, a, 0, w.Caug, ap, 0, a, (int)nb, 1, s);
-      e |= launch_copy2d(T, a, 0, w.Taug, ap, 0, a, a, 1, s);
-    }
-    if (rhs) {
-      e |= launch_copy2d(rhs, 1, 0, w.Caug + a, ap, 0, 1, (int)nb, 1, s);
-      if (a > 0) e |= launch_copy2d(rhs + nb, 1, 0, w.Taug + a, ap, 0, 1, a, 1, s);
-      e |= launch_fill(w.Taug + a + (long long)a * ap, 1, 0.0, s);
-    }
+  return factor_enqueue(ctx, sh, D, B, C, T, Dinv, rhs, logdet, info, w, (hipStream_t)stream);
+}
+
+int bta_factor_noalloc(adelia_ctx ctx, adelia_bta_shape sh, double* D, double* B, double* C,
+                       double* T, double* Dinv, double* rhs, double* logdet, int32_t* info,
+                       void* stream) {
+  if (int r = check_factor_args(ctx, sh, D, B, C, T, Dinv, rhs, logdet, info)) return r;
+  // the same bound as the workspace query (which assumes a right-hand side), with or without one
+  const size_t need = factor_ws_layout(sh, sh.a + 1, nullptr).bytes;
+  if (need > kNoAllocBytes) {
+    set_last_error("bta_factor_noalloc: this shape needs " + std::to_string(need) +
+                   " bytes of scratch; the static scratch holds " +
+                   std::to_string(kNoAllocBytes) + " (use bta_factor with a workspace)");
+    return ADELIA_E_WORKSPACE;
   }
-  if (e) return ADELIA_E_HIP;
-  BtaChains c{};
-  c.n = n; c.b = b; c.a = a; c.ap = ap; c.nz = 1;
-  c.D = D; c.zD = 0; c.slotsD = n;
-  c.Bin = B; c.zB = 0; c.slotsB = n > 1 ? n - 1 : 1;
-  c.C = w.Caug; c.zC = 0;
-  c.LBC = w.LBC; c.zLBC = 0; c.slotsLBC = 1;
-  c.T = w.Taug; c.zT = 0;
-  c.G = Dinv; c.zG = 0; c.slotsG = n;
-  c.ldpart = w.ldpart; c.zLd = 0;
-  c.info = info;
-  c.cnt = w.cnt;
-  c.scratch = w.S; c.zS = 0;
-  c.zsq = w.zsq;
-  // with the context's streams: look-ahead steps, and each block's inverse on the side stream
-  // (every block keeps its L_D and G slot), joined before returning
-  const bool side = ctx->has_streams;
-  c.invert = !side;
-  c.inv_maxwg = side ? ctx->side_maxwg : 0;
-  adelia::Lookahead la = ctx->la;
-  for (int i = 0; i < n; ++i) {
-    int r = bta_forward_block(c, i, s, side ? &la : nullptr);
-    if (r) return ADELIA_E_HIP;
-    if (side && (hipEventRecord(ctx->fork[i % 3], s) != hipSuccess ||
-                 hipStreamWaitEvent(ctx->s2, ctx->fork[i % 3], 0) != hipSuccess ||
-                 bta_invert_block(c, i, ctx->s2)))
-      return ADELIA_E_HIP;
-    // [L_Bi; L_Ci] leave the one-block scratch: L_Bi into B_i, L_Ci (and z_i) into block i of
-    // the augmented arrow
-    if (i < n - 1 && launch_copy2d(w.LBC, b + ap, 0, B + (long long)i * bb, b, 0, b, b, 1, s))
-      return ADELIA_E_HIP;
-    if (ap > 0 && launch_copy2d(w.LBC + b, b + ap, 0, w.LCaug + (long long)i * ap * b, ap, 0, ap,
-                                b, 1, s))
-      return ADELIA_E_HIP;
-  }
-  if (side && (hipEventRecord(ctx->join, ctx->s2) != hipSuccess ||
-               hipStreamWaitEvent(s, ctx->join, 0) != hipSuccess))
-    return ADELIA_E_HIP;
-  if (bta_tip(c, s)) return ADELIA_E_HIP;
-  if (ap > 0) {
-    if (a > 0) {
-      e |= launch_copy2d(w.LCaug, ap, 0, C, a, 0, a, (int)nb, 1, s);
-      e |= launch_copy2d(w.Taug, ap, 0, T, a, 0, a, a, 1, s);
-    }
-    if (rhs) {
-      e |= launch_copy2d(w.LCaug + a, ap, 0, rhs, 1, 0, 1, (int)nb, 1, s);
-      if (a > 0) e |= launch_copy2d(w.Taug + a, ap, 0, rhs + nb, 1, 0, 1, a, 1, s);
-    }
-  }
-  const int npanel = (b + kPanel - 1) / kPanel;
-  e |= bta_logdet_reduce(w.ldpart, 0, n * npanel + 1, logdet, 0, 1, s);
-  e |= launch_zero_upper(D, b, b, bb, n, 0, 1, s);
-  e |= launch_zero_upper(Dinv, b, b, bb, n, 0, 1, s);
-  e |= launch_finalize_info(info, 1, s);
-  return e ? ADELIA_E_HIP : 0;
+  if (!ctx->noalloc_scratch) return ADELIA_E_HIP;
+  const FactorWs w = factor_ws_layout(sh, sh.a + (rhs ? 1 : 0),
+                                      reinterpret_cast<char*>(ctx->noalloc_scratch));
+  return factor_enqueue(ctx, sh, D, B, C, T, Dinv, rhs, logdet, info, w, (hipStream_t)stream);
 }
 
 int bta_logdet(adelia_ctx ctx, adelia_bta_shape sh, const double* LD, const double* LT,

@@ -12,6 +12,8 @@ struct adelia_ctx_s {
   hipEvent_t fork[3], join;
   adelia::Lookahead la;
   int side_maxwg;
+  // device address of the static scratch of bta_factor_noalloc on this device
+  void* noalloc_scratch;
 };
 
 namespace adelia {

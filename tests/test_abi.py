@@ -97,6 +97,34 @@ def test_bta_factor_argument_codes():
     assert call(nb=256) == E_WORKSPACE
 
 
+def test_bta_factor_noalloc_argument_codes():
+    """The entry point without a workspace numbers its argument errors as bta_factor does and
+    rejects shapes whose factor workspace exceeds its static scratch before touching anything."""
+    L = _L()
+    ok = _shape(3, 64, 2)
+
+    def call(ctx=CTX, sh=ok, D=P, B=P, C=P, T=P, Dinv=P, rhs=None, ld=P, info=P):
+        return L.bta_factor_noalloc(ctx, sh, D, B, C, T, Dinv, rhs, ld, info, None)
+
+    assert call(ctx=None) == -1
+    assert call(sh=_shape(2, 16384, 2)) == -2
+    assert call(D=ODD) == -3
+    assert call(B=None) == -4
+    assert call(C=None) == -5
+    assert call(T=None) == -6
+    assert call(Dinv=None) == -7
+    assert call(rhs=ODD) == -8
+    assert call(ld=None) == -9
+    assert call(info=P + 2) == -10
+    cap = 64 << 20
+    big = _shape(2, 2048, 8)  # (2b + 9) b doubles of block scratch: 68 MB
+    assert L.adelia_bta_workspace_bytes(big, 1) > cap
+    assert call(sh=big) == E_WORKSPACE
+    assert b"static scratch" in L.adelia_last_error()
+    # the largest block that fits: the query stays inside the cap
+    assert L.adelia_bta_workspace_bytes(_shape(50, 1024, 6), 1) <= cap
+
+
 def test_bta_solve_selinv_logdet_argument_codes():
     L = _L()
     ok = _shape(3, 64, 2)
