@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct adelia_ctx_s* adelia_ctx;
 typedef struct inla_model_s* inla_model;
+typedef struct inla_batch_s* inla_batch;
 
 /* Largest block size b (also k * ns of an INLA model).  The matrix cores read every operand of
  * the sweeps (up to a b x (b + 65) block) through 32-bit buffer descriptors, so a block of 2 GiB
@@ -318,6 +319,38 @@ int inla_fd_hessian(inla_model model, const double* theta, double h, int32_t max
                     double* f, double* H, int32_t* info, void* ws, size_t ws_bytes,
                     void* stream);
 
+
+/* ---------------------------------------------------------------------------------------
+ * Uneven batch of INLA instances (Sec. III-A over many independent models at once; the
+ * batched evaluation of Sec. IV): `count` models of different sizes -- time steps, spatial
+ * size, fixed effects, observations -- evaluated together, each at its own theta.  Models with
+ * the same block size b = k * ns form a group whose Qc and Qp chains share every launch of the
+ * sweeps; inside a group the fixed effects are padded to the group's largest a with zero
+ * covariate columns (f and the gradient are unchanged: the padded effects are decoupled and
+ * keep their prior precision in Qp and Qc alike) and an instance with fewer time steps drops
+ * out of the launches past its last block.  Groups run one after another on the stream.
+ *   inla_batch_create: set-up call (allocates the per-member descriptors and padded covariate
+ *     copies, and the batch's own side streams).  All models must live on the context's device
+ *     and share the parameterisation, k and d; models of one block size must have the same
+ *     spatial size.  The batch references the models, which must outlive it.  Returns 0,
+ *     -k for argument k, ADELIA_E_SHAPE (message in adelia_last_error) or ADELIA_E_HIP.
+ *   inla_batch_workspace_bytes: mode ADELIA_MODE_OBJECTIVE or ADELIA_MODE_GRAD (0 if invalid).
+ *   inla_batch_objective: f of Eq. 1 for instance i at theta[i*d .. i*d+d) (device, row-major,
+ *     count x d); f: device, count; info: device int32, count (as inla_objective).
+ *   inla_batch_grad: f and the exact gradient (as inla_grad) of every instance; grad: device,
+ *     count x d row-major.
+ * Both evaluate calls enqueue only (capturable into a hipGraph) and return -k for argument k,
+ * ADELIA_E_WORKSPACE or ADELIA_E_HIP.
+ * --------------------------------------------------------------------------------------- */
+int inla_batch_create(adelia_ctx ctx, int count, const inla_model* models, inla_batch* out);
+int inla_batch_destroy(inla_batch batch);
+/* Number of block-size groups of the batch (0 for NULL). */
+int inla_batch_groups(inla_batch batch);
+size_t inla_batch_workspace_bytes(inla_batch batch, int mode);
+int inla_batch_objective(inla_batch batch, const double* theta, double* f, int32_t* info,
+                         void* ws, size_t ws_bytes, void* stream);
+int inla_batch_grad(inla_batch batch, const double* theta, double* f, double* grad,
+                    int32_t* info, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Opt-in kernel timing for measurement runs.  Between adelia_profile_start and

@@ -6,12 +6,14 @@ this package only marshals arguments.  Submodules:
 
 * ``bta``  -- bta_factor / bta_logdet / bta_solve / bta_selinv and a batched FP64 GEMM;
 * ``inla`` -- InlaModel, objective, gradient, GPU finite differences, the posterior Hessian,
-  the autograd Function and BatchRunner (graph-captured batched evaluation); the package
-  re-exports InlaModel, InlaObjective, BatchRunner, fd_grad and hessian.
+  the autograd Function, BatchRunner (graph-captured batched evaluation) and InlaBatch (an
+  uneven batch of models); the package re-exports InlaModel, InlaObjective, BatchRunner,
+  InlaBatch, fd_grad and hessian.
 """
-__all__ = ["bta", "inla", "InlaModel", "InlaObjective", "BatchRunner", "fd_grad", "hessian"]
+__all__ = ["bta", "inla", "InlaModel", "InlaObjective", "BatchRunner", "InlaBatch", "fd_grad",
+           "hessian"]
 
-_FROM_INLA = ("InlaModel", "InlaObjective", "BatchRunner", "fd_grad", "hessian")
+_FROM_INLA = ("InlaModel", "InlaObjective", "BatchRunner", "InlaBatch", "fd_grad", "hessian")
 
 
 def __getattr__(name):

@@ -74,6 +74,12 @@ SIGNATURES = {
     "inla_grad_batched": (c_int, [vp, vp, c_int32, vp, vp, vp, vp, c_size_t, vp]),
     "inla_hessian": (c_int, [vp, vp, c_double, c_int32, vp, vp, vp, vp, vp, c_size_t, vp]),
     "inla_fd_hessian": (c_int, [vp, vp, c_double, c_int32, vp, vp, vp, vp, c_size_t, vp]),
+    "inla_batch_create": (c_int, [vp, c_int, C.POINTER(vp), C.POINTER(vp)]),
+    "inla_batch_destroy": (c_int, [vp]),
+    "inla_batch_groups": (c_int, [vp]),
+    "inla_batch_workspace_bytes": (c_size_t, [vp, c_int]),
+    "inla_batch_objective": (c_int, [vp, vp, vp, vp, vp, c_size_t, vp]),
+    "inla_batch_grad": (c_int, [vp, vp, vp, vp, vp, vp, c_size_t, vp]),
     "adelia_profile_start": (c_int, [vp, c_int]),
     "adelia_profile_stop": (c_int, [vp, C.POINTER(KernelStats), c_int, C.POINTER(c_int)]),
 }

@@ -35,6 +35,7 @@ struct inla_model_s {
   int device;
   int param;
   ModelDev M;
+  const ModelDev* Md;  // device copy of M (inside dev_mem), read by the kernels
   void* dev_mem;
   SideRes side;
   bool has_side;
@@ -45,6 +46,15 @@ struct inla_model_s {
 };
 
 namespace {
+
+// What one evaluation runs on: the host description that sizes the workspace and the launches
+// (for an uneven batch, the largest instance of a group), the model(s) the kernels read, and for
+// an uneven batch the block count of every chain (its sweeps skip the steps past it).
+struct Eval {
+  const ModelDev& M;
+  Models dev;
+  const int32_t* zn;
+};
 
 struct InlaWs {
   int batch, nz, n, b, a, ap, k, d, npanel;
@@ -212,7 +222,7 @@ SelinvChains selinv_of(const InlaWs& w) {
 // chains keep HBM busy without crowding the work that runs beside it.
 constexpr int kWGroups = 512;
 
-int prepare_block(const ModelDev& M, const InlaWs& w, SelinvChains si, int j, hipStream_t s) {
+int prepare_block(const Eval& E, const InlaWs& w, SelinvChains si, int j, hipStream_t s) {
   const int b = w.b;
   // as many columns of G_j^T G_j per pass as fit in 64 KB of LDS (at most kWBatch)
   const int cb = std::min<int>(kWBatch, (int)((64 * 1024) / ((size_t)b * sizeof(double))));
@@ -226,7 +236,7 @@ int prepare_block(const ModelDev& M, const InlaWs& w, SelinvChains si, int j, hi
     const int wg = std::max(1, std::min((b + cb - 1) / cb, kWGroups / w.nz));
     const ProfToken t = prof_begin(s);
     hipLaunchKernelGGL(w_from_gtg_kernel, dim3(wg, 1, w.nz), dim3(256),
-                       (size_t)cb * b * sizeof(double), s, M, j, Y, w.zZD, Wm, w.zW, w.phi, cb);
+                       (size_t)cb * b * sizeof(double), s, E.dev, j, Y, w.zZD, Wm, w.zW, w.phi, cb);
     if (t.valid)  // G_j^T G_j read and W_j written once per chain
       prof_end(t, s, PK_WSPARSE, 0.0, 16.0 * w.nz * (double)bb);
     if (hipGetLastError() != hipSuccess) return ADELIA_E_HIP;
@@ -235,31 +245,34 @@ int prepare_block(const ModelDev& M, const InlaWs& w, SelinvChains si, int j, hi
 }
 
 // Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
-int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStream_t s,
+int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t s,
                 const SideRes* side) {
+  const ModelDev& M = E.M;
   const int nz = w.nz, n = w.n, b = w.b;
-  hipLaunchKernelGGL(param_kernel, dim3(w.batch), dim3(256), 0, s, M, theta, w.phi, w.dphi,
+  hipLaunchKernelGGL(param_kernel, dim3(w.batch), dim3(256), 0, s, E.dev, theta, w.phi, w.dphi,
                      w.tau);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
   if (launch_fill_i32(w.info, nz, INT32_MAX, s)) return ADELIA_E_HIP;
   if (launch_fill_i32(w.cnt, nz, 0, s)) return ADELIA_E_HIP;
   const long long nb = (long long)n * b;
   hipLaunchKernelGGL(assemble_arrow_kernel, dim3((unsigned)((nb + 255) / 256), 1, nz), dim3(256),
-                     0, s, M, w.C, w.zC, w.ap, w.tau);
-  hipLaunchKernelGGL(assemble_tip_kernel, dim3(w.ap * w.ap, 1, nz), dim3(256), 0, s, M, w.T,
+                     0, s, E.dev, w.C, w.zC, nb, w.ap, w.tau);
+  hipLaunchKernelGGL(assemble_tip_kernel, dim3(w.ap * w.ap, 1, nz), dim3(256), 0, s, E.dev, w.T,
                      w.zT, w.ap, w.tau);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
   const long long bb = (long long)b * b;
   const dim3 agrid(b, 1, nz);
   BtaChains c = chains_of(w);
+  c.zn = E.zn;
   SelinvChains si = selinv_of(w);
+  si.zn = E.zn;
   const bool fork = c.invert && side && w.slotsD == 3;
   if (fork) {
     c.invert = false;
     c.inv_maxwg = side->side_maxwg;
     si.prep_maxwg = side->side_maxwg;
   }
-  hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, 0, -1, w.D, w.zD,
+  hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, E.dev, 0, -1, w.D, w.zD,
                      w.Bin, w.zB, (long long)b, w.phi, w.tau);
   // With the side stream (a gradient: every block keeps its [L_B; L_C] slot), B_i is assembled
   // straight into the rows of [L_B; L_C] of block i instead of a separate slot.
@@ -275,7 +288,7 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
       double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * bb;
       double* Bslot = fork ? w.LBC + (long long)(i % w.slotsLBC) * ldT * b : w.Bin;
       const ProfToken t = prof_begin(s);
-      hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, td, tb, Dslot,
+      hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, E.dev, td, tb, Dslot,
                          w.zD, Bslot, fork ? w.zLBC : w.zB, fork ? ldT : (long long)b, w.phi,
                          w.tau);
       if (t.valid) prof_end(t, s, PK_ASSEMBLE, 0.0, 8.0 * bb * nz * ((td >= 0) + (tb >= 0)));
@@ -309,14 +322,14 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
         return ADELIA_E_HIP;
       if (bta_invert_block(c, j, side->s2)) return ADELIA_E_HIP;
       if (hipEventRecord(side->done[j % 3], side->s2) != hipSuccess) return ADELIA_E_HIP;
-      if (prepare_block(M, w, si, j, side->s2)) return ADELIA_E_HIP;
+      if (prepare_block(E, w, si, j, side->s2)) return ADELIA_E_HIP;
       return 0;
     };
     if (fork) {
       if (late && fork_block(i - 1, true)) return ADELIA_E_HIP;
       if (i == n - 1 && fork_block(i, false)) return ADELIA_E_HIP;
     } else if (w.grad && !w.carry) {
-      if (prepare_block(M, w, si, i, s)) return ADELIA_E_HIP;
+      if (prepare_block(E, w, si, i, s)) return ADELIA_E_HIP;
     }
   }
   // the side stream runs its work in order: an event after its last product joins all of it
@@ -328,17 +341,18 @@ int run_forward(const ModelDev& M, const InlaWs& w, const double* theta, hipStre
   return 0;
 }
 
-int run_objective(const ModelDev& M, const InlaWs& w, const double* theta, double* f,
+int run_objective(const Eval& E, const InlaWs& w, const double* theta, double* f,
                   int32_t* info, hipStream_t s, const SideRes* side = nullptr) {
-  int r = run_forward(M, w, theta, s, side);
+  int r = run_forward(E, w, theta, s, side);
   if (r) return r;
-  hipLaunchKernelGGL(objective_kernel, dim3((w.batch + 63) / 64), dim3(64), 0, s, M, theta,
+  hipLaunchKernelGGL(objective_kernel, dim3((w.batch + 63) / 64), dim3(64), 0, s, E.dev, theta,
                      w.batch, w.tau, w.ld, w.zsq, w.info, f, info);
   return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
 }
 
-int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double* f, double* grad,
+int run_backward(const Eval& E, const InlaWs& w, const double* theta, double* f, double* grad,
                  int32_t* info, double* terms, hipStream_t s, const SideRes* side) {
+  const ModelDev& M = E.M;
   const int n = w.n, b = w.b, a = w.a, ap = w.ap, nz = w.nz;
   // x* = Qc^-1 r by the upper sweep (Eqs. 3-5); z_t is the rhs row of L_C
   SolveChains sc{};
@@ -351,14 +365,16 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
   sc.x = w.x; sc.zx = w.zx;
   sc.y = w.y; sc.zy = w.zy;
+  sc.zn = E.zn;
   SelinvChains si = selinv_of(w);
+  si.zn = E.zn;
   const long long bb = (long long)b * b;
   const int ntrace = 2 * M.k * M.k * M.nch_rows + M.k * M.nch_obs;
   auto trace = [&](int j, hipStream_t ts) -> int {
     const double* ZDj = w.ZD + (long long)(j % w.slotsZD) * bb;
     const double* ZCj = w.ZC + (long long)(j % 2) * a * b;
     const ProfToken t = prof_begin(ts);
-    hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, ts, M, j, ZDj, w.zZD,
+    hipLaunchKernelGGL(trace_kernel, dim3(ntrace, 1, nz), dim3(256), 0, ts, E.dev, j, ZDj, w.zZD,
                        w.ZB, w.zZB, ZCj, w.zZC, w.ZT, w.zZT, w.TD, w.TB, w.O, w.zTr, w.zO);
     if (t.valid)  // the band of Z_D and Z_B at the base-matrix pattern, per sub-block pair
       prof_end(t, ts, PK_TRACE, 0.0, 8.0 * nz * 2.0 * M.k * M.k * M.nnz);
@@ -374,6 +390,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
     sc.LC = w.LCz; sc.zLC = w.zLCz; sc.ldLC = ap; sc.sLC = (long long)ap * b;
     sc.z = w.LCz + a; sc.zz = w.zLCz; sc.sz_blk = (long long)ap * b; sc.sz_elem = ap;
     BtaChains c = chains_of(w);
+    c.zn = E.zn;
     c.refactor = true;
     c.b_in_place = true;
     c.invert = false;
@@ -414,7 +431,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
       if (launch_copy2d(w.Dc + (long long)j * bb, b, w.zDc, Dslot, b, w.zD, b, b, nz, s))
         return ADELIA_E_HIP;
       if (j < n - 1) {
-        hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, M, -1, j, Dslot, w.zD,
+        hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, E.dev, -1, j, Dslot, w.zD,
                            w.LBC + (long long)(j % w.slotsLBC) * ldT * b, w.zLBC, ldT, w.phi,
                            w.tau);
         if (!LAUNCH_OK()) return ADELIA_E_HIP;
@@ -423,7 +440,7 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
       if (pipe && (hipEventRecord(built[j % 3], s) != hipSuccess ||
                    hipStreamWaitEvent(s2, built[j % 3], 0) != hipSuccess))
         return ADELIA_E_HIP;
-      if (bta_invert_block(c, j, s2) || prepare_block(M, w, si, j, s2)) return ADELIA_E_HIP;
+      if (bta_invert_block(c, j, s2) || prepare_block(E, w, si, j, s2)) return ADELIA_E_HIP;
       if (pipe && (hipEventRecord(prepared[j % 3], s2) != hipSuccess ||
                    hipStreamWaitEvent(s3, prepared[j % 3], 0) != hipSuccess))
         return ADELIA_E_HIP;
@@ -456,11 +473,11 @@ int run_backward(const ModelDev& M, const InlaWs& w, const double* theta, double
   if (forked && hipStreamWaitEvent(s, side->done[0], 0) != hipSuccess) return ADELIA_E_HIP;
   // Phase B (Eq. 8) and the likelihood residual, from the mode of Qc (chain 2p of point p)
   const int B = w.batch;
-  hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k, 1, B), dim3(256), 0, s, M, w.x, 2 * w.zx,
+  hipLaunchKernelGGL(phaseb_kernel, dim3(n * M.k, 1, B), dim3(256), 0, s, E.dev, w.x, 2 * w.zx,
                      w.qD, w.qB, w.zq);
-  hipLaunchKernelGGL(resid_kernel, dim3(M.k * M.nch_resid, 1, B), dim3(256), 0, s, M, w.x,
-                     2 * w.zx, w.resid, w.zr);
-  hipLaunchKernelGGL(grad_kernel, dim3(B), dim3(256), 0, s, M, theta, w.dphi, w.tau, w.TD, w.TB,
+  hipLaunchKernelGGL(resid_kernel, dim3(M.k * M.nch_resid, 1, B), dim3(256), 0, s, E.dev, w.x,
+                     2 * w.zx, w.n, w.resid, w.zr);
+  hipLaunchKernelGGL(grad_kernel, dim3(B), dim3(256), 0, s, E.dev, theta, w.dphi, w.tau, w.TD, w.TB,
                      w.zTr, w.O, w.zO, w.qD, w.qB, w.zq, w.resid, w.zr, w.ld, w.zsq, w.ZT, w.zZT,
                      w.info, f, grad, info, B == 1 ? terms : nullptr);
   return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
@@ -533,6 +550,198 @@ std::string check_csr(const char* name, const int32_t* ptr, const int32_t* idx, 
 }
 
 }  // namespace
+
+namespace {
+
+// ---- uneven batches of INLA instances -------------------------------------------------------
+// Instances with the same block size b (and k, parameterisation, d) form a group whose chains
+// share every launch.  Inside a group the arrow is padded to the largest a with zero covariate
+// columns (the padded fixed effects keep their prior precision in Qp and Qc alike, are decoupled
+// from everything else and have no theta dependence, so f and its gradient are unchanged:
+// their log-determinant terms cancel between Qp and Qc and every other term is zero), and an
+// instance with fewer blocks drops out of the sweeps past its last block (per-chain block
+// counts; its coupling block after the last one is zero).  Groups run one after another.
+struct BatchGroup {
+  ModelDev Mh;  // sizes of the group's layout: the largest nt, a, observation slices
+  ModelDev* Mv = nullptr;     // device: one model per member (a padded to the group's)
+  int32_t* zn = nullptr;      // device: block count per chain (2 per member)
+  int32_t* idx = nullptr;     // device: the member's position in the batch
+  std::vector<int> members;
+};
+
+__global__ void gather_rows_kernel(const double* src, int d, const int32_t* idx, int n,
+                                   double* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * d) return;
+  dst[i] = src[(long long)idx[i / d] * d + i % d];
+}
+
+__global__ void scatter_results_kernel(const double* f, const double* g, const int32_t* info,
+                                       int n, int d, const int32_t* idx, double* f_out,
+                                       double* g_out, int32_t* info_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * d) return;
+  const int p = i / d, c = i % d, q = idx[p];
+  if (g_out) g_out[(long long)q * d + c] = g[i];
+  if (c == 0) {
+    f_out[q] = f[p];
+    info_out[q] = info[p];
+  }
+}
+
+// X (n_obs x a, row-major) copied into n_obs x ap columns, the extra columns zero
+__global__ void pad_cols_kernel(const double* X, int n_obs, int a, int ap, double* Xp) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= (long long)n_obs * ap) return;
+  const long long o = i / ap;
+  const int c = (int)(i % ap);
+  Xp[i] = c < a ? X[o * a + c] : 0.0;
+}
+
+// Zero block slot zn[z] of every chain z with zn[z] < nmax (the Z_D block after an instance's
+// last block, read with a zero factor when its last block is inverted).
+__global__ void zero_next_slot_kernel(double* Z, long long zZ, long long slot, const int32_t* zn,
+                                      int nmax) {
+  const int z = blockIdx.z;
+  const int nzb = zn[z];
+  if (nzb >= nmax) return;
+  double* p = Z + (long long)z * zZ + (long long)nzb * slot;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < slot; e += (long long)gridDim.x * 256)
+    p[e] = 0.0;
+}
+
+// Scratch in front of a batch workspace: the gathered points and the group's results.
+struct BatchFront {
+  double *Th, *fv, *gv;
+  int32_t* finfo;
+  size_t bytes;
+};
+
+BatchFront batch_front(int count, int d, char* base) {
+  BatchFront b{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  b.Th = reinterpret_cast<double*>(take((size_t)count * d * 8));
+  b.fv = reinterpret_cast<double*>(take((size_t)count * 8));
+  b.gv = reinterpret_cast<double*>(take((size_t)count * d * 8));
+  b.finfo = reinterpret_cast<int32_t*>(take((size_t)count * 4));
+  b.bytes = off;
+  return b;
+}
+
+}  // namespace
+
+struct inla_batch_s {
+  int device, d, count;
+  std::vector<BatchGroup> groups;
+  void* dev_mem;
+  SideRes side;
+  bool has_side;
+};
+
+namespace {
+
+size_t batch_ws_bytes(const inla_batch_s* B, bool grad) {
+  size_t most = 0;
+  for (const BatchGroup& g : B->groups)
+    most = std::max(most, layout(g.Mh, (int)g.members.size(), grad, nullptr).bytes);
+  return batch_front(B->count, B->d, nullptr).bytes + most;
+}
+
+int batch_eval(inla_batch_s* B, const double* theta, double* f, double* grad, int32_t* info,
+               void* ws, hipStream_t s) {
+  const bool with_grad = grad != nullptr;
+  char* base = reinterpret_cast<char*>(ws);
+  const BatchFront fr = batch_front(B->count, B->d, base);
+  const SideRes* side = B->has_side ? &B->side : nullptr;
+  const int d = B->d;
+  for (const BatchGroup& g : B->groups) {
+    const int ng = (int)g.members.size();
+    InlaWs w = layout(g.Mh, ng, with_grad, base + fr.bytes);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((ng * d + 255) / 256), dim3(256), 0, s, theta, d,
+                       g.idx, ng, fr.Th);
+    if (!LAUNCH_OK()) return ADELIA_E_HIP;
+    // what the skipped steps of shorter instances would have written: zero log-determinant
+    // partials, and for the reverse pass a zero x and Z_C and a zero Z_D block after each
+    // instance's last block
+    if (launch_fill(w.ldpart, (long long)w.nz * w.zLd, 0.0, s)) return ADELIA_E_HIP;
+    const Eval E{g.Mh, Models{g.Mv, 1}, g.zn};
+    int r;
+    if (!with_grad) {
+      r = run_objective(E, w, fr.Th, fr.fv, fr.finfo, s, side);
+    } else {
+      const long long bb = (long long)w.b * w.b;
+      if (launch_fill(w.x, (long long)w.nz * w.zx, 0.0, s) ||
+          launch_fill(w.ZC, (long long)w.nz * w.zZC, 0.0, s))
+        return ADELIA_E_HIP;
+      hipLaunchKernelGGL(zero_next_slot_kernel, dim3(std::max(1, (int)std::min<long long>(bb / 256, 256)), 1, w.nz),
+                         dim3(256), 0, s, w.ZD, w.zZD, bb, g.zn, w.n);
+      if (!LAUNCH_OK()) return ADELIA_E_HIP;
+      r = run_forward(E, w, fr.Th, s, side);
+      if (!r) r = run_backward(E, w, fr.Th, fr.fv, fr.gv, fr.finfo, nullptr, s, side);
+    }
+    if (r) return r;
+    hipLaunchKernelGGL(scatter_results_kernel, dim3((ng * d + 255) / 256), dim3(256), 0, s, fr.fv,
+                       fr.gv, fr.finfo, ng, d, g.idx, f, grad, info);
+    if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  }
+  return 0;
+}
+
+long long batch_launches(const inla_batch_s* B, bool grad) {
+  long long t = 0;
+  for (const BatchGroup& g : B->groups)
+    t += 8 + launches_per_pass(g.Mh, B->has_side ? &B->side : nullptr, (int)g.members.size(), grad);
+  return t;
+}
+
+}  // namespace
+
+
+// The side stream, the look-ahead stream and their events (default priority), for the device
+// `device` (current).  The side stream's products (inversion, selected-inversion preparation)
+// run beside the panels of the sweep, whose workgroups each need a CU of their own (most of its
+// LDS): they are capped at 5/8 of the CUs in tile slots, two tiles per workgroup
+// (gemm_f64_dual_kernel), i.e. on 5/16 of the CUs (measured on 256 CUs: 144-168 slots all best,
+// 128 and 176 clearly worse).
+static bool make_side(SideRes& sr, int device) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  sr.la.maxwg = 0;
+  sr.la.cus = cus;
+  sr.la.mark = nullptr;
+  sr.la.mark_step = 0;
+  sr.side_maxwg = std::max(16, (5 * cus / 8) & ~15);
+  bool ok = hipStreamCreateWithFlags(&sr.s2, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&sr.la.ts, hipStreamNonBlocking) == hipSuccess;
+  for (int e = 0; e < 3 && ok; ++e)
+    ok = hipEventCreateWithFlags(&sr.ready[e], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&sr.done[e], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&sr.la.pdone[e], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&sr.la.tdone[e], hipEventDisableTiming) == hipSuccess;
+  return ok;
+}
+
+static void free_side(SideRes& sr) {
+  hipStreamSynchronize(sr.s2);
+  hipStreamSynchronize(sr.la.ts);
+  for (int e = 0; e < 3; ++e) {
+    hipEventDestroy(sr.ready[e]);
+    hipEventDestroy(sr.done[e]);
+    hipEventDestroy(sr.la.pdone[e]);
+    hipEventDestroy(sr.la.tdone[e]);
+  }
+  hipStreamDestroy(sr.s2);
+  hipStreamDestroy(sr.la.ts);
+}
+
+static Eval eval_of(inla_model m) { return Eval{m->M, Models{m->Md, 0}, nullptr}; }
 
 // Estimated launches of `npts` points evaluated in passes of at most `bmax` points.
 static long long planned_passes(inla_model m, int npts, int bmax, bool grad) {
@@ -650,7 +859,7 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
       {d->X, (size_t)n_obs * a * 8},     {d->y, (size_t)n_obs * 8},
       {obs_off.data(), obs_off.size() * 4}, {colptr.data(), colptr.size() * 4},
       {col_o.data(), col_o.size() * 4},  {col_e.data(), col_e.size() * 4},
-      {nullptr, (size_t)k * 8}};
+      {nullptr, (size_t)k * 8},          {nullptr, sizeof(ModelDev)}};
   size_t total = 0;
   std::vector<size_t> offsets;
   for (auto& pr : parts) {
@@ -720,52 +929,21 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
     }
   }
   hipLaunchKernelGGL(yy_kernel, dim3(k), dim3(256), 0, 0, M, (double*)M.yy);
-  if (hipDeviceSynchronize() != hipSuccess) {
+  m->Md = reinterpret_cast<const ModelDev*>(mem + offsets[15]);
+  if (hipMemcpy(mem + offsets[15], &M, sizeof(ModelDev), hipMemcpyHostToDevice) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     hipFree(mem);
     delete m;
     return ADELIA_E_HIP;
   }
-  {
-    // The side stream's products (inversion, selected-inversion preparation) run beside the
-    // panels of the sweep, whose workgroups each need a CU of their own (most of its LDS): cap
-    // them at 5/8 of the CUs in tile slots, two tiles per workgroup (gemm_f64_dual_kernel), i.e.
-    // on 5/16 of the CUs (measured on 256 CUs: 144-168 slots all best, 128 and 176 clearly
-    // worse).
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    m->side.la.maxwg = 0;
-    m->side.la.cus = cus;
-    m->side.la.mark = nullptr;
-    m->side.la.mark_step = 0;
-    m->side.side_maxwg = std::max(16, (5 * cus / 8) & ~15);
-  }
-  m->has_side = hipStreamCreateWithFlags(&m->side.s2, hipStreamNonBlocking) == hipSuccess &&
-                hipStreamCreateWithFlags(&m->side.la.ts, hipStreamNonBlocking) == hipSuccess;
-  for (int e = 0; e < 3 && m->has_side; ++e)
-    m->has_side = hipEventCreateWithFlags(&m->side.ready[e], hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&m->side.done[e], hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&m->side.la.pdone[e], hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&m->side.la.tdone[e], hipEventDisableTiming) == hipSuccess;
+  m->has_side = make_side(m->side, m->device);
   *out = m;
   return 0;
 }
 
 int inla_model_destroy(inla_model m) {
   if (!m) return 0;
-  if (m->has_side) {
-    hipStreamSynchronize(m->side.s2);
-    hipStreamSynchronize(m->side.la.ts);
-    for (int e = 0; e < 3; ++e) {
-      hipEventDestroy(m->side.ready[e]);
-      hipEventDestroy(m->side.done[e]);
-      hipEventDestroy(m->side.la.pdone[e]);
-      hipEventDestroy(m->side.la.tdone[e]);
-    }
-    hipStreamDestroy(m->side.s2);
-    hipStreamDestroy(m->side.la.ts);
-  }
+  if (m->has_side) free_side(m->side);
   hipFree(m->dev_mem);
   delete m;
   return 0;
@@ -798,7 +976,7 @@ int inla_objective(inla_model m, const double* theta, int32_t batch, double* f, 
                             launches_per_pass(m->M, m->has_side ? &m->side : nullptr, batch, save)))
     return r;
   m->saved_ws = save ? ws : (m->saved_ws == ws ? nullptr : m->saved_ws);
-  return run_objective(m->M, w, theta, f, info, (hipStream_t)stream,
+  return run_objective(eval_of(m), w, theta, f, info, (hipStream_t)stream,
                        m->has_side ? &m->side : nullptr);
 }
 
@@ -819,10 +997,10 @@ int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_
   if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   if (!(flags & ADELIA_REUSE_FACTORS)) {
-    int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
+    int r = run_forward(eval_of(m), w, theta, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
-  return run_backward(m->M, w, theta, f, grad, info, nullptr, s,
+  return run_backward(eval_of(m), w, theta, f, grad, info, nullptr, s,
                       m->has_side ? &m->side : nullptr);
 }
 
@@ -842,9 +1020,9 @@ int inla_grad_batched(inla_model m, const double* theta, int32_t batch, double* 
                                                  true)))
     return r;
   if (m->saved_ws == ws) m->saved_ws = nullptr;
-  int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
+  int r = run_forward(eval_of(m), w, theta, s, m->has_side ? &m->side : nullptr);
   if (r) return r;
-  return run_backward(m->M, w, theta, f, grad, info, nullptr, s,
+  return run_backward(eval_of(m), w, theta, f, grad, info, nullptr, s,
                       m->has_side ? &m->side : nullptr);
 }
 
@@ -864,11 +1042,11 @@ int inla_grad_terms(inla_model m, const double* theta, double* terms, int32_t* i
   if (m->saved_ws == ws) m->saved_ws = nullptr;
   hipStream_t s = (hipStream_t)stream;
   if (!(flags & ADELIA_REUSE_FACTORS)) {
-    int r = run_forward(m->M, w, theta, s, m->has_side ? &m->side : nullptr);
+    int r = run_forward(eval_of(m), w, theta, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
   const int d = m->M.d;
-  return run_backward(m->M, w, theta, terms, terms + 5 + 5 * d, info, terms, s,
+  return run_backward(eval_of(m), w, theta, terms, terms + 5 + 5 * d, info, terms, s,
                       m->has_side ? &m->side : nullptr);
 }
 
@@ -897,7 +1075,7 @@ int inla_fd_grad(inla_model m, const double* theta, double h, int32_t max_batch,
     // a smaller last sub-batch uses a prefix of the same workspace; the stencil scratch sits
     // at a fixed place in front of it
     InlaWs wb = layout(m->M, bs, false, reinterpret_cast<char*>(ws));
-    int r = run_objective(m->M, wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s,
+    int r = run_objective(eval_of(m), wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s,
                           m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
@@ -932,9 +1110,9 @@ int inla_hessian(inla_model m, const double* theta, double h, int32_t max_batch,
     const int bs = std::min(bmax, npts - p0);
     InlaWs wb = layout(m->M, bs, true, reinterpret_cast<char*>(ws));
     const double* th = w.Th + (long long)p0 * d;
-    int r = run_forward(m->M, wb, th, s, m->has_side ? &m->side : nullptr);
+    int r = run_forward(eval_of(m), wb, th, s, m->has_side ? &m->side : nullptr);
     if (r) return r;
-    r = run_backward(m->M, wb, th, w.fv + p0, w.gv + (long long)p0 * d, info + p0, nullptr, s,
+    r = run_backward(eval_of(m), wb, th, w.fv + p0, w.gv + (long long)p0 * d, info + p0, nullptr, s,
                      m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
@@ -966,13 +1144,157 @@ int inla_fd_hessian(inla_model m, const double* theta, double h, int32_t max_bat
   for (int p0 = 0; p0 < npts; p0 += bmax) {
     const int bs = std::min(bmax, npts - p0);
     InlaWs wb = layout(m->M, bs, false, reinterpret_cast<char*>(ws));
-    int r = run_objective(m->M, wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s,
+    int r = run_objective(eval_of(m), wb, w.Th + (long long)p0 * d, w.fv + p0, info + p0, s,
                           m->has_side ? &m->side : nullptr);
     if (r) return r;
   }
   hipLaunchKernelGGL(fd_hessian_kernel, dim3((d * d + 63) / 64), dim3(64), 0, s, w.fv, d, h, f,
                      H);
   return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+}
+
+int inla_batch_create(adelia_ctx ctx, int count, const inla_model* models, inla_batch* out) {
+  set_last_error("");
+  if (!ctx) return -1;
+  if (count < 1 || count > 32767) return -2;
+  if (!models) return -3;
+  if (!out) return -4;
+  for (int i = 0; i < count; ++i)
+    if (!models[i] || models[i]->device != ctx->device) return -3;
+  const inla_model m0 = models[0];
+  for (int i = 1; i < count; ++i) {
+    const inla_model m = models[i];
+    if (m->param != m0->param || m->M.k != m0->M.k || m->M.d != m0->M.d)
+      return fail("batched models need the same parameterisation, k and d");
+  }
+  // groups by block size, members in batch order
+  std::map<int, std::vector<int>> by_b;
+  for (int i = 0; i < count; ++i) by_b[models[i]->M.b].push_back(i);
+  std::vector<BatchGroup> groups;
+  size_t total = 0;
+  std::vector<size_t> xoff;  // per instance: offset of its padded X (or SIZE_MAX)
+  xoff.assign(count, SIZE_MAX);
+  std::vector<size_t> goff;  // per group: offset of its Mv, zn, idx arrays
+  for (auto& kv : by_b) {
+    BatchGroup g;
+    g.members = kv.second;
+    g.Mh = models[g.members[0]]->M;
+    for (int q : g.members) {
+      const ModelDev& M = models[q]->M;
+      if (M.ns != g.Mh.ns || M.nch_rows != g.Mh.nch_rows)
+        return fail("batched models of one block size need the same spatial size");
+      g.Mh.nt = std::max(g.Mh.nt, M.nt);
+      g.Mh.a = std::max(g.Mh.a, M.a);
+      g.Mh.nch_obs = std::max(g.Mh.nch_obs, M.nch_obs);
+      g.Mh.nch_resid = std::max(g.Mh.nch_resid, M.nch_resid);
+      g.Mh.n_obs = std::max(g.Mh.n_obs, M.n_obs);
+    }
+    if ((long long)g.Mh.b * g.Mh.nt + g.Mh.a > INT_MAX) return fail("batch group too large");
+    goff.push_back(total);
+    const int ng = (int)g.members.size();
+    total = align_up(total + (size_t)ng * sizeof(ModelDev));
+    total = align_up(total + (size_t)2 * ng * 4);
+    total = align_up(total + (size_t)ng * 4);
+    for (int q : g.members) {
+      const ModelDev& M = models[q]->M;
+      if (M.a < g.Mh.a && M.n_obs > 0) {
+        xoff[q] = total;
+        total = align_up(total + (size_t)M.n_obs * g.Mh.a * 8);
+      }
+    }
+    groups.push_back(std::move(g));
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return ADELIA_E_HIP;
+  char* mem = nullptr;
+  if (hipMalloc(&mem, std::max<size_t>(total, 256)) != hipSuccess) return ADELIA_E_HIP;
+  inla_batch B = new inla_batch_s();
+  B->device = ctx->device;
+  B->d = m0->M.d;
+  B->count = count;
+  B->dev_mem = mem;
+  bool ok = true;
+  for (size_t gi = 0; gi < groups.size() && ok; ++gi) {
+    BatchGroup& g = groups[gi];
+    const int ng = (int)g.members.size();
+    size_t off = goff[gi];
+    g.Mv = reinterpret_cast<ModelDev*>(mem + off);
+    off = align_up(off + (size_t)ng * sizeof(ModelDev));
+    g.zn = reinterpret_cast<int32_t*>(mem + off);
+    off = align_up(off + (size_t)2 * ng * 4);
+    g.idx = reinterpret_cast<int32_t*>(mem + off);
+    std::vector<ModelDev> mv;
+    std::vector<int32_t> zn, idx;
+    for (int q : g.members) {
+      ModelDev M = models[q]->M;
+      if (xoff[q] != SIZE_MAX) {
+        double* Xp = reinterpret_cast<double*>(mem + xoff[q]);
+        const long long cnt = (long long)M.n_obs * g.Mh.a;
+        hipLaunchKernelGGL(pad_cols_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, 0,
+                           M.X, M.n_obs, M.a, g.Mh.a, Xp);
+        M.X = Xp;
+      }
+      M.a = g.Mh.a;
+      mv.push_back(M);
+      zn.push_back(M.nt);
+      zn.push_back(M.nt);
+      idx.push_back(q);
+    }
+    ok = hipMemcpy(g.Mv, mv.data(), mv.size() * sizeof(ModelDev), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(g.zn, zn.data(), zn.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(g.idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok || hipDeviceSynchronize() != hipSuccess) {
+    hipFree(mem);
+    delete B;
+    return ADELIA_E_HIP;
+  }
+  B->groups = std::move(groups);
+  B->has_side = make_side(B->side, B->device);
+  *out = B;
+  return 0;
+}
+
+int inla_batch_destroy(inla_batch B) {
+  if (!B) return 0;
+  if (B->has_side) free_side(B->side);
+  hipFree(B->dev_mem);
+  delete B;
+  return 0;
+}
+
+int inla_batch_groups(inla_batch B) { return B ? (int)B->groups.size() : 0; }
+
+size_t inla_batch_workspace_bytes(inla_batch B, int mode) {
+  if (!B) return 0;
+  if (mode != ADELIA_MODE_OBJECTIVE && mode != ADELIA_MODE_GRAD) return 0;
+  return batch_ws_bytes(B, mode == ADELIA_MODE_GRAD);
+}
+
+int inla_batch_objective(inla_batch B, const double* theta, double* f, int32_t* info, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!B) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (!f || !aligned(f, 8)) return -3;
+  if (!info || !aligned(info, 4)) return -4;
+  if (!ws || !aligned(ws, 256)) return -5;
+  if (ws_bytes < batch_ws_bytes(B, false)) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (int r = capture_guard(s, batch_launches(B, false))) return r;
+  return batch_eval(B, theta, f, nullptr, info, ws, s);
+}
+
+int inla_batch_grad(inla_batch B, const double* theta, double* f, double* grad, int32_t* info,
+                    void* ws, size_t ws_bytes, void* stream) {
+  if (!B) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (!f || !aligned(f, 8)) return -3;
+  if (!grad || !aligned(grad, 8)) return -4;
+  if (!info || !aligned(info, 4)) return -5;
+  if (!ws || !aligned(ws, 256)) return -6;
+  if (ws_bytes < batch_ws_bytes(B, true)) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (int r = capture_guard(s, batch_launches(B, true))) return r;
+  return batch_eval(B, theta, f, grad, info, ws, s);
 }
 
 }  // extern "C"

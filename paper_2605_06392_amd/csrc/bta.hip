@@ -348,6 +348,8 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
     g.omode = OUT_ALL;
     g.tag = GT_SI_W;
     g.maxwg = c.prep_maxwg;
+    g.zn = c.zn;
+    g.step = j;
     if (g.M > 0 && launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // S3 (first term): lower triangle of Z_Dj = G_j^T G_j
@@ -367,6 +369,8 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
     g.omode = c.w_external ? OUT_LOWER_MIRROR : OUT_LOWER;  // W_j reads its full columns
     g.tag = GT_SI_D;
     g.maxwg = c.prep_maxwg;
+    g.zn = c.zn;
+    g.step = j;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;
@@ -403,6 +407,8 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.omode = OUT_ALL;
     g.tag = GT_SI_Z;
     g.maxwg = c.fin_maxwg;
+    g.zn = c.zn;
+    g.step = j;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     if (skinny) {  // Z_Cj = -(Z_C,j+1 W + Z_T V)
       Skinny k{};
@@ -413,6 +419,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
       k.B2 = p.V; k.ldb2 = a; k.zB2 = zW;
       k.C = p.ZCj; k.ldc = a; k.zC = c.zZC;
       k.alpha = -1.0; k.beta = 0.0;
+      k.zn = c.zn; k.step = j;
       if (launch_skinny(k, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   } else if (a) {
@@ -430,6 +437,8 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.omode = OUT_ALL;
     g.tag = GT_SI_Z;
     g.maxwg = c.fin_maxwg;
+    g.zn = c.zn;
+    g.step = j;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   // S3: Z_Dj -= [Z_Bj; Z_Cj]^T [W; V] on the lower triangle holding G^T G, mirrored to a full
@@ -454,6 +463,8 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.omode = OUT_LOWER_MIRROR;
     g.tag = GT_SI_D;
     g.maxwg = c.fin_maxwg;
+    g.zn = c.zn;
+    g.step = j;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;
@@ -485,6 +496,7 @@ int bta_upper_solve_block(const SolveChains& c, int i, hipStream_t s) {
     g.beta = 1.0;
     g.y = c.y; g.zy = c.zy; g.incy = 1;
     g.M = b; g.K = b; g.lowerA = 0;
+    g.zn = c.zn; g.step = i;
     if (launch_gemv_t(g, nz, s)) return ADELIA_E_HIP_INTERNAL;
     GemvT h{};
     h.A = c.G + blk_off(i, c.slotsG, bb); h.ld = b; h.zA = c.zG;
@@ -492,6 +504,7 @@ int bta_upper_solve_block(const SolveChains& c, int i, hipStream_t s) {
     h.alpha = 1.0;
     h.y = c.x + (long long)i * b; h.zy = c.zx; h.incy = 1;
     h.M = b; h.K = b; h.lowerA = 1;
+    h.zn = c.zn; h.step = i;
     if (launch_gemv_t(h, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;

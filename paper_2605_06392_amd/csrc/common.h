@@ -161,6 +161,10 @@ struct SelinvChains {
   // G_j^T G_j (W_j = L_Bj G_j = B_j D~_j^-1 = B_j G_j^T G_j, for a sparse B_j); selinv_prepare
   // then forms V_j and G_j^T G_j only
   bool w_external;
+  // per chain block count of an uneven batch (nullptr: n for every chain): chain z takes part
+  // in step j only while j < zn[z]; its block zn[z] - 1 has a zero coupling block (W = 0), and
+  // the Z_D and Z_C slots of block zn[z] must hold zeros (finite) when step zn[z] - 1 runs
+  const int32_t* zn;
 };
 // The parts of backward step j that do not depend on Z (they can run as soon as G_j exists):
 // [W_j; V_j] = [L_Bj; L_Cj] G_j, and Z_Dj's lower triangle set to G_j^T G_j.
@@ -184,6 +188,7 @@ struct SolveChains {
   const double* xT; long long zxT;               // a
   double* x; long long zx;                        // length n*b + a (contiguous)
   double* y; long long zy;                        // scratch b
+  const int32_t* zn;  // per chain block count (uneven batch; its x must start as zeros) or nullptr
 };
 int bta_upper_solve(const SolveChains& c, hipStream_t s);
 // One block of it (x_i from x_{i+1} and x_T), and the tip part of x (after block 0).
@@ -200,6 +205,7 @@ struct GemvT {
   const double* y0; long long zy0; long long incy0;
   double* y; long long zy; long long incy;
   int M, K; int lowerA; double alpha, alpha2, beta;
+  const int32_t* zn; int step;  // chain z takes part only while step < zn[z] (zn may be null)
 };
 int launch_gemv_t(const GemvT& g, int nz, hipStream_t s);
 

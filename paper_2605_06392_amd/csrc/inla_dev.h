@@ -38,27 +38,40 @@ struct ModelDev {
   int role_kind[kMaxTheta], role_idx[kMaxTheta];
 };
 
-__global__ void param_kernel(const ModelDev M, const double* theta, double* phi, double* dphi,
+// The model(s) a launch reads: one model for every theta point (each == 0: v[0]), or one per
+// point (each == 1: point p evaluates model v[p], an uneven batch of instances that share the
+// block size and arrow width; chain z belongs to point z / 2).  The kernels take their model
+// as a copy from device memory, so one launch can cover instances of different models.
+struct Models {
+  const ModelDev* v;
+  int each;
+};
+__device__ __forceinline__ ModelDev model_at(const Models& ms, int p) {
+  return ms.v[ms.each ? p : 0];
+}
+
+__global__ void param_kernel(const Models Ms, const double* theta, double* phi, double* dphi,
                              double* tau);
-__global__ void assemble_blocks_kernel(const ModelDev M, int td, int tb, double* D, long long zD,
+__global__ void assemble_blocks_kernel(const Models Ms, int td, int tb, double* D, long long zD,
                                        double* B, long long zB, long long ldB, const double* phi,
                                        const double* tau);
-__global__ void assemble_arrow_kernel(const ModelDev M, double* C, long long zC, int ap,
+__global__ void assemble_arrow_kernel(const Models Ms, double* C, long long zC, long long nb,
+                                      int ap,
                                       const double* tau);
-__global__ void assemble_tip_kernel(const ModelDev M, double* T, long long zT, int ap,
+__global__ void assemble_tip_kernel(const Models Ms, double* T, long long zT, int ap,
                                     const double* tau);
-__global__ void trace_kernel(const ModelDev M, int j, const double* ZD, long long zZD,
+__global__ void trace_kernel(const Models Ms, int j, const double* ZD, long long zZD,
                              const double* ZB, long long zZB, const double* ZC, long long zZC,
                              const double* ZT, long long zZT, double* TD, double* TB, double* O,
                              long long zTr, long long zO);
-__global__ void phaseb_kernel(const ModelDev M, const double* x, long long zxp, double* qD,
+__global__ void phaseb_kernel(const Models Ms, const double* x, long long zxp, double* qD,
                               double* qB, long long zq);
-__global__ void resid_kernel(const ModelDev M, const double* x, long long zxp, double* resid,
-                             long long zr);
-__global__ void objective_kernel(const ModelDev M, const double* theta, int batch,
+__global__ void resid_kernel(const Models Ms, const double* x, long long zxp, int nlay,
+                             double* resid, long long zr);
+__global__ void objective_kernel(const Models Ms, const double* theta, int batch,
                                  const double* tau, const double* ld, const double* zsq,
                                  const int32_t* info, double* f, int32_t* info_out);
-__global__ void grad_kernel(const ModelDev M, const double* theta, const double* dphi,
+__global__ void grad_kernel(const Models Ms, const double* theta, const double* dphi,
                             const double* tau, const double* TD, const double* TB, long long zTr,
                             const double* O, long long zO, const double* qD, const double* qB,
                             long long zq, const double* resid, long long zr, const double* ld,
@@ -70,7 +83,7 @@ __global__ void stencil_kernel(const double* theta, int d, double h, double* Th)
 __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad);
 __global__ void hess_stencil_kernel(const double* theta, int d, double h, double* Th);
 constexpr int kWBatch = 8;  // columns of W_t per pass of w_from_gtg_kernel (at most)
-__global__ void w_from_gtg_kernel(const ModelDev M, int t, const double* Y, long long zY,
+__global__ void w_from_gtg_kernel(const Models Ms, int t, const double* Y, long long zY,
                                   double* W, long long zW, const double* phi, int cb);
 __global__ void fd_hessian_kernel(const double* fv, int d, double h, double* f, double* H);
 __global__ void grad_hessian_kernel(const double* fv, const double* gv, int d, double h,

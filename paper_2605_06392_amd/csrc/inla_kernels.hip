@@ -44,12 +44,13 @@ __device__ __forceinline__ double tmat(const ModelDev& M, int r, int t, int off)
 }  // namespace
 
 // ---- per-theta coefficients ------------------------------------------------------------------
-__global__ __launch_bounds__(256) void param_kernel(const ModelDev M, const double* theta,
+__global__ __launch_bounds__(256) void param_kernel(const Models Ms, const double* theta,
                                                     double* phi, double* dphi, double* tau) {
   __shared__ double Li[kMaxFields][kMaxFields];
   __shared__ double dLi[kMaxTheta][kMaxFields][kMaxFields];  // indexed by coupling slot
   __shared__ double k2s[kMaxFields], e3s[kMaxFields];
   const int p = blockIdx.x;
+  const ModelDev M = model_at(Ms, p);
   const int k = M.k, d = M.d;
   const double* th = theta + (long long)p * d;
   const int ncoup = k + k * (k - 1) / 2;
@@ -136,23 +137,28 @@ __global__ __launch_bounds__(256) void param_kernel(const ModelDev M, const doub
 // 64-lane workgroup per column q: the lanes zero the column (coalesced), then write the
 // base-matrix entries of the column in parallel (distinct rows), and lane 0 adds the
 // observation term tau_m a_o a_o^T for Qc chains (z even) in a fixed order.
-__global__ __launch_bounds__(64) void assemble_blocks_kernel(const ModelDev M, int td, int tb,
+__global__ __launch_bounds__(64) void assemble_blocks_kernel(const Models Ms, int td, int tb,
                                                              double* D, long long zD,
                                                              double* B, long long zB,
                                                              long long ldB, const double* phi,
                                                              const double* tau) {
   const int z = blockIdx.z;
   const int p = z >> 1;
+  const ModelDev M = model_at(Ms, p);
   const bool qc = (z & 1) == 0;
   const int b = M.b, ns = M.ns, k = M.k;
   const int q = blockIdx.x;
   const int lane = threadIdx.x;
+  // an instance of an uneven batch with fewer blocks: nothing past its last block, and the
+  // coupling block after it is zero (the sweep then treats that block as a last block)
+  if (td >= M.nt) td = -1;
   double* Dc = td >= 0 ? D + (long long)z * zD + (long long)q * b : nullptr;
   double* Bc = tb >= 0 ? B + (long long)z * zB + (long long)q * ldB : nullptr;
   for (int r = lane; r < b; r += 64) {
     if (Dc) Dc[r] = 0.0;
     if (Bc) Bc[r] = 0.0;
   }
+  if (tb >= M.nt - 1) Bc = nullptr;
   __syncthreads();
   const int i2 = q / ns, qq = q % ns;
   const int NE = 9 * k * k;
@@ -191,19 +197,22 @@ __global__ __launch_bounds__(64) void assemble_blocks_kernel(const ModelDev M, i
 
 // Arrow rows of every block: C_t = sum_o tau X_o^T a_o (rows 0..a-1) and the rhs row
 // r_t = sum_o tau y_o a_o (row a); zero for the prior chains.
-__global__ __launch_bounds__(256) void assemble_arrow_kernel(const ModelDev M, double* C,
-                                                             long long zC, int ap,
+__global__ __launch_bounds__(256) void assemble_arrow_kernel(const Models Ms, double* C,
+                                                             long long zC, long long nb, int ap,
                                                              const double* tau) {
   const int z = blockIdx.z;
   const int p = z >> 1;
+  const ModelDev M = model_at(Ms, p);
   const bool qc = (z & 1) == 0;
   const long long g = blockIdx.x * 256LL + threadIdx.x;
+  // nb: the columns of the layout (n * b of the largest instance of an uneven batch); the
+  // columns past this instance's blocks are zero
+  if (g >= nb) return;
   const long long total = (long long)M.nt * M.b;
-  if (g >= total) return;
   const int a = M.a;
   double acc[65];
   for (int c = 0; c < ap; ++c) acc[c] = 0.0;
-  if (qc) {
+  if (qc && g < total) {
     for (int j = M.colptr[g]; j < M.colptr[g + 1]; ++j) {
       const int o = M.col_o[j];
       const double tw = tau[(long long)p * M.k + M.obs_f[o]] * M.obs_w[4 * o + M.col_e[j]];
@@ -217,12 +226,13 @@ __global__ __launch_bounds__(256) void assemble_arrow_kernel(const ModelDev M, d
 }
 
 // Arrowhead tip entries (r >= c) of the ap x ap tip, one workgroup per entry.
-__global__ __launch_bounds__(256) void assemble_tip_kernel(const ModelDev M, double* T,
+__global__ __launch_bounds__(256) void assemble_tip_kernel(const Models Ms, double* T,
                                                            long long zT, int ap,
                                                            const double* tau) {
   __shared__ double red[256];
   const int z = blockIdx.z;
   const int p = z >> 1;
+  const ModelDev M = model_at(Ms, p);
   const bool qc = (z & 1) == 0;
   const int r = blockIdx.x % ap, c = blockIdx.x / ap;
   if (r < c) return;
@@ -248,7 +258,7 @@ __global__ __launch_bounds__(256) void assemble_tip_kernel(const ModelDev M, dou
 // rows (<Z^(i1,i2), base_s> restricted to the slice), then k fields x nch_obs slices of
 // kTraceObs observations (sum_o a_o^T Zhat a_o).  Every workgroup writes one partial sum per
 // quantity; grad_kernel adds the slices in order.
-__global__ __launch_bounds__(256) void trace_kernel(const ModelDev M, int j, const double* ZD,
+__global__ __launch_bounds__(256) void trace_kernel(const Models Ms, int j, const double* ZD,
                                                     long long zZD, const double* ZB,
                                                     long long zZB, const double* ZC,
                                                     long long zZC, const double* ZT,
@@ -256,9 +266,12 @@ __global__ __launch_bounds__(256) void trace_kernel(const ModelDev M, int j, con
                                                     double* O, long long zTr, long long zO) {
   __shared__ double red[256];
   const int z = blockIdx.z;
+  const ModelDev M = model_at(Ms, z >> 1);
   const int k = M.k, ns = M.ns, b = M.b, a = M.a;
   const int w = blockIdx.x;
   const int kk = k * k, nr = M.nch_rows;
+  // past the instance's blocks or observation slices (uneven batch): nothing to add
+  if (j >= M.nt || w >= 2 * kk * nr + k * M.nch_obs) return;
   if (w < 2 * kk * nr) {
     const bool isB = w >= kk * nr;
     const int pair = (w % (kk * nr)) / nr, ch = w % nr;
@@ -319,10 +332,12 @@ __global__ __launch_bounds__(256) void trace_kernel(const ModelDev M, int j, con
 }
 
 // ---- Phase B: quadratic forms of the mode (Eq. 8) and the data residual -----------------------
-__global__ __launch_bounds__(256) void phaseb_kernel(const ModelDev M, const double* x,
+__global__ __launch_bounds__(256) void phaseb_kernel(const Models Ms, const double* x,
                                                      long long zxp, double* qD, double* qB,
                                                      long long zq) {
   __shared__ double red[256];
+  const ModelDev M = model_at(Ms, blockIdx.z);
+  if ((int)blockIdx.x >= M.nt * M.k) return;  // past the instance's blocks (uneven batch)
   // grid.z: theta point (x of its Qc chain at x + z * zxp; outputs at z * zq)
   x += blockIdx.z * zxp;
   qD += blockIdx.z * zq;
@@ -363,16 +378,19 @@ __global__ __launch_bounds__(256) void phaseb_kernel(const ModelDev M, const dou
     }
 }
 
-__global__ __launch_bounds__(256) void resid_kernel(const ModelDev M, const double* x,
-                                                    long long zxp, double* resid, long long zr) {
+__global__ __launch_bounds__(256) void resid_kernel(const Models Ms, const double* x,
+                                                    long long zxp, int nlay, double* resid,
+                                                    long long zr) {
   __shared__ double red[256];
+  const ModelDev M = model_at(Ms, blockIdx.z);
+  if ((int)blockIdx.x >= M.k * M.nch_resid) return;  // past the instance's slices
   // grid.z: theta point (x of its Qc chain at x + z * zxp; partial sums at z * zr)
   x += blockIdx.z * zxp;
   resid += blockIdx.z * zr;
   // grid.x = k fields x nch_resid slices of kResidObs observations; one partial sum each
   const int m = blockIdx.x / M.nch_resid, ch = blockIdx.x % M.nch_resid;
   const int a = M.a, b = M.b, ns = M.ns;
-  const double* xT = x + (long long)M.nt * b;
+  const double* xT = x + (long long)nlay * b;  // x: nlay blocks (the layout's), then the tip
   double s = 0.0;
   const int oend = min(M.n_obs, (ch + 1) * kResidObs);
   for (int o = ch * kResidObs + threadIdx.x; o < oend; o += 256) {
@@ -402,11 +420,12 @@ __device__ double objective_value(const ModelDev& M, const double* th, const dou
 }
 
 // f for every theta point; chain 2p is Qc, 2p+1 is Qp.
-__global__ void objective_kernel(const ModelDev M, const double* theta, int batch,
+__global__ void objective_kernel(const Models Ms, const double* theta, int batch,
                                  const double* tau, const double* ld, const double* zsq,
                                  const int32_t* info, double* f, int32_t* info_out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= batch) return;
+  const ModelDev M = model_at(Ms, p);
   f[p] = objective_value(M, theta + (long long)p * M.d, tau + (long long)p * M.k, ld[2 * p],
                          ld[2 * p + 1], zsq[2 * p]);
   const int32_t ic = info[2 * p], ip = info[2 * p + 1];
@@ -416,7 +435,7 @@ __global__ void objective_kernel(const ModelDev M, const double* theta, int batc
 // Gradient assembly, one workgroup per theta point p (chains 2p = Qc, 2p + 1 = Qp).  Optionally
 // (one point) writes the decomposition terms = [f, log|Qp|, log|Qc|, |z|^2, tr(Z_T of Qc),
 // PhaseA(d), PhaseB(d), PhaseC(d), dlog l(d), dlog p(d), grad(d)].
-__global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const double* theta,
+__global__ __launch_bounds__(256) void grad_kernel(const Models Ms, const double* theta,
                                                    const double* dphi, const double* tau,
                                                    const double* TD, const double* TB,
                                                    long long zTr, const double* O, long long zO,
@@ -430,9 +449,10 @@ __global__ __launch_bounds__(256) void grad_kernel(const ModelDev M, const doubl
   __shared__ double SA[9 * kMaxFields * kMaxFields];
   __shared__ double SB[9 * kMaxFields * kMaxFields];
   __shared__ double SC[9 * kMaxFields * kMaxFields];
+  const int p = blockIdx.x;
+  const ModelDev M = model_at(Ms, p);
   const int k = M.k, kk = k * k, nt = M.nt, d = M.d;
   const int NE = 9 * kk;
-  const int p = blockIdx.x;
   theta += (long long)p * d;
   dphi += (long long)p * NE * d;
   tau += (long long)p * k;
@@ -572,14 +592,23 @@ __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* 
 // columns of Y (stored in full) are loaded into LDS, then each row of B_t, its pattern and
 // values read once per batch, is applied to all of them.  Bound by the pattern reads (b/cb
 // passes over B_t) and by reading Y and writing W once: 16 b^2 bytes per chain.
-__global__ __launch_bounds__(256) void w_from_gtg_kernel(const ModelDev M, int t, const double* Y,
+__global__ __launch_bounds__(256) void w_from_gtg_kernel(const Models Ms, int t, const double* Y,
                                                          long long zY, double* W, long long zW,
                                                          const double* phi, int cb) {
   extern __shared__ double ys[];  // cb columns of Y, b each
   __shared__ double cB[kMaxFields][kMaxFields][3];
   const int z = blockIdx.z, p = z >> 1;
+  const ModelDev M = model_at(Ms, p);
   const int b = M.b, ns = M.ns, k = M.k;
   const double* Yz = Y + (long long)z * zY;
+  if (t >= M.nt - 1) {
+    // no coupling block after the instance's last block (uneven batch): W_t = 0
+    double* Wz = W + (long long)z * zW;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < (long long)b * b;
+         e += (long long)gridDim.x * 256)
+      Wz[e] = 0.0;
+    return;
+  }
   if (threadIdx.x < k * k * 3) {
     const int s = threadIdx.x % 3, i2 = (threadIdx.x / 3) % k, i1 = threadIdx.x / (3 * k);
     const double* ph = phi + (long long)p * 9 * k * k;

@@ -46,6 +46,7 @@ struct Skinny {
   const double* B2; long long ldb2, zB2;
   double* C; long long ldc, zC;
   double alpha, beta;
+  const int32_t* zn; int step;  // chain z takes part only while step < zn[z] (zn may be null)
 };
 int launch_skinny(const Skinny& g, int nz, hipStream_t s);
 }  // namespace adelia

@@ -54,6 +54,7 @@ __global__ void zero_upper_kernel(double* p, int b, long long ld, long long bs, 
 //                                             + alpha2*sum_c A2(c,m) x2(c)
 __global__ __launch_bounds__(256) void gemv_t_kernel(const GemvT g) {
   const int z = blockIdx.z;
+  if (g.zn && g.step >= g.zn[z]) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = blockIdx.x * 4 + wave;
   if (m >= g.M) return;
@@ -171,6 +172,7 @@ inline unsigned grid_for(long long n) {
 // are combined by a fixed-order reduce-scatter butterfly that leaves sum i on lane i.
 __global__ __launch_bounds__(256) void skinny_kernel(const Skinny g) {
   const int z = blockIdx.z;
+  if (g.zn && g.step >= g.zn[z]) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = (blockIdx.x * 4 + wave) * kSkinnyCols;
   if (n0 >= g.N) return;

@@ -320,6 +320,105 @@ class BatchRunner:
         return self.f, self.g, self.info
 
 
+class InlaBatch:
+    """An uneven batch of models (``inla_batch_create``): ``objective(theta)`` and
+    ``grad(theta)`` evaluate every model at its own theta (row i of a count x d array) in one
+    call; models with the same block size share every launch of the sweeps.  ``capture(kind)``
+    records one call into a hipGraph whose ``replay`` re-evaluates at the points then held in
+    ``self.theta``.  The models must outlive the batch."""
+
+    def __init__(self, models):
+        self.models = list(models)
+        self.device = self.models[0].device
+        self.count = len(self.models)
+        self.d = self.models[0].d
+        arr = (C.c_void_p * self.count)(*[m._h.value for m in self.models])
+        h = C.c_void_p()
+        dev_index = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        check(lib().inla_batch_create(context(dev_index), self.count, arr, C.byref(h)),
+              "inla_batch_create")
+        self._h = h
+        self.groups = int(lib().inla_batch_groups(h))
+        self._ws = {}
+        dev = self.device
+        self.theta = torch.zeros((self.count, self.d), dtype=torch.float64, device=dev)
+        self.f = torch.empty(self.count, dtype=torch.float64, device=dev)
+        self.g = torch.empty((self.count, self.d), dtype=torch.float64, device=dev)
+        self.info = torch.empty(self.count, dtype=torch.int32, device=dev)
+        self._graphs = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().inla_batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def workspace_bytes(self, mode):
+        return int(lib().inla_batch_workspace_bytes(self._h, mode))
+
+    def _workspace(self, mode):
+        if mode not in self._ws:
+            nbytes = self.workspace_bytes(mode)
+            if nbytes == 0:
+                raise ValueError("invalid workspace request")
+            buf = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=self.device)
+            self._ws[mode] = (buf, nbytes)
+        buf, nbytes = self._ws[mode]
+        p = buf.data_ptr()
+        return C.c_void_p(p + ((-p) % 256)), nbytes
+
+    def _run(self, kind):
+        ws, nb = self._workspace(MODE_GRAD if kind == "grad" else MODE_OBJECTIVE)
+        stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if kind == "grad":
+            check(lib().inla_batch_grad(self._h, C.c_void_p(self.theta.data_ptr()),
+                                        C.c_void_p(self.f.data_ptr()), C.c_void_p(self.g.data_ptr()),
+                                        C.c_void_p(self.info.data_ptr()), ws, nb, stream),
+                  "inla_batch_grad")
+        else:
+            check(lib().inla_batch_objective(self._h, C.c_void_p(self.theta.data_ptr()),
+                                             C.c_void_p(self.f.data_ptr()),
+                                             C.c_void_p(self.info.data_ptr()), ws, nb, stream),
+                  "inla_batch_objective")
+
+    def _set(self, theta):
+        if theta is not None:
+            th = torch.as_tensor(theta, dtype=torch.float64, device=self.device)
+            self.theta.copy_(th.reshape(self.count, self.d))
+
+    def objective(self, theta=None):
+        """f of every model at its theta: (f, info), views of the batch's own buffers."""
+        self._set(theta)
+        self._run("objective")
+        return self.f, self.info
+
+    def grad(self, theta=None):
+        """f and the exact gradient of every model: (f, grad, info), the batch's own buffers."""
+        self._set(theta)
+        self._run("grad")
+        return self.f, self.g, self.info
+
+    def capture(self, kind):
+        """Record one call of `kind` ("objective" or "grad") into a hipGraph (once)."""
+        if kind not in self._graphs:
+            self._run(kind)  # workspaces are allocated outside the capture
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                self._run(kind)
+            self._graphs[kind] = graph
+        return self._graphs[kind]
+
+    def replay(self, kind, theta=None):
+        self._set(theta)
+        self.capture(kind).replay()
+        if kind == "grad":
+            return self.f, self.g, self.info
+        return self.f, self.info
+
+
 def fd_grad(model, theta, h=1e-3, max_batch=None):
     """The GPU's (2d+1)-point central-difference gradient (Sec. II-D, Eq. 2): (f, grad, info)."""
     return model.fd_grad(theta, h=h, max_batch=max_batch)

@@ -1,0 +1,132 @@
+"""GPU parity of the uneven INLA batch (inla_batch_*): models of different block size, number of
+time steps, fixed effects and observations, each at its own theta, evaluated in one call
+(instances of one block size share every launch) against the dense CPU oracle per model, at
+the tolerances of the single-model tests (f: rel 1e-10; gradient: rel 1e-8 in the inf-norm).
+
+Inputs: seeded synthetic univariate SPDE models (workloads.make_model) on grids 5x4 (b = 20),
+7x6 (b = 42) and 13x10 (b = 130: three 64-wide panels, ragged), with 1 to 6 time steps, 1 to 5
+fixed effects and b/4 observations per step -- the shape mix of the uneven-batch workload
+(block sizes, lengths and arrow widths drawn per instance) at sizes the oracle finishes in
+seconds.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import make_model
+
+pytestmark = pytest.mark.gpu
+
+# (nx, ny, nt, a, seed)
+SPECS = [(5, 4, 3, 2, 1), (13, 10, 4, 5, 2), (7, 6, 6, 1, 3), (5, 4, 1, 3, 4), (13, 10, 2, 2, 5),
+         (7, 6, 2, 4, 6), (5, 4, 5, 5, 7), (13, 10, 3, 3, 8)]
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+def rel_inf(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+_cache = {}
+
+
+def _batch(specs):
+    from paper_2605_06392_amd.inla import InlaBatch, InlaModel
+    key = tuple(specs)
+    if key not in _cache:
+        dev = _dev()
+        models = [make_model(1, nx, ny, nt, a, max(1, nx * ny // 4), seed)
+                  for (nx, ny, nt, a, seed) in specs]
+        gms = [InlaModel(m, device=dev) for m in models]
+        _cache[key] = (models, gms, InlaBatch(gms))
+    return _cache[key]
+
+
+def test_uneven_batch_objectives_match_oracle():
+    models, _, B = _batch(SPECS)
+    assert B.groups == 3
+    theta = np.stack([m.theta for m in models])
+    f, info = B.objective(theta)
+    torch.cuda.synchronize()
+    f = f.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    for i, m in enumerate(models):
+        ref = oracle.objective(m, m.theta)["f"]
+        assert abs(f[i] - ref) <= 1e-10 * abs(ref), (i, f[i], ref)
+
+
+def test_uneven_batch_gradients_match_oracle():
+    models, _, B = _batch(SPECS)
+    theta = np.stack([m.theta for m in models])
+    f, g, info = B.grad(theta)
+    torch.cuda.synchronize()
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    for i, m in enumerate(models):
+        ref = oracle.gradient(m, m.theta)
+        assert abs(f[i] - ref["f"]) <= 1e-10 * abs(ref["f"]), i
+        assert rel_inf(g[i], ref["grad"]) <= 1e-8, (i, g[i], ref["grad"])
+
+
+def test_uneven_batch_agrees_with_single_model_calls():
+    """Each instance's result equals its own single-model evaluation (the padding of the arrow
+    and the shorter chains change only the rounding)."""
+    models, gms, B = _batch(SPECS)
+    rng = np.random.default_rng(11)
+    theta = 0.5 * rng.standard_normal((len(models), 4))
+    f, g, _ = B.grad(theta)
+    torch.cuda.synchronize()
+    f, g = f.cpu().numpy().copy(), g.cpu().numpy().copy()
+    for i, gm in enumerate(gms):
+        f1, g1, _ = gm.grad(torch.tensor(theta[i]))
+        torch.cuda.synchronize()
+        assert abs(f[i] - f1.item()) <= 1e-12 * abs(f1.item())
+        assert rel_inf(g[i], g1.cpu().numpy()) <= 1e-10
+
+
+def test_uneven_batch_graph_replay_matches_eager():
+    models, _, B = _batch(SPECS)
+    rng = np.random.default_rng(5)
+    th1 = 0.5 * rng.standard_normal((len(models), 4))
+    th2 = 0.5 * rng.standard_normal((len(models), 4))
+    for kind in ("objective", "grad"):
+        B.capture(kind)
+        for th in (th1, th2, th1):
+            out = [t.cpu().numpy().copy() for t in B.replay(kind, th)]
+            torch.cuda.synchronize()
+            eager = [t.cpu().numpy().copy() for t in
+                     (B.objective(th) if kind == "objective" else B.grad(th))]
+            for a, b in zip(out, eager):
+                assert np.array_equal(a, b), kind
+        # and the replay at th2 is right, not just repeatable
+        B.replay(kind, th2)
+        torch.cuda.synchronize()
+        for i in (0, 1, len(models) - 1):
+            if kind == "objective":
+                ref = oracle.objective(models[i], th2[i])["f"]
+                assert abs(B.f[i].item() - ref) <= 1e-10 * abs(ref)
+            else:
+                ref = oracle.gradient(models[i], th2[i])
+                assert rel_inf(B.g[i].cpu().numpy(), ref["grad"]) <= 1e-8
+
+
+def test_large_uneven_batch_split_schedule_matches_oracle():
+    """Enough instances of one block size that a panel's workgroups outnumber the CUs (the split
+    panel schedule, and the look-ahead stream), with every instance of its own length."""
+    specs = [(7, 6, 1 + (s % 4), 1 + (s % 3), 100 + s) for s in range(80)]
+    models, _, B = _batch(specs)
+    theta = np.stack([m.theta for m in models])
+    f, g, info = B.grad(theta)
+    torch.cuda.synchronize()
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    for i in range(0, 80, 7):
+        ref = oracle.gradient(models[i], models[i].theta)
+        assert abs(f[i] - ref["f"]) <= 1e-10 * abs(ref["f"]), i
+        assert rel_inf(g[i], ref["grad"]) <= 1e-8, i
