@@ -290,6 +290,8 @@ def single_thread_oracle(k, nx, ny, nt, a, obs, seed, N_full, nt_sample=2):
 
 
 UNEVEN_COUNT = 64
+# block size -> grid of the uneven batch's instances (b = nx * ny)
+UNEVEN_GRIDS = {128: (16, 8), 256: (16, 16), 512: (32, 16), 1024: (32, 32)}
 
 
 def uneven_shapes(seed, count=UNEVEN_COUNT):
@@ -301,13 +303,128 @@ def uneven_shapes(seed, count=UNEVEN_COUNT):
 
 
 def bench_uneven(args, torch):
-    """Batched factorisation (with the fused lower solve) of an uneven batch of BTA matrices in
-    one call: every launch of the sweep covers all matrices of a block size at once."""
+    """An uneven batch of 64 INLA instances (block sizes 128..1024 on 16x8..32x32 grids, 8..64
+    time steps, 2..8 fixed effects, b/8 observations per step, each at its own theta drawn from
+    the seed): objectives and exact gradients of all of them per call (inla_batch_objective /
+    inla_batch_grad, instances of one block size sharing every launch), timed from graph
+    replays.  Beside it, the batched BTA factorisation of random matrices of the same shapes."""
+    import numpy as np
+    from paper_2605_06392_amd import bta, inla
+    from workloads import make_model
+
+    dev = torch.device("cuda:0")
+    shapes = uneven_shapes(args.seed)
+    specs, models = [], []
+    for i, (n, b, a) in enumerate(shapes):
+        nx, ny = UNEVEN_GRIDS[b]
+        spec = make_model(1, nx, ny, n, a, b // 8, args.seed * 1000 + i)
+        specs.append(spec)
+        models.append(inla.InlaModel(spec, device=dev))
+        if PROGRESS:
+            print(f"instance {i + 1}/{len(shapes)} created", file=sys.stderr, flush=True)
+    B = inla.InlaBatch(models)
+    theta = torch.tensor(np.stack([s.theta for s in specs]), dtype=torch.float64, device=dev)
+    B.theta.copy_(theta)
+    torch.cuda.reset_peak_memory_stats()
+
+    def replay_times(kind, steps, warmup):
+        B.capture(kind)
+        for _ in range(warmup):
+            B.replay(kind)
+            if PROGRESS:
+                torch.cuda.synchronize()
+                print(f"{kind}: warm-up replay done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        out = []
+        for t in range(steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            B.replay(kind)
+            e1.record()
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1))
+            if PROGRESS:
+                print(f"{kind}: replay {t + 1}/{steps} done", file=sys.stderr, flush=True)
+        return out
+
+    t_obj = replay_times("objective", args.steps, args.warmup)
+    f_obj = B.f.clone()
+    t_grad = replay_times("grad", args.steps, args.warmup)
+    torch.cuda.synchronize()
+    f_b, g_b, info_b = B.f.cpu().numpy(), B.g.cpu().numpy(), B.info.cpu().numpy()
+    infos_ok = bool((info_b == 0).all())
+    peak = torch.cuda.max_memory_allocated()
+    # consistency: instances evaluated one at a time (smallest, largest, and one of each block
+    # size) give the same f and gradient
+    pick = sorted(range(len(shapes)), key=lambda i: shapes[i][0] * shapes[i][1] ** 2)
+    check_idx = {pick[0], pick[-1]}
+    for bb in UNEVEN_GRIDS:
+        members = [i for i in range(len(shapes)) if shapes[i][1] == bb]
+        if members:
+            check_idx.add(members[0])
+    rel_f = rel_g = 0.0
+    for i in sorted(check_idx):
+        f1, g1, inf1 = models[i].grad(theta[i])
+        torch.cuda.synchronize()
+        rel_f = max(rel_f, abs(f1.item() - f_b[i]) / abs(f1.item()))
+        rel_g = max(rel_g, float(np.abs(g1.cpu().numpy() - g_b[i]).max() /
+                                 np.abs(g1.cpu().numpy()).max()))
+        infos_ok = infos_ok and int(inf1.item()) == 0
+    obj_vs_grad_f = float((f_obj.cpu().numpy() - f_b).__abs__().max() / np.abs(f_b).max())
+
+    # App. B work of the instances: forward per matrix, selected inversion per block
+    fwd_fl = sum(2 * ((n - 1) * 7.0 / 3.0 + 1.0 / 3.0) * b ** 3 for n, b, _ in shapes)
+    si_fl = sum(2 * (14.0 / 3.0) * n * b ** 3 for n, b, _ in shapes)
+    ms_obj = sum(t_obj) / len(t_obj)
+    ms_grad = sum(t_grad) / len(t_grad)
+    d = B.d
+    count = len(shapes)
+    line = {
+        "metric": "INLA gradients/s and objectives/s, uneven batch of instances in one call",
+        "value": count * 1000.0 / ms_grad,
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_grad,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uneven64", "count": count, "seed": args.seed, "d": d,
+                   "b_counts": {str(bb): sum(1 for _, b, _ in shapes if b == bb)
+                                for bb in UNEVEN_GRIDS},
+                   "n_range": [min(n for n, _, _ in shapes), max(n for n, _, _ in shapes)],
+                   "a_range": [min(a for _, _, a in shapes), max(a for _, _, a in shapes)],
+                   "obs_per_step": "b/8", "groups": B.groups, "graph": True},
+        "objectives_per_s": count * 1000.0 / ms_obj,
+        "ms_per_objective_batch": median_ci(t_obj),
+        "ms_per_gradient_batch": median_ci(t_grad),
+        "fd_gradients_per_s_from_objective_batches": count * 1000.0 / ((2 * d + 1) * ms_obj),
+        "ad_over_fd_speedup": (2 * d + 1) * ms_obj / ms_grad,
+        "tflops_paper_flop_model": {"objective": fwd_fl / (ms_obj * 1e-3) / 1e12,
+                                    "gradient": (fwd_fl + si_fl) / (ms_grad * 1e-3) / 1e12},
+        "check": {"info_ok": infos_ok, "instances_vs_single_model": sorted(check_idx),
+                  "f_rel_vs_single": rel_f, "grad_rel_vs_single": rel_g,
+                  "objective_vs_gradient_call_f_rel": obj_vs_grad_f},
+        "peak_device_memory_gb": peak / 1e9,
+    }
+    del B, models
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    line["bta_factor_batched"] = bench_uneven_factor(args, torch, shapes)
+    print(json.dumps(line), flush=True)
+
+
+def bench_uneven_factor(args, torch, shapes):
+    """Batched factorisation (with the fused lower solve) of random BTA matrices of the uneven
+    batch's shapes in one bta_factor_batched call."""
     from paper_2605_06392_amd import bta
     from workloads.bta import random_bta_device
 
     dev = torch.device("cuda:0")
-    shapes = uneven_shapes(args.seed)
     keys = ("D", "B", "C", "T")
     pristine, work = [], []
     for i, (n, b, a) in enumerate(shapes):
@@ -333,7 +450,7 @@ def bench_uneven(args, torch):
     torch.cuda.synchronize()
     per_call = []
     infos_ok = True
-    for _ in range(args.steps):
+    for _ in range(max(3, args.steps // 2)):
         restore()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -352,32 +469,9 @@ def bench_uneven(args, torch):
         rel = max(rel, abs(ld1.item() - logdet[i].item()) / abs(ld1.item()))
         infos_ok = infos_ok and int(inf1.item()) == 0
     mean = sum(per_call) / len(per_call)
-    line = {
-        "metric": "BTA factorisations/s, uneven batch in one call",
-        "value": len(shapes) * 1000.0 / mean,
-        "unit": "matrices/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": mean,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "uneven64", "count": len(shapes), "seed": args.seed,
-                   "b_counts": {str(bb): sum(1 for _, b, _ in shapes if b == bb)
-                                for bb in (128, 256, 512, 1024)},
-                   "n_range": [min(n for n, _, _ in shapes), max(n for n, _, _ in shapes)],
-                   "a_range": [min(a for _, _, a in shapes), max(a for _, _, a in shapes)],
-                   "rhs": True},
-        "ms_per_call": median_ci(per_call),
-        "tflops_paper_flop_model": flops / (mean * 1e-3) / 1e12,
-        "algorithmic_flops_per_call": flops,
-        "check": {"info_ok": infos_ok, "logdet_vs_single_rel": rel},
-        "peak_device_memory_gb": torch.cuda.max_memory_allocated() / 1e9,
-    }
-    print(json.dumps(line), flush=True)
+    return {"matrices_per_s": len(shapes) * 1000.0 / mean, "ms_per_call": median_ci(per_call),
+            "tflops_paper_flop_model": flops / (mean * 1e-3) / 1e12,
+            "check": {"info_ok": infos_ok, "logdet_vs_single_rel": rel}}
 
 
 def bench_hessian(args, model, theta, spec, torch, np):
