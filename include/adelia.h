@@ -353,6 +353,39 @@ int inla_batch_grad(inla_batch batch, const double* theta, double* f, double* gr
                     int32_t* info, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * GEMM tile shapes and the autotuner (the tile choice per block size of the batched
+ * evaluation).  Every dense product of the sweeps runs on 64 x 64 or 32 x 32 output tiles per
+ * 256-thread workgroup; which one is kept in a process-wide table keyed by (block size b,
+ * role), read when a launch is enqueued (a captured graph keeps the choices of its capture).
+ * Roles (the profiler's GEMM groups): 1 trailing update, 2 block inversion, 4 Schur update,
+ * 5 selected inversion V = L_C G, 6 Z_B, 7 Z_D.  Role 3, the panel rows of the split schedule, is
+ * formed in place and always takes 64 x 64 tiles (each tile must hold all columns of its rows).
+ * Entries not set take 64.  A context created while $ADELIA_TUNE_CACHE names a readable JSON file
+ * ({"tiles": [{"b": 128, "role": "schur_update", "tile": 32}, ...]}) loads it; the autotuners
+ * write the table back to that file.
+ *   adelia_tune_set: -1 bad b, -2 bad role, -3 tile not 32 or 64.  adelia_tune_get: the tile
+ *   (0 for invalid arguments).  adelia_tune_save / _load: 0 / entries read; ADELIA_E_UNSUPPORTED
+ *   if the file cannot be written or read, ADELIA_E_SHAPE for a malformed file (nothing loaded).
+ *   inla_autotune: for the model's block size, each role in turn tries both tiles with the
+ *   others as chosen so far, timing `reps` runs of a batched objective (mode
+ *   ADELIA_MODE_OBJECTIVE) or gradient (ADELIA_MODE_GRAD) evaluation at the `batch` <= 2d + 1
+ *   points theta (device, batch x d), and keeps a tile only for a gain of more than 2%.
+ *   Workspace: inla_workspace_bytes(model, batch, mode).  *changed (host): roles whose choice
+ *   changed.  Synchronises the stream (set-up time; ADELIA_E_UNSUPPORTED while capturing).
+ *   inla_batch_autotune: the same for every block-size group of an uneven batch, timing that
+ *   group's part of inla_batch_objective / inla_batch_grad at theta (device, count x d).
+ * --------------------------------------------------------------------------------------- */
+int adelia_tune_set(int b, int role, int tile);
+int adelia_tune_get(int b, int role);
+int adelia_tune_clear(void);
+int adelia_tune_save(const char* path);
+int adelia_tune_load(const char* path);
+int inla_autotune(inla_model model, const double* theta, int32_t batch, int mode, int reps,
+                  void* ws, size_t ws_bytes, void* stream, int32_t* changed);
+int inla_batch_autotune(inla_batch batch, const double* theta, int mode, int reps, void* ws,
+                        size_t ws_bytes, void* stream, int32_t* changed);
+
+/* ---------------------------------------------------------------------------------------
  * Opt-in kernel timing for measurement runs.  Between adelia_profile_start and
  * adelia_profile_stop every launch of the library's main kernels is bracketed by two HIP events
  * recorded on the launch's own stream (this inserts small gaps between launches, so time

@@ -80,6 +80,13 @@ SIGNATURES = {
     "inla_batch_workspace_bytes": (c_size_t, [vp, c_int]),
     "inla_batch_objective": (c_int, [vp, vp, vp, vp, vp, c_size_t, vp]),
     "inla_batch_grad": (c_int, [vp, vp, vp, vp, vp, vp, c_size_t, vp]),
+    "adelia_tune_set": (c_int, [c_int, c_int, c_int]),
+    "adelia_tune_get": (c_int, [c_int, c_int]),
+    "adelia_tune_clear": (c_int, []),
+    "adelia_tune_save": (c_int, [C.c_char_p]),
+    "adelia_tune_load": (c_int, [C.c_char_p]),
+    "inla_autotune": (c_int, [vp, vp, c_int32, c_int, c_int, vp, c_size_t, vp, C.POINTER(c_int32)]),
+    "inla_batch_autotune": (c_int, [vp, vp, c_int, c_int, vp, c_size_t, vp, C.POINTER(c_int32)]),
     "adelia_profile_start": (c_int, [vp, c_int]),
     "adelia_profile_stop": (c_int, [vp, C.POINTER(KernelStats), c_int, C.POINTER(c_int)]),
 }

@@ -249,6 +249,8 @@ int adelia_create(adelia_ctx* ctx, int device) {
   // the device address of bta_factor_noalloc's static scratch, taken here with the device
   // current (null if the query fails: that entry point then returns ADELIA_E_HIP)
   c->noalloc_scratch = scratch_address(device);
+  // a GEMM tile table cached by an earlier autotuning run
+  tune_load_env();
   bool ok = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&c->la.ts, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;

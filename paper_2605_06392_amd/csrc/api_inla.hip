@@ -652,14 +652,17 @@ size_t batch_ws_bytes(const inla_batch_s* B, bool grad) {
   return batch_front(B->count, B->d, nullptr).bytes + most;
 }
 
+// Groups [g0, g1) of the batch (all: g1 < 0).  f == nullptr: results stay in the workspace
+// (timing runs of the autotuner); with_grad selects gradients.
 int batch_eval(inla_batch_s* B, const double* theta, double* f, double* grad, int32_t* info,
-               void* ws, hipStream_t s) {
-  const bool with_grad = grad != nullptr;
+               void* ws, hipStream_t s, bool with_grad, int g0 = 0, int g1 = -1) {
   char* base = reinterpret_cast<char*>(ws);
   const BatchFront fr = batch_front(B->count, B->d, base);
   const SideRes* side = B->has_side ? &B->side : nullptr;
   const int d = B->d;
-  for (const BatchGroup& g : B->groups) {
+  if (g1 < 0) g1 = (int)B->groups.size();
+  for (int gi = g0; gi < g1; ++gi) {
+    const BatchGroup& g = B->groups[gi];
     const int ng = (int)g.members.size();
     InlaWs w = layout(g.Mh, ng, with_grad, base + fr.bytes);
     hipLaunchKernelGGL(gather_rows_kernel, dim3((ng * d + 255) / 256), dim3(256), 0, s, theta, d,
@@ -685,11 +688,69 @@ int batch_eval(inla_batch_s* B, const double* theta, double* f, double* grad, in
       if (!r) r = run_backward(E, w, fr.Th, fr.fv, fr.gv, fr.finfo, nullptr, s, side);
     }
     if (r) return r;
+    if (!f) continue;
     hipLaunchKernelGGL(scatter_results_kernel, dim3((ng * d + 255) / 256), dim3(256), 0, s, fr.fv,
                        fr.gv, fr.finfo, ng, d, g.idx, f, grad, info);
     if (!LAUNCH_OK()) return ADELIA_E_HIP;
   }
   return 0;
+}
+
+// The roles whose tile edge the autotuners choose (the update part of a fused look-ahead step
+// always takes 64 x 64 tiles).
+// The panel-rows product of the split schedule, formed in place, keeps 64 x 64 tiles.
+constexpr int kTunedRoles[] = {GT_TRAIL, GT_TRTRI, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D};
+
+// Coordinate search over the roles at block size b: each role in turn tries 64 and 32 with the
+// other roles as chosen so far, timing `reps` runs of eval() (after one untimed run) with events
+// on s; a role switches only for a gain of more than 2%.  Returns 0 or ADELIA_E_HIP; *changed
+// counts the roles whose choice differs from before.
+template <class F>
+int tune_block_size(int b, F&& eval, int reps, hipStream_t s, int* changed) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return ADELIA_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return ADELIA_E_HIP;
+  }
+  auto run_ms = [&](float& ms) -> int {
+    if (eval()) return ADELIA_E_HIP;
+    std::vector<float> t;
+    for (int r = 0; r < reps; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess || eval() || hipEventRecord(e1, s) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess)
+        return ADELIA_E_HIP;
+      float v = 0.f;
+      if (hipEventElapsedTime(&v, e0, e1) != hipSuccess) return ADELIA_E_HIP;
+      t.push_back(v);
+    }
+    std::sort(t.begin(), t.end());
+    ms = t[t.size() / 2];
+    return 0;
+  };
+  int err = 0;
+  for (int role : kTunedRoles) {
+    const int before = tuned_tile(b, role);
+    int best = before;
+    float best_ms = 0.f;
+    if ((err = run_ms(best_ms))) break;
+    for (int tile : {64, 32}) {
+      if (tile == before) continue;
+      set_tuned_tile(b, role, tile);
+      float ms = 0.f;
+      if ((err = run_ms(ms))) break;
+      if (ms < 0.98f * best_ms) {
+        best = tile;
+        best_ms = ms;
+      }
+    }
+    set_tuned_tile(b, role, best);
+    if (err) break;
+    if (best != before) ++*changed;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return err;
 }
 
 long long batch_launches(const inla_batch_s* B, bool grad) {
@@ -1280,7 +1341,7 @@ int inla_batch_objective(inla_batch B, const double* theta, double* f, int32_t* 
   if (ws_bytes < batch_ws_bytes(B, false)) return ADELIA_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (int r = capture_guard(s, batch_launches(B, false))) return r;
-  return batch_eval(B, theta, f, nullptr, info, ws, s);
+  return batch_eval(B, theta, f, nullptr, info, ws, s, false);
 }
 
 int inla_batch_grad(inla_batch B, const double* theta, double* f, double* grad, int32_t* info,
@@ -1294,7 +1355,69 @@ int inla_batch_grad(inla_batch B, const double* theta, double* f, double* grad, 
   if (ws_bytes < batch_ws_bytes(B, true)) return ADELIA_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (int r = capture_guard(s, batch_launches(B, true))) return r;
-  return batch_eval(B, theta, f, grad, info, ws, s);
+  return batch_eval(B, theta, f, grad, info, ws, s, true);
+}
+
+int inla_autotune(inla_model m, const double* theta, int32_t batch, int mode, int reps, void* ws,
+                  size_t ws_bytes, void* stream, int32_t* changed) {
+  if (!m) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  const int d = m->M.d;
+  if (batch < 1 || batch > 2 * d + 1) return -3;
+  if (mode != ADELIA_MODE_OBJECTIVE && mode != ADELIA_MODE_GRAD) return -4;
+  if (reps < 1 || reps > 100) return -5;
+  if (!ws || !aligned(ws, 256)) return -6;
+  if (!changed) return -9;
+  const bool grad = mode == ADELIA_MODE_GRAD;
+  InlaWs w = layout(m->M, batch, grad, reinterpret_cast<char*>(ws));
+  if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone)
+    return ADELIA_E_UNSUPPORTED;  // it synchronises: set-up time only
+  if (m->saved_ws == ws) m->saved_ws = nullptr;
+  const SideRes* side = m->has_side ? &m->side : nullptr;
+  // the results land in the workspace's stencil scratch (room for 2d + 1 points)
+  auto eval = [&]() -> int {
+    if (!grad) return run_objective(eval_of(m), w, theta, w.fv, w.finfo, s, side);
+    int r = run_forward(eval_of(m), w, theta, s, side);
+    return r ? r : run_backward(eval_of(m), w, theta, w.fv, w.gv, w.finfo, nullptr, s, side);
+  };
+  *changed = 0;
+  int c = 0;
+  const int r = tune_block_size(m->M.b, eval, reps, s, &c);
+  *changed = c;
+  if (r) return r;
+  tune_save_env();
+  return 0;
+}
+
+int inla_batch_autotune(inla_batch B, const double* theta, int mode, int reps, void* ws,
+                        size_t ws_bytes, void* stream, int32_t* changed) {
+  if (!B) return -1;
+  if (!theta || !aligned(theta, 8)) return -2;
+  if (mode != ADELIA_MODE_OBJECTIVE && mode != ADELIA_MODE_GRAD) return -3;
+  if (reps < 1 || reps > 100) return -4;
+  if (!ws || !aligned(ws, 256)) return -5;
+  if (!changed) return -8;
+  const bool grad = mode == ADELIA_MODE_GRAD;
+  if (ws_bytes < batch_ws_bytes(B, grad)) return ADELIA_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone)
+    return ADELIA_E_UNSUPPORTED;
+  *changed = 0;
+  int c = 0;
+  for (int gi = 0; gi < (int)B->groups.size(); ++gi) {
+    auto eval = [&]() -> int {
+      return batch_eval(B, theta, nullptr, nullptr, nullptr, ws, s, grad, gi, gi + 1);
+    };
+    const int r = tune_block_size(B->groups[gi].Mh.b, eval, reps, s, &c);
+    *changed = c;
+    if (r) return r;
+  }
+  tune_save_env();
+  return 0;
 }
 
 }  // extern "C"

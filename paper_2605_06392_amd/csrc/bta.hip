@@ -70,6 +70,7 @@ int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
+      g.blk = c.b;
       g.maxwg = c.inv_maxwg;
       g.zn = c.zn;
       g.step = i;
@@ -92,6 +93,7 @@ int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
+      g.blk = c.b;
       g.maxwg = c.inv_maxwg;
       g.zn = c.zn;
       g.step = i;
@@ -139,6 +141,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     g.beta = 1.0;
     g.omode = OUT_LOWER;  // lower for the block's own rows, every column of the rows below
     g.tag = GT_TRAIL;
+    g.blk = c.b;
     g.zn = c.zn;
     g.step = i;
     return g;
@@ -194,6 +197,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_PROWS;
+    g.blk = c.b;
     g.zn = c.zn;
     g.step = i;
     return launch_gemm(g, 1, nz, s);
@@ -266,6 +270,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     }
     g.M = g.N = g.Mlast = g.Nlast = mT;
     g.tag = GT_SYRK;
+    g.blk = c.b;
     g.zn = c.zn;
     g.step = i;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
@@ -347,6 +352,7 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_SI_W;
+    g.blk = c.b;
     g.maxwg = c.prep_maxwg;
     g.zn = c.zn;
     g.step = j;
@@ -368,6 +374,7 @@ int selinv_prepare(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = c.w_external ? OUT_LOWER_MIRROR : OUT_LOWER;  // W_j reads its full columns
     g.tag = GT_SI_D;
+    g.blk = c.b;
     g.maxwg = c.prep_maxwg;
     g.zn = c.zn;
     g.step = j;
@@ -406,6 +413,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_SI_Z;
+    g.blk = c.b;
     g.maxwg = c.fin_maxwg;
     g.zn = c.zn;
     g.step = j;
@@ -436,6 +444,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 0.0;
     g.omode = OUT_ALL;
     g.tag = GT_SI_Z;
+    g.blk = c.b;
     g.maxwg = c.fin_maxwg;
     g.zn = c.zn;
     g.step = j;
@@ -462,6 +471,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.beta = 1.0;
     g.omode = OUT_LOWER_MIRROR;
     g.tag = GT_SI_D;
+    g.blk = c.b;
     g.maxwg = c.fin_maxwg;
     g.zn = c.zn;
     g.step = j;

@@ -4,6 +4,9 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <array>
+#include <vector>
+
 #define ADELIA_CHECK_HIP(expr)                                  \
   do {                                                          \
     hipError_t e_ = (expr);                                     \
@@ -67,7 +70,8 @@ struct GemmArgs {
   int M, N, Mlast, Nlast;
   double beta;
   int omode;
-  int tag;  // role of the launch, for the opt-in profiler (GemmTag)
+  int tag;  // role of the launch, for the opt-in profiler (GemmTag) and the tile table
+  int blk;  // block size of the sweep it belongs to (0: none): with tag, the tile table's key
   // Uneven batches: chain z takes part only while step < zn[z] (zn == nullptr: always).
   const int32_t* zn;
   int step;
@@ -84,6 +88,12 @@ View view_rowsplit(double* p0, long long ld0, long long zs0, double* p1, long lo
                    long long zs1, int rsplit, bool trans = false);
 void view_set_y(View& v, long long ystride);
 int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s);
+// Tile edge (64 or 32) of the launches of role `tag` in sweeps of block size blk: the table the
+// autotuner fills (process-wide, read when a launch is enqueued; 64 without an entry).
+int tuned_tile(int blk, int tag);
+void set_tuned_tile(int blk, int tag, int tile);
+std::vector<std::array<int, 3>> tuned_tiles();  // entries (blk, tag, tile) other than 64
+void clear_tuned_tiles();
 double gemm_flops(const GemmArgs& a, int ny);  // algorithmic flops of one chain
 
 // ---- small kernels (util.hip) -------------------------------------------------------------

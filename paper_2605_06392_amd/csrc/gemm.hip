@@ -3,6 +3,11 @@
 #include "common.h"
 #include "gemm_dev.h"
 #include "profile.h"
+
+#include <array>
+#include <map>
+#include <mutex>
+#include <vector>
 #include <climits>
 #include <cmath>
 #include <algorithm>
@@ -14,27 +19,94 @@ using namespace gemm_dev;
 namespace {
 
 // LOOP: a capped grid (GemmArgs::maxwg) whose workgroups walk the tiles.
-template <bool LOOP>
+template <bool LOOP, class T>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemm_f64_kernel(const GemmArgs args) {
-  __shared__ double As[2][BK][LDS_ROW];
-  __shared__ double Bs[2][BK][LDS_ROW];
+  __shared__ double As[2][BK][T::LDS_ROW];
+  __shared__ double Bs[2][BK][T::LDS_ROW];
   const int z = blockIdx.z, y = blockIdx.y;
   if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
   const bool lasty = (y == (int)gridDim.y - 1);
-  gemm_walk<LOOP>(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
+  gemm_walk<LOOP, T>(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
 }
 
 // Capped one-phase launches: two tiles per 512-thread workgroup (gemm_walk_dual).
+template <class T>
 __global__ __launch_bounds__(2 * NT) void gemm_f64_dual_kernel(const GemmArgs args) {
-  __shared__ double As[2][2][BK][LDS_ROW];
-  __shared__ double Bs[2][2][BK][LDS_ROW];
+  __shared__ double As[2][2][BK][T::LDS_ROW];
+  __shared__ double Bs[2][2][BK][T::LDS_ROW];
   const int z = blockIdx.z, y = blockIdx.y;
   if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
   const bool lasty = (y == (int)gridDim.y - 1);
-  gemm_walk_dual(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
+  gemm_walk_dual<T>(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
+}
+
+// Tile edge per (block size, role), set by the autotuner (autotune.hip) or a cache file; a
+// launch without an entry (or with blk == 0) takes 64.
+std::mutex g_tile_mu;
+std::map<std::pair<int, int>, int> g_tile;
+
+template <class T>
+int launch_gemm_t(const GemmArgs& a, int ny, int nz, hipStream_t s) {
+  const int tM = (a.M + T::BM - 1) / T::BM, tN = (a.N + T::BN - 1) / T::BN;
+  long long gx;
+  if (a.omode == OUT_ALL) {
+    gx = (long long)tM * tN;
+  } else {
+    // lower part of an M x N output with M >= N (a trapezoid when M > N)
+    if (a.M < a.N || a.Mlast < a.Nlast) return -1;
+    if ((a.Mlast + T::BM - 1) / T::BM > tM || (a.Nlast + T::BN - 1) / T::BN > tN) return -1;
+    gx = (long long)tN * (tN + 1) / 2 + (long long)(tM - tN) * tN;
+  }
+  if (gx <= 0) return 0;
+  if (gx > INT_MAX) return -1;
+  // the cap counts 64 x 64 tile slots; smaller tiles get proportionally more workgroups
+  const long long cap = a.maxwg > 0 ? (long long)a.maxwg * (64 / T::BM) * (64 / T::BN) : 0;
+  const bool capped = cap > 0 && gx > cap;
+  if (capped) gx = cap < 8 ? 8 : (cap & ~7LL);
+  if (gx > INT_MAX) return -1;
+  // a capped one-phase launch takes two tiles per workgroup: maxwg tile slots on maxwg / 2 CUs
+  const bool dual = capped && a.nph == 1 && gx >= 16;
+  const ProfToken t = prof_begin(s);
+  if (dual)
+    hipLaunchKernelGGL(gemm_f64_dual_kernel<T>, dim3((unsigned)(gx / 16 * 8), ny, nz),
+                       dim3(2 * NT), 0, s, a);
+  else if (capped)
+    hipLaunchKernelGGL((gemm_f64_kernel<true, T>), dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<false, T>), dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
+  if (t.valid) prof_end_role(t, s, PK_GEMM, (a.tag >= 0 && a.tag < GT_COUNT) ? a.tag : 0,
+                            gemm_flops(a, ny) * nz, 0.0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
+
+int tuned_tile(int blk, int tag) {
+  if (blk <= 0) return 64;
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  auto it = g_tile.find({blk, tag});
+  return it == g_tile.end() ? 64 : it->second;
+}
+
+void set_tuned_tile(int blk, int tag, int tile) {
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  if (tile == 64)
+    g_tile.erase({blk, tag});
+  else
+    g_tile[{blk, tag}] = tile;
+}
+
+std::vector<std::array<int, 3>> tuned_tiles() {
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  std::vector<std::array<int, 3>> out;
+  for (const auto& kv : g_tile) out.push_back({kv.first.first, kv.first.second, kv.second});
+  return out;
+}
+
+void clear_tuned_tiles() {
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  g_tile.clear();
+}
 
 
 // Algorithmic flops of one phase: 2 x the number of (m, n, k) products the mathematics needs,
@@ -110,33 +182,11 @@ int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || ny <= 0 || nz <= 0) return 0;
   if (a.nph < 1 || a.nph > 2) return -1;
   if (ny > 65535 || nz > 65535) return -1;
-  const int tM = (a.M + BM - 1) / BM, tN = (a.N + BN - 1) / BN;
-  long long gx;
-  if (a.omode == OUT_ALL) {
-    gx = (long long)tM * tN;
-  } else {
-    // lower part of an M x N output with M >= N (a trapezoid when M > N)
-    if (a.M < a.N || a.Mlast < a.Nlast) return -1;
-    if ((a.Mlast + BM - 1) / BM > tM || (a.Nlast + BN - 1) / BN > tN) return -1;
-    gx = (long long)tN * (tN + 1) / 2 + (long long)(tM - tN) * tN;
-  }
-  if (gx <= 0) return 0;
-  if (gx > INT_MAX) return -1;
-  const bool capped = a.maxwg > 0 && gx > a.maxwg;
-  if (capped) gx = a.maxwg < 8 ? 8 : (a.maxwg & ~7);
-  // a capped one-phase launch takes two tiles per workgroup: maxwg tile slots on maxwg / 2 CUs
-  const bool dual = capped && a.nph == 1 && gx >= 16;
-  const ProfToken t = prof_begin(s);
-  if (dual)
-    hipLaunchKernelGGL(gemm_f64_dual_kernel, dim3((unsigned)(gx / 16 * 8), ny, nz), dim3(2 * NT), 0,
-                       s, a);
-  else if (capped)
-    hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
-  else
-    hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
-  if (t.valid) prof_end_role(t, s, PK_GEMM, (a.tag >= 0 && a.tag < GT_COUNT) ? a.tag : 0,
-                            gemm_flops(a, ny) * nz, 0.0);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  // the panel-rows product is formed in place: each tile must cover all columns of its rows
+  // (N <= 64), which only the 64 x 64 tile does, so that no tile overwrites columns that another
+  // tile of the same rows still reads
+  if (a.tag != GT_PROWS && tuned_tile(a.blk, a.tag) == 32) return launch_gemm_t<Tile32>(a, ny, nz, s);
+  return launch_gemm_t<Tile64>(a, ny, nz, s);
 }
 
 }  // namespace adelia

@@ -5,9 +5,10 @@
 // (common.h), which lets one kernel read the block-plus-arrow operands of the BTA sweeps
 // ([L_B; L_C], the augmented inverse [[Z_D, Z_C^T]; [Z_C, Z_T]]) without copies.
 //
-// Tiling: a 256-thread workgroup owns a 64 x 64 tile of C; each of its four wavefronts owns
-// a 32 x 32 quarter as 2 x 2 fragments of v_mfma_f64_16x16x4.  K advances 32 at a time
-// through LDS with the next tile prefetched into registers.  On this instruction lane l holds
+// Tiling: a 256-thread workgroup owns a BM x BN tile of C (64 x 64, or 32 x 32 for products
+// with few tiles, chosen per block size and role by the autotuner); each of its four
+// wavefronts owns a quarter as (BM/32) x (BN/32) fragments of v_mfma_f64_16x16x4.  K advances
+// 32 at a time through LDS with the next tile prefetched into registers.  On this instruction lane l holds
 // A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4v][l%16] (v = 0..3); the kernel feeds the
 // B-fragment as the instruction's A operand so that each lane's results lie along a column of
 // C and 16 consecutive lanes write 16 consecutive doubles.
@@ -19,15 +20,27 @@
 namespace adelia {
 namespace gemm_dev {
 
-constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int BK = 32;
 // Four wavefronts per tile (eight, with half the MFMAs per wave and K step, measured slower):
-// wave w owns rows (w % 2) * 32 .. + 32 and columns (w / 2) * WN .. + WN, as 2 x FJ fragments.
+// wave w owns rows (w % 2) * WM .. + WM and columns (w / 2) * WN .. + WN, as FI x FJ fragments.
 constexpr int NT = 256;
-constexpr int NW = NT / 64;
-constexpr int WN = BN / (NW / 2);
-constexpr int FJ = WN / 16;
-constexpr int NR = BM * BK / NT;  // staging registers per thread per operand tile
-constexpr int LDS_ROW = BM + 1;  // odd pitch (doubles): K-contiguous tiles store without bank conflicts
+
+// A square tile shape.  Square, so that the lower-triangular output modes enumerate whole
+// tiles of the triangle the same way for every shape.
+template <int TILE>
+struct Tile {
+  static_assert(TILE == 32 || TILE == 64, "tile edge");
+  static constexpr int BM = TILE, BN = TILE;
+  static constexpr int WM = BM / 2, WN = BN / 2;
+  static constexpr int FI = WM / 16, FJ = WN / 16;
+  static constexpr int NR = BM * BK / NT;  // staging registers per thread per operand tile
+  static constexpr int LDS_ROW = BM + 1;  // odd pitch (doubles): K-contiguous tiles store without bank conflicts
+};
+using Tile64 = Tile<64>;
+using Tile32 = Tile<32>;
+// the panel step kernel's update part and the LDS budget of its union use the 64 x 64 tile
+constexpr int LDS_ROW = Tile64::LDS_ROW;
+constexpr int BM = Tile64::BM, BN = Tile64::BN;
 
 // A view with the chain (z) and sub-problem (y) offsets applied: four quadrant bases and
 // strides, formed once per workgroup from the uniform kernel arguments.
@@ -102,20 +115,22 @@ __device__ __forceinline__ bool tri_zero(int tri, int r, int c) {
 // quadrant boundary take the generic path (per-element addresses clamped into the operand).
 typedef const double __attribute__((address_space(1)))* gptr;
 
+template <class T>
 struct OpPipe {
   __amdgpu_buffer_rsrc_t rsrc;
   int q;            // quadrant of the current stretch (-1: none yet)
   int mode;         // 0: lanes along M/N, 1: lanes along K
   int kseg;         // K of the stretch's first tile
   long long sK;     // element stride along K inside the quadrant
-  unsigned voff[NR];
-  double v[NR];
+  unsigned voff[T::NR];
+  double v[T::NR];
 };
 
 // (row, col) of register j of a tile; rows run along M (or N), cols along K.
+template <class T>
 __device__ __forceinline__ void tile_pos(int mode, int j, int& r, int& c) {
   const int tid = threadIdx.x & (NT - 1);  // thread within the tile's wavefronts
-  const int r0 = tid & 63, c0 = (tid >> 6) + (NT / 64) * j;
+  const int r0 = tid & (T::BM - 1), c0 = tid / T::BM + (NT / T::BM) * j;
   const int r1 = (tid >> 5) + (NT / 32) * j, c1 = tid & 31;
   r = mode ? r1 : r0;
   c = mode ? c1 : c0;
@@ -123,8 +138,9 @@ __device__ __forceinline__ void tile_pos(int mode, int j, int& r, int& c) {
 
 // Quadrant holding the whole tile (tile rows [r0, r0+BM) clipped to R, K range [k0, k0+BK)
 // clipped to Kn), or -1 when it straddles a split.  colsfirst: the view's first index is K.
+template <class T>
 __device__ __forceinline__ int tile_quad(const VP& V, int R, int Kn, int r0, int k0, bool colsfirst) {
-  const int r1 = min(r0 + BM, R) - 1, k1 = min(k0 + BK, Kn) - 1;
+  const int r1 = min(r0 + T::BM, R) - 1, k1 = min(k0 + BK, Kn) - 1;
   const int vr0 = colsfirst ? k0 : r0, vr1 = colsfirst ? k1 : r1;
   const int vc0 = colsfirst ? r0 : k0, vc1 = colsfirst ? r1 : k1;
   const bool rb0 = vr0 >= V.rs, rb1 = vr1 >= V.rs, cb0 = vc0 >= V.cs, cb1 = vc1 >= V.cs;
@@ -133,9 +149,11 @@ __device__ __forceinline__ int tile_quad(const VP& V, int R, int Kn, int r0, int
 }
 
 // Issue the loads of tile (r0, k0).  Nothing reads the loaded registers before store_tile.
-__device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn, int r0, int k0,
+template <class T>
+__device__ __forceinline__ void load_tile(OpPipe<T>& P, const VP& V, int R, int Kn, int r0, int k0,
                                           bool colsfirst) {
-  const int q = tile_quad(V, R, Kn, r0, k0, colsfirst);
+  constexpr int NR = T::NR;
+  const int q = tile_quad<T>(V, R, Kn, r0, k0, colsfirst);
   if (q >= 0) {
     if (q != P.q) {  // a new stretch: descriptor and per-lane offsets
       QuadSel s = pick(V, q);
@@ -154,7 +172,7 @@ __device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn,
 #pragma unroll
       for (int j = 0; j < NR; ++j) {
         int r, c;
-        tile_pos(P.mode, j, r, c);
+        tile_pos<T>(P.mode, j, r, c);
         P.voff[j] = (unsigned)(8 * ((long long)(tr + r) * sR + (long long)(tk + c) * P.sK));
       }
       P.q = q;
@@ -174,7 +192,7 @@ __device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn,
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     int r, c;
-    tile_pos(0, j, r, c);
+    tile_pos<T>(0, j, r, c);
     const int gr = min(r0 + r, R - 1), gc = min(k0 + c, Kn - 1);
     ptr[j] = (gptr)(colsfirst ? elem_ptr(V, gc, gr) : elem_ptr(V, gr, gc));
   }
@@ -186,36 +204,39 @@ __device__ __forceinline__ void load_tile(OpPipe& P, const VP& V, int R, int Kn,
 // straight through; otherwise what lies outside the operand or on the zero side of a
 // triangular operand is written as zero.  tri is in the view's own (row, col) orientation: for
 // A that is (m, k), for B it is (k, n).
-__device__ __forceinline__ void store_tile(const OpPipe& P, double (*T)[LDS_ROW], int R, int Kn,
+template <class T>
+__device__ __forceinline__ void store_tile(const OpPipe<T>& P, double (*L)[T::LDS_ROW], int R, int Kn,
                                            int r0, int k0, int tri, bool colsfirst) {
-  const bool interior = (r0 + BM <= R) && (k0 + BK <= Kn) && tri == TRI_NONE;
+  constexpr int NR = T::NR;
+  const bool interior = (r0 + T::BM <= R) && (k0 + BK <= Kn) && tri == TRI_NONE;
   if (interior) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
       int r, c;
-      tile_pos(P.mode, j, r, c);
-      T[c][r] = P.v[j];
+      tile_pos<T>(P.mode, j, r, c);
+      L[c][r] = P.v[j];
     }
     return;
   }
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     int r, c;
-    tile_pos(P.mode, j, r, c);
+    tile_pos<T>(P.mode, j, r, c);
     const int gr = r0 + r, gc = k0 + c;
     bool ok = gr < R && gc < Kn;
     if (tri) ok = ok && !(colsfirst ? tri_zero(tri, gc, gr) : tri_zero(tri, gr, gc));
-    T[c][r] = ok ? P.v[j] : 0.0;
+    L[c][r] = ok ? P.v[j] : 0.0;
   }
 }
 
+template <class T>
 __device__ __forceinline__ void krange(int mode, int K, int m0, int n0, int& klo, int& khi) {
   klo = 0;
   khi = K;
   switch (mode) {
     case KR_GE_N0: klo = n0; break;
-    case KR_LT_N1: khi = min(K, n0 + BN); break;
-    case KR_LT_M1: khi = min(K, m0 + BM); break;
+    case KR_LT_N1: khi = min(K, n0 + T::BN); break;
+    case KR_LT_M1: khi = min(K, m0 + T::BM); break;
     case KR_GE_MAX: klo = max(m0, n0); break;
     default: break;
   }
@@ -223,22 +244,25 @@ __device__ __forceinline__ void krange(int mode, int K, int m0, int n0, int& klo
   if (klo > K) klo = K;
 }
 
-// One K step on the matrix cores: 8 x 2 FJ MFMAs per wave over a 32-deep slice of the LDS tiles.
-__device__ __forceinline__ void mfma_step(const double (*As)[LDS_ROW], const double (*Bs)[LDS_ROW],
-                                          int wm, int wn, int lane, v4d (&acc)[2][FJ]) {
+// One K step on the matrix cores: 8 x FI x FJ MFMAs per wave over a 32-deep slice of the LDS
+// tiles.
+template <class T>
+__device__ __forceinline__ void mfma_step(const double (*As)[T::LDS_ROW],
+                                          const double (*Bs)[T::LDS_ROW], int wm, int wn, int lane,
+                                          v4d (&acc)[T::FI][T::FJ]) {
 #pragma unroll
   for (int kk = 0; kk < BK / 4; ++kk) {
     const int kr = kk * 4 + (lane >> 4);
-    const double a0 = As[kr][wm + (lane & 15)];
-    const double a1 = As[kr][wm + 16 + (lane & 15)];
-    double b[FJ];
+    double a[T::FI], b[T::FJ];
 #pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) b[bj] = Bs[kr][wn + 16 * bj + (lane & 15)];
+    for (int bi = 0; bi < T::FI; ++bi) a[bi] = As[kr][wm + 16 * bi + (lane & 15)];
 #pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) {
-      acc[0][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[bj], a0, acc[0][bj], 0, 0, 0);
-      acc[1][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[bj], a1, acc[1][bj], 0, 0, 0);
-    }
+    for (int bj = 0; bj < T::FJ; ++bj) b[bj] = Bs[kr][wn + 16 * bj + (lane & 15)];
+#pragma unroll
+    for (int bj = 0; bj < T::FJ; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < T::FI; ++bi)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
   }
 }
 
@@ -246,42 +270,45 @@ __device__ __forceinline__ void mfma_step(const double (*As)[LDS_ROW], const dou
 // matters for short launches).  Iteration t issues the global loads of K tile t, runs tile t-1
 // from LDS on the matrix cores, then writes tile t to the other LDS buffer; one barrier per
 // iteration.  alpha is applied by the caller to the accumulators.
+template <class T>
 __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
-                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW],
-                                          v4d (&acc)[2][FJ]) {
+                                          double (*As)[BK][T::LDS_ROW],
+                                          double (*Bs)[BK][T::LDS_ROW],
+                                          v4d (&acc)[T::FI][T::FJ]) {
   const int K = lasty ? ph.Klast : ph.K;
   int klo, khi;
-  krange(ph.kmode, K, m0, n0, klo, khi);
+  krange<T>(ph.kmode, K, m0, n0, klo, khi);
   const int nk = klo < khi ? (khi - klo + BK - 1) / BK : 0;
   const VP A = make_vp(ph.A, z, y), B = make_vp(ph.B, z, y);
-  OpPipe pa, pb;
+  OpPipe<T> pa, pb;
   pa.q = -1;
   pb.q = -1;
   for (int t = 0; t <= nk; ++t) {
     const int k0 = klo + t * BK;
     if (t < nk) {
-      load_tile(pa, A, M, K, m0, k0, false);
-      load_tile(pb, B, N, K, n0, k0, true);
+      load_tile<T>(pa, A, M, K, m0, k0, false);
+      load_tile<T>(pb, B, N, K, n0, k0, true);
     }
-    if (t > 0) mfma_step(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
+    if (t > 0) mfma_step<T>(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
     if (t < nk) {
-      store_tile(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
-      store_tile(pb, Bs[t & 1], N, K, n0, k0, ph.triB, true);
+      store_tile<T>(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
+      store_tile<T>(pb, Bs[t & 1], N, K, n0, k0, ph.triB, true);
     }
     __syncthreads();
   }
 }
 
-// Addresses of the sixteen C entries of the calling lane: lane holds
+// Addresses of the FI x FJ x 4 C entries of the calling lane: lane holds
 // C(m0+wm+bi*16 + lane%16, n0+wn+bj*16 + lane/16 + 4v), clamped into C (out-of-range entries are
 // never stored).
+template <class T>
 __device__ __forceinline__ void tile_c_addr(const VP& C, int M, int N, int m0, int n0, int wm,
-                                            int wn, int lane, double* (&cp)[2][FJ][4]) {
+                                            int wn, int lane, double* (&cp)[T::FI][T::FJ][4]) {
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < FJ; ++bj)
+    for (int bj = 0; bj < T::FJ; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         cp[bi][bj][v] = elem_ptr(C, min(m0 + wm + bi * 16 + (lane & 15), M - 1),
@@ -290,24 +317,26 @@ __device__ __forceinline__ void tile_c_addr(const VP& C, int M, int N, int m0, i
 
 // C = beta C + acc on the tile (its written part), with cv the values of C read earlier (only
 // used when beta != 0; every tile's C is read and written by its own workgroup alone).
+template <class T>
 __device__ __forceinline__ void tile_finish(const GemmArgs& args, const VP& C, int M, int N,
                                             int m0, int n0, int wm, int wn, int lane,
-                                            double* (&cp)[2][FJ][4], const double (&cv)[2][FJ][4],
-                                            v4d (&acc)[2][FJ]) {
+                                            double* (&cp)[T::FI][T::FJ][4],
+                                            const double (&cv)[T::FI][T::FJ][4],
+                                            v4d (&acc)[T::FI][T::FJ]) {
   const double beta = args.beta;
   const bool lowerC = args.omode != OUT_ALL;
   if (beta != 0.0) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < FJ; ++bj)
+      for (int bj = 0; bj < T::FJ; ++bj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[bi][bj][v] = fma(beta, cv[bi][bj][v], acc[bi][bj][v]);
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi) {
+  for (int bi = 0; bi < T::FI; ++bi) {
 #pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) {
+    for (int bj = 0; bj < T::FJ; ++bj) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm + bi * 16 + (lane & 15);
@@ -323,47 +352,50 @@ __device__ __forceinline__ void tile_finish(const GemmArgs& args, const VP& C, i
 }
 
 // C = beta C + acc on the tile at (m0, n0) (its written part), C read now.
+template <class T>
 __device__ __forceinline__ void tile_store(const GemmArgs& args, int M, int N, int m0, int n0,
                                            int z, int y, int wm, int wn, int lane,
-                                           v4d (&acc)[2][FJ]) {
+                                           v4d (&acc)[T::FI][T::FJ]) {
   const VP C = make_vp(args.C, z, y);
-  double* cp[2][FJ][4];
-  tile_c_addr(C, M, N, m0, n0, wm, wn, lane, cp);
-  double cv[2][FJ][4];
+  double* cp[T::FI][T::FJ][4];
+  tile_c_addr<T>(C, M, N, m0, n0, wm, wn, lane, cp);
+  double cv[T::FI][T::FJ][4];
   if (args.beta != 0.0) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < FJ; ++bj)
+      for (int bj = 0; bj < T::FJ; ++bj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
   }
-  tile_finish(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc);
+  tile_finish<T>(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc);
 }
 
-// One 64 x 64 output tile at (m0, n0).
+// One BM x BN output tile at (m0, n0).
+template <class T>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
-                                          double (*As)[BK][LDS_ROW], double (*Bs)[BK][LDS_ROW]) {
+                                          double (*As)[BK][T::LDS_ROW],
+                                          double (*Bs)[BK][T::LDS_ROW]) {
   // with beta != 0 the reads of C are issued first, so that their latency overlaps the K loop
   // (short-K tiles, such as the rank-64 updates, would otherwise wait for them at the end)
   const VP C = make_vp(args.C, z, y);
-  double* cp[2][FJ][4];
-  tile_c_addr(C, M, N, m0, n0, wm, wn, lane, cp);
-  double cv[2][FJ][4];
+  double* cp[T::FI][T::FJ][4];
+  tile_c_addr<T>(C, M, N, m0, n0, wm, wn, lane, cp);
+  double cv[T::FI][T::FJ][4];
   if (args.beta != 0.0) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < FJ; ++bj)
+      for (int bj = 0; bj < T::FJ; ++bj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) cv[bi][bj][v] = *cp[bi][bj][v];
   }
-  v4d acc[2][FJ];
+  v4d acc[T::FI][T::FJ];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int bj = 0; bj < T::FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
   // acc collects sum_p alpha_p A_p B_p: the products of phase p are accumulated unscaled, the
   // running sum is rescaled by alpha_{p-1} / alpha_p before phase p and by the last alpha at the
   // end (exact for the +-1 used on the sweeps).
@@ -373,18 +405,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, in
     if (p > 0) {
       const double sc = alpha_prev / alpha;
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= sc;
+        for (int bj = 0; bj < T::FJ; ++bj) acc[bi][bj] *= sc;
     }
-    run_phase(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
+    run_phase<T>(args.ph[p], M, N, m0, n0, lasty, z, y, wm, wn, lane, As, Bs, acc);
     alpha_prev = alpha;
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= alpha_prev;
-  tile_finish(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc);
+    for (int bj = 0; bj < T::FJ; ++bj) acc[bi][bj] *= alpha_prev;
+  tile_finish<T>(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
@@ -396,37 +428,39 @@ __device__ __forceinline__ int xcd_remap(int L, int T) {
 }
 
 // K steps of the tile at (m0, n0) in phase ph.
+template <class T>
 __device__ __forceinline__ int tile_nk(const GemmPhase& ph, bool lasty, int m0, int n0) {
   int klo, khi;
-  krange(ph.kmode, lasty ? ph.Klast : ph.K, m0, n0, klo, khi);
+  krange<T>(ph.kmode, lasty ? ph.Klast : ph.K, m0, n0, klo, khi);
   return klo < khi ? (khi - klo + BK - 1) / BK : 0;
 }
 
 // run_phase for two tiles in one workgroup: both halves run nkr + 1 pipeline iterations (one
 // barrier each), a half whose tile has fewer K steps (or no tile) idles through the rest.
+template <class T>
 __device__ __forceinline__ void run_phase_locked(const GemmPhase& ph, int M, int N, int m0, int n0,
                                                  bool lasty, int z, int y, int wm, int wn,
-                                                 int lane, double (*As)[BK][LDS_ROW],
-                                                 double (*Bs)[BK][LDS_ROW], v4d (&acc)[2][FJ],
-                                                 bool has, int nkr) {
+                                                 int lane, double (*As)[BK][T::LDS_ROW],
+                                                 double (*Bs)[BK][T::LDS_ROW],
+                                                 v4d (&acc)[T::FI][T::FJ], bool has, int nkr) {
   const int K = lasty ? ph.Klast : ph.K;
   int klo, khi;
-  krange(ph.kmode, K, m0, n0, klo, khi);
+  krange<T>(ph.kmode, K, m0, n0, klo, khi);
   const int nk = has && klo < khi ? (khi - klo + BK - 1) / BK : 0;
   const VP A = make_vp(ph.A, z, y), B = make_vp(ph.B, z, y);
-  OpPipe pa, pb;
+  OpPipe<T> pa, pb;
   pa.q = -1;
   pb.q = -1;
   for (int t = 0; t <= nkr; ++t) {
     const int k0 = klo + t * BK;
     if (t < nk) {
-      load_tile(pa, A, M, K, m0, k0, false);
-      load_tile(pb, B, N, K, n0, k0, true);
+      load_tile<T>(pa, A, M, K, m0, k0, false);
+      load_tile<T>(pb, B, N, K, n0, k0, true);
     }
-    if (t > 0 && t <= nk) mfma_step(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
+    if (t > 0 && t <= nk) mfma_step<T>(As[(t - 1) & 1], Bs[(t - 1) & 1], wm, wn, lane, acc);
     if (t < nk) {
-      store_tile(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
-      store_tile(pb, Bs[t & 1], N, K, n0, k0, ph.triB, true);
+      store_tile<T>(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
+      store_tile<T>(pb, Bs[t & 1], N, K, n0, k0, ph.triB, true);
     }
     __syncthreads();
   }
@@ -454,77 +488,78 @@ __device__ __forceinline__ void tile_of(int omode, int L, int tilesM, int tilesN
 // that every SIMD holds two waves: a capped launch of one-phase products reaches the matrix
 // cores' two-wave rate on half as many CUs.  Workgroup b of G takes tile slots b and b + G, then
 // b + 2G and b + 3G, ...; with G a multiple of 8 every slot stays on its workgroup's XCD range.
+template <class T>
 __device__ __forceinline__ void gemm_walk_dual(const GemmArgs& args, int z, int y, bool lasty,
-                                               int b, int G, double (*As)[2][BK][LDS_ROW],
-                                               double (*Bs)[2][BK][LDS_ROW]) {
+                                               int b, int G, double (*As)[2][BK][T::LDS_ROW],
+                                               double (*Bs)[2][BK][T::LDS_ROW]) {
   const int M = lasty ? args.Mlast : args.M;
   const int N = lasty ? args.Nlast : args.N;
-  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  const int tilesM = (M + T::BM - 1) / T::BM, tilesN = (N + T::BN - 1) / T::BN;
   const int h = threadIdx.x >> 8;
   const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) & 3;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * WN;
+  const int wm = (wave & 1) * T::WM, wn = (wave >> 1) * T::WN;
   const int T0 = args.omode == OUT_ALL ? 0 : tilesN * (tilesN + 1) / 2;
-  const int T = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
+  const int NTL = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
   const bool remap = (G & 7) == 0;
   const GemmPhase& ph = args.ph[0];
-  for (int base = b; base < T; base += 2 * G) {
+  for (int base = b; base < NTL; base += 2 * G) {
     int nkr = 0, ti = 0, tj = 0;
     bool has = false;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int V = base + q * G;
-      if (V >= T) continue;
+      if (V >= NTL) continue;
       int qi, qj;
-      tile_of(args.omode, remap ? xcd_remap(V, T) : V, tilesM, tilesN, T0, qi, qj);
-      nkr = max(nkr, tile_nk(ph, lasty, qi * BM, qj * BN));
+      tile_of(args.omode, remap ? xcd_remap(V, NTL) : V, tilesM, tilesN, T0, qi, qj);
+      nkr = max(nkr, tile_nk<T>(ph, lasty, qi * T::BM, qj * T::BN));
       if (q == h) {
         has = true;
         ti = qi;
         tj = qj;
       }
     }
-    v4d acc[2][FJ];
+    v4d acc[T::FI][T::FJ];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
-    run_phase_locked(ph, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As[h], Bs[h], acc,
-                     has, nkr);
+      for (int bj = 0; bj < T::FJ; ++bj) acc[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+    run_phase_locked<T>(ph, M, N, ti * T::BM, tj * T::BN, lasty, z, y, wm, wn, lane, As[h], Bs[h],
+                        acc, has, nkr);
     if (has) {
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < FJ; ++bj) acc[bi][bj] *= ph.alpha;
-      tile_store(args, M, N, ti * BM, tj * BN, z, y, wm, wn, lane, acc);
+        for (int bj = 0; bj < T::FJ; ++bj) acc[bi][bj] *= ph.alpha;
+      tile_store<T>(args, M, N, ti * T::BM, tj * T::BN, z, y, wm, wn, lane, acc);
     }
   }
 }
 
 // The tiles of chain z, sub-problem y handled by workgroup slot v of nv: tile v alone, or with
 // LOOP tiles v, v + nv, ... (a capped grid; the XCD mapping is kept when nv is a multiple of 8).
-template <bool LOOP>
+template <bool LOOP, class T = Tile64>
 __device__ __forceinline__ void gemm_walk(const GemmArgs& args, int z, int y, bool lasty, int v,
-                                          int nv, double (*As)[BK][LDS_ROW],
-                                          double (*Bs)[BK][LDS_ROW]) {
+                                          int nv, double (*As)[BK][T::LDS_ROW],
+                                          double (*Bs)[BK][T::LDS_ROW]) {
   const int M = lasty ? args.Mlast : args.M;
   const int N = lasty ? args.Nlast : args.N;
-  const int tilesM = (M + BM - 1) / BM, tilesN = (N + BN - 1) / BN;
+  const int tilesM = (M + T::BM - 1) / T::BM, tilesN = (N + T::BN - 1) / T::BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * WN;
+  const int wm = (wave & 1) * T::WM, wn = (wave >> 1) * T::WN;
   const int T0 = args.omode == OUT_ALL ? 0 : tilesN * (tilesN + 1) / 2;
-  const int T = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
-  const bool remap = nv == T || (LOOP && (nv & 7) == 0);
+  const int NTL = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
+  const bool remap = nv == NTL || (LOOP && (nv & 7) == 0);
   if constexpr (LOOP) {
-    for (int V = v; V < T; V += nv) {
+    for (int V = v; V < NTL; V += nv) {
       int ti, tj;
-      tile_of(args.omode, remap ? xcd_remap(V, T) : V, tilesM, tilesN, T0, ti, tj);
-      gemm_tile(args, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As, Bs);
+      tile_of(args.omode, remap ? xcd_remap(V, NTL) : V, tilesM, tilesN, T0, ti, tj);
+      gemm_tile<T>(args, M, N, ti * T::BM, tj * T::BN, lasty, z, y, wm, wn, lane, As, Bs);
     }
   } else {
-    if (v >= T) return;
+    if (v >= NTL) return;
     int ti, tj;
-    tile_of(args.omode, remap ? xcd_remap(v, T) : v, tilesM, tilesN, T0, ti, tj);
-    gemm_tile(args, M, N, ti * BM, tj * BN, lasty, z, y, wm, wn, lane, As, Bs);
+    tile_of(args.omode, remap ? xcd_remap(v, NTL) : v, tilesM, tilesN, T0, ti, tj);
+    gemm_tile<T>(args, M, N, ti * T::BM, tj * T::BN, lasty, z, y, wm, wn, lane, As, Bs);
   }
 }
 

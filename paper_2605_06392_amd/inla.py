@@ -30,6 +30,27 @@ CARRY_ONLY = 2
 
 _token = itertools.count(1)
 
+# GEMM roles whose tile edge (64 or 32) the autotuner chooses, by the library's role number
+# (role 3, the split schedule's panel rows, is formed in place and keeps 64 x 64 tiles)
+TILE_ROLES = {1: "trailing", 2: "trtri", 4: "schur_update", 5: "si_W", 6: "si_ZB", 7: "si_ZD"}
+
+
+def tile_table(block_sizes):
+    """The tile edge of every tuned role at each block size: {b: {role name: 64 | 32}}."""
+    return {int(b): {name: int(lib().adelia_tune_get(int(b), r)) for r, name in TILE_ROLES.items()}
+            for b in block_sizes}
+
+
+def set_tiles(b, tile, roles=None):
+    """Set the tile edge of `roles` (names or numbers; default all) at block size b."""
+    for r, name in TILE_ROLES.items():
+        if roles is None or r in roles or name in roles:
+            check(lib().adelia_tune_set(int(b), r, int(tile)), "adelia_tune_set")
+
+
+def clear_tiles():
+    lib().adelia_tune_clear()
+
 
 def _ptr(a):
     return C.c_void_p(a.ctypes.data) if a is not None and a.size else C.c_void_p(0)
@@ -227,6 +248,20 @@ class InlaModel:
             self.saved_token = 0
         return f, g, inf
 
+    def autotune(self, theta, kind="grad", batch=1, reps=3):
+        """Choose the GEMM tile of each role at this model's block size by timing `batch`
+        (<= 2d + 1) evaluations of `kind` at theta (rows of a batch x d array); returns the
+        number of roles whose choice changed.  Synchronises."""
+        th = self._theta(theta).reshape(-1, self.d)[:batch].contiguous()
+        mode = MODE_GRAD if kind == "grad" else MODE_OBJECTIVE
+        ws, nb = self.workspace(int(th.shape[0]), mode)
+        changed = C.c_int32(0)
+        check(lib().inla_autotune(self._h, C.c_void_p(th.data_ptr()), int(th.shape[0]), mode,
+                                  int(reps), ws, nb, self._stream(), C.byref(changed)),
+              "inla_autotune")
+        self.saved_token = 0
+        return int(changed.value)
+
     def fitting_batch(self, npts, mode, fraction=0.5):
         """The largest batch (<= npts) whose workspace fits in `fraction` of the free memory."""
         free, _ = torch.cuda.mem_get_info(self.device)
@@ -399,6 +434,22 @@ class InlaBatch:
         self._set(theta)
         self._run("grad")
         return self.f, self.g, self.info
+
+    def autotune(self, kind="grad", reps=2, theta=None):
+        """Choose the GEMM tile of each role for every block size of the batch by timing that
+        group's part of a call of `kind` at the points in self.theta (or `theta`); returns the
+        number of (block size, role) choices that changed.  Synchronises; graphs captured
+        before keep their old choices, so they are dropped."""
+        self._set(theta)
+        mode = MODE_GRAD if kind == "grad" else MODE_OBJECTIVE
+        ws, nb = self._workspace(mode)
+        changed = C.c_int32(0)
+        check(lib().inla_batch_autotune(self._h, C.c_void_p(self.theta.data_ptr()), mode,
+                                        int(reps), ws, nb,
+                                        C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                        C.byref(changed)), "inla_batch_autotune")
+        self._graphs = {}
+        return int(changed.value)
 
     def capture(self, kind):
         """Record one call of `kind` ("objective" or "grad") into a hipGraph (once)."""

@@ -222,3 +222,52 @@ def test_inla_model_rejects_oversized_blocks():
     assert L.inla_model_create(CTX, ctypes.byref(d), ctypes.byref(h)) == E_SHAPE
     d.param = 7
     assert L.inla_model_create(CTX, ctypes.byref(d), ctypes.byref(h)) == E_SHAPE
+
+
+def test_tile_table_set_get_save_load(tmp_path):
+    """The GEMM tile table: argument codes, and a JSON cache that round-trips and whose
+    malformed forms are rejected without loading anything."""
+    L = _L()
+    L.adelia_tune_clear()
+    try:
+        assert L.adelia_tune_set(0, 4, 32) == -1
+        assert L.adelia_tune_set(16384, 4, 32) == -1
+        assert L.adelia_tune_set(128, 0, 32) == -2
+        assert L.adelia_tune_set(128, 8, 32) == -2
+        assert L.adelia_tune_set(128, 3, 32) == -2  # in-place panel rows keep 64
+        assert L.adelia_tune_set(128, 4, 48) == -3
+        assert L.adelia_tune_get(128, 4) == 64  # no entry: 64
+        assert L.adelia_tune_set(128, 4, 32) == 0
+        assert L.adelia_tune_set(1024, 7, 32) == 0
+        assert L.adelia_tune_get(128, 4) == 32 and L.adelia_tune_get(1024, 7) == 32
+        path = str(tmp_path / "tiles.json")
+        assert L.adelia_tune_save(path.encode()) == 0
+        import json
+        doc = json.load(open(path))
+        assert sorted((e["b"], e["role"], e["tile"]) for e in doc["tiles"]) == [
+            (128, "schur_update", 32), (1024, "si_ZD", 32)]
+        L.adelia_tune_clear()
+        assert L.adelia_tune_get(128, 4) == 64
+        assert L.adelia_tune_load(path.encode()) == 2
+        assert L.adelia_tune_get(128, 4) == 32 and L.adelia_tune_get(1024, 7) == 32
+        L.adelia_tune_clear()
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"tiles": [{"b": 128, "role": "schur_update", "tile": 16}]}')
+        assert L.adelia_tune_load(str(bad).encode()) == E_SHAPE
+        bad.write_text('{"tiles": [{"b": 128, "role": "no_such_role", "tile": 32}]}')
+        assert L.adelia_tune_load(str(bad).encode()) == E_SHAPE
+        assert L.adelia_tune_get(128, 4) == 64
+        assert L.adelia_tune_load(str(tmp_path / "missing.json").encode()) == E_UNSUPPORTED
+    finally:
+        L.adelia_tune_clear()
+
+
+def test_autotune_and_batch_argument_codes():
+    L = _L()
+    ch = ctypes.c_int32(0)
+    assert L.inla_autotune(None, P, 1, 1, 3, P, 1 << 30, None, ctypes.byref(ch)) == -1
+    assert L.inla_batch_autotune(None, P, 1, 2, P, 1 << 30, None, ctypes.byref(ch)) == -1
+    assert L.inla_batch_create(None, 1, None, None) == -1
+    assert L.inla_batch_objective(None, P, P, P, P, 1 << 30, None) == -1
+    assert L.inla_batch_grad(None, P, P, P, P, P, 1 << 30, None) == -1
+    assert L.inla_batch_workspace_bytes(None, 1) == 0
