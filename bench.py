@@ -348,6 +348,17 @@ def bench_uneven(args, torch):
                 print(f"{kind}: replay {t + 1}/{steps} done", file=sys.stderr, flush=True)
         return out
 
+    # first with every product on 64 x 64 tiles, then with the tiles the autotuner picks per block
+    # size and role (coordinate search over timed gradient calls of each block-size group)
+    inla.clear_tiles()
+    t_obj64 = replay_times("objective", args.steps, args.warmup)
+    t_grad64 = replay_times("grad", args.steps, args.warmup)
+    t0 = time.perf_counter()
+    changed = B.autotune("grad", reps=2)
+    tune_s = time.perf_counter() - t0
+    table = inla.tile_table(sorted(UNEVEN_GRIDS))
+    if PROGRESS:
+        print(f"autotune: {changed} choices changed in {tune_s:.1f} s", file=sys.stderr, flush=True)
     t_obj = replay_times("objective", args.steps, args.warmup)
     f_obj = B.f.clone()
     t_grad = replay_times("grad", args.steps, args.warmup)
@@ -402,6 +413,11 @@ def bench_uneven(args, torch):
         "objectives_per_s": count * 1000.0 / ms_obj,
         "ms_per_objective_batch": median_ci(t_obj),
         "ms_per_gradient_batch": median_ci(t_grad),
+        "autotune": {"changed": changed, "seconds": tune_s,
+                     "tiles_not_64": {str(bb): [r for r, t in roles.items() if t != 64]
+                                      for bb, roles in table.items()},
+                     "untuned_64x64": {"ms_per_objective_batch": median_ci(t_obj64),
+                                       "ms_per_gradient_batch": median_ci(t_grad64)}},
         "fd_gradients_per_s_from_objective_batches": count * 1000.0 / ((2 * d + 1) * ms_obj),
         "ad_over_fd_speedup": (2 * d + 1) * ms_obj / ms_grad,
         "tflops_paper_flop_model": {"objective": fwd_fl / (ms_obj * 1e-3) / 1e12,
