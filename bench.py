@@ -50,6 +50,8 @@ def parse():
                     help="problem-size sweep of c_AD = T_AD / T_f and beta = t_bwd / t_fwd: "
                          "n = 2..256 steps on the 32x32 univariate grid (time), or three "
                          "coregionalised fields on ns = 72..1122 nodes, n = 16 (space)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep every GEMM on 64 x 64 tiles instead of the autotuned table")
     ap.add_argument("--progress", action="store_true",
                     help="print a line to stderr after every timed step (long workloads)")
     ap.add_argument("--roofline-only", action="store_true",
@@ -698,6 +700,18 @@ def main():
     ad_step = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
     fd_step = lambda: model.fd_grad(theta, h=1e-3, max_batch=npts, f=f_fd, g=g_fd, info=i_fd)  # noqa: E731
     fwd_step = lambda: model.forward_saved(theta)  # noqa: E731
+    # GEMM tiles: every product on 64 x 64 tiles first, then (unless disabled) the autotuner's
+    # choice per role at this block size, timed on the gradient itself; FD is timed with the
+    # same table
+    inla.clear_tiles()
+    tune = None
+    if not args.no_autotune:
+        ms_ad64 = timed(lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad),
+                        max(3, args.steps // 2), args.warmup, use_graph, torch)
+        t0 = time.perf_counter()
+        changed = model.autotune(theta[None], kind="grad", reps=3)
+        tune = {"changed": changed, "seconds": time.perf_counter() - t0,
+                "tiles": inla.tile_table([model.b])[model.b], "ms_ad_all_64x64": ms_ad64}
     ms_ad = timed(ad_step, args.steps, args.warmup, use_graph, torch)
     g_ref = g_ad.clone()  # every replay of the full gradient recomputes it
     ms_fd = timed(fd_step, args.steps, args.warmup, use_graph, torch)
@@ -745,6 +759,7 @@ def main():
         "objectives_per_s_fd_batch": npts * 1000.0 / ms_fd,
         "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": ad_fd_rel, "info_ok": ok},
         "ms_ad_per_call": median_ci(TIMES.get(id(ad_step), [])),
+        "autotune": tune,
         "ms_fd_per_call": median_ci(TIMES.get(id(fd_step), [])),
         "carry_only": {"ms_per_gradient": ms_carry,
                        "workspace_gb": model.workspace_bytes(1, 2) / 1e9,

@@ -366,6 +366,13 @@ int run_backward(const Eval& E, const InlaWs& w, const double* theta, double* f,
   sc.x = w.x; sc.zx = w.zx;
   sc.y = w.y; sc.zy = w.zy;
   sc.zn = E.zn;
+  // Only the mode of Qc (chain 2p of point p) is read (Phase B, the data residual): the upper
+  // sweep runs on the Qc chains alone, seen as `batch` chains with doubled strides.
+  auto qc_only = [&](SolveChains& c) {
+    c.nz = w.batch;
+    c.zG *= 2; c.zLB *= 2; c.zLC *= 2; c.zz *= 2; c.zxT *= 2; c.zx *= 2; c.zy *= 2;
+    c.zn_stride = 2;
+  };
   SelinvChains si = selinv_of(w);
   si.zn = E.zn;
   const long long bb = (long long)b * b;
@@ -389,6 +396,7 @@ int run_backward(const Eval& E, const InlaWs& w, const double* theta, double* f,
     // from the last block down.
     sc.LC = w.LCz; sc.zLC = w.zLCz; sc.ldLC = ap; sc.sLC = (long long)ap * b;
     sc.z = w.LCz + a; sc.zz = w.zLCz; sc.sz_blk = (long long)ap * b; sc.sz_elem = ap;
+    qc_only(sc);
     BtaChains c = chains_of(w);
     c.zn = E.zn;
     c.refactor = true;
@@ -451,6 +459,7 @@ int run_backward(const Eval& E, const InlaWs& w, const double* theta, double* f,
     if (pipe && hipStreamWaitEvent(s, finished[0], 0) != hipSuccess) return ADELIA_E_HIP;
     if (bta_upper_solve_tip(sc, s)) return ADELIA_E_HIP;
   } else {
+    qc_only(sc);
     // x* is read only by Phase B and the residual at the end: with the side stream (idle after
     // the forward sweep's join) the upper sweep runs there, beside the selected inversion
     if (side) {

@@ -506,7 +506,7 @@ int bta_upper_solve_block(const SolveChains& c, int i, hipStream_t s) {
     g.beta = 1.0;
     g.y = c.y; g.zy = c.zy; g.incy = 1;
     g.M = b; g.K = b; g.lowerA = 0;
-    g.zn = c.zn; g.step = i;
+    g.zn = c.zn; g.step = i; g.zn_stride = c.zn_stride;
     if (launch_gemv_t(g, nz, s)) return ADELIA_E_HIP_INTERNAL;
     GemvT h{};
     h.A = c.G + blk_off(i, c.slotsG, bb); h.ld = b; h.zA = c.zG;
@@ -514,7 +514,7 @@ int bta_upper_solve_block(const SolveChains& c, int i, hipStream_t s) {
     h.alpha = 1.0;
     h.y = c.x + (long long)i * b; h.zy = c.zx; h.incy = 1;
     h.M = b; h.K = b; h.lowerA = 1;
-    h.zn = c.zn; h.step = i;
+    h.zn = c.zn; h.step = i; h.zn_stride = c.zn_stride;
     if (launch_gemv_t(h, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;

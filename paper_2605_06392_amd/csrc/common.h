@@ -199,6 +199,7 @@ struct SolveChains {
   double* x; long long zx;                        // length n*b + a (contiguous)
   double* y; long long zy;                        // scratch b
   const int32_t* zn;  // per chain block count (uneven batch; its x must start as zeros) or nullptr
+  int zn_stride = 1;  // chain z of the solve reads zn[z * zn_stride]
 };
 int bta_upper_solve(const SolveChains& c, hipStream_t s);
 // One block of it (x_i from x_{i+1} and x_T), and the tip part of x (after block 0).
@@ -215,7 +216,8 @@ struct GemvT {
   const double* y0; long long zy0; long long incy0;
   double* y; long long zy; long long incy;
   int M, K; int lowerA; double alpha, alpha2, beta;
-  const int32_t* zn; int step;  // chain z takes part only while step < zn[z] (zn may be null)
+  // chain z takes part only while step < zn[z * zn_stride] (zn may be null)
+  const int32_t* zn; int step; int zn_stride = 1;
 };
 int launch_gemv_t(const GemvT& g, int nz, hipStream_t s);
 

@@ -300,6 +300,8 @@ __global__ __launch_bounds__(256) void trace_kernel(const Models Ms, int j, cons
     }
     return;
   }
+  // the observation traces enter the gradient through the likelihood precision of Qc only
+  if (z & 1) return;
   const int no = M.nch_obs;
   const int m = (w - 2 * kk * nr) / no, ch = (w - 2 * kk * nr) % no;
   const double* Zd = ZD + (long long)z * zZD;

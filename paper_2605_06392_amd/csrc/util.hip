@@ -54,7 +54,7 @@ __global__ void zero_upper_kernel(double* p, int b, long long ld, long long bs, 
 //                                             + alpha2*sum_c A2(c,m) x2(c)
 __global__ __launch_bounds__(256) void gemv_t_kernel(const GemvT g) {
   const int z = blockIdx.z;
-  if (g.zn && g.step >= g.zn[z]) return;
+  if (g.zn && g.step >= g.zn[(long long)z * g.zn_stride]) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = blockIdx.x * 4 + wave;
   if (m >= g.M) return;
