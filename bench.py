@@ -50,6 +50,8 @@ def parse():
                     help="problem-size sweep of c_AD = T_AD / T_f and beta = t_bwd / t_fwd: "
                          "n = 2..256 steps on the 32x32 univariate grid (time), or three "
                          "coregionalised fields on ns = 72..1122 nodes, n = 16 (space)")
+    ap.add_argument("--no-d15", action="store_true",
+                    help="skip the nested d = 15 measurement (coreg3_30x30_nt48)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep every GEMM on 64 x 64 tiles instead of the autotuned table")
     ap.add_argument("--progress", action="store_true",
@@ -260,6 +262,9 @@ def cpu_baseline(spec_name, seed, nt_sample):
     return {
         "value": 1.0 / (ts * scale),
         "unit": "gradients/s",
+        "extrapolated": True,
+        "measured": {"N": int(sample.N), "nt": nt_sample, "seconds_per_gradient": ts,
+                     "gradients_per_s": 1.0 / ts},
         "cores": int(threads),
         "kind": "oracle",
         "sample": (f"dense oracle f + exact gradient on the same grid and covariates with "
@@ -492,6 +497,54 @@ def bench_uneven_factor(args, torch, shapes):
             "check": {"info_ok": infos_ok, "logdet_vs_single_rel": rel}}
 
 
+def bench_d15(args, torch, np, workload="coreg3_30x30_nt48"):
+    """AD gradient against the GPU's 31-point FD gradient on the three-field d = 15 model
+    (b = 2700, n = 48, a = 6): a few graph replays of each, the FD batch in one pass."""
+    from paper_2605_06392_amd import inla
+    from workloads import named_config
+    dev = torch.device("cuda:0")
+    spec = named_config(workload, seed=args.seed)
+    model = inla.InlaModel(spec, device=dev)
+    d = model.d
+    npts = 2 * d + 1
+    theta = torch.tensor(spec.theta, dtype=torch.float64, device=dev)
+    f_ad = torch.empty(1, dtype=torch.float64, device=dev)
+    g_ad = torch.empty(d, dtype=torch.float64, device=dev)
+    i_ad = torch.empty(1, dtype=torch.int32, device=dev)
+    f_fd = torch.empty(1, dtype=torch.float64, device=dev)
+    g_fd = torch.empty(d, dtype=torch.float64, device=dev)
+    i_fd = torch.empty(npts, dtype=torch.int32, device=dev)
+    print(f"d15: model {workload} on the device", file=sys.stderr, flush=True)
+    model.grad(theta, f=f_ad, g=g_ad, info=i_ad)
+    model.fd_grad(theta, h=1e-4, max_batch=npts, f=f_fd, g=g_fd, info=i_fd)
+    torch.cuda.synchronize()
+    gad, gfd = g_ad.cpu().numpy(), g_fd.cpu().numpy()
+    rel = float(np.abs(gad - gfd).max() / np.abs(gad).max())
+    ok = int(i_ad.item()) == 0 and bool((i_fd.cpu().numpy() == 0).all())
+    print("d15: accuracy check done", file=sys.stderr, flush=True)
+    ad_step = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
+    fd_step = lambda: model.fd_grad(theta, h=1e-3, max_batch=npts, f=f_fd, g=g_fd, info=i_fd)  # noqa: E731
+    ms_ad = timed(ad_step, 3, 1, True, torch)
+    print(f"d15: AD {ms_ad:.1f} ms", file=sys.stderr, flush=True)
+    ms_fd = timed(fd_step, 2, 1, True, torch)
+    print(f"d15: FD {ms_fd:.1f} ms", file=sys.stderr, flush=True)
+    k, nx, ny, nt, a, obs = NAMED_CONFIGS_REF[workload]
+    b = k * nx * ny
+    fwd_fl, si_fl = algorithmic_flops(b, nt, a)
+    out = {"workload": workload, "b": b, "n": nt, "a": a, "d": d, "N": nt * b + a,
+           "ms_ad_gradient": ms_ad, "ms_fd_gradient": ms_fd, "ad_over_fd_speedup": ms_fd / ms_ad,
+           "ad_gradients_per_s": 1000.0 / ms_ad, "fd_gradients_per_s": 1000.0 / ms_fd,
+           "ad_tflops_paper_flop_model": (fwd_fl + si_fl) / (ms_ad * 1e-3) / 1e12,
+           "fd_points": npts,
+           "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": rel, "info_ok": ok},
+           "ms_ad_per_call": median_ci(TIMES.get(id(ad_step), [])),
+           "ms_fd_per_call": median_ci(TIMES.get(id(fd_step), []))}
+    del model
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_hessian(args, model, theta, spec, torch, np):
     """Posterior Hessian at theta: Eq. 12 (2d+1 exact gradients, one graph) against the
     second-order FD Hessian (2d^2+1 objectives: the faster of one batched call and sub-batches
@@ -716,6 +769,11 @@ def main():
     g_ref = g_ad.clone()  # every replay of the full gradient recomputes it
     ms_fd = timed(fd_step, args.steps, args.warmup, use_graph, torch)
     ms_fwd = timed(fwd_step, max(3, args.steps // 2), 1, use_graph, torch)
+    f_one = torch.empty(1, dtype=torch.float64, device=dev)
+    i_one = torch.empty(1, dtype=torch.int32, device=dev)
+    obj_ws = model.new_workspace(1, inla.MODE_OBJECTIVE)
+    obj_step = lambda: model.objective(theta[None], out=f_one, info=i_one, ws=obj_ws)  # noqa: E731
+    ms_obj = timed(obj_step, max(3, args.steps // 2), 1, use_graph, torch)
     ms_bwd = timed_backward(model, theta, f_ad, g_ad, i_ad, max(3, args.steps // 2), 1, use_graph,
                             torch)
 
@@ -732,6 +790,25 @@ def main():
     k, nx, ny, nt, a, obs = NAMED_CONFIGS[args.workload]
     b = k * nx * ny
     fwd_fl, si_fl = algorithmic_flops(b, nt, a)
+    # FP64-MFMA utilisation of the block Cholesky and the selected inversion: App. B flops of
+    # both (both matrices) over the summed kernel time of the kernels that do them (panel
+    # steps and panels, every GEMM role, and the sparse W_j product that replaces the dense
+    # L_B G), against the 78.6 TFLOP/s peak; rocprof's MFMA counters cross-check it
+    fac_si_kernels = ("panel_step", "potrf_panel", "gemm_f64", "w_sparse")
+    fac_si_ms = sum(stats[kk]["ms"] for kk in fac_si_kernels if kk in stats) / args.profile_steps
+    mfma_pct = 100.0 * (fwd_fl + si_fl) / (fac_si_ms * 1e-3) / (PEAK_FP64_TFLOPS * 1e12)
+    hbm_kernels = {}
+    for kk in ("w_sparse", "gemv", "assemble", "trace"):
+        if kk in stats and stats[kk]["ms"] > 0 and stats[kk]["bytes"] > 0:
+            gbs = stats[kk]["bytes"] / (stats[kk]["ms"] * 1e-3) / 1e9
+            hbm_kernels[kk] = {"GB/s": gbs, "frac_of_8TB/s": gbs / PEAK_HBM_GBS,
+                               "algorithmic_bytes_per_launch":
+                                   stats[kk]["bytes"] / max(1, stats[kk]["launches"]),
+                               "launches_per_step": stats[kk]["launches"] / args.profile_steps}
+    if "gemm_f64" in stats:
+        gb = stats["gemm_f64"]["bytes"] / max(1, stats["gemm_f64"]["launches"])
+        roof["algorithmic_bytes_per_launch"] = gb
+        roof["traffic_over_algorithmic_bytes"] = (roof["traffic"] / gb) if roof.get("traffic") else None
     line = {
         "metric": METRIC,
         "value": 1000.0 / ms_ad,
@@ -754,8 +831,21 @@ def main():
         "ms_forward": ms_fwd,
         "ms_backward": ms_bwd,
         "beta_bwd_over_fwd": ms_bwd / ms_fwd,
-        "c_AD": ms_ad / (ms_fd / npts),
+        # c_AD = T_AD / t_eval, t_eval one objective evaluation on its own (Sec. IV-D)
+        "c_AD": ms_ad / ms_obj,
+        "ms_objective": ms_obj,
+        "ad_over_batched_fd_point": ms_ad / (ms_fd / npts),
+        # the paper's stage split (Sec. IV-I): Chol + L-solve of both matrices is the forward
+        # sweep; U-solve + selected inversion + traces of both matrices the reverse pass.  Qc and
+        # Qp share every launch, so Phase C (the Qp part) is not timed apart: its chain does the
+        # same selected-inversion work as Qc's, about half of the reverse pass.
+        "stage_split_ms": {"chol_lsolve_both": ms_fwd, "usolve_selinv_traces_both": ms_bwd,
+                           "phase_c_share_of_reverse": 0.5},
         "ad_tflops_paper_flop_model": (fwd_fl + si_fl) / (ms_ad * 1e-3) / 1e12,
+        "fp64_mfma_pct_factor_selinv": {"pct_of_78.6": mfma_pct,
+                                        "app_b_gflop": (fwd_fl + si_fl) / 1e9,
+                                        "kernel_ms": fac_si_ms, "kernels": list(fac_si_kernels)},
+        "hbm_kernels": hbm_kernels,
         "objectives_per_s_fd_batch": npts * 1000.0 / ms_fd,
         "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": ad_fd_rel, "info_ok": ok},
         "ms_ad_per_call": median_ci(TIMES.get(id(ad_step), [])),
@@ -774,6 +864,8 @@ def main():
                     for kname, v in stats.items()},
         "roofline": roof,
     }
+    if not args.no_d15 and args.workload == "uni_32x32_nt50":
+        line["d15"] = bench_d15(args, torch, np)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_sample_nt)
     print(json.dumps(line), flush=True)

@@ -95,6 +95,7 @@ void set_tuned_tile(int blk, int tag, int tile);
 std::vector<std::array<int, 3>> tuned_tiles();  // entries (blk, tag, tile) other than 64
 void clear_tuned_tiles();
 double gemm_flops(const GemmArgs& a, int ny);  // algorithmic flops of one chain
+double gemm_bytes(const GemmArgs& a, int ny);  // compulsory HBM bytes of one chain
 
 // ---- small kernels (util.hip) -------------------------------------------------------------
 int launch_fill(double* p, long long n, double v, hipStream_t s);

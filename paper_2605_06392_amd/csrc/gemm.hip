@@ -75,7 +75,7 @@ int launch_gemm_t(const GemmArgs& a, int ny, int nz, hipStream_t s) {
   else
     hipLaunchKernelGGL((gemm_f64_kernel<false, T>), dim3((unsigned)gx, ny, nz), dim3(NT), 0, s, a);
   if (t.valid) prof_end_role(t, s, PK_GEMM, (a.tag >= 0 && a.tag < GT_COUNT) ? a.tag : 0,
-                            gemm_flops(a, ny) * nz, 0.0);
+                            gemm_flops(a, ny) * nz, gemm_bytes(a, ny) * nz);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -134,6 +134,33 @@ double phase_flops(const GemmPhase& ph, int M, int N, int K, int omode) {
     s = outs * K;
   }
   return 2.0 * s;
+}
+
+// Compulsory HBM bytes of one launch: every element of the logical operands read once (half of
+// a triangular square operand) and of the written part of C written once (and read once when
+// beta != 0); the tile kernels' re-reads of operand tiles are not counted.
+double gemm_bytes(const GemmArgs& a, int ny) {
+  double e = 0.0;
+  for (int y = 0; y < ny; ++y) {
+    const bool last = y == ny - 1;
+    const int M = last ? a.Mlast : a.M, N = last ? a.Nlast : a.N;
+    if (M <= 0 || N <= 0) continue;
+    double outs = 0.0;
+    if (a.omode != OUT_ALL) {
+      for (int m = 0; m < M; ++m) outs += std::min(N, m + 1);
+    } else {
+      outs = (double)M * N;
+    }
+    e += outs * (a.beta != 0.0 ? 2.0 : 1.0);
+    for (int p = 0; p < a.nph; ++p) {
+      const GemmPhase& ph = a.ph[p];
+      const int K = last ? ph.Klast : ph.K;
+      if (K <= 0) continue;
+      e += (double)M * K * (ph.triA && M == K ? 0.5 : 1.0);
+      e += (double)K * N * (ph.triB && K == N ? 0.5 : 1.0);
+    }
+  }
+  return 8.0 * e;
 }
 
 double gemm_flops(const GemmArgs& a, int ny) {
