@@ -241,6 +241,10 @@ const char* adelia_last_error(void);
 /* A carry-only gradient workspace (see ADELIA_CARRY_ONLY): about n b^2 + 10 b^2 doubles per
  * matrix and point instead of (4n + 6) b^2. */
 #define ADELIA_MODE_GRAD_CARRY 2
+/* Workspaces of one objective or gradient by the two-sided split (ADELIA_SPLIT, batch 1): the
+ * two halves' chains (about half the blocks each) and the one-block reduced system. */
+#define ADELIA_MODE_OBJECTIVE_SPLIT 3
+#define ADELIA_MODE_GRAD_SPLIT 4
 size_t inla_workspace_bytes(inla_model model, int batch, int mode);
 
 /* f(theta) of Eq. 1 for `batch` points theta (device, batch x d, row-major):
@@ -249,6 +253,19 @@ size_t inla_workspace_bytes(inla_model model, int batch, int mode);
  * Qp = blkdiag(Q_x(theta), tip_prec I).  f: device, batch.  info: device int32, batch.
  * flags & ADELIA_SAVE_FACTORS (batch == 1, GRAD workspace): keep the factors for inla_grad. */
 #define ADELIA_SAVE_FACTORS 1
+/* flags & ADELIA_SPLIT (inla_objective with batch 1, inla_grad; workspace mode
+ * ADELIA_MODE_OBJECTIVE_SPLIT / ADELIA_MODE_GRAD_SPLIT; not with SAVE, REUSE or CARRY_ONLY):
+ * the two-phase decomposition of Sec. III-C with P = 2 partitions on one GPU.  The blocks are
+ * split at the separator block s = (n - 1) / 2: blocks 0..s-1 are eliminated from the top and
+ * blocks n-1..s+1 from the bottom (the sub-diagonal blocks of the model are symmetric, so the
+ * reversed half is again a BTA chain), both halves' chains in the same launches, so the
+ * sequence of block steps is about half as long; their Schur complements meet in the separator
+ * block and the tip, which form the reduced system (one block and the arrowhead), factored
+ * next.  The gradient runs the reduced system's selected inversion first and then both halves'
+ * reverse passes from it.  Same results as without the flag up to rounding; `info` numbers a
+ * failing column within its own half.  ADELIA_E_UNSUPPORTED for models with fewer than three
+ * time steps. */
+#define ADELIA_SPLIT 4
 int inla_objective(inla_model model, const double* theta, int32_t batch, double* f,
                    int32_t* info, void* ws, size_t ws_bytes, int flags, void* stream);
 

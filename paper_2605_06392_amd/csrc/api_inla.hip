@@ -43,6 +43,17 @@ struct inla_model_s {
   // inla_grad(REUSE_FACTORS) on it consumes them (the reverse pass overwrites G^T G with Z_D);
   // any other call on that workspace discards them
   const void* saved_ws;
+  // Two-sided split (ADELIA_SPLIT; the two-phase decomposition of Sec. III-C with P = 2 on one
+  // GPU): half A = blocks 0..sep, half B = blocks n-1..sep in reverse order, each a model of its
+  // own (B's separator block and fixed-effect prior are zero, its hyperparameter prior absent),
+  // swept in the same launches toward the separator block; the separator and the tip form the
+  // reduced system.  split_sep < 0: not available (n < 3).
+  int split_sep;
+  inla_model half[2];
+  ModelDev* half_dev;   // device: the two halves' descriptions, A then B
+  int32_t* zn_split;    // device: blocks swept per half chain [A, A, B, B]
+  ModelDev Mh;          // layout of the halves (the longer half)
+  ModelDev Mr;          // layout of the reduced system (one block)
 };
 
 namespace {
@@ -245,8 +256,10 @@ int prepare_block(const Eval& E, const InlaWs& w, SelinvChains si, int j, hipStr
 }
 
 // Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
+// tip == false (the halves of the two-sided split): the tips keep their Schur-complemented
+// values, unfactored, for the reduced system.
 int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t s,
-                const SideRes* side) {
+                const SideRes* side, bool tip = true) {
   const ModelDev& M = E.M;
   const int nz = w.nz, n = w.n, b = w.b;
   hipLaunchKernelGGL(param_kernel, dim3(w.batch), dim3(256), 0, s, E.dev, theta, w.phi, w.dphi,
@@ -336,9 +349,26 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
   if (fork && (hipEventRecord(side->done[n % 3], side->s2) != hipSuccess ||
                hipStreamWaitEvent(s, side->done[n % 3], 0) != hipSuccess))
     return ADELIA_E_HIP;
-  if (bta_tip(c, s)) return ADELIA_E_HIP;
+  if (tip && bta_tip(c, s)) return ADELIA_E_HIP;
   if (bta_logdet_reduce(w.ldpart, w.zLd, n * w.npanel + 1, w.ld, 1, nz, s)) return ADELIA_E_HIP;
   return 0;
+}
+
+// The upper sweep x = L^-T z over the factors kept in a gradient workspace (z_t is the rhs row
+// of L_C).
+SolveChains solve_of(const InlaWs& w) {
+  const int n = w.n, b = w.b, a = w.a, ap = w.ap;
+  SolveChains sc{};
+  sc.n = n; sc.b = b; sc.a = a; sc.nz = w.nz;
+  sc.G = w.G; sc.zG = w.zG; sc.slotsG = w.slotsG;
+  const long long sLBC = (long long)(b + ap) * b;
+  sc.LB = w.LBC; sc.zLB = w.zLBC; sc.slotsLB = w.slotsLBC; sc.ldLB = b + ap; sc.sLB = sLBC;
+  sc.LC = w.LBC + b; sc.zLC = w.zLBC; sc.ldLC = b + ap; sc.sLC = sLBC;
+  sc.z = w.LBC + b + a; sc.zz = w.zLBC; sc.sz_blk = sLBC; sc.sz_elem = b + ap;
+  sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
+  sc.x = w.x; sc.zx = w.zx;
+  sc.y = w.y; sc.zy = w.zy;
+  return sc;
 }
 
 int run_objective(const Eval& E, const InlaWs& w, const double* theta, double* f,
@@ -355,16 +385,7 @@ int run_backward(const Eval& E, const InlaWs& w, const double* theta, double* f,
   const ModelDev& M = E.M;
   const int n = w.n, b = w.b, a = w.a, ap = w.ap, nz = w.nz;
   // x* = Qc^-1 r by the upper sweep (Eqs. 3-5); z_t is the rhs row of L_C
-  SolveChains sc{};
-  sc.n = n; sc.b = b; sc.a = a; sc.nz = nz;
-  sc.G = w.G; sc.zG = w.zG; sc.slotsG = w.slotsG;
-  const long long sLBC = (long long)(b + ap) * b;
-  sc.LB = w.LBC; sc.zLB = w.zLBC; sc.slotsLB = w.slotsLBC; sc.ldLB = b + ap; sc.sLB = sLBC;
-  sc.LC = w.LBC + b; sc.zLC = w.zLBC; sc.ldLC = b + ap; sc.sLC = sLBC;
-  sc.z = w.LBC + b + a; sc.zz = w.zLBC; sc.sz_blk = sLBC; sc.sz_elem = b + ap;
-  sc.xT = a ? w.xT : nullptr; sc.zxT = w.zXT;
-  sc.x = w.x; sc.zx = w.zx;
-  sc.y = w.y; sc.zy = w.zy;
+  SolveChains sc = solve_of(w);
   sc.zn = E.zn;
   // Only the mode of Qc (chain 2p of point p) is read (Phase B, the data residual): the upper
   // sweep runs on the Qc chains alone, seen as `batch` chains with doubled strides.
@@ -813,6 +834,101 @@ static void free_side(SideRes& sr) {
 
 static Eval eval_of(inla_model m) { return Eval{m->M, Models{m->Md, 0}, nullptr}; }
 
+// ---- two-sided split (one gradient or objective) ----------------------------------------------
+// Workspace: theta twice (one row per half), the halves' results, the halves' layout (two
+// points: chains A-Qc, A-Qp, B-Qc, B-Qp) and the reduced system's (one block, chains Qc, Qp).
+struct SplitWs {
+  double *Th2, *fv, *gv;
+  int32_t* finfo;
+  InlaWs h, r;
+  size_t bytes;
+};
+
+static SplitWs split_layout(const inla_model_s* m, bool grad, char* base) {
+  SplitWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  const int d = m->M.d;
+  w.Th2 = reinterpret_cast<double*>(take((size_t)2 * d * 8));
+  w.fv = reinterpret_cast<double*>(take(2 * 8));
+  w.gv = reinterpret_cast<double*>(take((size_t)2 * d * 8));
+  w.finfo = reinterpret_cast<int32_t*>(take(2 * 4));
+  w.h = layout(m->Mh, 2, grad, base ? base + off : nullptr);
+  off = align_up(off + w.h.bytes);
+  w.r = layout(m->Mr, 1, grad, base ? base + off : nullptr);
+  off = align_up(off + w.r.bytes);
+  w.bytes = off;
+  return w;
+}
+
+// One objective (grad == nullptr) or gradient by the two-sided split: both halves' sweeps in the
+// same launches, toward the separator (Phase 1 of Sec. III-C); the separator block, its arrow
+// rows and the tip summed over the halves and factored as the reduced system (Phase 2); for the
+// gradient, the reduced system's selected inverse and mode seed both halves' reverse passes,
+// whose gradients add up.
+static int run_split(inla_model m, const SplitWs& sw, const double* theta, double* f,
+                     double* grad, int32_t* info, hipStream_t s) {
+  const SideRes* side = m->has_side ? &m->side : nullptr;
+  const Eval Eh{m->Mh, Models{m->half_dev, 1}, m->zn_split};
+  const InlaWs& h = sw.h;
+  const InlaWs& r = sw.r;
+  const int d = m->M.d, b = h.b, a = h.a, ap = h.ap;
+  const bool with_grad = grad != nullptr;
+  for (int q = 0; q < 2; ++q)
+    if (launch_copy2d(theta, d, 0, sw.Th2 + q * d, d, 0, d, 1, 1, s)) return ADELIA_E_HIP;
+  // the separator's panels and the halves' tips are never factored: zero partials
+  if (launch_fill(h.ldpart, (long long)h.nz * h.zLd, 0.0, s)) return ADELIA_E_HIP;
+  if (with_grad && (launch_fill(h.x, (long long)h.nz * h.zx, 0.0, s) ||
+                    launch_fill(h.ZC, (long long)h.nz * h.zZC, 0.0, s)))
+    return ADELIA_E_HIP;
+  if (int e = run_forward(Eh, h, sw.Th2, s, side, false)) return e;
+  const long long bb = (long long)b * b;
+  const long long tot = bb + (long long)ap * b + (long long)ap * ap;
+  hipLaunchKernelGGL(split_merge_kernel, dim3((unsigned)std::min<long long>((tot + 255) / 256, 1024), 1, 2),
+                     dim3(256), 0, s, h.D, h.zD, bb, h.slotsD, h.C, h.zC, (long long)ap * b, h.T,
+                     h.zT, m->zn_split, b, ap, r.D, r.zD, r.C, r.zC, r.T, r.zT);
+  if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  // the reduced system: one block with the arrow and the tip
+  BtaChains cr = chains_of(r);
+  cr.b_in_place = false;
+  if (launch_fill_i32(r.info, r.nz, INT32_MAX, s) || launch_fill_i32(r.cnt, r.nz, 0, s))
+    return ADELIA_E_HIP;
+  Lookahead la{};
+  if (side) {
+    la = side->la;
+    la.mark = nullptr;
+  }
+  if (bta_forward_block(cr, 0, s, side ? &la : nullptr) || bta_tip(cr, s) ||
+      bta_logdet_reduce(r.ldpart, r.zLd, r.npanel + 1, r.ld, 1, r.nz, s))
+    return ADELIA_E_HIP;
+  if (!with_grad) {
+    hipLaunchKernelGGL(split_combine_kernel, dim3(1), dim3(64), 0, s, Models{m->Md, 0}, theta,
+                       h.tau, h.ld, r.ld, r.zsq, h.info, r.info, nullptr, nullptr, f, nullptr,
+                       info);
+    return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+  }
+  // the reduced system's selected inverse and its part of the mode
+  const SelinvChains sir = selinv_of(r);
+  if (selinv_prepare(sir, 0, s) || selinv_finish(sir, 0, s)) return ADELIA_E_HIP;
+  SolveChains scr = solve_of(r);
+  scr.nz = 1;  // the mode of Qc only
+  if (bta_upper_solve(scr, s)) return ADELIA_E_HIP;
+  const long long stot = bb + (long long)a * b + (long long)a * a + b + a;
+  hipLaunchKernelGGL(split_seed_kernel, dim3((unsigned)std::min<long long>((stot + 255) / 256, 1024), 1, h.nz),
+                     dim3(256), 0, s, r.ZD, r.zZD, r.ZC, r.zZC, r.ZT, r.zZT, r.x, r.zx, r.xT,
+                     r.zXT, b, a, m->zn_split, h.slotsZD, h.ZD, h.zZD, h.ZC, h.zZC, h.ZT, h.zZT,
+                     h.x, h.zx, h.xT, h.zXT);
+  if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  if (int e = run_backward(Eh, h, sw.Th2, sw.fv, sw.gv, sw.finfo, nullptr, s, side)) return e;
+  hipLaunchKernelGGL(split_combine_kernel, dim3(1), dim3(64), 0, s, Models{m->Md, 0}, theta,
+                     h.tau, h.ld, r.ld, r.zsq, h.info, r.info, sw.gv, sw.finfo, f, grad, info);
+  return LAUNCH_OK() ? 0 : ADELIA_E_HIP;
+}
+
 // Estimated launches of `npts` points evaluated in passes of at most `bmax` points.
 static long long planned_passes(inla_model m, int npts, int bmax, bool grad) {
   const SideRes* side = m->has_side ? &m->side : nullptr;
@@ -823,8 +939,10 @@ static long long planned_passes(inla_model m, int npts, int bmax, bool grad) {
 
 extern "C" {
 
-int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out) {
-  set_last_error("");
+static int build_split(adelia_ctx ctx, const inla_model_desc* d, inla_model m);
+
+static int model_create_impl(adelia_ctx ctx, const inla_model_desc* d, inla_model* out,
+                             bool full) {
   if (!ctx) return -1;
   if (!d) return -2;
   if (!out) return -3;
@@ -1006,14 +1124,116 @@ int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out)
     delete m;
     return ADELIA_E_HIP;
   }
-  m->has_side = make_side(m->side, m->device);
+  m->split_sep = -1;
+  if (full) {
+    m->has_side = make_side(m->side, m->device);
+    if (int r = build_split(ctx, d, m)) {
+      inla_model_destroy(m);
+      return r;
+    }
+  }
   *out = m;
+  return 0;
+}
+
+int inla_model_create(adelia_ctx ctx, const inla_model_desc* d, inla_model* out) {
+  set_last_error("");
+  return model_create_impl(ctx, d, out, true);
+}
+
+// The halves of the two-sided split, created with the model (set-up time).  Half A is the model
+// on blocks 0..sep (temporal entries and observations of those blocks); half B the model on
+// blocks n-1, n-2, ..., sep (the temporal matrices read backwards; the sub-diagonal blocks are
+// symmetric, so the reversed chain uses them as they are), whose last block -- the separator --
+// has zero temporal coefficients and no observations, and whose fixed-effect prior precision is
+// zero: its Schur complements then add to A's in the separator and the tip.  B has no
+// hyperparameter prior (sigma = inf), so the two halves' gradients add up to the gradient.
+static int build_split(adelia_ctx ctx, const inla_model_desc* d, inla_model m) {
+  const int n = d->nt, k = d->k;
+  if (n < 3) return 0;
+  const int sep = (n - 1) / 2;
+  const int ntA = sep + 1, ntB = n - sep;
+  // half A: a prefix of the time steps and of the (time-sorted) observations
+  inla_model_desc da = *d;
+  da.nt = ntA;
+  int oA = 0;
+  while (oA < d->n_obs && d->obs_t[oA] <= sep) ++oA;
+  da.n_obs = oA;
+  // half B: reversed time, its observations re-sorted by (local time, field)
+  std::vector<double> tdiag[3], toff[3];
+  const double* diags[3] = {d->m0_diag, d->m1_diag, d->m2_diag};
+  const double* offs[3] = {d->m0_off, d->m1_off, d->m2_off};
+  for (int r = 0; r < 3; ++r) {
+    tdiag[r].assign(ntB, 0.0);
+    toff[r].assign(std::max(1, ntB - 1), 0.0);
+    for (int t = 0; t < ntB - 1; ++t) {
+      tdiag[r][t] = diags[r][n - 1 - t];
+      toff[r][t] = offs[r][n - 2 - t];
+    }
+  }
+  std::vector<int> ord;
+  for (int o = oA; o < d->n_obs; ++o) ord.push_back(o);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    const int tx = n - 1 - d->obs_t[x], ty = n - 1 - d->obs_t[y];
+    return tx != ty ? tx < ty : d->obs_field[x] < d->obs_field[y];
+  });
+  const int nB = (int)ord.size(), a = d->a;
+  std::vector<int32_t> bt(nB), bf(nB), bnode(4 * (size_t)nB);
+  std::vector<double> bw(4 * (size_t)nB), bX((size_t)nB * a), by(nB);
+  for (int i = 0; i < nB; ++i) {
+    const int o = ord[i];
+    bt[i] = n - 1 - d->obs_t[o];
+    bf[i] = d->obs_field[o];
+    for (int q = 0; q < 4; ++q) {
+      bnode[4 * i + q] = d->obs_node[4 * o + q];
+      bw[4 * i + q] = d->obs_w[4 * o + q];
+    }
+    for (int c = 0; c < a; ++c) bX[(size_t)i * a + c] = d->X[(size_t)o * a + c];
+    by[i] = d->y[o];
+  }
+  inla_model_desc db = *d;
+  db.nt = ntB;
+  db.m0_diag = tdiag[0].data(); db.m0_off = toff[0].data();
+  db.m1_diag = tdiag[1].data(); db.m1_off = toff[1].data();
+  db.m2_diag = tdiag[2].data(); db.m2_off = toff[2].data();
+  db.n_obs = nB;
+  db.obs_t = bt.data(); db.obs_field = bf.data(); db.obs_node = bnode.data();
+  db.obs_w = bw.data(); db.X = bX.data(); db.y = by.data();
+  if (int r = model_create_impl(ctx, &da, &m->half[0], false)) return r;
+  if (int r = model_create_impl(ctx, &db, &m->half[1], false)) return r;
+  ModelDev& MB = m->half[1]->M;
+  MB.tip = 0.0;
+  MB.sigma = INFINITY;
+  (void)k;
+  char* mem = nullptr;
+  const size_t bytes = align_up(2 * sizeof(ModelDev)) + 256;
+  if (hipMalloc(&mem, bytes) != hipSuccess) return ADELIA_E_HIP;
+  m->half_dev = reinterpret_cast<ModelDev*>(mem);
+  m->zn_split = reinterpret_cast<int32_t*>(mem + align_up(2 * sizeof(ModelDev)));
+  const int32_t zn[4] = {sep, sep, ntB - 1, ntB - 1};
+  ModelDev both[2] = {m->half[0]->M, MB};
+  if (hipMemcpy(m->half_dev, both, sizeof(both), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->zn_split, zn, sizeof(zn), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(mem);
+    m->half_dev = nullptr;
+    return ADELIA_E_HIP;
+  }
+  m->Mh = m->half[0]->M;
+  m->Mh.nt = std::max(ntA, ntB);
+  m->Mh.n_obs = std::max(m->half[0]->M.n_obs, MB.n_obs);
+  m->Mh.nch_obs = std::max(m->half[0]->M.nch_obs, MB.nch_obs);
+  m->Mh.nch_resid = std::max(m->half[0]->M.nch_resid, MB.nch_resid);
+  m->Mr = m->M;
+  m->Mr.nt = 1;
+  m->split_sep = sep;
   return 0;
 }
 
 int inla_model_destroy(inla_model m) {
   if (!m) return 0;
   if (m->has_side) free_side(m->side);
+  for (inla_model h : m->half) inla_model_destroy(h);
+  if (m->half_dev) hipFree(m->half_dev);
   hipFree(m->dev_mem);
   delete m;
   return 0;
@@ -1023,6 +1243,10 @@ int inla_model_dim(inla_model m) { return m ? m->M.d : 0; }
 
 size_t inla_workspace_bytes(inla_model m, int batch, int mode) {
   if (!m || batch < 1 || batch > 32767) return 0;
+  if (mode == ADELIA_MODE_OBJECTIVE_SPLIT || mode == ADELIA_MODE_GRAD_SPLIT)
+    return (batch == 1 && m->split_sep >= 0)
+               ? split_layout(m, mode == ADELIA_MODE_GRAD_SPLIT, nullptr).bytes
+               : 0;
   if (mode != ADELIA_MODE_OBJECTIVE && mode != ADELIA_MODE_GRAD && mode != ADELIA_MODE_GRAD_CARRY)
     return 0;
   return layout(m->M, batch, mode != ADELIA_MODE_OBJECTIVE, nullptr,
@@ -1037,9 +1261,18 @@ int inla_objective(inla_model m, const double* theta, int32_t batch, double* f, 
   if (!f || !aligned(f, 8)) return -4;
   if (!info || !aligned(info, 4)) return -5;
   if (!ws || !aligned(ws, 256)) return -6;
-  if (flags & ~ADELIA_SAVE_FACTORS) return -8;
+  if (flags & ~(ADELIA_SAVE_FACTORS | ADELIA_SPLIT)) return -8;
   const bool save = flags & ADELIA_SAVE_FACTORS;
   if (save && batch != 1) return -3;
+  if (flags & ADELIA_SPLIT) {
+    if (save) return -8;
+    if (batch != 1) return -3;
+    if (m->split_sep < 0) return ADELIA_E_UNSUPPORTED;
+    const SplitWs sw = split_layout(m, false, reinterpret_cast<char*>(ws));
+    if (ws_bytes < sw.bytes) return ADELIA_E_WORKSPACE;
+    if (m->saved_ws == ws) m->saved_ws = nullptr;
+    return run_split(m, sw, theta, f, nullptr, info, (hipStream_t)stream);
+  }
   InlaWs w = layout(m->M, batch, save, reinterpret_cast<char*>(ws));
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
   if (int r = capture_guard((hipStream_t)stream,
@@ -1058,9 +1291,17 @@ int inla_grad(inla_model m, const double* theta, double* f, double* grad, int32_
   if (!grad || !aligned(grad, 8)) return -4;
   if (!info || !aligned(info, 4)) return -5;
   if (!ws || !aligned(ws, 256)) return -6;
-  if (flags & ~(ADELIA_REUSE_FACTORS | ADELIA_CARRY_ONLY)) return -8;
+  if (flags & ~(ADELIA_REUSE_FACTORS | ADELIA_CARRY_ONLY | ADELIA_SPLIT)) return -8;
   const bool carry = flags & ADELIA_CARRY_ONLY;
   if (carry && (flags & ADELIA_REUSE_FACTORS)) return -8;
+  if (flags & ADELIA_SPLIT) {
+    if (flags & (ADELIA_REUSE_FACTORS | ADELIA_CARRY_ONLY)) return -8;
+    if (m->split_sep < 0) return ADELIA_E_UNSUPPORTED;
+    const SplitWs sw = split_layout(m, true, reinterpret_cast<char*>(ws));
+    if (ws_bytes < sw.bytes) return ADELIA_E_WORKSPACE;
+    if (m->saved_ws == ws) m->saved_ws = nullptr;
+    return run_split(m, sw, theta, f, grad, info, (hipStream_t)stream);
+  }
   InlaWs w = layout(m->M, 1, true, reinterpret_cast<char*>(ws), carry);
   if (ws_bytes < w.bytes) return ADELIA_E_WORKSPACE;
   if ((flags & ADELIA_REUSE_FACTORS) && m->saved_ws != ws) return ADELIA_E_STATE;

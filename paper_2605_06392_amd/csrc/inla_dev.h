@@ -79,6 +79,23 @@ __global__ void grad_kernel(const Models Ms, const double* theta, const double* 
                             const int32_t* info, double* f, double* grad, int32_t* info_out,
                             double* terms);
 __global__ void yy_kernel(const ModelDev M, double* yy);
+__global__ void split_merge_kernel(const double* D, long long zD, long long sD, int slotsD,
+                                   const double* C, long long zC, long long sC, const double* T,
+                                   long long zT, const int32_t* zn, int b, int ap, double* Dr,
+                                   long long zDr, double* Cr, long long zCr, double* Tr,
+                                   long long zTr);
+__global__ void split_seed_kernel(const double* ZDr, long long zZDr, const double* ZCr,
+                                  long long zZCr, const double* ZTr, long long zZTr,
+                                  const double* xr, long long zxr, const double* xTr,
+                                  long long zxTr, int b, int a, const int32_t* zn, int slotsZD,
+                                  double* ZD, long long zZD, double* ZC, long long zZC,
+                                  double* ZT, long long zZT, double* x, long long zx, double* xT,
+                                  long long zxT);
+__global__ void split_combine_kernel(const Models Ms, const double* theta, const double* tau,
+                                     const double* ldh, const double* ldr, const double* zsqr,
+                                     const int32_t* infh, const int32_t* infr, const double* gv,
+                                     const int32_t* ginfo, double* f, double* grad,
+                                     int32_t* info);
 __global__ void stencil_kernel(const double* theta, int d, double h, double* Th);
 __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad);
 __global__ void hess_stencil_kernel(const double* theta, int d, double h, double* Th);

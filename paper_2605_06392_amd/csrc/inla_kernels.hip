@@ -559,6 +559,94 @@ __global__ __launch_bounds__(256) void grad_kernel(const Models Ms, const double
   }
 }
 
+// ---- the two-sided split ---------------------------------------------------------------------
+// Chains of the halves: 0, 1 = half A's Qc, Qp; 2, 3 = half B's.  zn[z]: blocks swept by chain
+// z (its separator block is local block zn[z]).
+
+// The reduced system's block, arrow rows and tip (chain 0 = Qc, 1 = Qp): the sums of the two
+// halves' Schur-complemented separator blocks, separator arrow rows and tips.
+__global__ void split_merge_kernel(const double* D, long long zD, long long sD, int slotsD,
+                                   const double* C, long long zC, long long sC, const double* T,
+                                   long long zT, const int32_t* zn, int b, int ap, double* Dr,
+                                   long long zDr, double* Cr, long long zCr, double* Tr,
+                                   long long zTr) {
+  const int mat = blockIdx.z;
+  const int zA = mat, zB = 2 + mat;
+  const long long bb = (long long)b * b, cb = (long long)ap * b, tt = (long long)ap * ap;
+  const double* DA = D + zA * zD + (long long)(zn[zA] % slotsD) * sD;
+  const double* DB = D + zB * zD + (long long)(zn[zB] % slotsD) * sD;
+  const double* CA = C + zA * zC + (long long)zn[zA] * sC;
+  const double* CB = C + zB * zC + (long long)zn[zB] * sC;
+  const double* TA = T + zA * zT;
+  const double* TB = T + zB * zT;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < bb + cb + tt;
+       e += (long long)gridDim.x * 256) {
+    if (e < bb)
+      Dr[mat * zDr + e] = DA[e] + DB[e];
+    else if (e < bb + cb)
+      Cr[mat * zCr + (e - bb)] = CA[e - bb] + CB[e - bb];
+    else
+      Tr[mat * zTr + (e - bb - cb)] = TA[e - bb - cb] + TB[e - bb - cb];
+  }
+}
+
+// The reduced system's selected inverse and mode seed both halves: Z_D and Z_C of the
+// separator go into each half chain's slots of its local block zn[z], Z_T into its tip, x of
+// the separator into its block zn[z] of x and x_T into its tip part.
+__global__ void split_seed_kernel(const double* ZDr, long long zZDr, const double* ZCr,
+                                  long long zZCr, const double* ZTr, long long zZTr,
+                                  const double* xr, long long zxr, const double* xTr,
+                                  long long zxTr, int b, int a, const int32_t* zn, int slotsZD,
+                                  double* ZD, long long zZD, double* ZC, long long zZC,
+                                  double* ZT, long long zZT, double* x, long long zx, double* xT,
+                                  long long zxT) {
+  const int z = blockIdx.z, mat = z & 1;
+  const long long bb = (long long)b * b, cb = (long long)a * b;
+  const int j = zn[z];
+  double* zd = ZD + z * zZD + (long long)(j % slotsZD) * bb;
+  double* zc = ZC + z * zZC + (long long)(j % 2) * cb;
+  const long long tot = bb + cb + (long long)a * a + b + a;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+    if (e < bb) {
+      zd[e] = ZDr[mat * zZDr + e];
+    } else if (e < bb + cb) {
+      zc[e - bb] = ZCr[mat * zZCr + (e - bb)];
+    } else if (e < bb + cb + (long long)a * a) {
+      ZT[z * zZT + (e - bb - cb)] = ZTr[mat * zZTr + (e - bb - cb)];
+    } else if (e < bb + cb + (long long)a * a + b) {
+      const long long i = e - bb - cb - (long long)a * a;
+      x[z * zx + (long long)j * b + i] = xr[mat * zxr + i];
+    } else {
+      const long long i = e - bb - cb - (long long)a * a - b;
+      xT[z * zxT + i] = xTr[mat * zxTr + i];
+    }
+  }
+}
+
+__device__ __forceinline__ bool failed(int32_t v) { return v != 0 && v != INT32_MAX; }
+
+// f from the log-determinants of the halves and of the reduced system and |z|^2 of the reduced
+// tip, the gradient as the sum of the halves' gradients (gv: 2 x d, or null for f alone), and
+// the first failure of any chain (its column numbered within its own chain).
+__global__ void split_combine_kernel(const Models Ms, const double* theta, const double* tau,
+                                     const double* ldh, const double* ldr, const double* zsqr,
+                                     const int32_t* infh, const int32_t* infr, const double* gv,
+                                     const int32_t* ginfo, double* f, double* grad,
+                                     int32_t* info) {
+  const ModelDev M = model_at(Ms, 0);
+  const int d = M.d;
+  for (int q = threadIdx.x; q < d && gv; q += blockDim.x) grad[q] = gv[q] + gv[d + q];
+  if (threadIdx.x == 0) {
+    const double ldc = ldh[0] + ldh[2] + ldr[0], ldp = ldh[1] + ldh[3] + ldr[1];
+    f[0] = objective_value(M, theta, tau, ldc, ldp, zsqr[0]);
+    int32_t v = 0;
+    for (int z = 0; z < 4 && !v; ++z) if (failed(infh[z])) v = infh[z];
+    for (int z = 0; z < 2 && !v; ++z) if (failed(infr[z])) v = infr[z];
+    for (int z = 0; z < 2 && !v && ginfo; ++z) if (failed(ginfo[z])) v = ginfo[z];
+    info[0] = v;
+  }
+}
+
 __global__ void yy_kernel(const ModelDev M, double* yy) {
   __shared__ double red[256];
   const int m = blockIdx.x;

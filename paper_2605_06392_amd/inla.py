@@ -24,9 +24,12 @@ PARAM_COREG = 2
 MODE_OBJECTIVE = 0
 MODE_GRAD = 1
 MODE_GRAD_CARRY = 2
+MODE_OBJECTIVE_SPLIT = 3
+MODE_GRAD_SPLIT = 4
 SAVE_FACTORS = 1
 REUSE_FACTORS = 1
 CARRY_ONLY = 2
+SPLIT = 4
 
 _token = itertools.count(1)
 
@@ -159,16 +162,17 @@ class InlaModel:
         return t.contiguous()
 
     # -- evaluations ---------------------------------------------------------------------------
-    def objective(self, theta, out=None, info=None, ws=None):
+    def objective(self, theta, out=None, info=None, ws=None, split=False):
+        """f at a batch of points; split=True (one point): the two-sided split of the sweep."""
         th = self._theta(theta)
         th2 = th.reshape(-1, self.d)
         batch = th2.shape[0]
         f = out if out is not None else torch.empty(batch, dtype=torch.float64, device=self.device)
         inf = info if info is not None else torch.empty(batch, dtype=torch.int32, device=self.device)
-        ws, nb = self.workspace(batch, MODE_OBJECTIVE, ws)
+        ws, nb = self.workspace(batch, MODE_OBJECTIVE_SPLIT if split else MODE_OBJECTIVE, ws)
         check(lib().inla_objective(self._h, C.c_void_p(th2.data_ptr()), batch,
-                                   C.c_void_p(f.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb, 0,
-                                   self._stream()), "inla_objective")
+                                   C.c_void_p(f.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb,
+                                   SPLIT if split else 0, self._stream()), "inla_objective")
         return f, inf
 
     def forward_saved(self, theta):
@@ -182,15 +186,19 @@ class InlaModel:
         self.saved_token = next(_token)
         return f, inf, self.saved_token
 
-    def grad(self, theta, reuse=False, f=None, g=None, info=None, carry=False):
+    def grad(self, theta, reuse=False, f=None, g=None, info=None, carry=False, split=False):
         """f and the exact gradient; carry=True keeps only the per-block carries and rebuilds
-        the factors in the backward pass (less memory, one more block Cholesky per block)."""
+        the factors in the backward pass (less memory, one more block Cholesky per block);
+        split=True runs the two-sided split (both halves of the block chain at once, then the
+        separator block and the tip as the reduced system)."""
         th = self._theta(theta).reshape(self.d)
         f = f if f is not None else torch.empty(1, dtype=torch.float64, device=self.device)
         g = g if g is not None else torch.empty(self.d, dtype=torch.float64, device=self.device)
         inf = info if info is not None else torch.empty(1, dtype=torch.int32, device=self.device)
-        ws, nb = self.workspace(1, MODE_GRAD_CARRY if carry else MODE_GRAD)
-        flags = (REUSE_FACTORS if reuse else 0) | (CARRY_ONLY if carry else 0)
+        mode = MODE_GRAD_SPLIT if split else (MODE_GRAD_CARRY if carry else MODE_GRAD)
+        ws, nb = self.workspace(1, mode)
+        flags = ((REUSE_FACTORS if reuse else 0) | (CARRY_ONLY if carry else 0)
+                 | (SPLIT if split else 0))
         check(lib().inla_grad(self._h, C.c_void_p(th.data_ptr()), C.c_void_p(f.data_ptr()),
                               C.c_void_p(g.data_ptr()), C.c_void_p(inf.data_ptr()), ws, nb,
                               flags, self._stream()), "inla_grad")
