@@ -50,6 +50,8 @@ def parse():
                     help="problem-size sweep of c_AD = T_AD / T_f and beta = t_bwd / t_fwd: "
                          "n = 2..256 steps on the 32x32 univariate grid (time), or three "
                          "coregionalised fields on ns = 72..1122 nodes, n = 16 (space)")
+    ap.add_argument("--no-split", action="store_true",
+                    help="time the gradient without the two-sided split of the block chain")
     ap.add_argument("--no-d15", action="store_true",
                     help="skip the nested d = 15 measurement (coreg3_30x30_nt48)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -522,10 +524,14 @@ def bench_d15(args, torch, np, workload="coreg3_30x30_nt48"):
     rel = float(np.abs(gad - gfd).max() / np.abs(gad).max())
     ok = int(i_ad.item()) == 0 and bool((i_fd.cpu().numpy() == 0).all())
     print("d15: accuracy check done", file=sys.stderr, flush=True)
-    ad_step = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
     fd_step = lambda: model.fd_grad(theta, h=1e-3, max_batch=npts, f=f_fd, g=g_fd, info=i_fd)  # noqa: E731
+    plain = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
+    ms_plain = timed(plain, 3, 1, True, torch)
+    ad_step = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad, split=True)  # noqa: E731
     ms_ad = timed(ad_step, 3, 1, True, torch)
-    print(f"d15: AD {ms_ad:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    split_rel = float(np.abs(g_ad.cpu().numpy() - gad).max() / np.abs(gad).max())
+    print(f"d15: AD {ms_ad:.1f} ms (plain sweep {ms_plain:.1f} ms)", file=sys.stderr, flush=True)
     ms_fd = timed(fd_step, 2, 1, True, torch)
     print(f"d15: FD {ms_fd:.1f} ms", file=sys.stderr, flush=True)
     k, nx, ny, nt, a, obs = NAMED_CONFIGS_REF[workload]
@@ -536,7 +542,9 @@ def bench_d15(args, torch, np, workload="coreg3_30x30_nt48"):
            "ad_gradients_per_s": 1000.0 / ms_ad, "fd_gradients_per_s": 1000.0 / ms_fd,
            "ad_tflops_paper_flop_model": (fwd_fl + si_fl) / (ms_ad * 1e-3) / 1e12,
            "fd_points": npts,
-           "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": rel, "info_ok": ok},
+           "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": rel, "info_ok": ok,
+                     "split_vs_plain_grad_rel": split_rel},
+           "split": True, "ms_ad_plain_sweep": ms_plain,
            "ms_ad_per_call": median_ci(TIMES.get(id(ad_step), [])),
            "ms_fd_per_call": median_ci(TIMES.get(id(fd_step), []))}
     del model
@@ -750,7 +758,18 @@ def main():
     ok = int(i_ad.item()) == 0 and bool((i_fd.cpu().numpy() == 0).all())
 
     use_graph = not args.no_graph
-    ad_step = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
+    # the headline gradient: the two-sided split of the block chain (both halves swept at once,
+    # then the separator and the tip) when the model has one, else the plain sweep
+    split = (not args.no_split) and model.workspace_bytes(1, inla.MODE_GRAD_SPLIT) > 0
+    g_sp = torch.empty(d, dtype=torch.float64, device=dev)
+    if split:
+        model.grad(theta, f=f_ad, g=g_sp, info=i_ad, split=True)
+        torch.cuda.synchronize()
+        split_rel = float(np.abs(g_sp.cpu().numpy() - gad).max() / np.abs(gad).max())
+        ok = ok and int(i_ad.item()) == 0
+    plain_step = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
+    ad_step = ((lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad, split=True))  # noqa: E731
+               if split else plain_step)
     fd_step = lambda: model.fd_grad(theta, h=1e-3, max_batch=npts, f=f_fd, g=g_fd, info=i_fd)  # noqa: E731
     fwd_step = lambda: model.forward_saved(theta)  # noqa: E731
     # GEMM tiles: every product on 64 x 64 tiles first, then (unless disabled) the autotuner's
@@ -766,6 +785,8 @@ def main():
         tune = {"changed": changed, "seconds": time.perf_counter() - t0,
                 "tiles": inla.tile_table([model.b])[model.b], "ms_ad_all_64x64": ms_ad64}
     ms_ad = timed(ad_step, args.steps, args.warmup, use_graph, torch)
+    ms_ad_plain = (timed(plain_step, max(3, args.steps // 2), 1, use_graph, torch)
+                   if split else ms_ad)
     g_ref = g_ad.clone()  # every replay of the full gradient recomputes it
     ms_fd = timed(fd_step, args.steps, args.warmup, use_graph, torch)
     ms_fwd = timed(fwd_step, max(3, args.steps // 2), 1, use_graph, torch)
@@ -773,7 +794,13 @@ def main():
     i_one = torch.empty(1, dtype=torch.int32, device=dev)
     obj_ws = model.new_workspace(1, inla.MODE_OBJECTIVE)
     obj_step = lambda: model.objective(theta[None], out=f_one, info=i_one, ws=obj_ws)  # noqa: E731
-    ms_obj = timed(obj_step, max(3, args.steps // 2), 1, use_graph, torch)
+    ms_obj_plain = timed(obj_step, max(3, args.steps // 2), 1, use_graph, torch)
+    ms_obj = ms_obj_plain
+    if split:
+        obj_ws2 = model.new_workspace(1, inla.MODE_OBJECTIVE_SPLIT)
+        obj_split = lambda: model.objective(theta[None], out=f_one, info=i_one, ws=obj_ws2,  # noqa: E731
+                                            split=True)
+        ms_obj = timed(obj_split, max(3, args.steps // 2), 1, use_graph, torch)
     ms_bwd = timed_backward(model, theta, f_ad, g_ad, i_ad, max(3, args.steps // 2), 1, use_graph,
                             torch)
 
@@ -831,14 +858,16 @@ def main():
         "ms_forward": ms_fwd,
         "ms_backward": ms_bwd,
         "beta_bwd_over_fwd": ms_bwd / ms_fwd,
-        # c_AD = T_AD / t_eval, t_eval one objective evaluation on its own (Sec. IV-D)
+        # c_AD = T_AD / t_eval, t_eval one objective evaluation on its own (Sec. IV-D), both by
+        # the same sweep (split or plain)
         "c_AD": ms_ad / ms_obj,
         "ms_objective": ms_obj,
         "ad_over_batched_fd_point": ms_ad / (ms_fd / npts),
-        # the paper's stage split (Sec. IV-I): Chol + L-solve of both matrices is the forward
-        # sweep; U-solve + selected inversion + traces of both matrices the reverse pass.  Qc and
-        # Qp share every launch, so Phase C (the Qp part) is not timed apart: its chain does the
-        # same selected-inversion work as Qc's, about half of the reverse pass.
+        # the paper's stage split (Sec. IV-I), of the plain sweep: Chol + L-solve of both
+        # matrices is the forward sweep; U-solve + selected inversion + traces of both matrices
+        # the reverse pass.  Qc and Qp share every launch, so Phase C (the Qp part) is not timed
+        # apart: its chain does the same selected-inversion work as Qc's, about half of the
+        # reverse pass.
         "stage_split_ms": {"chol_lsolve_both": ms_fwd, "usolve_selinv_traces_both": ms_bwd,
                            "phase_c_share_of_reverse": 0.5},
         "ad_tflops_paper_flop_model": (fwd_fl + si_fl) / (ms_ad * 1e-3) / 1e12,
@@ -849,6 +878,9 @@ def main():
         "objectives_per_s_fd_batch": npts * 1000.0 / ms_fd,
         "check": {"ad_vs_gpu_fd_rel_inf_h1e-4": ad_fd_rel, "info_ok": ok},
         "ms_ad_per_call": median_ci(TIMES.get(id(ad_step), [])),
+        "split": {"used": split, "separator_block": (nt - 1) // 2 if split else None,
+                  "ms_ad_plain_sweep": ms_ad_plain, "ms_objective_plain_sweep": ms_obj_plain,
+                  "grad_rel_vs_plain": split_rel if split else None},
         "autotune": tune,
         "ms_fd_per_call": median_ci(TIMES.get(id(fd_step), [])),
         "carry_only": {"ms_per_gradient": ms_carry,
