@@ -316,15 +316,21 @@ __device__ __forceinline__ void tile_c_addr(const VP& C, int M, int N, int m0, i
 }
 
 // C = beta C + acc on the tile (its written part), with cv the values of C read earlier (only
-// used when beta != 0; every tile's C is read and written by its own workgroup alone).
+// used when beta != 0; every tile's C is read and written by its own workgroup alone).  The
+// mirrored upper triangle of OUT_LOWER_MIRROR: with `stage` (LDS of at least BM x (BN + 1)
+// doubles, free, and every thread of the workgroup calling) the tile goes through LDS and its
+// transpose is written with the lanes along the columns of the mirrored tile (coalesced);
+// without, each lane writes its own transposed entries.
 template <class T>
 __device__ __forceinline__ void tile_finish(const GemmArgs& args, const VP& C, int M, int N,
                                             int m0, int n0, int wm, int wn, int lane,
                                             double* (&cp)[T::FI][T::FJ][4],
                                             const double (&cv)[T::FI][T::FJ][4],
-                                            v4d (&acc)[T::FI][T::FJ]) {
+                                            v4d (&acc)[T::FI][T::FJ], double* stage = nullptr) {
   const double beta = args.beta;
   const bool lowerC = args.omode != OUT_ALL;
+  const bool mirror = args.omode == OUT_LOWER_MIRROR;
+  const bool staged = mirror && stage != nullptr;
   if (beta != 0.0) {
 #pragma unroll
     for (int bi = 0; bi < T::FI; ++bi)
@@ -345,9 +351,31 @@ __device__ __forceinline__ void tile_finish(const GemmArgs& args, const VP& C, i
         if (lowerC && m < n) continue;
         const double val = acc[bi][bj][v];
         *cp[bi][bj][v] = val;
-        if (args.omode == OUT_LOWER_MIRROR && m > n) *elem_ptr(C, n, m) = val;
+        if (mirror && !staged && m > n) *elem_ptr(C, n, m) = val;
       }
     }
+  }
+  // a tile with entries below the diagonal (m > n) mirrors them through LDS; the condition is
+  // uniform over the workgroup, so are the barriers
+  if (staged && m0 + T::BM - 1 > n0) {
+    constexpr int P = T::BN + 1;
+    __syncthreads();  // the staging area (operand buffers) is free
+#pragma unroll
+    for (int bi = 0; bi < T::FI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < T::FJ; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          stage[(wm + bi * 16 + (lane & 15)) * P + wn + bj * 16 + (lane >> 4) + 4 * v] =
+              acc[bi][bj][v];
+    __syncthreads();
+    // entry (row n0 + r, column m0 + c) of the mirrored tile, r fastest across the lanes
+    for (int e = threadIdx.x & (NT - 1); e < T::BM * T::BN; e += NT) {
+      const int r = e % T::BN, c = e / T::BN;
+      const int m = m0 + c, n = n0 + r;
+      if (m < M && n < N && m > n) *elem_ptr(C, n, m) = stage[c * P + r];
+    }
+    __syncthreads();  // the next tile's operand loads reuse the area
   }
 }
 
@@ -416,7 +444,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, in
   for (int bi = 0; bi < T::FI; ++bi)
 #pragma unroll
     for (int bj = 0; bj < T::FJ; ++bj) acc[bi][bj] *= alpha_prev;
-  tile_finish<T>(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc);
+  // the two operand buffers of A (2 x BK x (BM + 1) doubles) hold a staged BM x (BN + 1) tile
+  static_assert(2 * BK * T::LDS_ROW >= T::BM * (T::BN + 1), "staging area");
+  tile_finish<T>(args, C, M, N, m0, n0, wm, wn, lane, cp, cv, acc, &As[0][0][0]);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
