@@ -235,6 +235,8 @@ def profiled_pass(args, ad_step, bta, torch):
         achieved = st["bytes"] / (kern_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    if name == "gemm_f64":
+        roof["algorithmic_bytes_per_launch"] = st["bytes"] / launches
     roof.update({"kernel": name, "kernel_symbol": KERNEL_SYMBOLS.get(name, name),
                  "launches_per_step": st["launches"] / args.profile_steps,
                  "avg_launch_us": per_launch_ms * 1e3,
@@ -728,7 +730,9 @@ def main():
         return
 
     if args.roofline_only:
-        ad_only = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad)  # noqa: E731
+        # the headline gradient (the two-sided split when the model has one)
+        sp = (not args.no_split) and model.workspace_bytes(1, inla.MODE_GRAD_SPLIT) > 0
+        ad_only = lambda: model.grad(theta, f=f_ad, g=g_ad, info=i_ad, split=sp)  # noqa: E731
         for _ in range(args.warmup):
             ad_only()
         stats, roof = profiled_pass(args, ad_only, bta, torch)
