@@ -210,19 +210,19 @@ __global__ __launch_bounds__(256) void assemble_arrow_kernel(const Models Ms, do
   if (g >= nb) return;
   const long long total = (long long)M.nt * M.b;
   const int a = M.a;
-  double acc[65];
-  for (int c = 0; c < ap; ++c) acc[c] = 0.0;
-  if (qc && g < total) {
-    for (int j = M.colptr[g]; j < M.colptr[g + 1]; ++j) {
+  // element (c, q) of block t at t*ap*b + q*ap + c == g*ap + c; one arrow row at a time over
+  // the few observations of the column (no per-thread array indexed at run time)
+  double* Cz = C + (long long)z * zC + g * ap;
+  const int j0 = (qc && g < total) ? M.colptr[g] : 0, j1 = (qc && g < total) ? M.colptr[g + 1] : 0;
+  for (int c = 0; c < ap; ++c) {
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) {
       const int o = M.col_o[j];
       const double tw = tau[(long long)p * M.k + M.obs_f[o]] * M.obs_w[4 * o + M.col_e[j]];
-      for (int c = 0; c < a; ++c) acc[c] += tw * M.X[(long long)o * a + c];
-      if (ap > a) acc[a] += tw * M.y[o];
+      acc += tw * (c < a ? M.X[(long long)o * a + c] : M.y[o]);
     }
+    Cz[c] = acc;
   }
-  // element (c, q) of block t at t*ap*b + q*ap + c == g*ap + c
-  double* Cz = C + (long long)z * zC + g * ap;
-  for (int c = 0; c < ap; ++c) Cz[c] = acc[c];
 }
 
 // Arrowhead tip entries (r >= c) of the ap x ap tip, one workgroup per entry.
