@@ -130,3 +130,25 @@ def test_large_uneven_batch_split_schedule_matches_oracle():
         ref = oracle.gradient(models[i], models[i].theta)
         assert abs(f[i] - ref["f"]) <= 1e-10 * abs(ref["f"]), i
         assert rel_inf(g[i], ref["grad"]) <= 1e-8, i
+
+
+def test_uneven_batch_of_coregional_models_matches_oracle():
+    """Three-field models (d = 15) of two block sizes (b = 3 x 16 and 3 x 20), different
+    lengths, fixed effects and observation counts, in one batch."""
+    from paper_2605_06392_amd.inla import InlaBatch, InlaModel
+    dev = _dev()
+    specs = [(4, 4, 3, 6, 5, 21), (5, 4, 2, 4, 6, 22), (4, 4, 4, 2, 4, 23), (5, 4, 3, 6, 3, 24)]
+    models = [make_model(3, nx, ny, nt, a, obs, seed) for (nx, ny, nt, a, obs, seed) in specs]
+    B = InlaBatch([InlaModel(m, device=dev) for m in models])
+    assert B.groups == 2 and B.d == 15
+    theta = np.stack([m.theta for m in models])
+    f, g, info = B.grad(theta)
+    fo, io = B.objective(theta)
+    torch.cuda.synchronize()
+    f, g, fo = f.cpu().numpy().copy(), g.cpu().numpy().copy(), fo.cpu().numpy().copy()
+    assert (info.cpu().numpy() == 0).all() and (io.cpu().numpy() == 0).all()
+    for i, m in enumerate(models):
+        ref = oracle.gradient(m, m.theta)
+        assert abs(f[i] - ref["f"]) <= 1e-10 * abs(ref["f"]), i
+        assert abs(fo[i] - ref["f"]) <= 1e-10 * abs(ref["f"]), i
+        assert rel_inf(g[i], ref["grad"]) <= 1e-8, i
