@@ -74,6 +74,9 @@ struct InlaWs {
   // its arrow rows [L_C | z] (LCz, ld ap) instead of the factors; the backward rebuilds
   // L_D, L_B, G, W and G^T G block by block in small rings
   bool carry;
+  // stored-factor gradient: every block's L_D is kept as well, and the Z-independent part of the
+  // selected inversion (G, [W; V], G^T G) is formed for all blocks in one pass after the sweep
+  bool defer;
   double *Dc, *LCz;
   long long zDc, zLCz;
   int slotsW, slotsZD;
@@ -105,8 +108,9 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = 
   const long long bb = (long long)M.b * M.b;
   const int n = M.nt;
   const bool stored = grad && !w.carry;  // every block's factor kept
+  w.defer = stored;
   // carry-only: rings of three blocks for the pipelined reverse pass
-  w.slotsD = (stored || w.carry) ? 3 : 2;
+  w.slotsD = stored ? n : (w.carry ? 3 : 2);
   w.slotsB = 1;
   w.slotsLBC = stored ? n : (w.carry ? 3 : 1);
   w.slotsG = stored ? n : (w.carry ? 3 : 1);
@@ -233,33 +237,174 @@ SelinvChains selinv_of(const InlaWs& w) {
 // chains keep HBM busy without crowding the work that runs beside it.
 constexpr int kWGroups = 512;
 
+// Columns of Y per LDS pass of the banded W_t kernel (0: the pattern does not suit it).
+static int w_band_cols(const ModelDev& M) {
+  if (!M.wband || M.wdeg > kWDeg || M.k < 1 || M.k > kMaxFields) return 0;
+  const long long per = (long long)M.k * M.wband_w * (long long)sizeof(double);
+  return (int)std::min<long long>(16, (64 * 1024) / per);
+}
+
+// Columns of Y per pass of the LDS-batched W_t kernel (0: a column does not fit in 64 KB).
+static int w_gtg_cols(int b) {
+  return std::min<int>(kWBatch, (int)((64 * 1024) / ((size_t)b * sizeof(double))));
+}
+
+// W_t = B_t Y for nzl problems in grid.z (zdiv == 0: block t of each chain; zdiv > 0: the
+// (chain, block) pairs of prepare_all), Y = G_t^T G_t stored in full: the banded kernel when the
+// pattern suits it, else the LDS-batched one.
+static int launch_w(const ModelDev& M, Models dev, int t, int zdiv, const int32_t* zn,
+                    const double* Y, long long zY, double* W, long long zW, const double* phi,
+                    int nzl, hipStream_t s) {
+  const int b = M.b;
+  const long long bb = (long long)b * b;
+  const ProfToken tok = prof_begin(s);
+  if (const int cb = w_band_cols(M)) {
+    const int tiles = (M.ns + kWRows - 1) / kWRows;
+    // about 2048 workgroups in all, each slice a whole number of LDS passes
+    const int want = (int)std::max<long long>(1, 2048 / ((long long)nzl * tiles));
+    const int passes = (b + cb - 1) / cb;
+    const int slices0 = std::min(want, passes);
+    const int cs = ((passes + slices0 - 1) / slices0) * cb;
+    const int slices = (b + cs - 1) / cs;
+    const dim3 grid(tiles, slices, nzl);
+    const size_t lds = (size_t)M.k * cb * M.wband_w * sizeof(double);
+    switch (M.k) {
+      case 1: hipLaunchKernelGGL(w_band_kernel<1>, grid, dim3(256), lds, s, dev, t, zdiv, zn, Y, zY, W, zW, phi, cb, cs); break;
+      case 2: hipLaunchKernelGGL(w_band_kernel<2>, grid, dim3(256), lds, s, dev, t, zdiv, zn, Y, zY, W, zW, phi, cb, cs); break;
+      case 3: hipLaunchKernelGGL(w_band_kernel<3>, grid, dim3(256), lds, s, dev, t, zdiv, zn, Y, zY, W, zW, phi, cb, cs); break;
+      default: hipLaunchKernelGGL(w_band_kernel<4>, grid, dim3(256), lds, s, dev, t, zdiv, zn, Y, zY, W, zW, phi, cb, cs); break;
+    }
+  } else {
+    const int cg = w_gtg_cols(b);
+    if (cg < 1) return ADELIA_E_HIP_INTERNAL;
+    const int wg = std::max(1, std::min((b + cg - 1) / cg, kWGroups / nzl));
+    hipLaunchKernelGGL(w_from_gtg_kernel, dim3(wg, 1, nzl), dim3(256),
+                       (size_t)cg * b * sizeof(double), s, dev, t, zdiv, zn, Y, zY, W, zW, phi,
+                       cg);
+  }
+  if (tok.valid)  // G^T G read and W written once per problem
+    prof_end(tok, s, PK_WSPARSE, 0.0, 16.0 * nzl * (double)bb);
+  return hipGetLastError() == hipSuccess ? 0 : ADELIA_E_HIP;
+}
+
+// Whether W_t can be formed from G_t^T G_t (else the dense product [L_B; L_C] G).
+static bool w_sparse_ok(const ModelDev& M) { return w_band_cols(M) > 0 || w_gtg_cols(M.b) > 0; }
+
 int prepare_block(const Eval& E, const InlaWs& w, SelinvChains si, int j, hipStream_t s) {
   const int b = w.b;
-  // as many columns of G_j^T G_j per pass as fit in 64 KB of LDS (at most kWBatch)
-  const int cb = std::min<int>(kWBatch, (int)((64 * 1024) / ((size_t)b * sizeof(double))));
-  const bool sparse_w = j < w.n - 1 && cb >= 1;
+  const bool sparse_w = j < w.n - 1 && w_sparse_ok(E.M);
   si.w_external = sparse_w;
   if (selinv_prepare(si, j, s)) return ADELIA_E_HIP;
   if (sparse_w) {
     const long long bb = (long long)b * b;
     const double* Y = w.ZD + (long long)(j % w.slotsZD) * bb;
     double* Wm = w.W + (long long)(j % w.slotsW) * (bb + (long long)w.a * b);
-    const int wg = std::max(1, std::min((b + cb - 1) / cb, kWGroups / w.nz));
-    const ProfToken t = prof_begin(s);
-    hipLaunchKernelGGL(w_from_gtg_kernel, dim3(wg, 1, w.nz), dim3(256),
-                       (size_t)cb * b * sizeof(double), s, E.dev, j, Y, w.zZD, Wm, w.zW, w.phi, cb);
-    if (t.valid)  // G_j^T G_j read and W_j written once per chain
-      prof_end(t, s, PK_WSPARSE, 0.0, 16.0 * w.nz * (double)bb);
-    if (hipGetLastError() != hipSuccess) return ADELIA_E_HIP;
+    return launch_w(E.M, E.dev, j, 0, nullptr, Y, w.zZD, Wm, w.zW, w.phi, w.nz, s);
+  }
+  return 0;
+}
+
+// The Z-independent part of the selected inversion of every block of every chain, once the
+// sweep has left all factors in place (a stored-factor gradient): G_j = L_Dj^-1 by recursive
+// doubling (block j's Z_D slot is its scratch), V_j = L_Cj G_j, G_j^T G_j in Z_Dj (mirrored to
+// a full block for the W_j product) and W_j = B_j G_j^T G_j.  Each launch covers every (chain,
+// block) pair in grid.z, z = chain * n + block, which the workspace's consecutive per-block
+// slots make one stride; the chains go in groups that keep grid.z within its limit.
+int prepare_all(const Eval& E, const InlaWs& w, hipStream_t s) {
+  const int n = w.n, b = w.b, a = w.a, ap = w.ap;
+  if (!w.defer || w.slotsD != n || w.slotsG != n || w.slotsLBC != n || w.slotsW != n ||
+      w.slotsZD != n)
+    return ADELIA_E_HIP_INTERNAL;
+  const long long bb = (long long)b * b;
+  const long long sLBC = (long long)(b + ap) * b;
+  const long long sW = bb + (long long)a * b;
+  const bool sparse_w = w_sparse_ok(E.M);
+  const int per = std::max(2, (65535 / n) & ~1);  // whole points (two chains each)
+  const long long sphi = 9LL * w.k * w.k;
+  for (int c0 = 0; c0 < w.nz; c0 += per) {
+    const int nzb = std::min(per, w.nz - c0) * n;
+    const int32_t* zn = E.zn ? E.zn + c0 : nullptr;
+    double* D = w.D + c0 * w.zD;
+    double* G = w.G + c0 * w.zG;
+    double* ZD = w.ZD + c0 * w.zZD;
+    double* LC = w.LBC + c0 * w.zLBC + b;
+    double* Wm = w.W + c0 * w.zW;
+    if (bta_invert_blocks(D, G, ZD, b, nzb, n, zn, s)) return ADELIA_E_HIP;
+    if (!sparse_w) {
+      // W_j cannot be formed from G_j^T G_j: the per-block dense products of the sweep's own
+      // preparation
+      SelinvChains si = selinv_of(w);
+      si.zn = E.zn;
+      if (c0 == 0)
+        for (int j = 0; j < n; ++j)
+          if (selinv_prepare(si, j, s)) return ADELIA_E_HIP;
+      continue;
+    }
+    if (a > 0 && a <= kSkinnyRows) {  // V_j: a rows, G_j lower triangular
+      Skinny k{};
+      k.m = a; k.N = b; k.K1 = b; k.K2 = 0;
+      k.A1 = LC; k.lda1 = b + ap; k.zA1 = sLBC;
+      k.B1 = G; k.ldb1 = b; k.zB1 = bb;
+      k.C = Wm + bb; k.ldc = a; k.zC = sW;
+      k.alpha = 1.0; k.beta = 0.0;
+      k.zn = zn; k.zdiv = n; k.lowerB = 1;
+      if (launch_skinny(k, nzb, s)) return ADELIA_E_HIP;
+    } else if (a > 0) {
+      GemmArgs g{};
+      g.nph = 1;
+      g.ph[0].A = view_plain(LC, b + ap, sLBC);
+      g.ph[0].B = view_plain(G, b, bb);
+      g.ph[0].K = g.ph[0].Klast = b;
+      g.ph[0].kmode = KR_GE_N0;
+      g.ph[0].triB = TRI_LOWER;
+      g.ph[0].alpha = 1.0;
+      g.C = view_plain(Wm + bb, a, sW);
+      g.M = g.Mlast = a;
+      g.N = g.Nlast = b;
+      g.beta = 0.0;
+      g.omode = OUT_ALL;
+      g.tag = GT_SI_W;
+      g.blk = b;
+      g.zn = zn;
+      g.zdiv = n;
+      if (launch_gemm(g, 1, nzb, s)) return ADELIA_E_HIP;
+    }
+    {  // G_j^T G_j, full (the W_j product reads whole columns)
+      GemmArgs g{};
+      g.nph = 1;
+      g.ph[0].A = view_plain(G, b, bb, true);
+      g.ph[0].B = view_plain(G, b, bb);
+      g.ph[0].K = g.ph[0].Klast = b;
+      g.ph[0].kmode = KR_GE_MAX;
+      g.ph[0].triA = TRI_UPPER;
+      g.ph[0].triB = TRI_LOWER;
+      g.ph[0].alpha = 1.0;
+      g.C = view_plain(ZD, b, bb);
+      g.M = g.N = g.Mlast = g.Nlast = b;
+      g.beta = 0.0;
+      g.omode = OUT_LOWER_MIRROR;
+      g.tag = GT_SI_D;
+      g.blk = b;
+      g.zn = zn;
+      g.zdiv = n;
+      if (launch_gemm(g, 1, nzb, s)) return ADELIA_E_HIP;
+    }
+    // W_j = B_j G_j^T G_j
+    Models dev = E.dev;
+    if (dev.each) dev.v += c0 / 2;
+    if (launch_w(E.M, dev, 0, n, zn, ZD, bb, Wm, sW, w.phi + (c0 / 2) * sphi, nzb, s))
+      return ADELIA_E_HIP;
   }
   return 0;
 }
 
 // Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
 // tip == false (the halves of the two-sided split): the tips keep their Schur-complemented
-// values, unfactored, for the reduced system.
+// values, unfactored, for the reduced system.  A stored-factor gradient forms the
+// Z-independent part of the selected inversion after the sweep (prepare_all) unless prep is
+// false (the caller runs it).
 int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t s,
-                const SideRes* side, bool tip = true) {
+                const SideRes* side, bool tip = true, bool prep = true) {
   const ModelDev& M = E.M;
   const int nz = w.nz, n = w.n, b = w.b;
   hipLaunchKernelGGL(param_kernel, dim3(w.batch), dim3(256), 0, s, E.dev, theta, w.phi, w.dphi,
@@ -279,6 +424,11 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
   c.zn = E.zn;
   SelinvChains si = selinv_of(w);
   si.zn = E.zn;
+  // The gradient's side work used to run block by block beside the sweep (on the side stream,
+  // or inline without one); it now runs after the sweep for all blocks at once: beside the
+  // panels its long product tiles held the CUs the next panel launch needed, and on a shared
+  // hardware queue it delayed the look-ahead updates behind it.
+  if (w.defer) c.invert = false;
   const bool fork = c.invert && side && w.slotsD == 3;
   if (fork) {
     c.invert = false;
@@ -289,7 +439,7 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
                      w.Bin, w.zB, (long long)b, w.phi, w.tau);
   // With the side stream (a gradient: every block keeps its [L_B; L_C] slot), B_i is assembled
   // straight into the rows of [L_B; L_C] of block i instead of a separate slot.
-  c.b_in_place = fork;
+  c.b_in_place = fork || w.defer;
   const long long ldT = (long long)b + w.ap;
   for (int i = 0; i < n; ++i) {
     // the slot about to receive D_{i+1} held D_{i-2}: its inverse must be complete
@@ -299,11 +449,12 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
     const int tb = i < n - 1 ? i : -1;
     if (td >= 0 || tb >= 0) {
       double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * bb;
-      double* Bslot = fork ? w.LBC + (long long)(i % w.slotsLBC) * ldT * b : w.Bin;
+      const bool inplace = c.b_in_place;
+      double* Bslot = inplace ? w.LBC + (long long)(i % w.slotsLBC) * ldT * b : w.Bin;
       const ProfToken t = prof_begin(s);
       hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, E.dev, td, tb, Dslot,
-                         w.zD, Bslot, fork ? w.zLBC : w.zB, fork ? ldT : (long long)b, w.phi,
-                         w.tau);
+                         w.zD, Bslot, inplace ? w.zLBC : w.zB, inplace ? ldT : (long long)b,
+                         w.phi, w.tau);
       if (t.valid) prof_end(t, s, PK_ASSEMBLE, 0.0, 8.0 * bb * nz * ((td >= 0) + (tb >= 0)));
       if (!LAUNCH_OK()) return ADELIA_E_HIP;
     }
@@ -341,10 +492,11 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
     if (fork) {
       if (late && fork_block(i - 1, true)) return ADELIA_E_HIP;
       if (i == n - 1 && fork_block(i, false)) return ADELIA_E_HIP;
-    } else if (w.grad && !w.carry) {
+    } else if (w.grad && !w.carry && !w.defer) {
       if (prepare_block(E, w, si, i, s)) return ADELIA_E_HIP;
     }
   }
+  if (w.defer && prep && prepare_all(E, w, s)) return ADELIA_E_HIP;
   // the side stream runs its work in order: an event after its last product joins all of it
   if (fork && (hipEventRecord(side->done[n % 3], side->s2) != hipSuccess ||
                hipStreamWaitEvent(s, side->done[n % 3], 0) != hipSuccess))
@@ -520,7 +672,9 @@ bool aligned(const void* p, size_t al) { return ((uintptr_t)p % al) == 0; }
 // the panel launches (fused steps: one per panel; split panels: the diagonal tile, its rows'
 // GEMM and the trailing update; otherwise panel plus trailing update), the Schur update, and for
 // a gradient the inversion (two GEMMs per doubling level), the selected-inversion preparation
-// (three), its finish with the trace (four) and the upper solve (two).
+// (three), its finish with the trace (four) and the upper solve (two).  Counted per block, an
+// upper bound: a stored-factor gradient runs the inversion and the preparation once for all
+// blocks.
 long long launches_per_pass(const ModelDev& M, const SideRes* side, int batch, bool grad) {
   const int b = M.b, ap = M.a + 1, nz = 2 * batch;
   const int npanel = (b + kPanel - 1) / kPanel;
@@ -885,7 +1039,17 @@ static int run_split(inla_model m, const SplitWs& sw, const double* theta, doubl
   if (with_grad && (launch_fill(h.x, (long long)h.nz * h.zx, 0.0, s) ||
                     launch_fill(h.ZC, (long long)h.nz * h.zZC, 0.0, s)))
     return ADELIA_E_HIP;
-  if (int e = run_forward(Eh, h, sw.Th2, s, side, false)) return e;
+  if (int e = run_forward(Eh, h, sw.Th2, s, side, false, false)) return e;
+  // the halves' selected-inversion preparation (every block but the separator, which belongs
+  // to the reduced system) runs on the side stream beside the reduced system's factorisation,
+  // whose two chains leave most CUs idle
+  const bool fork_prep = with_grad && side;
+  if (fork_prep && (hipEventRecord(side->ready[1], s) != hipSuccess ||
+                    hipStreamWaitEvent(side->s2, side->ready[1], 0) != hipSuccess ||
+                    prepare_all(Eh, h, side->s2) ||
+                    hipEventRecord(side->done[1], side->s2) != hipSuccess))
+    return ADELIA_E_HIP;
+  if (with_grad && !side && prepare_all(Eh, h, s)) return ADELIA_E_HIP;
   const long long bb = (long long)b * b;
   const long long tot = bb + (long long)ap * b + (long long)ap * ap;
   hipLaunchKernelGGL(split_merge_kernel, dim3((unsigned)std::min<long long>((tot + 255) / 256, 1024), 1, 2),
@@ -923,6 +1087,7 @@ static int run_split(inla_model m, const SplitWs& sw, const double* theta, doubl
                      r.zXT, b, a, m->zn_split, h.slotsZD, h.ZD, h.zZD, h.ZC, h.zZC, h.ZT, h.zZT,
                      h.x, h.zx, h.xT, h.zXT);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
+  if (fork_prep && hipStreamWaitEvent(s, side->done[1], 0) != hipSuccess) return ADELIA_E_HIP;
   if (int e = run_backward(Eh, h, sw.Th2, sw.fv, sw.gv, sw.finfo, nullptr, s, side)) return e;
   hipLaunchKernelGGL(split_combine_kernel, dim3(1), dim3(64), 0, s, Models{m->Md, 0}, theta,
                      h.tau, h.ld, r.ld, r.zsq, h.info, r.info, sw.gv, sw.finfo, f, grad, info);
@@ -1001,6 +1166,24 @@ static int model_create_impl(adelia_ctx ctx, const inla_model_desc* d, inla_mode
     uptr[r + 1] = (int32_t)uidx.size();
   }
   const int nnz = (int)uidx.size();
+  // per tile of kWRows pattern rows: the pattern columns [lo, hi) its rows touch
+  const int wtiles = (ns + kWRows - 1) / kWRows;
+  std::vector<int32_t> wband(2 * (size_t)wtiles, 0);
+  int wband_w = 1, wdeg = 0;
+  for (int tt = 0; tt < wtiles; ++tt) {
+    int lo = INT_MAX, hi = INT_MIN;
+    for (int r = tt * kWRows; r < std::min(ns, (tt + 1) * kWRows); ++r) {
+      wdeg = std::max(wdeg, uptr[r + 1] - uptr[r]);
+      for (int e = uptr[r]; e < uptr[r + 1]; ++e) {
+        lo = std::min(lo, uidx[e]);
+        hi = std::max(hi, uidx[e] + 1);
+      }
+    }
+    if (lo > hi) lo = 0, hi = 1;  // no entries
+    wband[2 * tt] = lo;
+    wband[2 * tt + 1] = hi;
+    wband_w = std::max(wband_w, hi - lo);
+  }
   std::vector<double> uval;
   uval.insert(uval.end(), u0.begin(), u0.end());
   uval.insert(uval.end(), u1.begin(), u1.end());
@@ -1047,7 +1230,8 @@ static int model_create_impl(adelia_ctx ctx, const inla_model_desc* d, inla_mode
       {d->X, (size_t)n_obs * a * 8},     {d->y, (size_t)n_obs * 8},
       {obs_off.data(), obs_off.size() * 4}, {colptr.data(), colptr.size() * 4},
       {col_o.data(), col_o.size() * 4},  {col_e.data(), col_e.size() * 4},
-      {nullptr, (size_t)k * 8},          {nullptr, sizeof(ModelDev)}};
+      {nullptr, (size_t)k * 8},          {nullptr, sizeof(ModelDev)},
+      {wband.data(), wband.size() * 4}};
   size_t total = 0;
   std::vector<size_t> offsets;
   for (auto& pr : parts) {
@@ -1093,6 +1277,9 @@ static int model_create_impl(adelia_ctx ctx, const inla_model_desc* d, inla_mode
   M.col_o = (const int32_t*)(mem + offsets[12]);
   M.col_e = (const int32_t*)(mem + offsets[13]);
   M.yy = (const double*)(mem + offsets[14]);
+  M.wband = (const int32_t*)(mem + offsets[16]);
+  M.wband_w = wband_w;
+  M.wdeg = wdeg;
   for (int i = 0; i < k; ++i) M.nobs_field[i] = nobs[i];
   const int nl = k * (k - 1) / 2;
   if (d->param == ADELIA_PARAM_UNIVARIATE) {
@@ -1499,6 +1686,8 @@ int inla_batch_create(adelia_ctx ctx, int count, const inla_model* models, inla_
       g.Mh.nch_obs = std::max(g.Mh.nch_obs, M.nch_obs);
       g.Mh.nch_resid = std::max(g.Mh.nch_resid, M.nch_resid);
       g.Mh.n_obs = std::max(g.Mh.n_obs, M.n_obs);
+      g.Mh.wband_w = std::max(g.Mh.wband_w, M.wband_w);
+      g.Mh.wdeg = std::max(g.Mh.wdeg, M.wdeg);
     }
     if ((long long)g.Mh.b * g.Mh.nt + g.Mh.a > INT_MAX) return fail("batch group too large");
     goff.push_back(total);

@@ -26,9 +26,6 @@ namespace adelia {
 
 static inline long long blk_off(int t, int slots, long long bb) { return (long long)(t % slots) * bb; }
 
-// G_i = L_Di^-1 by recursive doubling over the 64 x 64 diagonal inverses left by the panels:
-// X21 = -X22 (L21 X11), two GEMMs per level.  Reads block i's L_Di and G_i slots and the
-// scratch; may run on another stream than the sweep once block i's panels are done.
 // CUs of the current device (cached per device)
 static int device_cus() {
   static int cache[64] = {0};
@@ -43,64 +40,81 @@ static int device_cus() {
   return cache[dev];
 }
 
-int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
-  const int b = c.b, nz = c.nz;
-  const long long bb = (long long)b * b;
-  double* Dblk = c.D + blk_off(i, c.slotsD, bb);
-  double* Gblk = c.G + blk_off(i, c.slotsG, bb);
+// G = L_D^-1 by recursive doubling over the 64 x 64 diagonal inverses left by the panels:
+// X21 = -X22 (L21 X11), two GEMMs per level, for nz problems in grid.z: problem z's L_D, G and
+// scratch are the b x b blocks at D + z*zD, G + z*zG and S + z*zS (zn, step, zdiv: which
+// problems take part, as in GemmArgs).  bta_invert_block reads block i's L_Di and G_i slots and
+// the chain's scratch; it may run on another stream than the sweep once block i's panels are
+// done.
+static int invert_levels(double* D, long long zD, double* G, long long zG, double* S,
+                         long long zS, int b, int nz, const int32_t* zn, int step, int zdiv,
+                         int maxwg, hipStream_t s) {
   for (int sz = kPanel; sz < b; sz *= 2) {
     const int P = (b - sz + 2 * sz - 1) / (2 * sz);
     const int s2 = b - 2 * (P - 1) * sz - sz < sz ? b - 2 * (P - 1) * sz - sz : sz;
     const long long ystep = 2LL * sz * (b + 1);
-    double* S = c.scratch;
     {  // T = L21 * X11  (X11 lower)
       GemmArgs g{};
       g.nph = 1;
-      g.ph[0].A = view_plain(Dblk + sz, b, c.zD);
-      g.ph[0].B = view_plain(Gblk, b, c.zG);
+      g.ph[0].A = view_plain(D + sz, b, zD);
+      g.ph[0].B = view_plain(G, b, zG);
       g.ph[0].K = g.ph[0].Klast = sz;
       g.ph[0].kmode = KR_GE_N0;
       g.ph[0].triB = TRI_LOWER;
       g.ph[0].alpha = 1.0;
       view_set_y(g.ph[0].A, ystep);
       view_set_y(g.ph[0].B, ystep);
-      g.C = view_plain(S + sz, b, c.zS);
+      g.C = view_plain(S + sz, b, zS);
       view_set_y(g.C, ystep);
       g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
-      g.blk = c.b;
-      g.maxwg = c.inv_maxwg;
-      g.zn = c.zn;
-      g.step = i;
+      g.blk = b;
+      g.maxwg = maxwg;
+      g.zn = zn;
+      g.step = step;
+      g.zdiv = zdiv;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
     {  // X21 = -X22 * T  (X22 lower)
       GemmArgs g{};
       g.nph = 1;
-      g.ph[0].A = view_plain(Gblk + sz + (long long)sz * b, b, c.zG);
-      g.ph[0].B = view_plain(S + sz, b, c.zS);
+      g.ph[0].A = view_plain(G + sz + (long long)sz * b, b, zG);
+      g.ph[0].B = view_plain(S + sz, b, zS);
       g.ph[0].K = sz; g.ph[0].Klast = s2;
       g.ph[0].kmode = KR_LT_M1;
       g.ph[0].triA = TRI_LOWER;
       g.ph[0].alpha = -1.0;
       view_set_y(g.ph[0].A, ystep);
       view_set_y(g.ph[0].B, ystep);
-      g.C = view_plain(Gblk + sz, b, c.zG);
+      g.C = view_plain(G + sz, b, zG);
       view_set_y(g.C, ystep);
       g.M = sz; g.Mlast = s2; g.N = g.Nlast = sz;
       g.beta = 0.0;
       g.omode = OUT_ALL;
       g.tag = GT_TRTRI;
-      g.blk = c.b;
-      g.maxwg = c.inv_maxwg;
-      g.zn = c.zn;
-      g.step = i;
+      g.blk = b;
+      g.maxwg = maxwg;
+      g.zn = zn;
+      g.step = step;
+      g.zdiv = zdiv;
       if (launch_gemm(g, P, nz, s)) return ADELIA_E_HIP_INTERNAL;
     }
   }
   return 0;
+}
+
+int bta_invert_block(const BtaChains& c, int i, hipStream_t s) {
+  const long long bb = (long long)c.b * c.b;
+  return invert_levels(c.D + blk_off(i, c.slotsD, bb), c.zD, c.G + blk_off(i, c.slotsG, bb),
+                       c.zG, c.scratch, c.zS, c.b, c.nz, c.zn, i, 0, c.inv_maxwg, s);
+}
+
+int bta_invert_blocks(double* D, double* G, double* S, int b, int nzb, int zdiv,
+                      const int32_t* zn, hipStream_t s) {
+  const long long bb = (long long)b * b;
+  return invert_levels(D, bb, G, bb, S, bb, b, nzb, zn, 0, zdiv, 0, s);
 }
 
 int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead* la) {

@@ -75,12 +75,22 @@ struct GemmArgs {
   // Uneven batches: chain z takes part only while step < zn[z] (zn == nullptr: always).
   const int32_t* zn;
   int step;
+  // zdiv > 0: grid.z runs over (chain, block) pairs, z = chain * zdiv + block (the views' z
+  // strides are then block strides), and the pair takes part only while block < zn[chain]
+  int zdiv;
   // 0: one workgroup per output tile; otherwise at most maxwg workgroups (a multiple of 8, at
   // least 8), each walking several tiles, which leaves CUs free for work on other streams
   int maxwg;
 };
 
 enum GemmTag { GT_OTHER = 0, GT_TRAIL, GT_TRTRI, GT_PROWS, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D, GT_COUNT };
+
+// Whether grid.z index z of a launch with per-chain block counts zn (null: none) has no work:
+// its chain's block count is reached at `step`, or (zdiv > 0) z names a block past it.
+__host__ __device__ inline bool z_idle(const int32_t* zn, int step, int zdiv, int z) {
+  if (!zn) return false;
+  return zdiv > 0 ? (z % zdiv) >= zn[z / zdiv] : step >= zn[z];
+}
 
 // ---- host helpers (gemm.hip) --------------------------------------------------------------
 View view_plain(double* p, long long ld, long long zstride, bool trans = false);
@@ -152,6 +162,11 @@ struct Lookahead {
 int bta_forward_block(const BtaChains& c, int i, hipStream_t s,
                       const Lookahead* la = nullptr);  // one block step
 int bta_invert_block(const BtaChains& c, int i, hipStream_t s);   // G_i = L_Di^-1 after step i
+// G = L_D^-1 for many blocks at once: nzb problems in grid.z, z = chain * zdiv + block; problem
+// z's L_D, G and scratch are the consecutive b x b slots at D + z*b*b, G + z*b*b, S + z*b*b;
+// blocks at or past zn[chain] are skipped (zn may be null).
+int bta_invert_blocks(double* D, double* G, double* S, int b, int nzb, int zdiv,
+                      const int32_t* zn, hipStream_t s);
 int bta_tip(const BtaChains& c, hipStream_t s);
 int bta_logdet_reduce(const double* ldpart, long long zLd, int nparts, double* out, long long zout,
                       int nz, hipStream_t s);

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   __shared__ double As[2][BK][T::LDS_ROW];
   __shared__ double Bs[2][BK][T::LDS_ROW];
   const int z = blockIdx.z, y = blockIdx.y;
-  if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
+  if (z_idle(args.zn, args.step, args.zdiv, z)) return;  // no block of chain z here
   const bool lasty = (y == (int)gridDim.y - 1);
   gemm_walk<LOOP, T>(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
 }
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(2 * NT) void gemm_f64_dual_kernel(const GemmArgs ar
   __shared__ double As[2][2][BK][T::LDS_ROW];
   __shared__ double Bs[2][2][BK][T::LDS_ROW];
   const int z = blockIdx.z, y = blockIdx.y;
-  if (args.zn && args.step >= args.zn[z]) return;  // chain z has no block at this step
+  if (z_idle(args.zn, args.step, args.zdiv, z)) return;  // no block of chain z here
   const bool lasty = (y == (int)gridDim.y - 1);
   gemm_walk_dual<T>(args, z, y, lasty, blockIdx.x, gridDim.x, As, Bs);
 }

@@ -451,9 +451,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& args, int M, int N, in
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give every XCD
 // a contiguous range of tiles so that neighbouring tiles, which share operand tiles, share an L2.
-__device__ __forceinline__ int xcd_remap(int L, int T) {
-  const int x = L & 7, idx = L >> 3;
+// With a triangular operand the K range, and so the work, of a tile depends on its row or
+// column, and a fixed assignment would hand one XCD the longest tiles of every problem: when the
+// ranges are of equal size (T a multiple of 8) the assignment is rotated by `rot` (the problem's
+// grid index), so that over a batch every XCD takes every range equally often.
+__device__ __forceinline__ int xcd_remap(int L, int T, int rot = 0) {
   const int per = T >> 3, rem = T & 7;
+  const int x = rem == 0 ? ((L + rot) & 7) : (L & 7), idx = L >> 3;
   return x * per + min(x, rem) + idx;
 }
 
@@ -540,7 +544,7 @@ __device__ __forceinline__ void gemm_walk_dual(const GemmArgs& args, int z, int 
       const int V = base + q * G;
       if (V >= NTL) continue;
       int qi, qj;
-      tile_of(args.omode, remap ? xcd_remap(V, NTL) : V, tilesM, tilesN, T0, qi, qj);
+      tile_of(args.omode, remap ? xcd_remap(V, NTL, z + y) : V, tilesM, tilesN, T0, qi, qj);
       nkr = max(nkr, tile_nk<T>(ph, lasty, qi * T::BM, qj * T::BN));
       if (q == h) {
         has = true;
@@ -582,13 +586,13 @@ __device__ __forceinline__ void gemm_walk(const GemmArgs& args, int z, int y, bo
   if constexpr (LOOP) {
     for (int V = v; V < NTL; V += nv) {
       int ti, tj;
-      tile_of(args.omode, remap ? xcd_remap(V, NTL) : V, tilesM, tilesN, T0, ti, tj);
+      tile_of(args.omode, remap ? xcd_remap(V, NTL, z + y) : V, tilesM, tilesN, T0, ti, tj);
       gemm_tile<T>(args, M, N, ti * T::BM, tj * T::BN, lasty, z, y, wm, wn, lane, As, Bs);
     }
   } else {
     if (v >= NTL) return;
     int ti, tj;
-    tile_of(args.omode, remap ? xcd_remap(v, NTL) : v, tilesM, tilesN, T0, ti, tj);
+    tile_of(args.omode, remap ? xcd_remap(v, NTL, z + y) : v, tilesM, tilesN, T0, ti, tj);
     gemm_tile<T>(args, M, N, ti * T::BM, tj * T::BN, lasty, z, y, wm, wn, lane, As, Bs);
   }
 }

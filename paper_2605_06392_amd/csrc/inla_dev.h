@@ -32,6 +32,10 @@ struct ModelDev {
   const int32_t* col_o;
   const int32_t* col_e;
   const double* yy;         // k: sum of y^2 per field
+  // the banded W_t product: per tile of kWRows pattern rows, the range [lo, hi) of pattern
+  // columns its rows touch; the widest range and the most entries in one pattern row
+  const int32_t* wband;
+  int wband_w, wdeg;
   int nobs_field[kMaxFields];
   int idx_range[kMaxFields], idx_temporal[kMaxFields], idx_prec[kMaxFields];
   int idx_lambda[kMaxFields * (kMaxFields - 1) / 2], idx_tau[kMaxFields];
@@ -100,8 +104,20 @@ __global__ void stencil_kernel(const double* theta, int d, double h, double* Th)
 __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* grad);
 __global__ void hess_stencil_kernel(const double* theta, int d, double h, double* Th);
 constexpr int kWBatch = 8;  // columns of W_t per pass of w_from_gtg_kernel (at most)
-__global__ void w_from_gtg_kernel(const Models Ms, int t, const double* Y, long long zY,
-                                  double* W, long long zW, const double* phi, int cb);
+constexpr int kWRows = 256;  // pattern rows per workgroup of w_band_kernel
+constexpr int kWDeg = 16;    // most entries per pattern row that w_band_kernel holds
+// W_t = B_t Y as w_from_gtg_kernel, for patterns with at most kWDeg entries per row; KF >= the
+// models' k.  Grid: x over tiles of kWRows pattern rows, y over slices of cs columns, z as in
+// w_from_gtg_kernel; dynamic LDS k * cb * (widest band) doubles.
+template <int KF>
+__global__ void w_band_kernel(const Models Ms, int t, int zdiv, const int32_t* zn,
+                              const double* Y, long long zY, double* W, long long zW,
+                              const double* phi, int cb, int cs);
+// zdiv > 0: grid.z runs over (chain, block) pairs, z = chain * zdiv + block (t is then the
+// block, zY and zW block strides, and blocks at or past zn[chain] are skipped; zn may be null)
+__global__ void w_from_gtg_kernel(const Models Ms, int t, int zdiv, const int32_t* zn,
+                                  const double* Y, long long zY, double* W, long long zW,
+                                  const double* phi, int cb);
 __global__ void fd_hessian_kernel(const double* fv, int d, double h, double* f, double* H);
 __global__ void grad_hessian_kernel(const double* fv, const double* gv, int d, double h,
                                     double* f, double* grad, double* H);

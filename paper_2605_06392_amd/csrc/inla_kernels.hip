@@ -682,12 +682,16 @@ __global__ void fd_kernel(const double* fv, int d, double h, double* f, double* 
 // columns of Y (stored in full) are loaded into LDS, then each row of B_t, its pattern and
 // values read once per batch, is applied to all of them.  Bound by the pattern reads (b/cb
 // passes over B_t) and by reading Y and writing W once: 16 b^2 bytes per chain.
-__global__ __launch_bounds__(256) void w_from_gtg_kernel(const Models Ms, int t, const double* Y,
+__global__ __launch_bounds__(256) void w_from_gtg_kernel(const Models Ms, int t, int zdiv,
+                                                         const int32_t* zn, const double* Y,
                                                          long long zY, double* W, long long zW,
                                                          const double* phi, int cb) {
   extern __shared__ double ys[];  // cb columns of Y, b each
   __shared__ double cB[kMaxFields][kMaxFields][3];
-  const int z = blockIdx.z, p = z >> 1;
+  const int z = blockIdx.z;
+  if (zdiv > 0) t = z % zdiv;
+  if (z_idle(zn, t, zdiv, z)) return;
+  const int p = (zdiv > 0 ? z / zdiv : z) >> 1;
   const ModelDev M = model_at(Ms, p);
   const int b = M.b, ns = M.ns, k = M.k;
   const double* Yz = Y + (long long)z * zY;
@@ -736,6 +740,121 @@ __global__ __launch_bounds__(256) void w_from_gtg_kernel(const Models Ms, int t,
     }
   }
 }
+
+// W_t = B_t Y, the product of w_from_gtg_kernel, with the pattern held in registers.  A
+// workgroup owns a tile of kWRows pattern rows rr (for every field i1: the rows i1 ns + rr of
+// W_t) and a slice of the columns; each thread keeps its pattern row's entries (column offsets
+// and the values of the three base matrices, padded with zeros to kWDeg) for the whole kernel.
+// The tile's rows touch pattern columns [lo, hi) only (a band, per field of Y), so cb columns of
+// those rows of Y go through LDS at a time, column-major with the band rows contiguous: the
+// threads of a wave read neighbouring addresses.  For each column a thread forms the three
+// base-matrix products T_s(i2) = sum_e U_s(rr, e) Y(i2 ns + qq_e, c) for every field i2 of Y and
+// combines them with the coupling coefficients: W_t(i1 ns + rr, c) =
+// sum_{i2, s} cB(i1, i2, s) T_s(i2).  Bound by reading Y's bands and writing W_t once.
+template <int KF>
+__global__ __launch_bounds__(256) void w_band_kernel(const Models Ms, int t, int zdiv,
+                                                     const int32_t* zn, const double* Y,
+                                                     long long zY, double* W, long long zW,
+                                                     const double* phi, int cb, int cs) {
+  extern __shared__ double ys[];  // k x cb x bw: (field, column, band row), band row fastest
+  __shared__ double cB[KF][KF][3];
+  const int z = blockIdx.z;
+  if (zdiv > 0) t = z % zdiv;
+  if (z_idle(zn, t, zdiv, z)) return;
+  const int p = (zdiv > 0 ? z / zdiv : z) >> 1;
+  const ModelDev M = model_at(Ms, p);
+  const int b = M.b, ns = M.ns, k = M.k;
+  const int r0 = blockIdx.x * kWRows;
+  if (r0 >= ns) return;  // a tile past this instance's pattern (uniform over the workgroup)
+  const int rr = r0 + threadIdx.x;
+  const bool act = rr < ns;
+  const int c0s = blockIdx.y * cs, c1s = min(b, c0s + cs);
+  const double* Yz = Y + (long long)z * zY;
+  double* Wz = W + (long long)z * zW;
+  if (t >= M.nt - 1) {
+    // no coupling block after the instance's last block (uneven batch): W_t = 0
+    if (act)
+      for (int c = c0s; c < c1s; ++c)
+        for (int i1 = 0; i1 < k; ++i1) Wz[(long long)c * b + i1 * ns + rr] = 0.0;
+    return;
+  }
+  if (threadIdx.x < k * k * 3) {
+    const int sidx = threadIdx.x % 3, i2 = (threadIdx.x / 3) % k, i1 = threadIdx.x / (3 * k);
+    const double* ph = phi + (long long)p * 9 * k * k;
+    double v = 0.0;
+    for (int r = 0; r < 3; ++r) v += tmat(M, r, t, 1) * ph[((r * k + i1) * k + i2) * 3 + sidx];
+    cB[i1][i2][sidx] = v;
+  }
+  const int lo = M.wband[2 * blockIdx.x], bw = M.wband[2 * blockIdx.x + 1] - lo;
+  int off[kWDeg];
+  double u0[kWDeg], u1[kWDeg], u2[kWDeg];
+  {
+    const int e0 = act ? M.uptr[rr] : 0;
+    const int ne = act ? M.uptr[rr + 1] - e0 : 0;
+#pragma unroll
+    for (int e = 0; e < kWDeg; ++e) {
+      const bool ok = e < ne;
+      const int ee = ok ? e0 + e : 0;
+      off[e] = ok ? M.uidx[ee] - lo : 0;
+      u0[e] = ok ? M.uval[ee] : 0.0;
+      u1[e] = ok ? M.uval[M.nnz + ee] : 0.0;
+      u2[e] = ok ? M.uval[2 * M.nnz + ee] : 0.0;
+    }
+  }
+  for (int cc0 = c0s; cc0 < c1s; cc0 += cb) {
+    const int nc = min(cb, c1s - cc0);
+    __syncthreads();  // the previous batch's reads of ys are done (and cB is written)
+    for (int ic = 0; ic < k * nc; ++ic) {
+      const int i2 = ic / nc, c = ic % nc;
+      const double* src = Yz + (long long)(cc0 + c) * b + i2 * ns + lo;
+      double* dst = ys + (i2 * cb + c) * bw;
+      for (int q = threadIdx.x; q < bw; q += 256) dst[q] = src[q];
+    }
+    __syncthreads();
+    if (!act) continue;
+    for (int c = 0; c < nc; ++c) {
+      double T[3][KF];
+#pragma unroll
+      for (int i2 = 0; i2 < KF; ++i2) {
+        T[0][i2] = 0.0;
+        T[1][i2] = 0.0;
+        T[2][i2] = 0.0;
+        if (i2 < k) {
+          const double* yc = ys + (i2 * cb + c) * bw;
+#pragma unroll
+          for (int e = 0; e < kWDeg; ++e) {
+            const double y = yc[off[e]];
+            T[0][i2] = fma(u0[e], y, T[0][i2]);
+            T[1][i2] = fma(u1[e], y, T[1][i2]);
+            T[2][i2] = fma(u2[e], y, T[2][i2]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i1 = 0; i1 < KF; ++i1) {
+        if (i1 >= k) break;
+        double w = 0.0;
+#pragma unroll
+        for (int i2 = 0; i2 < KF; ++i2) {
+          if (i2 >= k) break;
+          w = fma(cB[i1][i2][0], T[0][i2], w);
+          w = fma(cB[i1][i2][1], T[1][i2], w);
+          w = fma(cB[i1][i2][2], T[2][i2], w);
+        }
+        Wz[(long long)(cc0 + c) * b + i1 * ns + rr] = w;
+      }
+    }
+  }
+}
+
+template __global__ void w_band_kernel<1>(const Models, int, int, const int32_t*, const double*,
+                                          long long, double*, long long, const double*, int, int);
+template __global__ void w_band_kernel<2>(const Models, int, int, const int32_t*, const double*,
+                                          long long, double*, long long, const double*, int, int);
+template __global__ void w_band_kernel<3>(const Models, int, int, const int32_t*, const double*,
+                                          long long, double*, long long, const double*, int, int);
+template __global__ void w_band_kernel<4>(const Models, int, int, const int32_t*, const double*,
+                                          long long, double*, long long, const double*, int, int);
 
 // Points of the second-order central-difference Hessian (2d^2 + 1): 0 the centre; 1 + 2j and
 // 2 + 2j the steps +h e_j and -h e_j; then, for each pair j < k in order, four points

@@ -47,6 +47,8 @@ struct Skinny {
   double* C; long long ldc, zC;
   double alpha, beta;
   const int32_t* zn; int step;  // chain z takes part only while step < zn[z] (zn may be null)
+  int zdiv;    // > 0: grid.z runs over (chain, block) pairs as in GemmArgs::zdiv
+  int lowerB;  // B1 lower triangular: B1(k, n) = 0 for k < n is neither read nor summed
 };
 int launch_skinny(const Skinny& g, int nz, hipStream_t s);
 }  // namespace adelia

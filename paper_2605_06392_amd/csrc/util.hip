@@ -172,29 +172,34 @@ inline unsigned grid_for(long long n) {
 // are combined by a fixed-order reduce-scatter butterfly that leaves sum i on lane i.
 __global__ __launch_bounds__(256) void skinny_kernel(const Skinny g) {
   const int z = blockIdx.z;
-  if (g.zn && g.step >= g.zn[z]) return;
+  if (z_idle(g.zn, g.step, g.zdiv, z)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = (blockIdx.x * 4 + wave) * kSkinnyCols;
   if (n0 >= g.N) return;
   double v[kSkinnyRows * kSkinnyCols];
 #pragma unroll
   for (int i = 0; i < kSkinnyRows * kSkinnyCols; ++i) v[i] = 0.0;
-  auto part = [&](const double* A, long long lda, const double* B, long long ldb, int K) {
-    for (int k = lane; k < K; k += 64) {
+  // lower: B(k, n) = 0 for k < n, so the walk starts at the wave's first column and each column
+  // masks the rows above its own
+  auto part = [&](const double* A, long long lda, const double* B, long long ldb, int K,
+                  bool lower) {
+    for (int k = (lower ? n0 : 0) + lane; k < K; k += 64) {
       double av[kSkinnyRows];
 #pragma unroll
       for (int r = 0; r < kSkinnyRows; ++r) av[r] = r < g.m ? A[r + (long long)k * lda] : 0.0;
 #pragma unroll
       for (int j = 0; j < kSkinnyCols; ++j) {
-        const double bv = B[k + (long long)min(n0 + j, g.N - 1) * ldb];
+        const double bl = B[k + (long long)min(n0 + j, g.N - 1) * ldb];
+        const double bv = (lower && k < n0 + j) ? 0.0 : bl;
 #pragma unroll
         for (int r = 0; r < kSkinnyRows; ++r) v[r * kSkinnyCols + j] = fma(av[r], bv, v[r * kSkinnyCols + j]);
       }
     }
   };
-  part(g.A1 + (long long)z * g.zA1, g.lda1, g.B1 + (long long)z * g.zB1, g.ldb1, g.K1);
+  part(g.A1 + (long long)z * g.zA1, g.lda1, g.B1 + (long long)z * g.zB1, g.ldb1, g.K1,
+       g.lowerB != 0);
   if (g.A2 && g.K2 > 0)
-    part(g.A2 + (long long)z * g.zA2, g.lda2, g.B2 + (long long)z * g.zB2, g.ldb2, g.K2);
+    part(g.A2 + (long long)z * g.zA2, g.lda2, g.B2 + (long long)z * g.zB2, g.ldb2, g.K2, false);
   // reduce-scatter: at offset o a lane keeps half of its current values (the upper half if bit
   // o of its lane id is set) and adds the partner's copy of that half
 #pragma unroll
@@ -302,9 +307,15 @@ int launch_skinny(const Skinny& g, int nz, hipStream_t s) {
   const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(skinny_kernel, dim3((g.N + 4 * kSkinnyCols - 1) / (4 * kSkinnyCols), 1, nz),
                      dim3(256), 0, s, g);
-  if (t.valid)
-    prof_end(t, s, PK_GEMV, nz * 2.0 * g.m * (double)g.N * (g.K1 + g.K2),
-             nz * 8.0 * ((double)g.N * (g.K1 + g.K2) + (double)g.m * (g.K1 + g.K2) + g.m * g.N));
+  if (t.valid) {
+    // products taking part: all of the second pair; of the first, those on or below B1's
+    // diagonal when it is lower triangular
+    const double k1 = g.lowerB ? (double)g.N * g.K1 - 0.5 * (double)g.N * (g.N - 1)
+                               : (double)g.N * g.K1;
+    const double kk = k1 + (double)g.N * g.K2;
+    prof_end(t, s, PK_GEMV, nz * 2.0 * g.m * kk,
+             nz * 8.0 * (kk + (double)g.m * (g.K1 + g.K2) + g.m * g.N));
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
