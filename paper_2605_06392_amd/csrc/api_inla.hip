@@ -83,6 +83,7 @@ struct InlaWs {
   int slotsD, slotsB, slotsLBC, slotsG;
   double *D, *Bin, *LBC, *G, *C, *T, *S, *ldpart, *ld, *zsq, *ZT, *xT;
   long long zD, zB, zLBC, zG, zC, zT, zS, zLd, zZT, zXT;
+  long long sD;  // slot stride of D
   int32_t* info;
   int32_t* cnt;   // panel write-back counters (nz), zero between launches
   double *phi, *dphi, *tau;
@@ -137,7 +138,10 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = 
     off = align_up(off + (size_t)npts * sizeof(int32_t));
   }
   const int nz = w.nz;
-  w.D = take(w.slotsD * bb, nz, w.zD);
+  // a stored-factor gradient factors D_t in the slot of [W_t; V_t] (b^2 + a b doubles), free
+  // until the side work has read L_Dt; the other modes keep a ring of b x b slots
+  w.sD = bb;
+  if (!stored) w.D = take(w.slotsD * bb, nz, w.zD);
   w.Bin = take(w.slotsB * bb, nz, w.zB);
   w.LBC = take((long long)w.slotsLBC * (M.b + w.ap) * M.b, nz, w.zLBC);
   w.G = take(w.slotsG * bb, nz, w.zG);
@@ -167,6 +171,11 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = 
     // [W_t; V_t] and G_t^T G_t (the Z-independent parts of the selected inversion) are formed
     // during the forward sweep, so they get a slot per block
     w.W = take((long long)w.slotsW * (bb + (long long)M.a * M.b), nz, w.zW);
+    if (stored) {
+      w.D = w.W;
+      w.zD = w.zW;
+      w.sD = bb + (long long)M.a * M.b;
+    }
     w.ZD = take((long long)w.slotsZD * bb, nz, w.zZD);
     if (w.carry) {
       w.Dc = take((long long)n * bb, nz, w.zDc);
@@ -188,7 +197,7 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = 
 BtaChains chains_of(const InlaWs& w) {
   BtaChains c{};
   c.n = w.n; c.b = w.b; c.a = w.a; c.ap = w.ap; c.nz = w.nz;
-  c.D = w.D; c.zD = w.zD; c.slotsD = w.slotsD;
+  c.D = w.D; c.zD = w.zD; c.slotsD = w.slotsD; c.sD = w.sD;
   c.Bin = w.Bin; c.zB = w.zB; c.slotsB = w.slotsB;
   c.C = w.C; c.zC = w.zC;
   c.LBC = w.LBC; c.zLBC = w.zLBC; c.slotsLBC = w.slotsLBC;
@@ -299,7 +308,9 @@ int prepare_block(const Eval& E, const InlaWs& w, SelinvChains si, int j, hipStr
     const long long bb = (long long)b * b;
     const double* Y = w.ZD + (long long)(j % w.slotsZD) * bb;
     double* Wm = w.W + (long long)(j % w.slotsW) * (bb + (long long)w.a * b);
-    return launch_w(E.M, E.dev, j, 0, nullptr, Y, w.zZD, Wm, w.zW, w.phi, w.nz, s);
+    // chains past their block count skip the step: for the halves of the split their slot j
+    // holds the separator's diagonal block
+    return launch_w(E.M, E.dev, j, 0, E.zn, Y, w.zZD, Wm, w.zW, w.phi, w.nz, s);
   }
   return 0;
 }
@@ -313,7 +324,7 @@ int prepare_block(const Eval& E, const InlaWs& w, SelinvChains si, int j, hipStr
 int prepare_all(const Eval& E, const InlaWs& w, hipStream_t s) {
   const int n = w.n, b = w.b, a = w.a, ap = w.ap;
   if (!w.defer || w.slotsD != n || w.slotsG != n || w.slotsLBC != n || w.slotsW != n ||
-      w.slotsZD != n)
+      w.slotsZD != n || w.zD != (long long)n * w.sD)
     return ADELIA_E_HIP_INTERNAL;
   const long long bb = (long long)b * b;
   const long long sLBC = (long long)(b + ap) * b;
@@ -329,7 +340,7 @@ int prepare_all(const Eval& E, const InlaWs& w, hipStream_t s) {
     double* ZD = w.ZD + c0 * w.zZD;
     double* LC = w.LBC + c0 * w.zLBC + b;
     double* Wm = w.W + c0 * w.zW;
-    if (bta_invert_blocks(D, G, ZD, b, nzb, n, zn, s)) return ADELIA_E_HIP;
+    if (bta_invert_blocks(D, w.sD, G, ZD, b, nzb, n, zn, s)) return ADELIA_E_HIP;
     if (!sparse_w) {
       // W_j cannot be formed from G_j^T G_j: the per-block dense products of the sweep's own
       // preparation
@@ -398,6 +409,15 @@ int prepare_all(const Eval& E, const InlaWs& w, hipStream_t s) {
   return 0;
 }
 
+// Whether a stored-factor gradient forms its side work (G_j, [W_j; V_j], G_j^T G_j) block by
+// block on the side stream beside the sweep rather than for all blocks after it: when the
+// panel workgroups of a step fill at most half the CUs, the products have room beside them
+// (b = 1024, one gradient: 44.5 against 47.0 ms); with more chains the side stream's tiles hold
+// the CUs the next panel launch needs (four chains: 37.5 ms deferred against 40.0).
+static bool side_beside_sweep(const InlaWs& w, const SideRes* side) {
+  return side && 2LL * w.nz * panel_workgroups(w.b, 0, w.b + w.ap) <= side->la.cus;
+}
+
 // Assembly plus the forward sweeps of Qc and Qp for every theta point of the batch.
 // tip == false (the halves of the two-sided split): the tips keep their Schur-complemented
 // values, unfactored, for the reduced system.  A stored-factor gradient forms the
@@ -424,12 +444,13 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
   c.zn = E.zn;
   SelinvChains si = selinv_of(w);
   si.zn = E.zn;
-  // The gradient's side work used to run block by block beside the sweep (on the side stream,
-  // or inline without one); it now runs after the sweep for all blocks at once: beside the
-  // panels its long product tiles held the CUs the next panel launch needed, and on a shared
-  // hardware queue it delayed the look-ahead updates behind it.
-  if (w.defer) c.invert = false;
-  const bool fork = c.invert && side && w.slotsD == 3;
+  // The gradient's side work runs block by block beside the sweep when the panels leave room
+  // for it (side_beside_sweep), else after the sweep for all blocks at once (prepare_all):
+  // beside panels that fill the CUs its long product tiles delay the next panel launch, and on
+  // the look-ahead stream's hardware queue it delays the look-ahead updates behind it.
+  const bool defer = w.defer && !side_beside_sweep(w, side);
+  if (defer) c.invert = false;
+  const bool fork = c.invert && side && w.slotsD >= 3;
   if (fork) {
     c.invert = false;
     c.inv_maxwg = side->side_maxwg;
@@ -439,16 +460,17 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
                      w.Bin, w.zB, (long long)b, w.phi, w.tau);
   // With the side stream (a gradient: every block keeps its [L_B; L_C] slot), B_i is assembled
   // straight into the rows of [L_B; L_C] of block i instead of a separate slot.
-  c.b_in_place = fork || w.defer;
+  c.b_in_place = fork || defer;
   const long long ldT = (long long)b + w.ap;
   for (int i = 0; i < n; ++i) {
-    // the slot about to receive D_{i+1} held D_{i-2}: its inverse must be complete
+    // the sweep stays at most two blocks ahead of the side stream (without this wait: 46.1
+    // against 44.4 ms per gradient at b = 1024), which also keeps a ring of three D slots safe
     if (fork && i >= 2 && hipStreamWaitEvent(s, side->done[(i - 2) % 3], 0) != hipSuccess)
       return ADELIA_E_HIP;
     const int td = i + 1 < n ? i + 1 : -1;
     const int tb = i < n - 1 ? i : -1;
     if (td >= 0 || tb >= 0) {
-      double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * bb;
+      double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * w.sD;
       const bool inplace = c.b_in_place;
       double* Bslot = inplace ? w.LBC + (long long)(i % w.slotsLBC) * ldT * b : w.Bin;
       const ProfToken t = prof_begin(s);
@@ -472,7 +494,7 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
       la.mark_step = 0;
     }
     // carry-only: the diagonal block about to be factored is D_i - S_{i-1}
-    if (w.carry && launch_copy2d(w.D + (long long)(i % w.slotsD) * bb, b, w.zD,
+    if (w.carry && launch_copy2d(w.D + (long long)(i % w.slotsD) * w.sD, b, w.zD,
                                  w.Dc + (long long)i * bb, b, w.zDc, b, b, nz, s))
       return ADELIA_E_HIP;
     if (bta_forward_block(c, i, s, side ? &la : nullptr)) return ADELIA_E_HIP;
@@ -492,11 +514,11 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
     if (fork) {
       if (late && fork_block(i - 1, true)) return ADELIA_E_HIP;
       if (i == n - 1 && fork_block(i, false)) return ADELIA_E_HIP;
-    } else if (w.grad && !w.carry && !w.defer) {
+    } else if (w.grad && !w.carry && !defer) {
       if (prepare_block(E, w, si, i, s)) return ADELIA_E_HIP;
     }
   }
-  if (w.defer && prep && prepare_all(E, w, s)) return ADELIA_E_HIP;
+  if (defer && prep && prepare_all(E, w, s)) return ADELIA_E_HIP;
   // the side stream runs its work in order: an event after its last product joins all of it
   if (fork && (hipEventRecord(side->done[n % 3], side->s2) != hipSuccess ||
                hipStreamWaitEvent(s, side->done[n % 3], 0) != hipSuccess))
@@ -608,7 +630,7 @@ int run_backward(const Eval& E, const InlaWs& w, const double* theta, double* f,
     for (int j = n - 1; j >= 0; --j) {
       if (pipe && j + 2 <= n - 1 && hipStreamWaitEvent(s, finished[(j + 2) % 3], 0) != hipSuccess)
         return ADELIA_E_HIP;
-      double* Dslot = w.D + (long long)(j % w.slotsD) * bb;
+      double* Dslot = w.D + (long long)(j % w.slotsD) * w.sD;
       if (launch_copy2d(w.Dc + (long long)j * bb, b, w.zDc, Dslot, b, w.zD, b, b, nz, s))
         return ADELIA_E_HIP;
       if (j < n - 1) {
@@ -680,7 +702,7 @@ long long launches_per_pass(const ModelDev& M, const SideRes* side, int batch, b
   const int npanel = (b + kPanel - 1) / kPanel;
   const int cus = side ? side->la.cus : 256;
   const long long wg = (long long)nz * panel_workgroups(b, 0, b + ap);
-  const int per_panel = side && 2 * wg <= cus ? 1 : (wg > cus ? 3 : 2);
+  const int per_panel = side && wg <= cus ? 1 : (wg > cus ? 3 : 2);
   int levels = 0;
   for (int sz = kPanel; sz < b; sz *= 2) ++levels;
   long long per_block = 4 + (long long)per_panel * npanel;
@@ -1043,17 +1065,18 @@ static int run_split(inla_model m, const SplitWs& sw, const double* theta, doubl
   // the halves' selected-inversion preparation (every block but the separator, which belongs
   // to the reduced system) runs on the side stream beside the reduced system's factorisation,
   // whose two chains leave most CUs idle
-  const bool fork_prep = with_grad && side;
+  const bool deferred = with_grad && !side_beside_sweep(h, side);
+  const bool fork_prep = deferred && side;
   if (fork_prep && (hipEventRecord(side->ready[1], s) != hipSuccess ||
                     hipStreamWaitEvent(side->s2, side->ready[1], 0) != hipSuccess ||
                     prepare_all(Eh, h, side->s2) ||
                     hipEventRecord(side->done[1], side->s2) != hipSuccess))
     return ADELIA_E_HIP;
-  if (with_grad && !side && prepare_all(Eh, h, s)) return ADELIA_E_HIP;
+  if (deferred && !side && prepare_all(Eh, h, s)) return ADELIA_E_HIP;
   const long long bb = (long long)b * b;
   const long long tot = bb + (long long)ap * b + (long long)ap * ap;
   hipLaunchKernelGGL(split_merge_kernel, dim3((unsigned)std::min<long long>((tot + 255) / 256, 1024), 1, 2),
-                     dim3(256), 0, s, h.D, h.zD, bb, h.slotsD, h.C, h.zC, (long long)ap * b, h.T,
+                     dim3(256), 0, s, h.D, h.zD, h.sD, h.slotsD, h.C, h.zC, (long long)ap * b, h.T,
                      h.zT, m->zn_split, b, ap, r.D, r.zD, r.C, r.zC, r.T, r.zT);
   if (!LAUNCH_OK()) return ADELIA_E_HIP;
   // the reduced system: one block with the arrow and the tip

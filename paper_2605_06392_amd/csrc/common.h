@@ -122,6 +122,7 @@ int launch_zero_upper(double* p, int b, long long ld, long long blockstride, int
 struct BtaChains {
   int n, b, a, ap, nz;
   double* D; long long zD; int slotsD;      // in: D_t (lower) ; out: L_Dt
+  long long sD;                             // slot stride of D (0: b*b)
   const double* Bin; long long zB; int slotsB;  // B_t, ld b
   double* C; long long zC;                  // n blocks ap x b (ld ap): in C_t|r_t, updated in place
   // (b+ap) x b blocks, ld b+ap: out [L_Bt; L_Ct | z_t] (the rows solved with the panels of
@@ -148,12 +149,12 @@ struct BtaChains {
 int bta_forward(const BtaChains& c, hipStream_t s);
 // Look-ahead for the block Cholesky: each panel launch first applies the previous panel's
 // rank-64 update to its own columns, and the update of the columns after them runs beside the
-// next panel.  Batches whose panel launches leave most CUs idle get it in the same launch
+// next panel.  Batches whose panel workgroups fit on the CUs get it in the same launch
 // (launch_panel_step, consecutive steps in stream order); larger batches run it on stream ts,
 // ordered by events (panel k waits for the update issued after panel k-2).
 struct Lookahead {
   int maxwg;  // workgroup cap of the update part of a fused step (0: one per tile)
-  int cus;    // CUs of the device: fused steps while 2 x (panel workgroups) <= cus
+  int cus;    // CUs of the device: fused steps while the panel workgroups <= cus
   hipEvent_t mark;  // if not null: recorded on the sweep's stream after step (panel) mark_step
   int mark_step;
   hipStream_t ts;
@@ -163,9 +164,9 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s,
                       const Lookahead* la = nullptr);  // one block step
 int bta_invert_block(const BtaChains& c, int i, hipStream_t s);   // G_i = L_Di^-1 after step i
 // G = L_D^-1 for many blocks at once: nzb problems in grid.z, z = chain * zdiv + block; problem
-// z's L_D, G and scratch are the consecutive b x b slots at D + z*b*b, G + z*b*b, S + z*b*b;
-// blocks at or past zn[chain] are skipped (zn may be null).
-int bta_invert_blocks(double* D, double* G, double* S, int b, int nzb, int zdiv,
+// z's L_D, G and scratch are the b x b blocks at D + z*sD, G + z*b*b, S + z*b*b; blocks at or
+// past zn[chain] are skipped (zn may be null).
+int bta_invert_blocks(double* D, long long sD, double* G, double* S, int b, int nzb, int zdiv,
                       const int32_t* zn, hipStream_t s);
 int bta_tip(const BtaChains& c, hipStream_t s);
 int bta_logdet_reduce(const double* ldpart, long long zLd, int nparts, double* out, long long zout,
