@@ -235,7 +235,7 @@ def profiled_pass(args, ad_step, bta, torch):
         achieved = st["bytes"] / (kern_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    if name == "gemm_f64":
+    if st["bytes"] > 0:
         roof["algorithmic_bytes_per_launch"] = st["bytes"] / launches
     roof.update({"kernel": name, "kernel_symbol": KERNEL_SYMBOLS.get(name, name),
                  "launches_per_step": st["launches"] / args.profile_steps,
@@ -836,10 +836,9 @@ def main():
                                "algorithmic_bytes_per_launch":
                                    stats[kk]["bytes"] / max(1, stats[kk]["launches"]),
                                "launches_per_step": stats[kk]["launches"] / args.profile_steps}
-    if "gemm_f64" in stats:
-        gb = stats["gemm_f64"]["bytes"] / max(1, stats["gemm_f64"]["launches"])
-        roof["algorithmic_bytes_per_launch"] = gb
-        roof["traffic_over_algorithmic_bytes"] = (roof["traffic"] / gb) if roof.get("traffic") else None
+    # HBM traffic over the compulsory bytes of the dominant kernel (both per launch)
+    gb = roof.get("algorithmic_bytes_per_launch")
+    roof["traffic_over_algorithmic_bytes"] = (roof["traffic"] / gb) if (gb and roof.get("traffic")) else None
     line = {
         "metric": METRIC,
         "value": 1000.0 / ms_ad,

@@ -15,9 +15,11 @@ int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double*
                        long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
                        int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
                        int upd, int nz, hipStream_t s);
-// Workgroups of one panel launch per chain, and its algorithmic flops per chain.
+// Workgroups of one panel launch per chain, and its algorithmic flops and compulsory HBM bytes
+// per chain.
 int panel_workgroups(int b, int c0, int mT);
 double panel_flops(int b, int c0, int mT, int upd);
+double panel_bytes(int b, int c0, int mT, int upd);
 // Panel launch fused with the trailing update U of the previous panel (step.hip); U == nullptr
 // or an empty U: the panel alone.  At most maxw workgroups (0: one per tile) walk U's tiles.
 int launch_panel_step(double* D, long long zD, double* G, long long zG, double* ldp,

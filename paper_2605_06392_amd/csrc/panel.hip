@@ -32,6 +32,17 @@ double panel_flops(int b, int c0, int mT, int upd) {
   return ww * ww * ww / 3.0 + below * ww * ww + updfl;
 }
 
+double panel_bytes(int b, int c0, int mT, int upd) {
+  const double ww = (b - c0) < NB ? (b - c0) : NB;
+  const double below = (double)(b - c0) - ww + mT;
+  // the panel's columns read and written once (lower part of the diagonal tile and every row
+  // below), the diagonal tile's inverse written, and with upd the previous panel's columns on
+  // the same rows read
+  const double cols = ww * (ww + 1) / 2.0 + below * ww;
+  const double prev = (upd && c0 >= NB) ? (ww + below) * NB : 0.0;
+  return 8.0 * (2.0 * cols + ww * ww + prev);
+}
+
 int launch_panel_diag(double* D, long long zD, double* G, long long zG, double* ldp,
                       long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
                       int b, int c0, long long gcol0, int upd, double* V, long long zV, int nz,
@@ -41,7 +52,9 @@ int launch_panel_diag(double* D, long long zD, double* G, long long zG, double* 
               V, zV};
   const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(potrf_panel_kernel, dim3(1, 1, nz), dim3(256), 0, s, P);
-  if (t.valid) prof_end(t, s, PK_PANEL, nz * panel_flops(std::min(b, c0 + NB), c0, 0, upd), 0.0);
+  if (t.valid)
+    prof_end(t, s, PK_PANEL, nz * panel_flops(std::min(b, c0 + NB), c0, 0, upd),
+             nz * panel_bytes(std::min(b, c0 + NB), c0, 0, upd));
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -56,7 +69,8 @@ int launch_potrf_panel(double* D, long long zD, double* G, long long zG, double*
   const int rows = panel_workgroups(b, c0, mT);
   const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(potrf_panel_kernel, dim3(rows, 1, nz), dim3(256), 0, s, P);
-  if (t.valid) prof_end(t, s, PK_PANEL, nz * panel_flops(b, c0, mT, upd), 0.0);
+  if (t.valid)
+    prof_end(t, s, PK_PANEL, nz * panel_flops(b, c0, mT, upd), nz * panel_bytes(b, c0, mT, upd));
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -69,7 +69,8 @@ int launch_panel_step(double* D, long long zD, double* G, long long zG, double* 
   const ProfToken t = prof_begin(s);
   hipLaunchKernelGGL(panel_step_kernel, dim3(npw + ntw, 1, nz), dim3(256), 0, s, P, npw, *U, ntw);
   if (t.valid)
-    prof_end(t, s, PK_STEP, nz * panel_flops(b, c0, mT, upd) + gemm_flops(*U, 1) * nz, 0.0);
+    prof_end(t, s, PK_STEP, nz * panel_flops(b, c0, mT, upd) + gemm_flops(*U, 1) * nz,
+             nz * panel_bytes(b, c0, mT, upd) + gemm_bytes(*U, 1) * nz);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
