@@ -436,3 +436,36 @@ def test_batch_runner_replay_keeps_saved_factors():
     assert rel_inf(theta.grad.cpu().numpy(), ref["grad"]) <= 1e-8
     ref_o = oracle.gradient(spec, other)
     assert rel_inf(g_other[0].cpu().numpy(), ref_o["grad"]) <= 1e-8
+
+
+def test_long_pattern_rows_match_oracle():
+    """A mesh whose stiffness matrix couples node 0 with twelve distant nodes (each pair adds the
+    positive semidefinite eps (e_0 - e_j)(e_0 - e_j)^T) has a pattern row of more than 16
+    entries, longer than the banded W_t kernel holds in registers, so W_t = B_t G_t^T G_t goes
+    through the LDS-batched kernel, per block and for all blocks at once (split).  f and the
+    gradient match the oracle on the same matrices."""
+    import dataclasses
+    import scipy.sparse as sp
+    from paper_2605_06392_amd.inla import InlaModel
+    dev = _dev()
+    spec = make_model(1, 8, 6, 5, 3, 9, 31)
+    ns = spec.nx * spec.ny
+    g1 = spec.g1.tolil()
+    eps = 0.05
+    for j in range(ns - 12, ns):
+        g1[0, 0] += eps
+        g1[j, j] += eps
+        g1[0, j] -= eps
+        g1[j, 0] -= eps
+    spec = dataclasses.replace(spec, g1=sp.csr_matrix(g1))
+    union = (abs(spec.c0) + abs(spec.g1) + abs(spec.g2)).tocsr()
+    assert np.diff(union.indptr).max() > 16
+    m = InlaModel(spec, device=dev)
+    th = torch.tensor(spec.theta)
+    ref = oracle.gradient(spec, spec.theta)
+    for split in (False, True):
+        f, g, info = m.grad(th, split=split)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0, split
+        assert abs(f.item() - ref["f"]) <= 1e-10 * abs(ref["f"]), split
+        assert rel_inf(g.cpu().numpy(), ref["grad"]) <= 1e-8, split
