@@ -1,12 +1,13 @@
 // Panel step of the blocked Cholesky of a diagonal block (Sec. III-A-1, Alg. 1, chol()).
 //
 // The 64 x 64 diagonal tile of panel k is factored, together with its inverse, as two 32 x 32
-// leaves: each leaf is eliminated two columns per step by ONE wavefront (registers hold 2 x 2
-// sub-blocks, the current column pair travels through LDS; a single wave needs no workgroup
-// barrier between steps because its LDS operations complete in program order), and the
-// off-diagonal solve L21 = A21 X11^T, the update A22 -= L21 L21^T and the inverse merge
-// X21 = -X22 L21 X11 run on the matrix cores across the four waves.  Workgroup x > 0 also
-// solves its 64-row tile of the panel as A_jk L_kk^-T.
+// leaves, each two 16 x 16 leaves eliminated by ONE wavefront four columns per step in the
+// matrix cores' accumulator layout (each step's rank-4 updates of the leaf and of its inverse
+// are one 16 x 16 x 4 product each; a single wave needs no workgroup barrier because its LDS
+// operations complete in program order), and the off-diagonal solve L21 = A21 X11^T, the
+// update A22 -= L21 L21^T and the inverse merge X21 = -X22 L21 X11 run on the matrix cores
+// across the four waves.  Workgroup x > 0 also solves its 64-row tile of the panel as
+// A_jk L_kk^-T.
 //
 // The leaves are serial, so the other three waves work beside them: with the look-ahead
 // update (the previous panel's rank-64 contribution to this panel's columns, applied here
@@ -76,143 +77,104 @@ __device__ __forceinline__ void pivot(double d, double& pv, double& invs) {
 
 constexpr int QB = 16;  // edge of the serially eliminated leaves
 
-// Columns j0 = 2 JQ and j1 = j0 + 1 of a 16 x 16 leaf held as 2 x 2 blocks, one per lane (lane
-// (br, bc) holds rows 2 br.., columns 2 bc..).  The column pair has been published to LDS
-// updated but unscaled (cp: column j0 then column j1; xp: rows j0 and j1 of L^-1 before their
-// scaling), so every lane factors the 2 x 2 pivot block itself, scales the entries it needs and
-// applies the rank-2 update to the trailing part of L and to the rows of L^-1 below j1; then
-// the lanes holding pair JQ + 1 publish it.  Masks are selects on the operands: lanes above the
-// diagonal compute finite values that are never read.
+// A double from lane `src` of the wavefront (src a compile-time constant: uniform).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One step of the 16 x 16 leaf: columns j0 = 4 JQ .. j0 + 3.  The wavefront holds the leaf A
+// (being overwritten by L) and X^T (X becoming L^-1) in the accumulator layout of the matrix
+// cores: lane (m, c) = (lane % 16, lane / 16) holds column c + 4v of row m, v = 0..3.  So the
+// column block of this step is s[JQ], element (m, j0 + c) on lane (m, c).  Every lane factors
+// the 4 x 4 pivot block itself (read from the lanes holding it; the result is the same on
+// every lane) into L_p and M = L_p^-1; then lane (m, c) forms L(m, j0 + c) = sum_c' A(m, j0 + c')
+// M(c, c') and the scaled pivot row X_new(j0 + c, m) = sum_c' M(c, c') X(j0 + c', m) from the
+// three other lanes of its row, and the rank-4 updates of the trailing part of A and of the rows
+// of X below the block are each one 16 x 16 x 4 product with those values as its operands.
 template <int JQ>
-__device__ __forceinline__ void leaf_pair(double (&a)[2][2], double (&x)[2][2], double* cp,
-                                          double* xp, double* piv, int o, int br, int bc,
+__device__ __forceinline__ void leaf_step(v4d& s, v4d& xt, double* piv, int o, int m, int c,
                                           int lane) {
-  constexpr int j0 = 2 * JQ, j1 = j0 + 1;
-  const double* c0 = cp;
-  const double* c1 = cp + QB;
-  const double a00 = c0[j0], a10 = c0[j1], a11 = c1[j1];
-  double c0r[2], c1r[2], c0c[2], c1c[2], x0c[2], x1c[2];
+  constexpr int j0 = 4 * JQ;
+  // the pivot block (lower part), from the lanes holding it
+  double P[4][4];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    c0r[q] = c0[2 * br + q];
-    c1r[q] = c1[2 * br + q];
-    c0c[q] = c0[2 * bc + q];
-    c1c[q] = c1[2 * bc + q];
-    x0c[q] = xp[2 * bc + q];
-    x1c[q] = xp[QB + 2 * bc + q];
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q <= r; ++q) P[r][q] = lane_value(s[JQ], (j0 + r) + 16 * q);
+  // row m of the block column and rows j0.. of X at column m, from the lanes of row m
+  double a[4], xs[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    a[q] = __shfl(s[JQ], m + 16 * q, 64);
+    xs[q] = __shfl(xt[JQ], m + 16 * q, 64);
   }
-  double p0, r0, p1, r1;
-  pivot(a00, p0, r0);
-  const double l10 = a10 * r0;
-  const double d1 = fma(-l10, l10, a11);
+  // L_p (pivots d_r, reciprocal square roots r_r) and M = L_p^-1
+  double d0, d1, d2, d3, p0, p1, p2, p3, r0, r1, r2, r3;
+  d0 = P[0][0];
+  pivot(d0, p0, r0);
+  const double l10 = P[1][0] * r0, l20 = P[2][0] * r0, l30 = P[3][0] * r0;
+  d1 = fma(-l10, l10, P[1][1]);
   pivot(d1, p1, r1);
+  const double l21 = fma(-l20, l10, P[2][1]) * r1, l31 = fma(-l30, l10, P[3][1]) * r1;
+  d2 = fma(-l21, l21, fma(-l20, l20, P[2][2]));
+  pivot(d2, p2, r2);
+  const double l32 = fma(-l31, l21, fma(-l30, l20, P[3][2])) * r2;
+  d3 = fma(-l32, l32, fma(-l31, l31, fma(-l30, l30, P[3][3])));
+  pivot(d3, p3, r3);
   if (lane == 0) {
-    piv[o + j0] = a00;
-    piv[o + j1] = d1;
+    piv[o + j0] = d0;
+    piv[o + j0 + 1] = d1;
+    piv[o + j0 + 2] = d2;
+    piv[o + j0 + 3] = d3;
   }
-  const bool rowm = br > JQ, colm = bc > JQ;
-  double L0r[2], L1r[2], L0c[2], L1c[2], X0[2], X1[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    L0r[q] = c0r[q] * r0;
-    L1r[q] = fma(-L0r[q], l10, c1r[q]) * r1;
-    L0c[q] = c0c[q] * r0;
-    L1c[q] = fma(-L0c[q], l10, c1c[q]) * r1;
-    X0[q] = x0c[q] * r0;
-    X1[q] = fma(-l10, X0[q], x1c[q]) * r1;
-  }
-#pragma unroll
-  for (int ii = 0; ii < 2; ++ii) {
-    const double u0 = rowm ? L0r[ii] : 0.0, u1 = rowm ? L1r[ii] : 0.0;
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const double v0 = colm ? L0c[jj] : 0.0, v1 = colm ? L1c[jj] : 0.0;
-      a[ii][jj] = fma(-u0, v0, fma(-u1, v1, a[ii][jj]));
-      x[ii][jj] = fma(-u0, X0[jj], fma(-u1, X1[jj], x[ii][jj]));
-    }
-  }
-  if (bc == JQ) {
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii) {
-      a[ii][0] = L0r[ii];
-      a[ii][1] = L1r[ii];
-    }
-  }
-  if (br == JQ) {
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      x[0][jj] = X0[jj];
-      x[1][jj] = X1[jj];
-    }
-  }
-  wave_order();  // every lane has read pair JQ before it is replaced
-  if constexpr (JQ + 1 < QB / 2) {
-    if (bc == JQ + 1) {
-#pragma unroll
-      for (int ii = 0; ii < 2; ++ii) {
-        cp[2 * br + ii] = a[ii][0];
-        cp[QB + 2 * br + ii] = a[ii][1];
-      }
-    }
-    if (br == JQ + 1) {
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        xp[2 * bc + jj] = x[0][jj];
-        xp[QB + 2 * bc + jj] = x[1][jj];
-      }
-    }
-    wave_order();
-  }
+  const double M10 = -r1 * (l10 * r0);
+  const double M21 = -r2 * (l21 * r1);
+  const double M20 = -r2 * fma(l21, M10, l20 * r0);
+  const double M32 = -r3 * (l32 * r2);
+  const double M31 = -r3 * fma(l32, M21, l31 * r1);
+  const double M30 = -r3 * fma(l32, M20, fma(l31, M10, l30 * r0));
+  // row c of M (zero right of the diagonal)
+  const double mc0 = c == 0 ? r0 : (c == 1 ? M10 : (c == 2 ? M20 : M30));
+  const double mc1 = c == 0 ? 0.0 : (c == 1 ? r1 : (c == 2 ? M21 : M31));
+  const double mc2 = c <= 1 ? 0.0 : (c == 2 ? r2 : M32);
+  const double mc3 = c <= 2 ? 0.0 : r3;
+  double ell = fma(a[3], mc3, fma(a[2], mc2, fma(a[1], mc1, a[0] * mc0)));
+  const double xn = fma(mc3, xs[3], fma(mc2, xs[2], fma(mc1, xs[1], mc0 * xs[0])));
+  // L(m, j0 + c) lives on or below the diagonal; the rows below the block update X
+  ell = m >= j0 + c ? ell : 0.0;
+  const double ellb = m >= j0 + 4 ? ell : 0.0;
+  s = __builtin_amdgcn_mfma_f64_16x16x4f64(ell, -ell, s, 0, 0, 0);
+  xt = __builtin_amdgcn_mfma_f64_16x16x4f64(ellb, -xn, xt, 0, 0, 0);
+  s[JQ] = ell;
+  xt[JQ] = xn;
 }
 
 // Factor the 16 x 16 leaf at (o, o) of S (lower triangle, already updated) with one wavefront.
 // On exit S holds L (lower, zeros above) and X holds L^-1 on that leaf; piv[o + j] = pivot^2.
-__device__ void leaf16(double (*S)[LP], double (*X)[LP], double* cp, double* xp, double* piv,
-                       int o) {
+__device__ void leaf16(double (*S)[LP], double (*X)[LP], double* piv, int o) {
   const int lane = threadIdx.x & 63;
-  const int br = lane >> 3, bc = lane & 7;
-  double a[2][2], x[2][2];
+  const int m = lane & 15, c = lane >> 4;
+  v4d s, xt;
 #pragma unroll
-  for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int r = 2 * br + ii, c = 2 * bc + jj;
-      const double v = S[o + r][o + c];
-      a[ii][jj] = (r >= c) ? v : 0.0;
-      x[ii][jj] = (r == c) ? 1.0 : 0.0;
-    }
-  if (bc == 0) {
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii) {
-      cp[2 * br + ii] = a[ii][0];
-      cp[QB + 2 * br + ii] = a[ii][1];
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int n = c + 4 * v;
+    const double val = S[o + m][o + n];
+    s[v] = m >= n ? val : 0.0;
+    xt[v] = m == n ? 1.0 : 0.0;
   }
-  if (br == 0) {
+  leaf_step<0>(s, xt, piv, o, m, c, lane);
+  leaf_step<1>(s, xt, piv, o, m, c, lane);
+  leaf_step<2>(s, xt, piv, o, m, c, lane);
+  leaf_step<3>(s, xt, piv, o, m, c, lane);
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      xp[2 * bc + jj] = x[0][jj];
-      xp[QB + 2 * bc + jj] = x[1][jj];
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int n = c + 4 * v;
+    S[o + m][o + n] = m >= n ? s[v] : 0.0;  // L(m, n)
+    X[o + n][o + m] = n >= m ? xt[v] : 0.0;  // X(n, m) from X^T(m, n)
   }
-  wave_order();
-  leaf_pair<0>(a, x, cp, xp, piv, o, br, bc, lane);
-  leaf_pair<1>(a, x, cp, xp, piv, o, br, bc, lane);
-  leaf_pair<2>(a, x, cp, xp, piv, o, br, bc, lane);
-  leaf_pair<3>(a, x, cp, xp, piv, o, br, bc, lane);
-  leaf_pair<4>(a, x, cp, xp, piv, o, br, bc, lane);
-  leaf_pair<5>(a, x, cp, xp, piv, o, br, bc, lane);
-  leaf_pair<6>(a, x, cp, xp, piv, o, br, bc, lane);
-  leaf_pair<7>(a, x, cp, xp, piv, o, br, bc, lane);
-#pragma unroll
-  for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int r = 2 * br + ii, c = 2 * bc + jj;
-      const bool low = r >= c;
-      S[o + r][o + c] = low ? a[ii][jj] : 0.0;
-      X[o + r][o + c] = low ? x[ii][jj] : 0.0;
-    }
   wave_order();
 }
 
@@ -235,12 +197,11 @@ __device__ __forceinline__ v4d frag16(FA A, FB B, int fm, int fn, int K) {
 // 16 x 16 leaves, the coupling L21 = A21 X11^T, the update A22 -= L21 L21^T and the inverse
 // merge X21 = -X22 (L21 X11) on the matrix cores.  The wave orders its own LDS traffic, so no
 // workgroup barrier is needed; every fragment is read completely before it is overwritten.
-__device__ void leaf32(double (*S)[LP], double (*X)[LP], double* col, double* xr, double* piv,
-                       int o) {
+__device__ void leaf32(double (*S)[LP], double (*X)[LP], double* piv, int o) {
   const int lane = threadIdx.x & 63;
   const int m = lane & 15, n0 = lane >> 4;
   const int h = o + QB;
-  leaf16(S, X, col, xr, piv, o);
+  leaf16(S, X, piv, o);
   v4d t = frag16([&](int r, int k) { return S[h + r][o + k]; },
                  [&](int k, int c) { return X[o + c][o + k]; }, 0, 0, QB);
 #pragma unroll
@@ -251,7 +212,7 @@ __device__ void leaf32(double (*S)[LP], double (*X)[LP], double* col, double* xr
 #pragma unroll
   for (int v = 0; v < 4; ++v) S[h + m][h + n0 + 4 * v] -= t[v];
   wave_order();
-  leaf16(S, X, col, xr, piv, h);
+  leaf16(S, X, piv, h);
   t = frag16([&](int r, int k) { return S[h + r][o + k]; },
              [&](int k, int c) { return X[o + k][o + c]; }, 0, 0, QB);
 #pragma unroll
@@ -295,7 +256,7 @@ struct PanelSmem {
   double X[NB][LP];  // L_kk^-1
   double Q[NB][LP];  // previous panel on the diagonal tile's rows (with the update)
   double W[NB][LP];  // previous panel on this tile's rows, then the updated row tile
-  double col[2 * QB], xr[2 * QB], piv[NB];
+  double piv[NB];
   int writer;
 };
 
@@ -305,8 +266,6 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
   double (*X)[LP] = sm.X;
   double (*Q)[LP] = sm.Q;
   double (*W)[LP] = sm.W;
-  double* col = sm.col;
-  double* xr = sm.xr;
   double* piv = sm.piv;
   int& writer = sm.writer;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -395,7 +354,7 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
     __syncthreads();
   }
   if (wave == 0) {
-    leaf32(S, X, col, xr, piv, 0);
+    leaf32(S, X, piv, 0);
   } else {
     // beside the first leaf (which touches rows 0..31 of S and X only): the rest of the
     // diagonal tile's update, rows 32..63 (waves 2 and 3), and the updated row tile
@@ -444,7 +403,7 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
   for (int v = 0; v < 4; ++v) S[HB + fm + lm][HB + fn + lk + 4 * v] -= t[v];
   __syncthreads();
   if (wave == 0) {
-    leaf32(S, X, col, xr, piv, HB);
+    leaf32(S, X, piv, HB);
   } else if (rows) {
     // beside the second leaf (columns 32..63 of S and X): the row tile's first half
     // R1 = W1 X11^T, stored at once, and W2 -= R1 L21^T, so that R2 = W2 X22^T is all that
