@@ -469,3 +469,40 @@ def test_long_pattern_rows_match_oracle():
         assert int(info.item()) == 0, split
         assert abs(f.item() - ref["f"]) <= 1e-10 * abs(ref["f"]), split
         assert rel_inf(g.cpu().numpy(), ref["grad"]) <= 1e-8, split
+
+
+@pytest.mark.parametrize("k,nx,ny,nt,obs,seed", [(1, 6, 5, 5, 6, 51), (3, 4, 3, 4, 4, 52)])
+def test_no_fixed_effects_match_oracle(k, nx, ny, nt, obs, seed):
+    """a = 0: the arrow holds only the right-hand-side row (no V, no Z_C products, an empty
+    tip), for the plain sweep, the two-sided split and the carry-only mode."""
+    from paper_2605_06392_amd.inla import InlaModel
+    spec = make_model(k, nx, ny, nt, 0, obs, seed=seed)
+    m = InlaModel(spec, device=_dev())
+    ref = oracle.gradient(spec, spec.theta)
+    th = torch.tensor(spec.theta)
+    for kw in ({}, {"split": True}, {"carry": True}):
+        f, g, info = m.grad(th, **kw)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0, kw
+        assert abs(f.item() - ref["f"]) <= 1e-10 * abs(ref["f"]), kw
+        assert rel_inf(g.cpu().numpy(), ref["grad"]) <= 1e-8, kw
+        fo, io = m.objective(th[None], **kw) if "carry" not in kw else m.objective(th[None])
+        torch.cuda.synchronize()
+        assert int(io.item()) == 0, kw
+        assert abs(fo.item() - ref["f"]) <= 1e-10 * abs(ref["f"]), kw
+
+
+def test_many_fixed_effects_match_oracle():
+    """a = 10 > 8 arrow rows: V_t = L_Ct G_t and Z_Ct go through the tile GEMM instead of the
+    short-product kernel (plain sweep, split, carry-only)."""
+    from paper_2605_06392_amd.inla import InlaModel
+    spec = make_model(1, 6, 5, 5, 10, 12, seed=53)
+    m = InlaModel(spec, device=_dev())
+    ref = oracle.gradient(spec, spec.theta)
+    th = torch.tensor(spec.theta)
+    for kw in ({}, {"split": True}, {"carry": True}):
+        f, g, info = m.grad(th, **kw)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0, kw
+        assert abs(f.item() - ref["f"]) <= 1e-10 * abs(ref["f"]), kw
+        assert rel_inf(g.cpu().numpy(), ref["grad"]) <= 1e-8, kw
