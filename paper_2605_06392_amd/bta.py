@@ -176,9 +176,9 @@ class profile:
 
     def __exit__(self, *exc):
         from ._lib import KernelStats
-        arr = (KernelStats * 16)()
+        arr = (KernelStats * 32)()
         n = C.c_int(0)
-        check(lib().adelia_profile_stop(context(self.device), arr, 16, C.byref(n)), "profile_stop")
+        check(lib().adelia_profile_stop(context(self.device), arr, 32, C.byref(n)), "profile_stop")
         for i in range(n.value):
             s = arr[i]
             self.stats[s.name.decode()] = dict(launches=int(s.launches), ms=float(s.ms),

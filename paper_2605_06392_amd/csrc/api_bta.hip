@@ -245,6 +245,7 @@ int adelia_create(adelia_ctx* ctx, int device) {
       cus <= 0)
     cus = 256;
   c->la.cus = cus;
+  c->la.slots = cus * gemm_resident_per_cu();
   c->side_maxwg = std::max(16, (5 * cus / 8) & ~15);
   // the device address of bta_factor_noalloc's static scratch, taken here with the device
   // current (null if the query fails: that entry point then returns ADELIA_E_HIP)

@@ -95,6 +95,7 @@ struct InlaWs {
   long long zVp;
   double *x, *y, *W, *ZD, *ZB, *ZC, *TD, *TB, *O, *qD, *qB, *resid;
   long long zx, zy, zW, zZD, zZB, zZC, zTr, zO;
+  double* tws;  // kTailTiles partial tiles: the K split of the main stream's long products
   size_t bytes;
 };
 
@@ -160,6 +161,7 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = 
     w.cnt = w.info ? w.info + nz : nullptr;
     off = align_up(off + (size_t)2 * nz * sizeof(int32_t));
   }
+  w.tws = take((long long)kTailTiles * 64 * 64, 1, dummy);
   const long long NE = 9LL * M.k * M.k;
   w.phi = take(NE, batch, dummy);
   w.dphi = take(NE * M.d, batch, dummy);
@@ -442,6 +444,7 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
   const dim3 agrid(b, 1, nz);
   BtaChains c = chains_of(w);
   c.zn = E.zn;
+  if (side) c.tail = TailWs{w.tws, kTailTiles, side->la.slots};  // the Schur updates on s
   SelinvChains si = selinv_of(w);
   si.zn = E.zn;
   // The gradient's side work runs block by block beside the sweep when the panels leave room
@@ -570,6 +573,9 @@ int run_backward(const Eval& E, const InlaWs& w, const double* theta, double* f,
   };
   SelinvChains si = selinv_of(w);
   si.zn = E.zn;
+  // selinv_finish's products run on one stream at a time (s, or s3 of the carry-only pass,
+  // which starts after the forward sweep's Schur updates)
+  if (side) si.tail = TailWs{w.tws, kTailTiles, side->la.slots};
   const long long bb = (long long)b * b;
   const int ntrace = 2 * M.k * M.k * M.nch_rows + M.k * M.nch_obs;
   auto trace = [&](int j, hipStream_t ts) -> int {
@@ -982,6 +988,7 @@ static bool make_side(SideRes& sr, int device) {
     cus = 256;
   sr.la.maxwg = 0;
   sr.la.cus = cus;
+  sr.la.slots = cus * gemm_resident_per_cu();
   sr.la.mark = nullptr;
   sr.la.mark_step = 0;
   sr.side_maxwg = std::max(16, (5 * cus / 8) & ~15);

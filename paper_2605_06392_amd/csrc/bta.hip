@@ -291,6 +291,7 @@ int bta_forward_block(const BtaChains& c, int i, hipStream_t s, const Lookahead*
     g.blk = c.b;
     g.zn = c.zn;
     g.step = i;
+    g.tail = c.tail;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;
@@ -435,6 +436,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.maxwg = c.fin_maxwg;
     g.zn = c.zn;
     g.step = j;
+    g.tail = c.tail;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
     if (skinny) {  // Z_Cj = -(Z_C,j+1 W + Z_T V)
       Skinny k{};
@@ -493,6 +495,7 @@ int selinv_finish(const SelinvChains& c, int j, hipStream_t s) {
     g.maxwg = c.fin_maxwg;
     g.zn = c.zn;
     g.step = j;
+    g.tail = c.tail;
     if (launch_gemm(g, 1, nz, s)) return ADELIA_E_HIP_INTERNAL;
   }
   return 0;

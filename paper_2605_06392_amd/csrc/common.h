@@ -63,6 +63,20 @@ struct GemmPhase {
   double alpha;
 };
 
+// K split of the last, partial round of a launch's output tiles (launch_gemm): when the tiles
+// of a one-phase launch (ny == 1) take r >= 2 rounds of the device's resident workgroups and the
+// last round is at most half full, the first r - 1 rounds run as usual and the tiles of the
+// last are split along K over otherwise idle workgroups, their partial tiles summed in a fixed
+// order by a second launch (deterministic).  p: room for `tiles` 64 x 64 partial tiles; slots:
+// resident workgroups of the GEMM kernel on the device.  p == nullptr: no split.  A workspace
+// serves one stream at a time, and C must not overlap A or B.
+struct TailWs {
+  double* p;
+  int tiles;
+  int slots;
+};
+constexpr int kTailTiles = 512;  // partial tiles of the INLA workspaces
+
 struct GemmArgs {
   GemmPhase ph[2];
   int nph;
@@ -81,6 +95,7 @@ struct GemmArgs {
   // 0: one workgroup per output tile; otherwise at most maxwg workgroups (a multiple of 8, at
   // least 8), each walking several tiles, which leaves CUs free for work on other streams
   int maxwg;
+  TailWs tail;  // the last round's K split (uncapped launches only)
 };
 
 enum GemmTag { GT_OTHER = 0, GT_TRAIL, GT_TRTRI, GT_PROWS, GT_SYRK, GT_SI_W, GT_SI_Z, GT_SI_D, GT_COUNT };
@@ -98,6 +113,9 @@ View view_rowsplit(double* p0, long long ld0, long long zs0, double* p1, long lo
                    long long zs1, int rsplit, bool trans = false);
 void view_set_y(View& v, long long ystride);
 int launch_gemm(const GemmArgs& a, int ny, int nz, hipStream_t s);
+// Workgroups of the one-tile-per-workgroup GEMM kernel that one CU holds at once (the runtime's
+// occupancy query, made once per process; 0 if it fails).
+int gemm_resident_per_cu();
 // Tile edge (64 or 32) of the launches of role `tag` in sweeps of block size blk: the table the
 // autotuner fills (process-wide, read when a launch is enqueued; 64 without an entry).
 int tuned_tile(int blk, int tag);
@@ -145,6 +163,7 @@ struct BtaChains {
   // rebuild a block's factor from its stored Schur-updated diagonal block: B_i already in the
   // rows of [L_B; L_C], the arrow rows stored elsewhere (not solved again), no Schur update
   bool refactor;
+  TailWs tail;  // K split of the Schur update's last round (its stream's own workspace)
 };
 int bta_forward(const BtaChains& c, hipStream_t s);
 // Look-ahead for the block Cholesky: each panel launch first applies the previous panel's
@@ -155,6 +174,7 @@ int bta_forward(const BtaChains& c, hipStream_t s);
 struct Lookahead {
   int maxwg;  // workgroup cap of the update part of a fused step (0: one per tile)
   int cus;    // CUs of the device: fused steps while the panel workgroups <= cus
+  int slots;  // resident workgroups of the GEMM kernel on the device (cus x its occupancy)
   hipEvent_t mark;  // if not null: recorded on the sweep's stream after step (panel) mark_step
   int mark_step;
   hipStream_t ts;
@@ -192,6 +212,7 @@ struct SelinvChains {
   // in step j only while j < zn[z]; its block zn[z] - 1 has a zero coupling block (W = 0), and
   // the Z_D and Z_C slots of block zn[z] must hold zeros (finite) when step zn[z] - 1 runs
   const int32_t* zn;
+  TailWs tail;  // K split of the Z_D update's last round (selinv_finish's stream's workspace)
 };
 // The parts of backward step j that do not depend on Z (they can run as soon as G_j exists):
 // [W_j; V_j] = [L_Bj; L_Cj] G_j, and Z_Dj's lower triangle set to G_j^T G_j.

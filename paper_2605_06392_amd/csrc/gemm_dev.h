@@ -269,17 +269,20 @@ __device__ __forceinline__ void mfma_step(const double (*As)[T::LDS_ROW],
 // One phase as a software pipeline with a single site per stage (the kernel stays small, which
 // matters for short launches).  Iteration t issues the global loads of K tile t, runs tile t-1
 // from LDS on the matrix cores, then writes tile t to the other LDS buffer; one barrier per
-// iteration.  alpha is applied by the caller to the accumulators.
+// iteration.  alpha is applied by the caller to the accumulators.  [s0, s1): the range of the
+// tile's K steps to run (all by default).
 template <class T>
 __device__ __forceinline__ void run_phase(const GemmPhase& ph, int M, int N, int m0, int n0,
                                           bool lasty, int z, int y, int wm, int wn, int lane,
                                           double (*As)[BK][T::LDS_ROW],
                                           double (*Bs)[BK][T::LDS_ROW],
-                                          v4d (&acc)[T::FI][T::FJ]) {
+                                          v4d (&acc)[T::FI][T::FJ], int s0 = 0,
+                                          int s1 = INT_MAX) {
   const int K = lasty ? ph.Klast : ph.K;
   int klo, khi;
   krange<T>(ph.kmode, K, m0, n0, klo, khi);
-  const int nk = klo < khi ? (khi - klo + BK - 1) / BK : 0;
+  const int nk = max(0, min(klo < khi ? (khi - klo + BK - 1) / BK : 0, s1) - s0);
+  klo += s0 * BK;
   const VP A = make_vp(ph.A, z, y), B = make_vp(ph.B, z, y);
   OpPipe<T> pa, pb;
   pa.q = -1;
@@ -582,17 +585,20 @@ __device__ __forceinline__ void gemm_walk(const GemmArgs& args, int z, int y, bo
   const int wm = (wave & 1) * T::WM, wn = (wave >> 1) * T::WN;
   const int T0 = args.omode == OUT_ALL ? 0 : tilesN * (tilesN + 1) / 2;
   const int NTL = args.omode == OUT_ALL ? tilesM * tilesN : T0 + (tilesM - tilesN) * tilesN;
-  const bool remap = nv == NTL || (LOOP && (nv & 7) == 0);
   if constexpr (LOOP) {
+    const bool remap = nv == NTL || (nv & 7) == 0;
     for (int V = v; V < NTL; V += nv) {
       int ti, tj;
       tile_of(args.omode, remap ? xcd_remap(V, NTL, z + y) : V, tilesM, tilesN, T0, ti, tj);
       gemm_tile<T>(args, M, N, ti * T::BM, tj * T::BN, lasty, z, y, wm, wn, lane, As, Bs);
     }
   } else {
-    if (v >= NTL) return;
+    // the grid may cover fewer tiles than the problem has (the first rounds of a launch whose
+    // last round is split along K): the first nv tiles
+    const int L = xcd_remap(v, nv, z + y);
+    if (L >= NTL) return;
     int ti, tj;
-    tile_of(args.omode, remap ? xcd_remap(v, NTL, z + y) : v, tilesM, tilesN, T0, ti, tj);
+    tile_of(args.omode, L, tilesM, tilesN, T0, ti, tj);
     gemm_tile<T>(args, M, N, ti * T::BM, tj * T::BN, lasty, z, y, wm, wn, lane, As, Bs);
   }
 }

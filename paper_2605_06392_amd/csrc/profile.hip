@@ -55,6 +55,7 @@ const char* kind_name(int k) {
     case PK_GEMM_ROLE0 + 5: return "gemm_f64:si_W";
     case PK_GEMM_ROLE0 + 6: return "gemm_f64:si_ZB";
     case PK_GEMM_ROLE0 + 7: return "gemm_f64:si_ZD";
+    case PK_GEMM_SPLIT: return "gemm_f64:split_last_round";
     default: return "other";
   }
 }
@@ -85,13 +86,14 @@ void prof_end(const ProfToken& t, hipStream_t s, int kind, double flops, double 
 }
 
 void prof_end_role(const ProfToken& t, hipStream_t s, int kind, int role, double flops,
-                   double bytes) {
+                   double bytes, int also) {
   if (!t.valid) return;
   ProfState& P = st();
   hipEventRecord(t.b, s);
   std::lock_guard<std::mutex> g(P.mu);
   P.recs.push_back(Rec{kind, t.a, t.b, flops, bytes});
   P.recs.push_back(Rec{PK_GEMM_ROLE0 + role, t.a, t.b, flops, bytes});
+  if (also >= 0 && also < PK_COUNT) P.recs.push_back(Rec{also, t.a, t.b, flops, bytes});
 }
 
 }  // namespace adelia
