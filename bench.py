@@ -222,7 +222,9 @@ def profiled_pass(args, ad_step, bta, torch):
     # taken off every launch interval of the dominant kernel.
     ovh_ms = event_gap_ms(torch)
     gemm_like = {k: v for k, v in stats.items() if ":" not in k}
-    name, st = max(gemm_like.items(), key=lambda kv: kv[1]["ms"])
+    # the dominant kernel by kernel time: its event time less one record gap per launch (a
+    # kernel launched often would otherwise be charged for its many gaps)
+    name, st = max(gemm_like.items(), key=lambda kv: kv[1]["ms"] - kv[1]["launches"] * ovh_ms)
     launches = max(st["launches"], 1)
     raw_ms = st["ms"]
     kern_ms = max(raw_ms - launches * ovh_ms, 1e-9)
