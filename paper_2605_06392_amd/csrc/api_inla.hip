@@ -252,7 +252,7 @@ constexpr int kWGroups = 512;
 static int w_band_cols(const ModelDev& M) {
   if (!M.wband || M.wdeg > kWDeg || M.k < 1 || M.k > kMaxFields) return 0;
   const long long per = (long long)M.k * M.wband_w * (long long)sizeof(double);
-  return (int)std::min<long long>(16, (64 * 1024) / per);
+  return (int)std::min<long long>(16, kWPassBytes / per);
 }
 
 // Columns of Y per pass of the LDS-batched W_t kernel (0: a column does not fit in 64 KB).

@@ -106,6 +106,7 @@ __global__ void hess_stencil_kernel(const double* theta, int d, double h, double
 constexpr int kWBatch = 8;  // columns of W_t per pass of w_from_gtg_kernel (at most)
 constexpr int kWRows = 256;  // pattern rows per workgroup of w_band_kernel
 constexpr int kWDeg = 16;    // most entries per pattern row that w_band_kernel holds
+constexpr int kWPassBytes = 64 * 1024;  // LDS of one w_band_kernel pass (k x cb x band doubles)
 // W_t = B_t Y as w_from_gtg_kernel, for patterns with at most kWDeg entries per row; KF >= the
 // models' k.  Grid: x over tiles of kWRows pattern rows, y over slices of cs columns, z as in
 // w_from_gtg_kernel; dynamic LDS k * cb * (widest band) doubles.
