@@ -603,5 +603,158 @@ __device__ __forceinline__ void gemm_walk(const GemmArgs& args, int z, int y, bo
   }
 }
 
+// ---- two tiles of a row per workgroup (the look-ahead step's update part) ----------------
+//
+// A kernel that holds one workgroup per CU (the look-ahead step: its panel workgroups need
+// 134 KB of LDS) runs one wave per SIMD, so a single tile's K steps leave the matrix cores idle
+// while its loads are in flight.  There the update's workgroups take two horizontally adjacent
+// tiles (ti, tj) and (ti, tj + 1) of the lower trapezoid at once: the A tile is loaded and read
+// from LDS once for both, and every wave has twice the independent matrix-core work per K step.
+// For one-phase products whose K range does not depend on the column (KR_FULL, KR_LT_M1) and
+// whose B is not triangular.
+
+// Units of the lower trapezoid of a tilesM x tilesN tile grid (M >= N): row ti holds
+// min(ti + 1, tilesN) tiles, paired from the left (an odd row ends with a single tile).
+// Rows 2p and 2p + 1 of the triangle hold p + 1 units each, so the triangle's first 2q rows
+// hold q (q + 1) units and its first 2q + 1 rows (q + 1)^2.
+__host__ __device__ inline long long pair_units(int tilesM, int tilesN) {
+  const long long q = tilesN / 2;
+  const long long tri = (tilesN & 1) ? (q + 1) * (q + 1) : q * (q + 1);
+  return tri + (long long)(tilesM - tilesN) * ((tilesN + 1) / 2);
+}
+
+// Unit L: row ti, first column tj0 and its tile count (1 or 2).
+__device__ __forceinline__ void pair_of(int L, int tilesN, int& ti, int& tj0, int& cnt) {
+  const int qn = tilesN / 2;
+  const int UT = (tilesN & 1) ? (qn + 1) * (qn + 1) : qn * (qn + 1);
+  int len;
+  if (L < UT) {
+    int q = (int)((sqrt(4.0 * L + 1.0) - 1.0) * 0.5);  // largest q with q (q + 1) <= L
+    while (q * (q + 1) > L) --q;
+    while ((q + 1) * (q + 2) <= L) ++q;
+    if (L < (q + 1) * (q + 1)) {
+      ti = 2 * q;
+      tj0 = 2 * (L - q * (q + 1));
+    } else {
+      ti = 2 * q + 1;
+      tj0 = 2 * (L - (q + 1) * (q + 1));
+    }
+    len = ti + 1;
+  } else {
+    const int uN = (tilesN + 1) / 2;
+    ti = tilesN + (L - UT) / uN;
+    tj0 = 2 * ((L - UT) % uN);
+    len = tilesN;
+  }
+  cnt = min(2, len - tj0);
+}
+
+// One K step of both tiles: per wave 8 x FI x FJ x 2 MFMAs, the A fragments read once.
+template <class T>
+__device__ __forceinline__ void mfma_step2(const double (*As)[T::LDS_ROW],
+                                           const double (*B0)[T::LDS_ROW],
+                                           const double (*B1)[T::LDS_ROW], int wm, int wn,
+                                           int lane, v4d (&acc0)[T::FI][T::FJ],
+                                           v4d (&acc1)[T::FI][T::FJ]) {
+#pragma unroll
+  for (int kk = 0; kk < BK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+    double a[T::FI], b0[T::FJ], b1[T::FJ];
+#pragma unroll
+    for (int bi = 0; bi < T::FI; ++bi) a[bi] = As[kr][wm + 16 * bi + (lane & 15)];
+#pragma unroll
+    for (int bj = 0; bj < T::FJ; ++bj) {
+      b0[bj] = B0[kr][wn + 16 * bj + (lane & 15)];
+      b1[bj] = B1[kr][wn + 16 * bj + (lane & 15)];
+    }
+#pragma unroll
+    for (int bj = 0; bj < T::FJ; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < T::FI; ++bi) {
+        acc0[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0[bj], a[bi], acc0[bi][bj], 0, 0, 0);
+        acc1[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1[bj], a[bi], acc1[bi][bj], 0, 0, 0);
+      }
+  }
+}
+
+// run_phase for the tiles at (m0, n0) and (m0, n0 + BN), one pipeline.
+template <class T>
+__device__ __forceinline__ void run_phase2(const GemmPhase& ph, int M, int N, int m0, int n0,
+                                           int z, int wm, int wn, int lane,
+                                           double (*As)[BK][T::LDS_ROW],
+                                           double (*B0)[BK][T::LDS_ROW],
+                                           double (*B1)[BK][T::LDS_ROW],
+                                           v4d (&acc0)[T::FI][T::FJ], v4d (&acc1)[T::FI][T::FJ]) {
+  const int K = ph.Klast;
+  int klo, khi;
+  krange<T>(ph.kmode, K, m0, n0, klo, khi);
+  const int nk = klo < khi ? (khi - klo + BK - 1) / BK : 0;
+  const VP A = make_vp(ph.A, z, 0), B = make_vp(ph.B, z, 0);
+  OpPipe<T> pa, pb0, pb1;
+  pa.q = -1;
+  pb0.q = -1;
+  pb1.q = -1;
+  for (int t = 0; t <= nk; ++t) {
+    const int k0 = klo + t * BK;
+    if (t < nk) {
+      load_tile<T>(pa, A, M, K, m0, k0, false);
+      load_tile<T>(pb0, B, N, K, n0, k0, true);
+      load_tile<T>(pb1, B, N, K, n0 + T::BN, k0, true);
+    }
+    if (t > 0)
+      mfma_step2<T>(As[(t - 1) & 1], B0[(t - 1) & 1], B1[(t - 1) & 1], wm, wn, lane, acc0, acc1);
+    if (t < nk) {
+      store_tile<T>(pa, As[t & 1], M, K, m0, k0, ph.triA, false);
+      store_tile<T>(pb0, B0[t & 1], N, K, n0, k0, ph.triB, true);
+      store_tile<T>(pb1, B1[t & 1], N, K, n0 + T::BN, k0, ph.triB, true);
+    }
+    __syncthreads();
+  }
+}
+
+// The units of chain z handled by workgroup slot v of nv (v, v + nv, ...), a one-phase lower
+// product with ny == 1; the XCD mapping is kept when nv covers the units or is a multiple of 8.
+template <class T = Tile64>
+__device__ __forceinline__ void gemm_walk_pairs(const GemmArgs& args, int z, int v, int nv,
+                                                double (*As)[BK][T::LDS_ROW],
+                                                double (*B0)[BK][T::LDS_ROW],
+                                                double (*B1)[BK][T::LDS_ROW]) {
+  const int M = args.Mlast, N = args.Nlast;
+  const int tilesM = (M + T::BM - 1) / T::BM, tilesN = (N + T::BN - 1) / T::BN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave & 1) * T::WM, wn = (wave >> 1) * T::WN;
+  const int NU = (int)pair_units(tilesM, tilesN);
+  const bool remap = nv == NU || (nv & 7) == 0;
+  const GemmPhase& ph = args.ph[0];
+  for (int V = v; V < NU; V += nv) {
+    int ti, tj0, cnt;
+    pair_of(remap ? xcd_remap(V, NU, z) : V, tilesN, ti, tj0, cnt);
+    const int m0 = ti * T::BM, n0 = tj0 * T::BN;
+    // C is read in the epilogue: reading both tiles' C before the K loop, as gemm_tile does,
+    // took the kernel to 256 VGPRs + 68 AGPRs and the split gradient from 33.6 to 34.8 ms
+    v4d acc0[T::FI][T::FJ], acc1[T::FI][T::FJ];
+#pragma unroll
+    for (int bi = 0; bi < T::FI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < T::FJ; ++bj) {
+        acc0[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+        acc1[bi][bj] = (v4d){0.0, 0.0, 0.0, 0.0};
+      }
+    if (cnt == 2)
+      run_phase2<T>(ph, M, N, m0, n0, z, wm, wn, lane, As, B0, B1, acc0, acc1);
+    else
+      run_phase<T>(ph, M, N, m0, n0, true, z, 0, wm, wn, lane, As, B0, acc0);
+#pragma unroll
+    for (int bi = 0; bi < T::FI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < T::FJ; ++bj) {
+        acc0[bi][bj] *= ph.alpha;
+        acc1[bi][bj] *= ph.alpha;
+      }
+    tile_store<T>(args, M, N, m0, n0, z, 0, wm, wn, lane, acc0);
+    if (cnt == 2) tile_store<T>(args, M, N, m0, n0 + T::BN, z, 0, wm, wn, lane, acc1);
+  }
+}
+
 }  // namespace gemm_dev
 }  // namespace adelia

@@ -15,18 +15,26 @@ namespace adelia {
 
 namespace {
 
+// the update part of a step computes two tiles of a row per workgroup (gemm_walk_pairs)
+constexpr bool kStepPairs = true;
+
 struct GemmSmem {
   double As[2][gemm_dev::BK][gemm_dev::LDS_ROW];
   double Bs[2][gemm_dev::BK][gemm_dev::LDS_ROW];
+  double Bs1[2][gemm_dev::BK][gemm_dev::LDS_ROW];  // the second tile of a pair
 };
 
 union StepSmem {
   panel_dev::PanelSmem p;
   GemmSmem g;
 };
+static_assert(sizeof(GemmSmem) <= sizeof(panel_dev::PanelSmem),
+              "the update's operand buffers fit in the panel's LDS");
 
+// pairs: the update's workgroups take two tiles of a row at once (gemm_walk_pairs; ntw counts
+// units), else one tile each (gemm_walk).
 __global__ __launch_bounds__(256) void panel_step_kernel(const panel_dev::PanelArgs P, int npw,
-                                                         const GemmArgs U, int ntw) {
+                                                         const GemmArgs U, int ntw, int pairs) {
   static_assert(gemm_dev::NT == 256, "the panel and the tile GEMM share the workgroup shape");
   __shared__ StepSmem sm;
   const int bx = blockIdx.x;
@@ -36,7 +44,10 @@ __global__ __launch_bounds__(256) void panel_step_kernel(const panel_dev::PanelA
   }
   const int z = blockIdx.z;
   if (U.zn && U.step >= U.zn[z]) return;  // chain z has no block at this step
-  gemm_dev::gemm_walk<true>(U, z, 0, true, bx - npw, ntw, sm.g.As, sm.g.Bs);
+  if (pairs)
+    gemm_dev::gemm_walk_pairs(U, z, bx - npw, ntw, sm.g.As, sm.g.Bs, sm.g.Bs1);
+  else
+    gemm_dev::gemm_walk<true>(U, z, 0, true, bx - npw, ntw, sm.g.As, sm.g.Bs);
 }
 
 }  // namespace
@@ -45,7 +56,7 @@ int launch_panel_step(double* D, long long zD, double* G, long long zG, double* 
                       long long zLd, int32_t* info, int32_t* cnt, const int32_t* zn, int step,
                       int b, int c0, long long gcol0, double* T, long long zT, int ldT, int mT,
                       int upd, int nz, const GemmArgs* U, int maxw, hipStream_t s) {
-  long long tiles = 0;
+  long long tiles = 0, units = 0;
   if (U) {
     // one sub-problem, one phase, lower output (the trailing update)
     if (U->nph != 1 || U->omode == OUT_ALL || U->M != U->Mlast || U->N != U->Nlast ||
@@ -54,7 +65,11 @@ int launch_panel_step(double* D, long long zD, double* G, long long zG, double* 
     const long long tM = (U->M + gemm_dev::BM - 1) / gemm_dev::BM;
     const long long tN = (U->N + gemm_dev::BN - 1) / gemm_dev::BN;
     tiles = U->N > 0 ? tN * (tN + 1) / 2 + (tM - tN) * tN : 0;
+    units = U->N > 0 ? gemm_dev::pair_units((int)tM, (int)tN) : 0;
   }
+  // tile pairs: the K range may not depend on the column, and B may not be triangular
+  const bool pairs = U && kStepPairs && (U->ph[0].kmode == KR_FULL || U->ph[0].kmode == KR_LT_M1) &&
+                     U->ph[0].triB == TRI_NONE;
   if (tiles == 0)
     return launch_potrf_panel(D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT,
                               ldT, mT, upd, nz, s);
@@ -64,10 +79,11 @@ int launch_panel_step(double* D, long long zD, double* G, long long zG, double* 
   panel_dev::PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT, ldT,
                          mT, upd};
   const int npw = panel_workgroups(b, c0, mT);
-  int ntw = (int)tiles;
+  int ntw = (int)(pairs ? units : tiles);
   if (maxw > 0 && ntw > maxw) ntw = maxw < 8 ? 8 : (maxw & ~7);
   const ProfToken t = prof_begin(s);
-  hipLaunchKernelGGL(panel_step_kernel, dim3(npw + ntw, 1, nz), dim3(256), 0, s, P, npw, *U, ntw);
+  hipLaunchKernelGGL(panel_step_kernel, dim3(npw + ntw, 1, nz), dim3(256), 0, s, P, npw, *U, ntw,
+                     pairs ? 1 : 0);
   if (t.valid)
     prof_end(t, s, PK_STEP, nz * panel_flops(b, c0, mT, upd) + gemm_flops(*U, 1) * nz,
              nz * panel_bytes(b, c0, mT, upd) + gemm_bytes(*U, 1) * nz);
