@@ -440,6 +440,12 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
   __syncthreads();
 
   if (writer) {
+    // L_kk first: it does not wait for the inverse merge, so its stores overlap it (thread
+    // (r, q) = (tid % 64, tid / 64) writes column entries (r, q + 4 i))
+    const int wr = tid & (NB - 1), wq = tid >> 6;
+#pragma unroll 4
+    for (int cc = wq; cc < w; cc += 4)
+      if (wr < w) D[(long long)(c0 + wr) + (long long)(c0 + cc) * b] = (wr >= cc) ? S[wr][cc] : 0.0;
     // X21 = -X22 (L21 X11), needed only for the stored inverse
     t = frag32([&](int m, int k) { return S[HB + m][k]; },
                [&](int k, int n) { return X[k][n]; }, fm, fn);
@@ -453,12 +459,9 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
     for (int v = 0; v < 4; ++v) X[HB + fm + lm][fn + lk + 4 * v] = -t[v];
     __syncthreads();
     double* G = P.G + (long long)z * P.zG;
-    for (int e = tid; e < w * w; e += 256) {
-      const int r = e % w, c = e / w;
-      const long long off = (long long)(c0 + r) + (long long)(c0 + c) * b;
-      D[off] = (r >= c) ? S[r][c] : 0.0;
-      G[off] = (r >= c) ? X[r][c] : 0.0;
-    }
+#pragma unroll 4
+    for (int cc = wq; cc < w; cc += 4)
+      if (wr < w) G[(long long)(c0 + wr) + (long long)(c0 + cc) * b] = (wr >= cc) ? X[wr][cc] : 0.0;
     if (P.V && upd) {
       // V = X Q: wave q takes rows 16q..16q+15 (X is zero past w and above the diagonal)
       double* V = P.V + (long long)z * P.zV;
