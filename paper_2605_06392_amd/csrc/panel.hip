@@ -14,7 +14,7 @@ namespace {
 
 __global__ __launch_bounds__(256) void potrf_panel_kernel(const PanelArgs P) {
   __shared__ PanelSmem sm;
-  panel_body(P, blockIdx.x, gridDim.x, sm);
+  panel_body(P, blockIdx.x, gridDim.x, sm, blockIdx.z);
 }
 
 }  // namespace

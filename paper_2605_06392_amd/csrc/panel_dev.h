@@ -260,8 +260,9 @@ struct PanelSmem {
   int writer;
 };
 
-// One workgroup of a panel launch: workgroup bx of nbx (x index within chain blockIdx.z).
-__device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, PanelSmem& sm) {
+// One workgroup of a panel launch: workgroup bx of nbx of chain z.
+__device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, PanelSmem& sm,
+                                           int z) {
   double (*S)[LP] = sm.S;
   double (*X)[LP] = sm.X;
   double (*Q)[LP] = sm.Q;
@@ -270,7 +271,6 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
   int& writer = sm.writer;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lm = lane & 15, lk = lane >> 4;
-  const int z = blockIdx.z;
   if (P.zn && P.step >= P.zn[z]) return;  // chain z has no block at this step
   const int b = P.b, c0 = P.c0;
   const int w = min(NB, b - c0);

@@ -11,6 +11,8 @@
 #include "panel_dev.h"
 #include "profile.h"
 
+#include <climits>
+
 namespace adelia {
 
 namespace {
@@ -31,23 +33,32 @@ union StepSmem {
 static_assert(sizeof(GemmSmem) <= sizeof(panel_dev::PanelSmem),
               "the update's operand buffers fit in the panel's LDS");
 
-// pairs: the update's workgroups take two tiles of a row at once (gemm_walk_pairs; ntw counts
-// units), else one tile each (gemm_walk).
+// A one-dimensional grid: the panel workgroups of every chain first (npw per chain, the range
+// padded to a multiple of 8), so that all of them are placed in the first round of
+// workgroups, then ntw update workgroups per chain (ntw a multiple of 8, so that an update
+// workgroup's index within its chain and within the grid fall on the same XCD).  pairs: the
+// update's workgroups take two tiles of a row at once (gemm_walk_pairs; ntw covers units),
+// else one tile each (gemm_walk).
 __global__ __launch_bounds__(256) void panel_step_kernel(const panel_dev::PanelArgs P, int npw,
-                                                         const GemmArgs U, int ntw, int pairs) {
+                                                         const GemmArgs U, int ntw, int pairs,
+                                                         int nz) {
   static_assert(gemm_dev::NT == 256, "the panel and the tile GEMM share the workgroup shape");
   __shared__ StepSmem sm;
   const int bx = blockIdx.x;
-  if (bx < npw) {
-    panel_dev::panel_body(P, bx, npw, sm.p);
+  const int np = ((npw * nz + 7) & ~7);
+  if (bx < np) {
+    if (bx >= npw * nz) return;
+    const int z = bx / npw;
+    panel_dev::panel_body(P, bx - z * npw, npw, sm.p, z);
     return;
   }
-  const int z = blockIdx.z;
+  const int u = bx - np;
+  const int z = u / ntw;
   if (U.zn && U.step >= U.zn[z]) return;  // chain z has no block at this step
   if (pairs)
-    gemm_dev::gemm_walk_pairs(U, z, bx - npw, ntw, sm.g.As, sm.g.Bs, sm.g.Bs1);
+    gemm_dev::gemm_walk_pairs(U, z, u - z * ntw, ntw, sm.g.As, sm.g.Bs, sm.g.Bs1);
   else
-    gemm_dev::gemm_walk<true>(U, z, 0, true, bx - npw, ntw, sm.g.As, sm.g.Bs);
+    gemm_dev::gemm_walk<true>(U, z, 0, true, u - z * ntw, ntw, sm.g.As, sm.g.Bs);
 }
 
 }  // namespace
@@ -79,11 +90,14 @@ int launch_panel_step(double* D, long long zD, double* G, long long zG, double* 
   panel_dev::PanelArgs P{D, zD, G, zG, ldp, zLd, info, cnt, zn, step, b, c0, gcol0, T, zT, ldT,
                          mT, upd};
   const int npw = panel_workgroups(b, c0, mT);
-  int ntw = (int)(pairs ? units : tiles);
+  long long ntw = pairs ? units : tiles;
   if (maxw > 0 && ntw > maxw) ntw = maxw < 8 ? 8 : (maxw & ~7);
+  ntw = (ntw + 7) & ~7LL;
+  const long long grid = (((long long)npw * nz + 7) & ~7LL) + ntw * nz;
+  if (grid > INT_MAX) return -1;
   const ProfToken t = prof_begin(s);
-  hipLaunchKernelGGL(panel_step_kernel, dim3(npw + ntw, 1, nz), dim3(256), 0, s, P, npw, *U, ntw,
-                     pairs ? 1 : 0);
+  hipLaunchKernelGGL(panel_step_kernel, dim3((unsigned)grid), dim3(256), 0, s, P, npw, *U,
+                     (int)ntw, pairs ? 1 : 0, nz);
   if (t.valid)
     prof_end(t, s, PK_STEP, nz * panel_flops(b, c0, mT, upd) + gemm_flops(*U, 1) * nz,
              nz * panel_bytes(b, c0, mT, upd) + gemm_bytes(*U, 1) * nz);
