@@ -465,6 +465,13 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
   // straight into the rows of [L_B; L_C] of block i instead of a separate slot.
   c.b_in_place = fork || defer;
   const long long ldT = (long long)b + w.ap;
+  // Stored factors, side work after the sweep and fused steps (the look-ahead stream idle):
+  // D_{i+2} and B_{i+1} are assembled on the look-ahead stream beside block i's last steps,
+  // which leave CUs idle (they only read theta, into slots no launch of block i touches), so
+  // that block i+1 starts without them
+  const int npanel = (b + kPanel - 1) / kPanel;
+  const bool pre_asm = defer && side && w.slotsD == n && w.slotsLBC == n && c.b_in_place &&
+                       1LL * nz * panel_workgroups(b, 0, b + w.ap) <= side->la.cus;
   for (int i = 0; i < n; ++i) {
     // the sweep stays at most two blocks ahead of the side stream (without this wait: 46.1
     // against 44.4 ms per gradient at b = 1024), which also keeps a ring of three D slots safe
@@ -472,7 +479,10 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
       return ADELIA_E_HIP;
     const int td = i + 1 < n ? i + 1 : -1;
     const int tb = i < n - 1 ? i : -1;
-    if (td >= 0 || tb >= 0) {
+    if ((td >= 0 || tb >= 0) && pre_asm && i >= 1) {
+      // assembled beside block i - 1
+      if (hipStreamWaitEvent(s, side->la.tdone[i % 3], 0) != hipSuccess) return ADELIA_E_HIP;
+    } else if (td >= 0 || tb >= 0) {
       double* Dslot = w.D + (long long)((i + 1) % w.slotsD) * w.sD;
       const bool inplace = c.b_in_place;
       double* Bslot = inplace ? w.LBC + (long long)(i % w.slotsLBC) * ldT * b : w.Bin;
@@ -496,11 +506,27 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
       la.mark = side->ready[(i - 1) % 3];
       la.mark_step = 0;
     }
+    const bool ahead = pre_asm && i + 2 < n;  // D_{i+2} and B_{i+1} exist
+    if (ahead) {
+      la.mark = side->la.pdone[i % 3];
+      la.mark_step = std::max(0, npanel - 4);
+    }
     // carry-only: the diagonal block about to be factored is D_i - S_{i-1}
     if (w.carry && launch_copy2d(w.D + (long long)(i % w.slotsD) * w.sD, b, w.zD,
                                  w.Dc + (long long)i * bb, b, w.zDc, b, b, nz, s))
       return ADELIA_E_HIP;
     if (bta_forward_block(c, i, s, side ? &la : nullptr)) return ADELIA_E_HIP;
+    if (ahead) {
+      hipStream_t ts = side->la.ts;
+      if (hipStreamWaitEvent(ts, side->la.pdone[i % 3], 0) != hipSuccess) return ADELIA_E_HIP;
+      const ProfToken t = prof_begin(ts);
+      hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, ts, E.dev, i + 2, i + 1,
+                         w.D + (long long)(i + 2) * w.sD, w.zD,
+                         w.LBC + (long long)(i + 1) * ldT * b, w.zLBC, ldT, w.phi, w.tau);
+      if (t.valid) prof_end(t, ts, PK_ASSEMBLE, 0.0, 16.0 * bb * nz);
+      if (!LAUNCH_OK() || hipEventRecord(side->la.tdone[(i + 1) % 3], ts) != hipSuccess)
+        return ADELIA_E_HIP;
+    }
     if (w.carry && w.ap > 0 &&
         launch_copy2d(w.LBC + (long long)(i % w.slotsLBC) * ldT * b + b, ldT, w.zLBC,
                       w.LCz + (long long)i * w.ap * b, w.ap, w.zLCz, w.ap, b, nz, s))
