@@ -18,9 +18,10 @@
 //
 // Every workgroup reads the unfactored diagonal tile, so L_kk may only be written back once
 // all of them have loaded it: each workgroup bumps a per-chain counter after its load, and the
-// one that sees the count complete stores L_kk, L_kk^-1, the log-diagonal sum and the pivot
-// check (all workgroups compute bit-identical tiles) and resets the counter for the next
-// launch.  No workgroup ever waits on another.
+// one that sees the count complete stores L_kk, the log-diagonal sum and the pivot check (all
+// workgroups compute bit-identical tiles) and resets the counter for the next launch.  L_kk^-1,
+// which no workgroup of the launch reads, is merged and stored by workgroup 0 (it owns no row
+// tile).  No workgroup ever waits on another.
 #pragma once
 #include "common.h"
 #include <cmath>
@@ -49,7 +50,7 @@ struct PanelArgs {
   // apply the previous panel's rank-64 update to this panel's columns first (the trailing
   // update of the remaining columns then runs beside the next panels)
   int upd;
-  // if not null (and upd): the writer also stores V = L_kk^-1 Q (64 x 64, column-major, chain
+  // if not null (and upd): workgroup 0 also stores V = L_kk^-1 Q (64 x 64, column-major, chain
   // stride zV), Q the previous panel's columns on the diagonal rows, so that rows solved
   // elsewhere get R = A L_kk^-T - P V^T without the updated diagonal tile
   double* V; long long zV;
@@ -439,13 +440,30 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
   }
   __syncthreads();
 
+  // L_kk, the log-diagonal and the pivot check are stored by the writer (the last workgroup to
+  // have loaded the unfactored tile); the inverse, which no workgroup of this launch reads, by
+  // workgroup 0, which owns no row tile and would otherwise idle while the others solve theirs
+  // (when it is also the writer it does both).  Thread (r, q) = (tid % 64, tid / 64) stores the
+  // column entries (r, q + 4 i).
+  const int wr = tid & (NB - 1), wq = tid >> 6;
   if (writer) {
-    // L_kk first: it does not wait for the inverse merge, so its stores overlap it (thread
-    // (r, q) = (tid % 64, tid / 64) writes column entries (r, q + 4 i))
-    const int wr = tid & (NB - 1), wq = tid >> 6;
 #pragma unroll 4
     for (int cc = wq; cc < w; cc += 4)
       if (wr < w) D[(long long)(c0 + wr) + (long long)(c0 + cc) * b] = (wr >= cc) ? S[wr][cc] : 0.0;
+    if (wave == 0) {
+      const double dj = piv[lane];
+      double lg = (lane < w) ? 0.5 * log(dj) : 0.0;
+      const bool bad = (lane < w) && !(dj > 0.0);
+      const unsigned long long badmask = __ballot(bad);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) lg += __shfl_xor(lg, off, 64);
+      if (lane == 0) {
+        P.ldp[(long long)z * P.zLd] = lg;
+        if (badmask) atomicMin(P.info + z, (int32_t)(P.gcol0 + c0 + __ffsll((long long)badmask) - 1 + 1));
+      }
+    }
+  }
+  if (bx == 0) {
     // X21 = -X22 (L21 X11), needed only for the stored inverse
     t = frag32([&](int m, int k) { return S[HB + m][k]; },
                [&](int k, int n) { return X[k][n]; }, fm, fn);
@@ -471,18 +489,6 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
                              [&](int k, int n) { return Q[k][n]; }, 16 * wave, fn, NB);
 #pragma unroll
         for (int v = 0; v < 4; ++v) V[(16 * wave + lm) + (long long)(fn + lk + 4 * v) * NB] = t[v];
-      }
-    }
-    if (wave == 0) {
-      const double dj = piv[lane];
-      double lg = (lane < w) ? 0.5 * log(dj) : 0.0;
-      const bool bad = (lane < w) && !(dj > 0.0);
-      const unsigned long long badmask = __ballot(bad);
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) lg += __shfl_xor(lg, off, 64);
-      if (lane == 0) {
-        P.ldp[(long long)z * P.zLd] = lg;
-        if (badmask) atomicMin(P.info + z, (int32_t)(P.gcol0 + c0 + __ffsll((long long)badmask) - 1 + 1));
       }
     }
   }
