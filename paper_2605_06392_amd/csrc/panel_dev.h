@@ -18,9 +18,9 @@
 //
 // Every workgroup reads the unfactored diagonal tile, so L_kk may only be written back once
 // all of them have loaded it: each workgroup bumps a per-chain counter after its load, and the
-// one that sees the count complete stores L_kk, the log-diagonal sum and the pivot check (all
-// workgroups compute bit-identical tiles) and resets the counter for the next launch.  L_kk^-1,
-// which no workgroup of the launch reads, is merged and stored by workgroup 0 (it owns no row
+// one that sees the count complete stores L_kk (all workgroups compute bit-identical tiles) and
+// resets the counter for the next launch.  L_kk^-1, the log-diagonal sum and the pivot check,
+// which no workgroup of the launch reads, are formed and stored by workgroup 0 (it owns no row
 // tile).  No workgroup ever waits on another.
 #pragma once
 #include "common.h"
@@ -440,8 +440,8 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
   }
   __syncthreads();
 
-  // L_kk, the log-diagonal and the pivot check are stored by the writer (the last workgroup to
-  // have loaded the unfactored tile); the inverse, which no workgroup of this launch reads, by
+  // L_kk is stored by the writer (the last workgroup to have loaded the unfactored tile); the
+  // inverse, the log-diagonal and the pivot check, which no workgroup of this launch reads, by
   // workgroup 0, which owns no row tile and would otherwise idle while the others solve theirs
   // (when it is also the writer it does both).  Thread (r, q) = (tid % 64, tid / 64) stores the
   // column entries (r, q + 4 i).
@@ -450,6 +450,8 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
 #pragma unroll 4
     for (int cc = wq; cc < w; cc += 4)
       if (wr < w) D[(long long)(c0 + wr) + (long long)(c0 + cc) * b] = (wr >= cc) ? S[wr][cc] : 0.0;
+  }
+  if (bx == 0) {
     if (wave == 0) {
       const double dj = piv[lane];
       double lg = (lane < w) ? 0.5 * log(dj) : 0.0;
@@ -462,8 +464,6 @@ __device__ __forceinline__ void panel_body(const PanelArgs& P, int bx, int nbx, 
         if (badmask) atomicMin(P.info + z, (int32_t)(P.gcol0 + c0 + __ffsll((long long)badmask) - 1 + 1));
       }
     }
-  }
-  if (bx == 0) {
     // X21 = -X22 (L21 X11), needed only for the stored inverse
     t = frag32([&](int m, int k) { return S[HB + m][k]; },
                [&](int k, int n) { return X[k][n]; }, fm, fn);
