@@ -111,10 +111,12 @@ InlaWs layout(const ModelDev& M, int batch, bool grad, char* base, bool carry = 
   const int n = M.nt;
   const bool stored = grad && !w.carry;  // every block's factor kept
   w.defer = stored;
-  // carry-only: rings of three blocks for the pipelined reverse pass
-  w.slotsD = stored ? n : (w.carry ? 3 : 2);
+  // carry-only: rings of three blocks for the pipelined reverse pass; an objective: three D
+  // slots and two [L_B; L_C] slots, so that D_{i+2} and B_{i+1} can be assembled while block
+  // i is factored (D_{i-1} and [L_B; L_C]_{i-1} are no longer read by then)
+  w.slotsD = stored ? n : 3;
   w.slotsB = 1;
-  w.slotsLBC = stored ? n : (w.carry ? 3 : 1);
+  w.slotsLBC = stored ? n : (w.carry ? 3 : 2);
   w.slotsG = stored ? n : (w.carry ? 3 : 1);
   w.slotsW = stored ? n : 3;
   w.slotsZD = stored ? n : 3;
@@ -461,16 +463,19 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
   }
   hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, s, E.dev, 0, -1, w.D, w.zD,
                      w.Bin, w.zB, (long long)b, w.phi, w.tau);
-  // With the side stream (a gradient: every block keeps its [L_B; L_C] slot), B_i is assembled
-  // straight into the rows of [L_B; L_C] of block i instead of a separate slot.
-  c.b_in_place = fork || defer;
+  // B_i is assembled straight into the rows of [L_B; L_C] of block i instead of a separate
+  // slot (then copied) when that slot is free before block i starts: a gradient keeps every
+  // block's slot, an objective a ring of two
+  const bool ring = !w.grad && w.slotsD >= 3 && w.slotsLBC >= 2;
+  c.b_in_place = fork || defer || ring;
   const long long ldT = (long long)b + w.ap;
-  // Stored factors, side work after the sweep and fused steps (the look-ahead stream idle):
-  // D_{i+2} and B_{i+1} are assembled on the look-ahead stream beside block i's last steps,
-  // which leave CUs idle (they only read theta, into slots no launch of block i touches), so
-  // that block i+1 starts without them
+  // Fused steps (the look-ahead stream idle) and stored factors with the side work after the
+  // sweep, or an objective's rings: D_{i+2} and B_{i+1} are assembled on the look-ahead stream
+  // beside block i's last steps, which leave CUs idle (they only read theta, into slots no
+  // launch of block i touches), so that block i+1 starts without them
   const int npanel = (b + kPanel - 1) / kPanel;
-  const bool pre_asm = defer && side && w.slotsD == n && w.slotsLBC == n && c.b_in_place &&
+  const bool pre_asm = side && c.b_in_place &&
+                       (defer ? w.slotsD == n && w.slotsLBC == n : ring) &&
                        1LL * nz * panel_workgroups(b, 0, b + w.ap) <= side->la.cus;
   for (int i = 0; i < n; ++i) {
     // the sweep stays at most two blocks ahead of the side stream (without this wait: 46.1
@@ -521,8 +526,9 @@ int run_forward(const Eval& E, const InlaWs& w, const double* theta, hipStream_t
       if (hipStreamWaitEvent(ts, side->la.pdone[i % 3], 0) != hipSuccess) return ADELIA_E_HIP;
       const ProfToken t = prof_begin(ts);
       hipLaunchKernelGGL(assemble_blocks_kernel, agrid, dim3(64), 0, ts, E.dev, i + 2, i + 1,
-                         w.D + (long long)(i + 2) * w.sD, w.zD,
-                         w.LBC + (long long)(i + 1) * ldT * b, w.zLBC, ldT, w.phi, w.tau);
+                         w.D + (long long)((i + 2) % w.slotsD) * w.sD, w.zD,
+                         w.LBC + (long long)((i + 1) % w.slotsLBC) * ldT * b, w.zLBC, ldT,
+                         w.phi, w.tau);
       if (t.valid) prof_end(t, ts, PK_ASSEMBLE, 0.0, 16.0 * bb * nz);
       if (!LAUNCH_OK() || hipEventRecord(side->la.tdone[(i + 1) % 3], ts) != hipSuccess)
         return ADELIA_E_HIP;
