@@ -271,3 +271,34 @@ def test_autotune_and_batch_argument_codes():
     assert L.inla_batch_objective(None, P, P, P, P, 1 << 30, None) == -1
     assert L.inla_batch_grad(None, P, P, P, P, P, 1 << 30, None) == -1
     assert L.inla_batch_workspace_bytes(None, 1) == 0
+
+
+def test_product_path_has_no_host_fallback():
+    """The bindings only marshal arguments: without the built library, or without a GPU, every
+    entry of the product path raises instead of computing anything on the host."""
+    import subprocess
+    import sys
+    code = (
+        "from paper_2605_06392_amd import _lib\n"
+        "_lib.LIB_PATH = '/nonexistent/libadelia.so'\n"
+        "_lib._lib = None\n"
+        "try:\n"
+        "    _lib.lib()\n"
+        "except RuntimeError as e:\n"
+        "    assert 'no CPU fallback' in str(e), e\n"
+        "    print('raised')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                       cwd=ROOT)
+    assert r.returncode == 0 and r.stdout.strip() == "raised", r.stderr
+    from paper_2605_06392_amd._lib import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("library not built")
+    import torch
+    from workloads import named_config
+    from paper_2605_06392_amd.inla import InlaModel
+    spec = named_config("uni_6x5_nt5", 0)
+    with pytest.raises(ValueError):
+        InlaModel(spec, device="cpu")
+    if not torch.cuda.is_available():
+        with pytest.raises(RuntimeError):
+            InlaModel(spec, device="cuda:0")
